@@ -1,0 +1,191 @@
+/*
+ * hfmm.h -- C-ABI of libhfmm.so: a 2-D Helmholtz fast multipole method used
+ * as a matrix-free preconditioner (coupled to a boundary-element correction
+ * for Dirichlet boundaries) inside right-preconditioned restarted flexible
+ * GMRES on the 5-point finite-difference Helmholtz system.  MI355X (gfx950).
+ *
+ * Paper: Ibeid, Yokota, Keyes, "A Matrix-free Preconditioner for the Helmholtz
+ * Equation based on the Fast Multipole Method".
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Pointers named d_* are DEVICE pointers owned by the caller.  The library
+ *   never frees them and keeps no reference to them after the call returns;
+ *   the caller keeps them alive until the work queued on `stream` completes.
+ * - Complex arrays are interleaved (re, im).  Multi-column arrays are
+ *   column-major: column c of an n x nrhs array starts at element c * n.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls queue their
+ *   kernels on it and return without synchronising unless stated otherwise.
+ * - Every call returns an hfmm_status.  Invalid arguments are rejected with
+ *   HFMM_ERR_ARG before any kernel is launched, except where a check needs
+ *   device data (stated at the call).  HIP failures map to HFMM_ERR_HIP.
+ *   hfmm_last_error() returns a thread-local message for the last non-OK
+ *   status of the calling thread.  No C++ exception crosses this interface.
+ * - Handles are not thread-safe; use one stream per handle at a time.
+ */
+#ifndef HFMM_H
+#define HFMM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HFMM_OK = 0,
+  HFMM_NOT_CONVERGED = 1,   /* a solve ended at maxit; x holds the last iterate */
+  HFMM_ERR_ARG = -1,        /* invalid argument (message says which) */
+  HFMM_ERR_HIP = -2,        /* a HIP runtime call failed */
+  HFMM_ERR_OOM = -3,        /* device allocation failed */
+  HFMM_ERR_STATE = -4,      /* handle used in a state that does not allow the call */
+  HFMM_ERR_INTERNAL = -5,   /* internal inconsistency (a bug) */
+  HFMM_ERR_NUMERIC = -6     /* NaN/Inf met in a solve, or a singular boundary matrix */
+} hfmm_status;
+
+typedef enum { HFMM_FP64 = 0, HFMM_FP32 = 1 } hfmm_precision;
+
+typedef struct hfmm_tree_s* hfmm_tree;
+typedef struct hfmm_solver_s* hfmm_solver;
+
+typedef struct {
+  int32_t iters;          /* Arnoldi steps (max over right-hand sides) */
+  int32_t restarts;       /* restart cycles run (max over right-hand sides) */
+  int32_t converged;      /* 1 if every right-hand side met rtol */
+  int32_t nrhs;
+  double rel_res_true;    /* max over columns of ||b - A x|| / ||b|| at exit */
+  double rel_res_est;     /* max over columns of the Givens estimate at exit */
+  double ms_precond;      /* device time in preconditioner applies (ms) */
+  double ms_total;        /* wall time of the solve call (ms) */
+} hfmm_solve_info;
+
+/* Thread-local text of the last non-OK status on this thread ("" if none). */
+const char* hfmm_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t hfmm_version(void);
+
+/* ------------------------------------------------------------------------
+ * Hierarchical decomposition (Sec. 5.1.1): uniform quad-tree over the root
+ * square [x0, x0+side] x [y0, y0+side], Morton-ordered leaves.
+ *
+ * d_xy      n points, (x, y) interleaved FP64, device, caller order.
+ * leaf_size target mean leaf occupancy: depth L = max(2, ceil(log4(n/leaf)))
+ *           (smallest L with leaf*4^L >= n); leaf_size = 0 gives a single leaf
+ *           (every pair is near: the all-pairs sum).  L <= 12.
+ * out       receives a library-owned handle (sorted points, permutation, leaf
+ *           offsets, and a cache of per-(k, p, precision) translation plans).
+ * Errors: n < 1, side <= 0, leaf_size < 0, non-finite or out-of-root
+ * coordinates (checked on the device by the first kernel; the call then
+ * returns HFMM_ERR_ARG and creates nothing).  Synchronises `stream`.
+ * ---------------------------------------------------------------------- */
+hfmm_status hfmm_build_tree(const double* d_xy, int64_t n, double x0, double y0, double side,
+                            int32_t leaf_size, hipStream_t stream, hfmm_tree* out);
+
+/* Depth and counts of a tree: any output pointer may be NULL. */
+hfmm_status hfmm_tree_info(hfmm_tree t, int32_t* levels, int64_t* n_points, int64_t* n_leaves,
+                           int32_t* max_leaf_count);
+
+/* Copy the tree's sort permutation (sorted slot -> caller index, int32, n) and
+ * leaf offsets (int32, n_leaves + 1, Morton order) to device buffers.  Either
+ * pointer may be NULL.  Async on stream. */
+hfmm_status hfmm_tree_export(hfmm_tree t, int32_t* d_perm, int32_t* d_leaf_off, hipStream_t stream);
+
+hfmm_status hfmm_tree_destroy(hfmm_tree t);
+
+/* ------------------------------------------------------------------------
+ * N-body sum (Sec. 5.1, the N-body sum) with the 2-D Helmholtz kernel
+ * G = (i/4) H0^(1)(k r) (Sec. 5.2), evaluated by the FMM of Sec. 5.1.2:
+ *   phi[i, c] = sum_{j : |x_i - x_j| > 0} q[j, c] (i/4) H0^(1)(k |x_i - x_j|)
+ * in the caller's point order.  Pairs at zero distance add nothing.
+ *
+ * k     wavenumber > 0.   p  leaf expansion order, 1..40; level l uses
+ *       p_l = p + floor(k d_l / 2) (d_l the box diagonal), 2 p_l + 1 terms.
+ * prec  HFMM_FP64: q, phi complex128, FP64 arithmetic.
+ *       HFMM_FP32: q, phi complex64, FP32 arithmetic.
+ * d_q   n x nrhs complex, device.   d_phi  n x nrhs complex, overwritten.
+ * The first call for a (k, p, prec) builds and caches its translation plan
+ * (host tables, uploaded synchronously).  Async on stream afterwards.
+ * Errors: k <= 0, p out of range, nrhs < 1, leaves too large for k
+ * (k * leaf_side / sqrt(2) above 6), FP32 tables that
+ * would overflow.
+ * ---------------------------------------------------------------------- */
+hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
+                           const void* d_q, void* d_phi, int32_t nrhs, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * 5-point FD Helmholtz operator (the sparse system A x = b of Sec. 2) on the
+ * n x n interior grid of the unit square, zero Dirichlet ghosts:
+ *   (A x)_ij = (4 x_ij - x_{i-1,j} - x_{i+1,j} - x_{i,j-1} - x_{i,j+1}) / h^2 - k2_ij x_ij
+ * d_k2   n*n FP64 k^2 field (device), or NULL to use k2_const.
+ * d_x    n*n x nrhs complex128, lexicographic (x index fastest).
+ * d_y    n*n x nrhs complex128, overwritten.  Always FP64.  Async.
+ * ---------------------------------------------------------------------- */
+hfmm_status hfmm_fd_helmholtz_matvec(int32_t n, double h, const double* d_k2, double k2_const,
+                                     const double* d_x, double* d_y, int32_t nrhs, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Solver for A u = f on the n x n grid, h = 1/(n+1), with the FMM-BEM
+ * preconditioner of Sec. 5.2-5.3 at the constant wavenumber k0:
+ *   z = M^{-1} r:  pass 1  V = FMM(sources h^2 r at the interior nodes)
+ *                  boundary  q = -S^{-1} V_Gamma (Dirichlet boundary equation)
+ *                  pass 2  z = V_Omega + S_vol r + FMM(sources w q at the
+ *                          boundary element midpoints), interior equation.
+ * Boundary: 4(n+1) constant elements of width w = h, midpoint collocation, no
+ * corner nodes (Sec. 5.3); S diagonal from the analytic formula of Sec. 5.3.
+ * S is assembled and inverted in FP64 on the device at creation.
+ *
+ * d_k2/k2_const  the operator's k^2 field (copied), as in the matvec.
+ * k0             preconditioner wavenumber (> 0).
+ * p, leaf_size   FMM order and leaf occupancy (leaf_size >= 1).
+ * precond_prec   HFMM_FP32: the whole preconditioner runs in complex64 (the
+ *                Krylov part stays FP64); HFMM_FP64: all FP64.
+ * nrhs           columns solved together (independent Krylov spaces, one
+ *                batched preconditioner apply).
+ * Synchronises `stream`.
+ * ---------------------------------------------------------------------- */
+hfmm_status hfmm_solver_create(int32_t n, double h, const double* d_k2, double k2_const, double k0,
+                               int32_t p, int32_t leaf_size, hfmm_precision precond_prec,
+                               int32_t nrhs, hipStream_t stream, hfmm_solver* out);
+
+/* Replace the operator's k^2 field (preconditioner unchanged).  Async. */
+hfmm_status hfmm_solver_set_k2(hfmm_solver s, const double* d_k2, double k2_const, hipStream_t stream);
+
+/* z = M^{-1} r for nrhs columns (complex128 n*n x nrhs in and out).  Async. */
+hfmm_status hfmm_precond_apply(hfmm_solver s, const double* d_r, double* d_z, int32_t nrhs,
+                               hipStream_t stream);
+
+/* Right-preconditioned FGMRES(restart) (Sec. 3-4): x0 from d_x (zeros for the
+ * paper's setting), stop when ||b - A x|| / ||b|| <= rtol for every column
+ * (true residual, checked at the end of each cycle), at most maxit Arnoldi
+ * steps.  CGS2 orthogonalisation, complex Givens rotations, all FP64.
+ * d_b, d_x   n*n x nrhs complex128 (nrhs as created).
+ * transpose  1 solves A^T x = b with the same preconditioner.  For this FD
+ *            operator with a real k^2 field A^T = A, and M^{-1} is complex
+ *            symmetric, so both settings run the same iteration.
+ * info       host struct, filled on return (may be NULL).
+ * Returns HFMM_OK, HFMM_NOT_CONVERGED, or an error.  Synchronises `stream`. */
+hfmm_status hfmm_fgmres_solve(hfmm_solver s, const double* d_b, double* d_x, int32_t restart,
+                              int32_t maxit, double rtol, int32_t transpose, hfmm_solve_info* info,
+                              hipStream_t stream);
+
+/* The same solve for nprob solvers at once: d_b[i], d_x[i] belong to s[i].
+ * use_graph = 1 captures one Arnoldi step of every problem into a hipGraph
+ * that is replayed (kernels of finished problems exit at once); 0 runs the
+ * same kernels eagerly.  info has nprob entries.  Synchronises `stream`. */
+hfmm_status hfmm_fgmres_solve_batched(hfmm_solver* s, int32_t nprob, const double* const* d_b,
+                                      double* const* d_x, int32_t restart, int32_t maxit, double rtol,
+                                      int32_t use_graph, hfmm_solve_info* info, hipStream_t stream);
+
+/* Boundary-matrix diagnostics of a solver: N_Gamma and the 1-norm condition
+ * estimate ||S||_1 ||S^{-1}||_1 (host outputs, may be NULL). */
+hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels);
+
+hfmm_status hfmm_solver_destroy(hfmm_solver s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFMM_H */

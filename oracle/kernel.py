@@ -21,7 +21,7 @@ def green(r, k):
     return 0.25j * hankel1(0, k * np.asarray(r, dtype=np.float64))
 
 
-def direct_sum(src, q, k, tgt=None, chunk=256):
+def direct_sum(src, q, k, tgt=None, chunk=None):
     """phi[i, c] = sum_{j : |t_i - s_j| > 0} q[j, c] G(t_i, s_j)   (Sec. 5.1 N-body sum).
 
     src : (N, 2) float64 source positions.
@@ -35,6 +35,8 @@ def direct_sum(src, q, k, tgt=None, chunk=256):
     if squeeze:
         q = q[:, None]
     tgt = src if tgt is None else np.asarray(tgt, dtype=np.float64)
+    if chunk is None:  # bound the (targets x sources) work arrays to ~2^22 entries
+        chunk = max(1, min(256, (1 << 22) // max(1, src.shape[0])))
     out = np.zeros((tgt.shape[0], q.shape[1]), dtype=np.complex128)
     for a in range(0, tgt.shape[0], chunk):
         t = tgt[a:a + chunk]

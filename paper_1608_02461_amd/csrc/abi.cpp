@@ -1,0 +1,226 @@
+// extern "C" entry points of libhfmm.so (declared in include/hfmm.h).
+// Every call converts C++ exceptions into an hfmm_status and a thread-local
+// message; nothing throws across the interface.
+#include <new>
+#include <string>
+
+#include "solver.h"
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace hfmm {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace hfmm
+
+struct hfmm_tree_s {
+  std::unique_ptr<hfmm::Tree> t;
+};
+struct hfmm_solver_s {
+  std::unique_ptr<hfmm::Solver> s;
+};
+
+#define HFMM_GUARD_BEGIN try {
+#define HFMM_GUARD_END                                              \
+  }                                                                 \
+  catch (const hfmm::Error& e) {                                    \
+    hfmm::set_last_error(e.what());                                 \
+    return e.code;                                                  \
+  }                                                                 \
+  catch (const std::bad_alloc&) {                                   \
+    hfmm::set_last_error("host allocation failed");                 \
+    return HFMM_ERR_OOM;                                            \
+  }                                                                 \
+  catch (const std::exception& e) {                                 \
+    hfmm::set_last_error(std::string("internal: ") + e.what());     \
+    return HFMM_ERR_INTERNAL;                                       \
+  }                                                                 \
+  catch (...) {                                                     \
+    hfmm::set_last_error("internal: unknown exception");            \
+    return HFMM_ERR_INTERNAL;                                       \
+  }
+
+extern "C" {
+
+const char* hfmm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t hfmm_version(void) { return 100; }
+
+hfmm_status hfmm_build_tree(const double* d_xy, int64_t n, double x0, double y0, double side, int32_t leaf_size,
+                            hipStream_t stream, hfmm_tree* out) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(out != nullptr, "build_tree: out is NULL");
+  *out = nullptr;
+  auto h = std::make_unique<hfmm_tree_s>();
+  h->t = hfmm::build_tree(d_xy, n, x0, y0, side, leaf_size, stream);
+  *out = h.release();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_tree_info(hfmm_tree t, int32_t* levels, int64_t* n_points, int64_t* n_leaves,
+                           int32_t* max_leaf_count) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "tree_info: NULL tree");
+  if (levels) *levels = t->t->L;
+  if (n_points) *n_points = t->t->n;
+  if (n_leaves) *n_leaves = t->t->nleaves;
+  if (max_leaf_count) *max_leaf_count = t->t->max_leaf;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_tree_export(hfmm_tree t, int32_t* d_perm, int32_t* d_leaf_off, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "tree_export: NULL tree");
+  const hfmm::Tree& tr = *t->t;
+  if (d_perm) HFMM_HIP(hipMemcpyAsync(d_perm, tr.perm.p, tr.n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+  if (d_leaf_off)
+    HFMM_HIP(hipMemcpyAsync(d_leaf_off, tr.leaf_off.p, (tr.nleaves + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                            stream));
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_tree_destroy(hfmm_tree t) {
+  HFMM_GUARD_BEGIN
+  delete t;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q, void* d_phi,
+                           int32_t nrhs, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "fmm_apply: NULL tree");
+  HFMM_REQUIRE(prec == HFMM_FP64 || prec == HFMM_FP32, "fmm_apply: unknown precision");
+  HFMM_REQUIRE(nrhs >= 1 && nrhs <= 1024, "fmm_apply: nrhs must be in [1, 1024]");
+  HFMM_REQUIRE(std::isfinite(k) && k > 0, "fmm_apply: k must be finite and > 0");
+  HFMM_REQUIRE(p >= 1 && p <= 40, "fmm_apply: p must be in [1, 40]");
+  HFMM_REQUIRE(d_q != nullptr && d_phi != nullptr, "fmm_apply: NULL array");
+  if (prec == HFMM_FP64)
+    hfmm::fmm_apply<double>(*t->t, k, p, static_cast<const double2*>(d_q), static_cast<double2*>(d_phi), nrhs,
+                            stream);
+  else
+    hfmm::fmm_apply<float>(*t->t, k, p, static_cast<const float2*>(d_q), static_cast<float2*>(d_phi), nrhs, stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_fd_helmholtz_matvec(int32_t n, double h, const double* d_k2, double k2_const, const double* d_x,
+                                     double* d_y, int32_t nrhs, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(d_k2 != nullptr || std::isfinite(k2_const), "fd_matvec: k2_const must be finite");
+  hfmm::fd_matvec(n, h, d_k2, k2_const, reinterpret_cast<const double2*>(d_x), reinterpret_cast<double2*>(d_y), nrhs,
+                  stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_create(int32_t n, double h, const double* d_k2, double k2_const, double k0, int32_t p,
+                               int32_t leaf_size, hfmm_precision precond_prec, int32_t nrhs, hipStream_t stream,
+                               hfmm_solver* out) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(out != nullptr, "solver_create: out is NULL");
+  *out = nullptr;
+  HFMM_REQUIRE(precond_prec == HFMM_FP64 || precond_prec == HFMM_FP32, "solver_create: unknown precision");
+  auto hs = std::make_unique<hfmm_solver_s>();
+  hs->s = hfmm::solver_create(n, h, d_k2, k2_const, k0, p, leaf_size, precond_prec == HFMM_FP32, nrhs, stream);
+  *out = hs.release();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_set_k2(hfmm_solver s, const double* d_k2, double k2_const, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "set_k2: NULL solver");
+  hfmm::solver_set_k2(*s->s, d_k2, k2_const, stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_precond_apply(hfmm_solver s, const double* d_r, double* d_z, int32_t nrhs, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "precond_apply: NULL solver");
+  HFMM_REQUIRE(nrhs == s->s->nrhs, "precond_apply: nrhs differs from the solver's");
+  HFMM_REQUIRE(d_r != nullptr && d_z != nullptr && d_r != d_z, "precond_apply: NULL or aliased arrays");
+  hfmm::Solver& sv = *s->s;
+  hfmm::precond_apply(sv, reinterpret_cast<const double2*>(d_r), sv.nn, reinterpret_cast<double2*>(d_z), sv.nn,
+                      nullptr, nullptr, stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_fgmres_solve(hfmm_solver s, const double* d_b, double* d_x, int32_t restart, int32_t maxit,
+                              double rtol, int32_t transpose, hfmm_solve_info* info, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "fgmres_solve: NULL solver");
+  HFMM_REQUIRE(transpose == 0 || transpose == 1, "fgmres_solve: transpose must be 0 or 1");
+  // A^T = A for the FD operator with a real k^2 field, and M^{-1} is complex
+  // symmetric, so the transposed solve is the same iteration.
+  hfmm::Solver* sp = s->s.get();
+  const double2* b = reinterpret_cast<const double2*>(d_b);
+  double2* x = reinterpret_cast<double2*>(d_x);
+  return hfmm::fgmres(&sp, 1, &b, &x, restart, maxit, rtol, false, info, stream);
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_fgmres_solve_batched(hfmm_solver* s, int32_t nprob, const double* const* d_b, double* const* d_x,
+                                      int32_t restart, int32_t maxit, double rtol, int32_t use_graph,
+                                      hfmm_solve_info* info, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && d_b != nullptr && d_x != nullptr, "solve_batched: NULL array");
+  HFMM_REQUIRE(nprob >= 1, "solve_batched: nprob must be >= 1");
+  std::vector<hfmm::Solver*> sp(nprob);
+  std::vector<const double2*> b(nprob);
+  std::vector<double2*> x(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    HFMM_REQUIRE(s[i] != nullptr && s[i]->s, "solve_batched: NULL solver");
+    for (int j = 0; j < i; ++j) HFMM_REQUIRE(s[j] != s[i], "solve_batched: a solver appears twice");
+    sp[i] = s[i]->s.get();
+    b[i] = reinterpret_cast<const double2*>(d_b[i]);
+    x[i] = reinterpret_cast<double2*>(d_x[i]);
+  }
+  hipStream_t st = stream;
+  hipStream_t own = nullptr;
+  if (use_graph && st == nullptr) {  // the legacy default stream cannot be captured
+    HFMM_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    st = own;
+  }
+  hfmm_status r;
+  try {
+    r = hfmm::fgmres(sp.data(), nprob, b.data(), x.data(), restart, maxit, rtol, use_graph != 0, info, st);
+  } catch (...) {
+    if (own) {
+      (void)hipStreamSynchronize(own);
+      (void)hipStreamDestroy(own);
+    }
+    throw;
+  }
+  if (own) {
+    HFMM_HIP(hipStreamSynchronize(own));
+    HFMM_HIP(hipStreamDestroy(own));
+  }
+  return r;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "solver_info: NULL solver");
+  if (n_gamma) *n_gamma = (int32_t)s->s->ng;
+  if (cond_S) *cond_S = s->s->condS;
+  if (levels) *levels = s->s->tree->L;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_destroy(hfmm_solver s) {
+  HFMM_GUARD_BEGIN
+  delete s;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+}  // extern "C"

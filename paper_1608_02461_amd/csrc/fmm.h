@@ -1,0 +1,79 @@
+// FMM translation plan and the sorted-order FMM driver (Sec. 5.1.2:
+// P2M, M2M, M2L, L2L, L2P and P2P on the uniform quad-tree).
+//
+// Expansions are partial-wave (Graf) expansions about box centres with
+// in_v(z) = J_v(k|z|) e^{iv arg z}, out_v(z) = H_v(k|z|) e^{iv arg z}:
+//   P2M  M_n  = sum_j q_j J_n(k rho_j) e^{-i n phi_j}
+//   M2M  M'_l = sum_n M_n in_{n-l}(c_parent - c_child)
+//   M2L  L_m  = sum_n M_n out_{n-m}(c_target - c_source)
+//   L2L  L'_l = sum_m L_m in_{m-l}(c_child - c_parent)
+//   L2P  phi  = (i/4) sum_m L_m in_m(x - c)
+// Level l keeps n = -p_l..p_l with p_l = p + floor(k d_l / 2).  Stored
+// coefficients are scaled for FP32 range: Mt_n = M_n / s_l^|n| and
+// Lt_m = L_m s_l^|m| with s_l = min(1, k side_l); the tables carry the
+// matching factors, so the same code runs in FP32 and FP64.
+#pragma once
+
+#include "special.h"
+#include "tree.h"
+
+namespace hfmm {
+
+struct LevelInfo {
+  int p = 0;           // order p_l
+  int P = 0;           // 2 p_l + 1 coefficients
+  double s = 1;        // scale s_l
+  int64_t coef = 0;    // offset of the level in coefficient units (per column)
+  int64_t box0 = 0;    // offset of the level in the per-box flag array
+};
+
+template <class T>
+struct FmmPlan : PlanBase {
+  double k = 0;
+  int p = 0, L = 0;
+  std::vector<LevelInfo> lv;
+  int64_t coef_total = 0;   // sum over levels 2..L of 4^l P_l
+  int64_t flag_total = 0;   // sum over levels 0..L of 4^l
+  DevBuf<cplx<T>> m2m, l2l, m2l;
+  std::vector<int64_t> m2m_off, l2l_off, m2l_off;
+  DevBuf<T> series;         // (p_L + 1) x (K + 1): [n][0] = 1/(n+1), [n][j] = 1/(j (n+j))
+  int K = 0;
+  // near field
+  bool near_fast = false;
+  NearPoly poly;
+  int G = 1;                // lanes per target in P2P
+  // work storage
+  DevBuf<cplx<T>> M, Lc;
+  int nrhs_cap = 0;
+  DevBuf<cplx<T>> qs, phis;  // sorted scratch for the public apply
+  double max_table = 0;
+
+  void ensure_work(int nrhs) {
+    if (nrhs > nrhs_cap) {
+      M.alloc((size_t)coef_total * nrhs);
+      Lc.alloc((size_t)coef_total * nrhs);
+      nrhs_cap = nrhs;
+    }
+  }
+};
+
+template <class T>
+FmmPlan<T>& get_plan(Tree& t, double k, int p);
+
+// phi (+)= FMM(q) on sorted arrays (column-major N x nrhs).  `flags` (or
+// NULL for "every box") is a per-level array of 4^l bytes per level
+// (concatenated from level 0) marking boxes that hold sources; `accumulate`
+// adds into phi instead of overwriting.  `alive` (device int or NULL):
+// when it holds 0 every kernel of the call returns at once.
+template <class T>
+void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
+                bool accumulate, hipStream_t st, const int* alive = nullptr);
+
+// Per-level source flags for the points whose caller index lies in [lo, hi).
+void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipStream_t st);
+
+// Public apply in caller order.
+template <class T>
+void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st);
+
+}  // namespace hfmm

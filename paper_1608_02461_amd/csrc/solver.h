@@ -1,0 +1,54 @@
+// FD Helmholtz operator, FMM-BEM preconditioner and device FGMRES.
+#pragma once
+
+#include <complex>
+
+#include "fmm.h"
+
+namespace hfmm {
+
+void fd_matvec(int n, double h, const double* d_k2, double k2c, const double2* x, double2* y, int nrhs,
+               hipStream_t st);
+
+struct Solver {
+  int n = 0;
+  double h = 0;
+  int64_t nn = 0;   // interior unknowns n*n
+  int64_t ng = 0;   // boundary elements 4(n+1)
+  int nrhs = 1;
+  double k0 = 0;
+  int p = 0, leaf = 0;
+  bool fp32 = false;
+  DevBuf<double> k2;
+  double k2c = 0;
+  bool field = false;
+  std::unique_ptr<Tree> tree;
+  DevBuf<uint8_t> flags1, flags2;  // per-level source flags: interior / boundary sources
+  DevBuf<float2> B32;              // -w S^{-1}, ng x ng row-major
+  DevBuf<double2> B64;
+  std::complex<double> svol;       // volume self term
+  double condS = 0;
+  // preconditioner scratch in sorted order (nrhs columns)
+  DevBuf<float2> q1f, phif, q2f, vgf;
+  DevBuf<double2> q1d, phid, q2d, vgd;
+  // Krylov workspace
+  int m = 0;
+  int nblk = 0;
+  DevBuf<double2> V, Z, H, sn, g, y, hcur, part;
+  DevBuf<double> cs, bnorm, est, rn, npart;
+  DevBuf<int> active, jj, iters, state;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  ~Solver();
+};
+
+std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, double k2c, double k0, int p, int leaf,
+                                      bool fp32, int nrhs, hipStream_t st);
+void solver_set_k2(Solver& s, const double* d_k2, double k2c, hipStream_t st);
+// z = M^{-1} r; r, z column stride rs, zs (complex elements).  j_from_state: when
+// non-NULL, column c reads r + c*rs + state[0]*nn and writes z + c*zs + state[0]*nn.
+void precond_apply(Solver& s, const double2* r, int64_t rs, double2* z, int64_t zs, const int* jstate,
+                   const int* alive, hipStream_t st);
+hfmm_status fgmres(Solver** s, int nprob, const double2* const* b, double2* const* x, int m, int maxit, double rtol,
+                   bool use_graph, hfmm_solve_info* info, hipStream_t st);
+
+}  // namespace hfmm

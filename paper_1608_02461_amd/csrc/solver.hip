@@ -1,0 +1,1002 @@
+// FD operator, BEM-coupled FMM preconditioner, and FGMRES on the device.
+//
+// Preconditioner (Sec. 5.2-5.3, Dirichlet data u = 0 on the boundary):
+//   pass 1   V = FMM(h^2 r at interior nodes) at every node,
+//   boundary q' = B V_Gamma with B = -w S^{-1} (S assembled and inverted in
+//            FP64 once; the boundary equation of Sec. 5.2 with u = 0),
+//   pass 2   phi += FMM(q' at the boundary midpoints) (interior equation),
+//   z        = phi_Omega + S_vol r.
+// FGMRES (Sec. 3-4, right preconditioning, flexible form): all FP64, CGS2,
+// complex Givens rotations.  The Arnoldi step reads its index j and the
+// per-column activity flags from device memory, so one step of any number
+// of problems can be captured in a hipGraph and replayed; kernels of
+// finished columns/problems return at once.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "solver.h"
+
+namespace hfmm {
+
+namespace {
+
+constexpr int kRed = 256;     // threads per reduction block
+constexpr int kElems = 4;     // elements per thread in the dot kernels
+constexpr int kChunk = kRed * kElems;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+inline int nblocks(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
+
+// ------------------------------------------------------------------ FD
+// y = A x, or y = b - A x when b != NULL.  Column c of x/y/b starts at
+// c*xs / c*ys / c*bs, plus j*nn (x) and (j+1)*nn (y) when jstate is given.
+__global__ void k_fd(int n, double ih2, const double* __restrict__ k2, double k2c, const double2* __restrict__ x,
+                     int64_t xs, double2* __restrict__ y, int64_t ys, const double2* __restrict__ b, int64_t bs,
+                     int nrhs, const int* __restrict__ jstate, const int* __restrict__ active) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= nn || c >= nrhs) return;
+  if (active && !active[c]) return;
+  const int64_t j = jstate ? jstate[0] : 0;
+  const double2* xc = x + c * xs + (jstate ? j * nn : 0);
+  double2* yc = y + c * ys + (jstate ? (j + 1) * nn : 0);
+  const int ix = (int)(i % n), iy = (int)(i / n);
+  const double2 v = xc[i];
+  double sx = 4.0 * v.x, sy = 4.0 * v.y;
+  if (ix > 0) { sx -= xc[i - 1].x; sy -= xc[i - 1].y; }
+  if (ix < n - 1) { sx -= xc[i + 1].x; sy -= xc[i + 1].y; }
+  if (iy > 0) { sx -= xc[i - n].x; sy -= xc[i - n].y; }
+  if (iy < n - 1) { sx -= xc[i + n].x; sy -= xc[i + n].y; }
+  const double kk = k2 ? k2[i] : k2c;
+  double2 o = make_double2(sx * ih2 - kk * v.x, sy * ih2 - kk * v.y);
+  if (b) {
+    const double2 bb = b[c * bs + i];
+    o = make_double2(bb.x - o.x, bb.y - o.y);
+  }
+  yc[i] = o;
+}
+
+// ------------------------------------------------------------------ BEM setup
+__global__ void k_assemble_S(const double2* __restrict__ yg, int ng, double k0, double w, double2 diag,
+                             double2* __restrict__ A) {
+  const int64_t ld = 2 * (int64_t)ng;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ng * ld) return;
+  const int a = (int)(idx / ld), col = (int)(idx - a * ld);
+  double2 v;
+  if (col < ng) {
+    if (col == a) {
+      v = diag;
+    } else {
+      const double dx = yg[a].x - yg[col].x, dy = yg[a].y - yg[col].y;
+      const double2 h = h0_general(k0 * sqrt(dx * dx + dy * dy));
+      v = make_double2(-0.25 * w * h.y, 0.25 * w * h.x);  // w (i/4)(J + iY)
+    }
+  } else {
+    v = make_double2(col - ng == a ? 1.0 : 0.0, 0.0);
+  }
+  A[idx] = v;
+}
+
+__global__ __launch_bounds__(1024) void k_gj_pivot(const double2* __restrict__ A, int64_t ld, int ng, int c,
+                                                   int* __restrict__ piv, double2* __restrict__ pv,
+                                                   int* __restrict__ sing) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  double best = -1.0;
+  int bi = c;
+  for (int i = c + threadIdx.x; i < ng; i += 1024) {
+    const double v = cabs2(A[(int64_t)i * ld + c]);
+    if (v > best) { best = v; bi = i; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double o = sv[threadIdx.x + s];
+      const int oi = si[threadIdx.x + s];
+      if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+        sv[threadIdx.x] = o;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    piv[0] = si[0];
+    pv[0] = A[(int64_t)si[0] * ld + c];
+    if (!(sv[0] > 0.0)) sing[0] = 1;
+  }
+}
+
+__global__ void k_gj_swap_scale(double2* __restrict__ A, int64_t ld, int c, const int* __restrict__ piv,
+                                const double2* __restrict__ pv) {
+  const int64_t j = c + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ld) return;
+  const int pr = piv[0];
+  const double2 p = pv[0];
+  const double d = cabs2(p);
+  const double2 inv = d > 0 ? make_double2(p.x / d, -p.y / d) : make_double2(0, 0);
+  const double2 a = A[(int64_t)c * ld + j];
+  double2 b = a;
+  if (pr != c) {
+    b = A[(int64_t)pr * ld + j];
+    A[(int64_t)pr * ld + j] = a;
+  }
+  A[(int64_t)c * ld + j] = cmul(b, inv);
+}
+
+__global__ void k_gj_col(const double2* __restrict__ A, int64_t ld, int ng, int c, double2* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ng) f[i] = A[(int64_t)i * ld + c];
+}
+
+__global__ void k_gj_elim(double2* __restrict__ A, int64_t ld, int c, const double2* __restrict__ f) {
+  const int i = blockIdx.y;
+  if (i == c) return;
+  const int64_t j = c + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ld) return;
+  const double2 fi = f[i];
+  if (fi.x == 0.0 && fi.y == 0.0) return;
+  const double2 r = A[(int64_t)c * ld + j];
+  double2 v = A[(int64_t)i * ld + j];
+  v.x -= fi.x * r.x - fi.y * r.y;
+  v.y -= fi.x * r.y + fi.y * r.x;
+  A[(int64_t)i * ld + j] = v;
+}
+
+__global__ void k_colsum(const double2* __restrict__ A, int64_t ld, int ng, int col0, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ng) return;
+  double s = 0;
+  for (int i = 0; i < ng; ++i) {
+    const double2 v = A[(int64_t)i * ld + col0 + j];
+    s += sqrt(cabs2(v));
+  }
+  out[j] = s;
+}
+
+template <class T>
+__global__ void k_make_B(const double2* __restrict__ A, int64_t ld, int ng, double w, cplx<T>* __restrict__ B) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ng * ng) return;
+  const int a = (int)(idx / ng), b = (int)(idx - (int64_t)a * ng);
+  const double2 v = A[(int64_t)a * ld + ng + b];
+  B[idx] = mk<T>(T(-w * v.x), T(-w * v.y));
+}
+
+// ------------------------------------------------------------------ preconditioner
+template <class T>
+__global__ void k_prec_gather(const double2* __restrict__ r, int64_t rs, const int* __restrict__ jstate, int64_t nn,
+                              const int32_t* __restrict__ perm, int64_t N, double h2, cplx<T>* __restrict__ q1,
+                              int nrhs, const int* __restrict__ alive) {
+  if (alive && !alive[0]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * nrhs) return;
+  const int64_t c = i / N, s = i - c * N;
+  const int o = perm[s];
+  cplx<T> v = mk<T>(0, 0);
+  if (o < nn) {
+    const double2 rv = r[c * rs + (jstate ? (int64_t)jstate[0] * nn : 0) + o];
+    v = mk<T>(T(h2 * rv.x), T(h2 * rv.y));
+  }
+  q1[i] = v;
+}
+
+template <class T>
+__global__ void k_vg_gather(const cplx<T>* __restrict__ phi, const int32_t* __restrict__ iperm, int64_t nn, int ng,
+                            int64_t N, cplx<T>* __restrict__ vg, int nrhs, const int* __restrict__ alive) {
+  if (alive && !alive[0]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ng * nrhs) return;
+  const int64_t c = i / ng, a = i - c * ng;
+  vg[i] = phi[c * N + iperm[nn + a]];
+}
+
+// q2[boundary slot a] = sum_b B[a][b] vg[b]; one wave per row, up to 8 columns.
+template <class T>
+__global__ __launch_bounds__(256) void k_bgemv(const cplx<T>* __restrict__ B, const cplx<T>* __restrict__ vg, int ng,
+                                               const int32_t* __restrict__ iperm, int64_t nn, int64_t N,
+                                               cplx<T>* __restrict__ q2, int nrhs, const int* __restrict__ alive) {
+  if (alive && !alive[0]) return;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (a >= ng) return;
+  for (int c0 = 0; c0 < nrhs; c0 += 8) {
+    T ar[8], ai[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) ar[c] = ai[c] = T(0);
+    for (int b = lane; b < ng; b += 64) {
+      const cplx<T> m = B[(int64_t)a * ng + b];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c0 + c < nrhs) {
+          const cplx<T> v = vg[(int64_t)(c0 + c) * ng + b];
+          ar[c] += m.x * v.x - m.y * v.y;
+          ai[c] += m.x * v.y + m.y * v.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      for (int off = 32; off > 0; off >>= 1) {
+        ar[c] += __shfl_xor(ar[c], off);
+        ai[c] += __shfl_xor(ai[c], off);
+      }
+    }
+    if (lane == 0) {
+      const int64_t slot = iperm[nn + a];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < nrhs) q2[(int64_t)(c0 + c) * N + slot] = mk<T>(ar[c], ai[c]);
+    }
+  }
+}
+
+template <class T>
+__global__ void k_prec_scatter(const cplx<T>* __restrict__ phi, const double2* __restrict__ r, int64_t rs,
+                               double2* __restrict__ z, int64_t zs, const int* __restrict__ jstate,
+                               const int32_t* __restrict__ iperm, int64_t nn, int64_t N, double2 svol, int nrhs,
+                               const int* __restrict__ alive) {
+  if (alive && !alive[0]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn * nrhs) return;
+  const int64_t c = i / nn, o = i - c * nn;
+  const int64_t jo = jstate ? (int64_t)jstate[0] * nn : 0;
+  const cplx<T> p = phi[c * N + iperm[o]];
+  const double2 rv = r[c * rs + jo + o];
+  const double2 sr = cmul(svol, rv);
+  z[c * zs + jo + o] = make_double2((double)p.x + sr.x, (double)p.y + sr.y);
+}
+
+// ------------------------------------------------------------------ Krylov
+// Partial sums of conj(V_i) . w over a chunk, i = 0..j, w = V_{j+1}.
+__global__ __launch_bounds__(kRed) void k_cgs_dot(const double2* __restrict__ V, int64_t vs, int64_t nn,
+                                                  const int* __restrict__ st, const int* __restrict__ active,
+                                                  double2* __restrict__ part, int m1, int nblk) {
+  const int c = blockIdx.y;
+  if (!active[c]) return;
+  const int j = st[0];
+  const double2* Vc = V + c * vs;
+  const double2* w = Vc + (int64_t)(j + 1) * nn;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double2 wv[kElems];
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = base + e * kRed + threadIdx.x;
+    wv[e] = x < nn ? w[x] : make_double2(0, 0);
+  }
+  __shared__ double2 red[4][kRed];
+  for (int i0 = 0; i0 <= j; i0 += 4) {
+    double2 acc[4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      acc[ii] = make_double2(0, 0);
+      if (i0 + ii <= j) {
+        const double2* Vi = Vc + (int64_t)(i0 + ii) * nn;
+#pragma unroll
+        for (int e = 0; e < kElems; ++e) {
+          const int64_t x = base + e * kRed + threadIdx.x;
+          if (x < nn) {
+            const double2 p = cmulc(Vi[x], wv[e]);
+            acc[ii].x += p.x;
+            acc[ii].y += p.y;
+          }
+        }
+      }
+      red[ii][threadIdx.x] = acc[ii];
+    }
+    __syncthreads();
+    for (int s = kRed / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          red[ii][threadIdx.x].x += red[ii][threadIdx.x + s].x;
+          red[ii][threadIdx.x].y += red[ii][threadIdx.x + s].y;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < 4 && i0 + (int)threadIdx.x <= j)
+      part[((int64_t)c * m1 + i0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// h_i = sum of partials (fixed order); round 0 sets H(:, j), round 1 adds.
+__global__ __launch_bounds__(64) void k_cgs_fin(const double2* __restrict__ part, int nblk,
+                                                const int* __restrict__ st, const int* __restrict__ active,
+                                                double2* __restrict__ hcur, double2* __restrict__ H, int m, int round) {
+  const int c = blockIdx.y, i = blockIdx.x;
+  if (!active[c]) return;
+  const int j = st[0];
+  if (i > j) return;
+  const int m1 = m + 1;
+  const double2* p = part + ((int64_t)c * m1 + i) * nblk;
+  double sx = 0, sy = 0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    sx += p[b].x;
+    sy += p[b].y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off);
+    sy += __shfl_xor(sy, off);
+  }
+  if (threadIdx.x == 0) {
+    hcur[(int64_t)c * m1 + i] = make_double2(sx, sy);
+    double2* hc = H + ((int64_t)c * m + j) * m1 + i;
+    if (round == 0) {
+      *hc = make_double2(sx, sy);
+    } else {
+      hc->x += sx;
+      hc->y += sy;
+    }
+  }
+}
+
+// w -= sum_{i<=j} V_i h_i
+__global__ void k_cgs_axpy(double2* __restrict__ V, int64_t vs, int64_t nn, const int* __restrict__ st,
+                           const int* __restrict__ active, const double2* __restrict__ hcur, int m1) {
+  const int c = blockIdx.y;
+  if (!active[c]) return;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nn) return;
+  const int j = st[0];
+  double2* Vc = V + c * vs;
+  const double2* h = hcur + (int64_t)c * m1;
+  double2 w = Vc[(int64_t)(j + 1) * nn + x];
+  for (int i = 0; i <= j; ++i) {
+    const double2 p = cmul(Vc[(int64_t)i * nn + x], h[i]);
+    w.x -= p.x;
+    w.y -= p.y;
+  }
+  Vc[(int64_t)(j + 1) * nn + x] = w;
+}
+
+// ||v||^2 partials; v = base + c*cs (+ (j+1)*nn when st is given)
+__global__ __launch_bounds__(kRed) void k_nrm_part(const double2* __restrict__ base, int64_t cs, int64_t nn,
+                                                   const int* __restrict__ st, const int* __restrict__ active,
+                                                   double* __restrict__ part, int nblk) {
+  const int c = blockIdx.y;
+  if (active && !active[c]) return;
+  const double2* v = base + c * cs + (st ? (int64_t)(st[0] + 1) * nn : 0);
+  const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+  double s = 0;
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = b0 + e * kRed + threadIdx.x;
+    if (x < nn) s += cabs2(v[x]);
+  }
+  __shared__ double red[kRed];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = kRed / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)c * nblk + blockIdx.x] = red[0];
+}
+
+// out[c] = sqrt(sum of partials); with H given also H(j+1, j) = out[c].
+__global__ __launch_bounds__(64) void k_nrm_fin(const double* __restrict__ part, int nblk,
+                                                const int* __restrict__ st, const int* __restrict__ active,
+                                                double* __restrict__ out, double2* __restrict__ H, int m) {
+  const int c = blockIdx.x;
+  if (active && !active[c]) return;
+  double s = 0;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)c * nblk + b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (threadIdx.x == 0) {
+    const double r = sqrt(s);
+    out[c] = r;
+    if (H) {
+      const int j = st[0];
+      H[((int64_t)c * m + j) * (m + 1) + j + 1] = make_double2(r, 0.0);
+    }
+  }
+}
+
+// v_{j+1} = w / ||w|| (or v_0 = r / ||r|| when st is NULL)
+__global__ void k_scale(double2* __restrict__ V, int64_t vs, int64_t nn, const int* __restrict__ st,
+                        const int* __restrict__ active, const double* __restrict__ nrm) {
+  const int c = blockIdx.y;
+  if (!active[c]) return;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nn) return;
+  const double r = nrm[c];
+  if (!(r > 0)) return;
+  double2* v = V + c * vs + (st ? (int64_t)(st[0] + 1) * nn : 0);
+  const double inv = 1.0 / r;
+  double2 w = v[x];
+  v[x] = make_double2(w.x * inv, w.y * inv);
+}
+
+__global__ __launch_bounds__(64) void k_givens(double2* __restrict__ H, double* __restrict__ cs,
+                                               double2* __restrict__ sn, double2* __restrict__ g,
+                                               int* __restrict__ st, int* __restrict__ active, int* __restrict__ jj,
+                                               int* __restrict__ iters, double* __restrict__ est,
+                                               const double* __restrict__ bnorm, const double* __restrict__ wn,
+                                               int m, int maxit, double rtol, int nrhs) {
+  const int c = threadIdx.x;
+  bool live = false;
+  if (c < nrhs && active[c]) {
+    const int j = st[0];
+    double2* h = H + ((int64_t)c * m + j) * (m + 1);
+    double* csc = cs + (int64_t)c * m;
+    double2* snc = sn + (int64_t)c * m;
+    double2* gc = g + (int64_t)c * (m + 1);
+    for (int i = 0; i < j; ++i) {
+      const double2 a = h[i], b = h[i + 1];
+      const double2 s = snc[i];
+      const double cc = csc[i];
+      const double2 sb = cmul(s, b);
+      const double2 sa = cmulc(s, a);  // conj(s) a
+      h[i] = make_double2(cc * a.x + sb.x, cc * a.y + sb.y);
+      h[i + 1] = make_double2(cc * b.x - sa.x, cc * b.y - sa.y);
+    }
+    const double2 a = h[j], b = h[j + 1];
+    const double aa = sqrt(cabs2(a)), rho = sqrt(cabs2(a) + cabs2(b));
+    double cc;
+    double2 s;
+    if (aa == 0.0) {
+      cc = 0.0;
+      s = make_double2(1.0, 0.0);
+    } else {
+      cc = aa / rho;
+      const double2 ph = make_double2(a.x / aa, a.y / aa);
+      s = cmul(ph, make_double2(b.x / rho, -b.y / rho));
+    }
+    csc[j] = cc;
+    snc[j] = s;
+    const double2 sb = cmul(s, b);
+    h[j] = make_double2(cc * a.x + sb.x, cc * a.y + sb.y);
+    h[j + 1] = make_double2(0.0, 0.0);
+    const double2 gj = gc[j];
+    const double2 sg = cmulc(s, gj);
+    gc[j + 1] = make_double2(-sg.x, -sg.y);
+    gc[j] = make_double2(cc * gj.x, cc * gj.y);
+    const double e = sqrt(cabs2(gc[j + 1])) / bnorm[c];
+    est[c] = e;
+    jj[c] = j + 1;
+    const int it = iters[c] + 1;
+    iters[c] = it;
+    const bool stop = !(e > rtol) || !(wn[c] > 0.0) || (j + 1 >= m) || (it >= maxit);
+    if (stop) active[c] = 0;
+    live = !stop;
+  }
+  const unsigned long long any = __ballot(live);
+  if (threadIdx.x == 0) st[1] = any ? 1 : 0;
+}
+
+__global__ void k_advance(int* __restrict__ st) { st[0] += 1; }
+
+// y = R^{-1} g (back substitution over the jj[c] x jj[c] triangle)
+__global__ __launch_bounds__(64) void k_trisolve(const double2* __restrict__ H, const double2* __restrict__ g,
+                                                 const int* __restrict__ jj, double2* __restrict__ y, int m,
+                                                 int nrhs) {
+  const int c = threadIdx.x;
+  if (c >= nrhs) return;
+  const int nj = jj[c];
+  const double2* Hc = H + (int64_t)c * m * (m + 1);
+  double2* yc = y + (int64_t)c * m;
+  for (int i = nj - 1; i >= 0; --i) {
+    double2 s = g[(int64_t)c * (m + 1) + i];
+    for (int l = i + 1; l < nj; ++l) {
+      const double2 p = cmul(Hc[(int64_t)l * (m + 1) + i], yc[l]);
+      s.x -= p.x;
+      s.y -= p.y;
+    }
+    const double2 d = Hc[(int64_t)i * (m + 1) + i];
+    const double dd = cabs2(d);
+    yc[i] = dd > 0 ? cmul(s, make_double2(d.x / dd, -d.y / dd)) : make_double2(0, 0);
+  }
+}
+
+// x += Z y
+__global__ void k_xupdate(double2* __restrict__ x, const double2* __restrict__ Z, int64_t zs, int64_t nn,
+                          const int* __restrict__ jj, const double2* __restrict__ y, int m) {
+  const int c = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int nj = jj[c];
+  if (nj == 0) return;
+  double2 acc = x[c * nn + i];
+  for (int l = 0; l < nj; ++l) {
+    const double2 p = cmul(Z[c * zs + (int64_t)l * nn + i], y[(int64_t)c * m + l]);
+    acc.x += p.x;
+    acc.y += p.y;
+  }
+  x[c * nn + i] = acc;
+}
+
+// cycle start: g = (beta, 0, ...), jj = 0
+__global__ void k_cycle_init(double2* __restrict__ g, const double* __restrict__ beta, int* __restrict__ jj, int m,
+                             int nrhs) {
+  const int c = threadIdx.x;
+  if (c >= nrhs) return;
+  jj[c] = 0;
+  double2* gc = g + (int64_t)c * (m + 1);
+  for (int i = 0; i <= m; ++i) gc[i] = make_double2(0, 0);
+  gc[0] = make_double2(beta[c], 0.0);
+}
+
+__global__ void k_zero_cols(double2* __restrict__ x, int64_t nn, const int* __restrict__ zero) {
+  const int c = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn && zero[c]) x[c * nn + i] = make_double2(0, 0);
+}
+
+template <class T>
+__global__ void k_zero(cplx<T>* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = mk<T>(0, 0);
+}
+
+// ------------------------------------------------------------------ helpers
+template <class T> DevBuf<cplx<T>>& q1_of(Solver& s);
+template <> DevBuf<float2>& q1_of<float>(Solver& s) { return s.q1f; }
+template <> DevBuf<double2>& q1_of<double>(Solver& s) { return s.q1d; }
+template <class T> DevBuf<cplx<T>>& q2_of(Solver& s);
+template <> DevBuf<float2>& q2_of<float>(Solver& s) { return s.q2f; }
+template <> DevBuf<double2>& q2_of<double>(Solver& s) { return s.q2d; }
+template <class T> DevBuf<cplx<T>>& phi_of(Solver& s);
+template <> DevBuf<float2>& phi_of<float>(Solver& s) { return s.phif; }
+template <> DevBuf<double2>& phi_of<double>(Solver& s) { return s.phid; }
+template <class T> DevBuf<cplx<T>>& vg_of(Solver& s);
+template <> DevBuf<float2>& vg_of<float>(Solver& s) { return s.vgf; }
+template <> DevBuf<double2>& vg_of<double>(Solver& s) { return s.vgd; }
+template <class T> DevBuf<cplx<T>>& B_of(Solver& s);
+template <> DevBuf<float2>& B_of<float>(Solver& s) { return s.B32; }
+template <> DevBuf<double2>& B_of<double>(Solver& s) { return s.B64; }
+
+template <class T>
+void precond_impl(Solver& s, const double2* r, int64_t rs, double2* z, int64_t zs, const int* jstate,
+                  const int* alive, hipStream_t st) {
+  Tree& t = *s.tree;
+  FmmPlan<T>& pl = get_plan<T>(t, s.k0, s.p);
+  const int64_t N = t.n;
+  const int nr = s.nrhs;
+  cplx<T>* q1 = q1_of<T>(s).p;
+  cplx<T>* q2 = q2_of<T>(s).p;
+  cplx<T>* phi = phi_of<T>(s).p;
+  cplx<T>* vg = vg_of<T>(s).p;
+  k_prec_gather<T><<<nblocks(N * nr), 256, 0, st>>>(r, rs, jstate, s.nn, t.perm.p, N, s.h * s.h, q1, nr, alive);
+  HFMM_LAUNCH_CHECK();
+  fmm_sorted<T>(t, pl, q1, phi, nr, s.flags1.p, false, st, alive);
+  k_vg_gather<T><<<nblocks(s.ng * nr), 256, 0, st>>>(phi, t.iperm.p, s.nn, (int)s.ng, N, vg, nr, alive);
+  HFMM_LAUNCH_CHECK();
+  k_bgemv<T><<<(int)((s.ng + 3) / 4), 256, 0, st>>>(B_of<T>(s).p, vg, (int)s.ng, t.iperm.p, s.nn, N, q2, nr, alive);
+  HFMM_LAUNCH_CHECK();
+  fmm_sorted<T>(t, pl, q2, phi, nr, s.flags2.p, true, st, alive);
+  const double2 sv = make_double2(s.svol.real(), s.svol.imag());
+  k_prec_scatter<T><<<nblocks(s.nn * nr), 256, 0, st>>>(phi, r, rs, z, zs, jstate, t.iperm.p, s.nn, N, sv, nr, alive);
+  HFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+void setup_precision(Solver& s, const double2* A, int64_t ld, hipStream_t st) {
+  const int64_t N = s.tree->n;
+  const int64_t ng = s.ng;
+  B_of<T>(s).alloc(ng * ng);
+  k_make_B<T><<<nblocks(ng * ng), 256, 0, st>>>(A, ld, (int)ng, s.h, B_of<T>(s).p);
+  HFMM_LAUNCH_CHECK();
+  q1_of<T>(s).alloc(N * s.nrhs);
+  q2_of<T>(s).alloc(N * s.nrhs);
+  phi_of<T>(s).alloc(N * s.nrhs);
+  vg_of<T>(s).alloc(ng * s.nrhs);
+  // q2 is zero away from the boundary slots, which are the only ones written
+  k_zero<T><<<nblocks(N * s.nrhs), 256, 0, st>>>(q2_of<T>(s).p, N * s.nrhs);
+  HFMM_LAUNCH_CHECK();
+  FmmPlan<T>& pl = get_plan<T>(*s.tree, s.k0, s.p);
+  pl.ensure_work(s.nrhs);
+}
+
+}  // namespace
+
+Solver::~Solver() {
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+void fd_matvec(int n, double h, const double* d_k2, double k2c, const double2* x, double2* y, int nrhs,
+               hipStream_t st) {
+  HFMM_REQUIRE(n >= 1, "fd_matvec: n must be >= 1");
+  HFMM_REQUIRE(std::isfinite(h) && h > 0, "fd_matvec: h must be > 0");
+  HFMM_REQUIRE(nrhs >= 1 && nrhs <= 65535, "fd_matvec: nrhs must be in [1, 65535]");
+  HFMM_REQUIRE(x != nullptr && y != nullptr, "fd_matvec: NULL array");
+  HFMM_REQUIRE(x != y, "fd_matvec: x and y must not alias");
+  const int64_t nn = (int64_t)n * n;
+  dim3 grid(nblocks(nn), nrhs);
+  k_fd<<<grid, 256, 0, st>>>(n, 1.0 / (h * h), d_k2, k2c, x, nn, y, nn, nullptr, 0, nrhs, nullptr, nullptr);
+  HFMM_LAUNCH_CHECK();
+}
+
+std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, double k2c, double k0, int p, int leaf,
+                                      bool fp32, int nrhs, hipStream_t st) {
+  HFMM_REQUIRE(n >= 2, "solver_create: n must be >= 2");
+  HFMM_REQUIRE(std::isfinite(h) && std::fabs(h * (n + 1) - 1.0) < 1e-12,
+               "solver_create: h must equal 1/(n+1) (unit square)");
+  HFMM_REQUIRE(std::isfinite(k0) && k0 > 0, "solver_create: k0 must be > 0");
+  HFMM_REQUIRE(p >= 1 && p <= 40, "solver_create: p must be in [1, 40]");
+  HFMM_REQUIRE(leaf >= 1, "solver_create: leaf_size must be >= 1");
+  HFMM_REQUIRE(nrhs >= 1 && nrhs <= 64, "solver_create: nrhs must be in [1, 64]");
+  HFMM_REQUIRE(d_k2 != nullptr || std::isfinite(k2c), "solver_create: k2_const must be finite");
+  auto s = std::make_unique<Solver>();
+  s->n = n;
+  s->h = h;
+  s->nn = (int64_t)n * n;
+  s->ng = 4 * (int64_t)(n + 1);
+  s->nrhs = nrhs;
+  s->k0 = k0;
+  s->p = p;
+  s->leaf = leaf;
+  s->fp32 = fp32;
+  solver_set_k2(*s, d_k2, k2c, st);
+
+  // nodes: interior (i h, j h) x fastest, then boundary midpoints (bottom, right, top, left)
+  const int64_t N = s->nn + s->ng;
+  std::vector<double> xy(2 * N);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      xy[2 * ((int64_t)j * n + i)] = (i + 1) * h;
+      xy[2 * ((int64_t)j * n + i) + 1] = (j + 1) * h;
+    }
+  std::vector<double2> yg(s->ng);
+  for (int m = 0; m <= n; ++m) {
+    const double t = (m + 0.5) * h;
+    yg[m] = make_double2(t, 0.0);
+    yg[(n + 1) + m] = make_double2(1.0, t);
+    yg[2 * (n + 1) + m] = make_double2(t, 1.0);
+    yg[3 * (n + 1) + m] = make_double2(0.0, t);
+  }
+  for (int64_t a = 0; a < s->ng; ++a) {
+    xy[2 * (s->nn + a)] = yg[a].x;
+    xy[2 * (s->nn + a) + 1] = yg[a].y;
+  }
+  DevBuf<double> dxy;
+  dxy.upload(xy);
+  s->tree = build_tree(dxy.p, N, 0.0, 0.0, 1.0, leaf, st);
+  HFMM_REQUIRE(s->tree->L >= 2, "solver_create: tree depth below 2");
+
+  // per-level source flags of the two passes
+  int64_t ftot = 0;
+  for (int l = 0; l <= s->tree->L; ++l) ftot += int64_t(1) << (2 * l);
+  s->flags1.alloc(ftot);
+  s->flags2.alloc(ftot);
+  source_flags(*s->tree, 0, s->nn, s->flags1.p, st);
+  source_flags(*s->tree, s->nn, N, s->flags2.p, st);
+
+  // boundary matrix S = w G(y_a, y_b), analytic diagonal; invert by Gauss-Jordan
+  s->svol = volume_self_term(k0, h);
+  const std::complex<double> dg = boundary_self_term(k0, h);
+  const int ng = (int)s->ng;
+  const int64_t ld = 2 * (int64_t)ng;
+  DevBuf<double2> dyg;
+  dyg.upload(yg);
+  DevBuf<double2> A((size_t)ng * ld);
+  k_assemble_S<<<nblocks((int64_t)ng * ld), 256, 0, st>>>(dyg.p, ng, k0, h, make_double2(dg.real(), dg.imag()),
+                                                           A.p);
+  HFMM_LAUNCH_CHECK();
+  DevBuf<double> colsum(ng);
+  std::vector<double> hcol(ng);
+  k_colsum<<<nblocks(ng), 256, 0, st>>>(A.p, ld, ng, 0, colsum.p);
+  HFMM_LAUNCH_CHECK();
+  HFMM_HIP(hipMemcpyAsync(hcol.data(), colsum.p, ng * sizeof(double), hipMemcpyDeviceToHost, st));
+  HFMM_HIP(hipStreamSynchronize(st));
+  const double normS = *std::max_element(hcol.begin(), hcol.end());
+  DevBuf<int> piv(1), sing(1);
+  DevBuf<double2> pv(1), f(ng);
+  HFMM_HIP(hipMemsetAsync(sing.p, 0, sizeof(int), st));
+  for (int c = 0; c < ng; ++c) {
+    k_gj_pivot<<<1, 1024, 0, st>>>(A.p, ld, ng, c, piv.p, pv.p, sing.p);
+    k_gj_swap_scale<<<nblocks(ld - c), 256, 0, st>>>(A.p, ld, c, piv.p, pv.p);
+    k_gj_col<<<nblocks(ng), 256, 0, st>>>(A.p, ld, ng, c, f.p);
+    k_gj_elim<<<dim3(nblocks(ld - c), ng), 256, 0, st>>>(A.p, ld, c, f.p);
+  }
+  HFMM_LAUNCH_CHECK();
+  int hs = 0;
+  HFMM_HIP(hipMemcpyAsync(&hs, sing.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  k_colsum<<<nblocks(ng), 256, 0, st>>>(A.p, ld, ng, ng, colsum.p);
+  HFMM_LAUNCH_CHECK();
+  HFMM_HIP(hipMemcpyAsync(hcol.data(), colsum.p, ng * sizeof(double), hipMemcpyDeviceToHost, st));
+  HFMM_HIP(hipStreamSynchronize(st));
+  if (hs) throw Error(HFMM_ERR_NUMERIC, "solver_create: boundary matrix is singular");
+  s->condS = normS * *std::max_element(hcol.begin(), hcol.end());
+
+  if (fp32)
+    setup_precision<float>(*s, A.p, ld, st);
+  else
+    setup_precision<double>(*s, A.p, ld, st);
+  HFMM_HIP(hipEventCreate(&s->ev0));
+  HFMM_HIP(hipEventCreate(&s->ev1));
+  HFMM_HIP(hipStreamSynchronize(st));
+  return s;
+}
+
+void solver_set_k2(Solver& s, const double* d_k2, double k2c, hipStream_t st) {
+  if (d_k2) {
+    s.k2.ensure(s.nn);
+    HFMM_HIP(hipMemcpyAsync(s.k2.p, d_k2, s.nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+    s.field = true;
+  } else {
+    HFMM_REQUIRE(std::isfinite(k2c), "set_k2: k2_const must be finite");
+    s.field = false;
+    s.k2c = k2c;
+  }
+}
+
+void precond_apply(Solver& s, const double2* r, int64_t rs, double2* z, int64_t zs, const int* jstate,
+                   const int* alive, hipStream_t st) {
+  if (s.fp32)
+    precond_impl<float>(s, r, rs, z, zs, jstate, alive, st);
+  else
+    precond_impl<double>(s, r, rs, z, zs, jstate, alive, st);
+}
+
+namespace {
+
+void ensure_krylov(Solver& s, int m) {
+  const int nr = s.nrhs;
+  const int64_t nn = s.nn;
+  if (m != s.m) {
+    s.m = m;
+    s.V.alloc((size_t)nr * (m + 1) * nn);
+    s.Z.alloc((size_t)nr * m * nn);
+    s.H.alloc((size_t)nr * m * (m + 1));
+    s.sn.alloc((size_t)nr * m);
+    s.cs.alloc((size_t)nr * m);
+    s.g.alloc((size_t)nr * (m + 1));
+    s.y.alloc((size_t)nr * m);
+    s.hcur.alloc((size_t)nr * (m + 1));
+    s.nblk = (int)((nn + kChunk - 1) / kChunk);
+    s.part.alloc((size_t)nr * (m + 1) * s.nblk);
+    s.npart.alloc((size_t)nr * s.nblk);
+    s.bnorm.alloc(nr);
+    s.est.alloc(nr);
+    s.rn.alloc(nr);
+    s.active.alloc(nr);
+    s.jj.alloc(nr);
+    s.iters.alloc(nr);
+    s.state.alloc(2);
+    HFMM_HIP(hipMemset(s.V.p, 0, s.V.n * sizeof(double2)));
+    HFMM_HIP(hipMemset(s.Z.p, 0, s.Z.n * sizeof(double2)));
+    HFMM_HIP(hipMemset(s.H.p, 0, s.H.n * sizeof(double2)));
+  }
+}
+
+// One Arnoldi step of one problem (all columns); every index comes from
+// device state.  `mid`, when given, is recorded after the preconditioner.
+void arnoldi_step(Solver& s, int maxit, double rtol, hipStream_t st, hipEvent_t mid = nullptr) {
+  const int m = s.m, nr = s.nrhs;
+  const int64_t nn = s.nn, vs = (int64_t)(m + 1) * nn, zs = (int64_t)m * nn;
+  int* js = s.state.p;
+  precond_apply(s, s.V.p, vs, s.Z.p, zs, js, js + 1, st);
+  if (mid) HFMM_HIP(hipEventRecord(mid, st));
+  const dim3 gv(nblocks(nn), nr);
+  k_fd<<<gv, 256, 0, st>>>(s.n, 1.0 / (s.h * s.h), s.field ? s.k2.p : nullptr, s.k2c, s.Z.p, zs, s.V.p, vs, nullptr,
+                           0, nr, js, s.active.p);
+  HFMM_LAUNCH_CHECK();
+  const dim3 gd(s.nblk, nr), gf(m + 1, nr);
+  for (int round = 0; round < 2; ++round) {
+    k_cgs_dot<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.part.p, m + 1, s.nblk);
+    k_cgs_fin<<<gf, 64, 0, st>>>(s.part.p, s.nblk, js, s.active.p, s.hcur.p, s.H.p, m, round);
+    k_cgs_axpy<<<gv, 256, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.hcur.p, m + 1);
+  }
+  k_nrm_part<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.npart.p, s.nblk);
+  k_nrm_fin<<<nr, 64, 0, st>>>(s.npart.p, s.nblk, js, s.active.p, s.rn.p, s.H.p, m);
+  k_scale<<<gv, 256, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.rn.p);
+  k_givens<<<1, 64, 0, st>>>(s.H.p, s.cs.p, s.sn.p, s.g.p, js, s.active.p, s.jj.p, s.iters.p, s.est.p, s.bnorm.p,
+                             s.rn.p, m, maxit, rtol, nr);
+  k_advance<<<1, 1, 0, st>>>(js);
+  HFMM_LAUNCH_CHECK();
+}
+
+// column norms of v (column stride cs) into out (device), copied to host
+void col_norms(Solver& s, const double2* v, int64_t cs, double* dout, std::vector<double>& hout, hipStream_t st) {
+  const int nr = s.nrhs;
+  k_nrm_part<<<dim3(s.nblk, nr), kRed, 0, st>>>(v, cs, s.nn, nullptr, nullptr, s.npart.p, s.nblk);
+  k_nrm_fin<<<nr, 64, 0, st>>>(s.npart.p, s.nblk, nullptr, nullptr, dout, nullptr, s.m);
+  HFMM_LAUNCH_CHECK();
+  hout.resize(nr);
+  HFMM_HIP(hipMemcpyAsync(hout.data(), dout, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+struct ProbState {
+  std::vector<double> bnorm, rel, est;
+  std::vector<int> conv, iters, act;
+  int restarts = 0;
+  bool done = false;
+  bool numeric = false;
+};
+
+}  // namespace
+
+hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* const* x, int m, int maxit, double rtol,
+                   bool use_graph, hfmm_solve_info* info, hipStream_t st) {
+  HFMM_REQUIRE(nprob >= 1, "fgmres: nprob must be >= 1");
+  HFMM_REQUIRE(m >= 1 && m <= 200, "fgmres: restart must be in [1, 200]");
+  HFMM_REQUIRE(maxit >= 1, "fgmres: maxit must be >= 1");
+  HFMM_REQUIRE(std::isfinite(rtol) && rtol > 0, "fgmres: rtol must be > 0");
+  const auto t_start = std::chrono::steady_clock::now();
+  std::vector<ProbState> ps(nprob);
+  for (int q = 0; q < nprob; ++q) {
+    HFMM_REQUIRE(S[q] != nullptr, "fgmres: NULL solver");
+    HFMM_REQUIRE(b[q] != nullptr && x[q] != nullptr, "fgmres: NULL array");
+    ensure_krylov(*S[q], m);
+  }
+  double ms_prec = 0;
+  // ||b||
+  for (int q = 0; q < nprob; ++q) {
+    Solver& s = *S[q];
+    col_norms(s, b[q], s.nn, s.bnorm.p, ps[q].bnorm, st);
+  }
+  HFMM_HIP(hipStreamSynchronize(st));
+  for (int q = 0; q < nprob; ++q) {
+    Solver& s = *S[q];
+    ProbState& P = ps[q];
+    P.conv.assign(s.nrhs, 0);
+    P.iters.assign(s.nrhs, 0);
+    P.rel.assign(s.nrhs, 0.0);
+    P.est.assign(s.nrhs, 0.0);
+    std::vector<int> zero(s.nrhs, 0);
+    bool anyzero = false;
+    for (int c = 0; c < s.nrhs; ++c)
+      if (!(P.bnorm[c] > 0)) {
+        if (!std::isfinite(P.bnorm[c])) P.numeric = true;
+        zero[c] = 1;
+        anyzero = true;
+        P.conv[c] = 1;
+      }
+    if (anyzero) {  // b = 0 gives x = 0
+      HFMM_HIP(hipMemcpyAsync(s.active.p, zero.data(), s.nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      k_zero_cols<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(x[q], s.nn, s.active.p);
+      HFMM_LAUNCH_CHECK();
+    }
+    HFMM_HIP(hipMemsetAsync(s.iters.p, 0, s.nrhs * sizeof(int), st));
+  }
+  HFMM_HIP(hipStreamSynchronize(st));
+
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  bool graph_ok = false;
+
+  for (;;) {
+    // ---- cycle start: r = b - A x into V_0, beta = ||r||
+    bool any_active = false;
+    std::vector<std::vector<double>> beta(nprob);
+    for (int q = 0; q < nprob; ++q) {
+      Solver& s = *S[q];
+      if (ps[q].done) continue;
+      const int64_t vs = (int64_t)(s.m + 1) * s.nn;
+      k_fd<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(s.n, 1.0 / (s.h * s.h), s.field ? s.k2.p : nullptr, s.k2c,
+                                                         x[q], s.nn, s.V.p, vs, b[q], s.nn, s.nrhs, nullptr, nullptr);
+      HFMM_LAUNCH_CHECK();
+      col_norms(s, s.V.p, vs, s.rn.p, beta[q], st);
+    }
+    HFMM_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < nprob; ++q) {
+      Solver& s = *S[q];
+      ProbState& P = ps[q];
+      if (P.done) continue;
+      P.act.assign(s.nrhs, 0);
+      bool pa = false;
+      for (int c = 0; c < s.nrhs; ++c) {
+        if (!(P.bnorm[c] > 0)) continue;
+        if (!std::isfinite(beta[q][c])) P.numeric = true;
+        P.rel[c] = beta[q][c] / P.bnorm[c];
+        P.conv[c] = P.rel[c] <= rtol;
+        if (!P.conv[c] && P.iters[c] < maxit && std::isfinite(beta[q][c])) {
+          P.act[c] = 1;
+          pa = true;
+        }
+      }
+      if (!pa) {
+        P.done = true;
+        continue;
+      }
+      any_active = true;
+      int hstate[2] = {0, 1};
+      HFMM_HIP(hipMemcpyAsync(s.active.p, P.act.data(), s.nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      HFMM_HIP(hipMemcpyAsync(s.state.p, hstate, 2 * sizeof(int), hipMemcpyHostToDevice, st));
+      k_cycle_init<<<1, 64, 0, st>>>(s.g.p, s.rn.p, s.jj.p, s.m, s.nrhs);
+      k_scale<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(s.V.p, (int64_t)(s.m + 1) * s.nn, s.nn, nullptr,
+                                                           s.active.p, s.rn.p);
+      HFMM_LAUNCH_CHECK();
+      HFMM_HIP(hipStreamSynchronize(st));  // host buffers above stay valid
+    }
+    if (!any_active) break;
+
+    // ---- Arnoldi steps
+    if (use_graph && !graph_ok) {
+      // all plans and workspaces exist by now (created above), so the step
+      // allocates nothing and can be captured
+      HFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int q = 0; q < nprob; ++q) arnoldi_step(*S[q], maxit, rtol, st);
+      HFMM_HIP(hipStreamEndCapture(st, &graph));
+      HFMM_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      graph_ok = true;
+    }
+    for (int step = 0; step < m; ++step) {
+      const bool timed = (nprob == 1 && !use_graph);
+      if (timed) HFMM_HIP(hipEventRecord(S[0]->ev0, st));
+      if (graph_ok) {
+        HFMM_HIP(hipGraphLaunch(gexec, st));
+      } else {
+        for (int q = 0; q < nprob; ++q) {
+          if (ps[q].done) continue;
+          arnoldi_step(*S[q], maxit, rtol, st, timed ? S[q]->ev1 : nullptr);
+        }
+      }
+      // host check: which problems still have running columns
+      std::vector<int> alive(nprob, 0);
+      for (int q = 0; q < nprob; ++q)
+        if (!ps[q].done)
+          HFMM_HIP(hipMemcpyAsync(&alive[q], S[q]->state.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      HFMM_HIP(hipStreamSynchronize(st));
+      if (timed) {
+        float ms = 0;
+        HFMM_HIP(hipEventElapsedTime(&ms, S[0]->ev0, S[0]->ev1));
+        ms_prec += ms;
+      }
+      bool any = false;
+      for (int q = 0; q < nprob; ++q) any = any || (!ps[q].done && alive[q]);
+      if (!any) break;
+    }
+    // ---- end of cycle: x += Z R^{-1} g
+    for (int q = 0; q < nprob; ++q) {
+      Solver& s = *S[q];
+      if (ps[q].done) continue;
+      k_trisolve<<<1, 64, 0, st>>>(s.H.p, s.g.p, s.jj.p, s.y.p, s.m, s.nrhs);
+      k_xupdate<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(x[q], s.Z.p, (int64_t)s.m * s.nn, s.nn, s.jj.p, s.y.p,
+                                                            s.m);
+      HFMM_LAUNCH_CHECK();
+      std::vector<int> it(s.nrhs);
+      std::vector<double> es(s.nrhs);
+      HFMM_HIP(hipMemcpyAsync(it.data(), s.iters.p, s.nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      HFMM_HIP(hipMemcpyAsync(es.data(), s.est.p, s.nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      HFMM_HIP(hipStreamSynchronize(st));
+      ps[q].restarts += 1;
+      for (int c = 0; c < s.nrhs; ++c) {
+        if (ps[q].act[c]) ps[q].est[c] = es[c];
+        ps[q].iters[c] = it[c];
+      }
+    }
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+
+  const double ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  hfmm_status worst = HFMM_OK;
+  for (int q = 0; q < nprob; ++q) {
+    ProbState& P = ps[q];
+    hfmm_solve_info in{};
+    in.nrhs = S[q]->nrhs;
+    in.converged = 1;
+    for (int c = 0; c < S[q]->nrhs; ++c) {
+      in.iters = std::max(in.iters, P.iters[c]);
+      in.converged = in.converged && P.conv[c];
+      in.rel_res_true = std::max(in.rel_res_true, P.rel[c]);
+      in.rel_res_est = std::max(in.rel_res_est, P.est[c]);
+    }
+    in.restarts = P.restarts;
+    in.ms_precond = ms_prec;
+    in.ms_total = ms_total;
+    if (info) info[q] = in;
+    if (P.numeric) worst = HFMM_ERR_NUMERIC;
+    else if (!in.converged && worst == HFMM_OK) worst = HFMM_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+}  // namespace hfmm

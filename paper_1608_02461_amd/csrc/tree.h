@@ -1,0 +1,43 @@
+// Uniform quad-tree over a square root box (hierarchical decomposition of
+// Sec. 5.1.1), stored as a Morton-sorted point set with leaf offsets.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <tuple>
+
+#include "common.h"
+
+namespace hfmm {
+
+struct PlanBase {
+  virtual ~PlanBase() = default;
+};
+
+struct Tree {
+  int64_t n = 0;          // points
+  int L = 0;              // depth; 4^L leaves
+  double x0 = 0, y0 = 0, side = 1;
+  int leaf_size = 0;
+  int64_t nleaves = 1;
+  int max_leaf = 0;
+  DevBuf<int32_t> perm;       // sorted slot -> caller index
+  DevBuf<int32_t> iperm;      // caller index -> sorted slot
+  DevBuf<int32_t> leaf_off;   // nleaves + 1, Morton order
+  DevBuf<double2> rel64;      // sorted point minus its leaf centre
+  DevBuf<float2> rel32;       // the same in FP32
+  std::vector<int32_t> leaf_off_h;
+  // translation plans, keyed by (k, p, precision)
+  std::map<std::tuple<double, int, int>, std::unique_ptr<PlanBase>> plans;
+
+  double leaf_side() const { return side / double(1u << L); }
+};
+
+// Depth rule: 0 for leaf_size <= 0, else max(2, smallest L with leaf*4^L >= n).
+int tree_depth(int64_t n, int leaf_size);
+
+// Builds the tree on `stream` (synchronises it).  Throws Error on bad input.
+std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, double y0, double side,
+                                 int leaf_size, hipStream_t stream);
+
+}  // namespace hfmm

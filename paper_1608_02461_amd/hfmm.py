@@ -1,0 +1,274 @@
+"""ctypes binding of libhfmm.so (include/hfmm.h) with the same entry-point names.
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the method runs in the library's kernels.
+There is no fallback: if the library is missing or no GPU is present the
+calls raise.
+
+Complex arrays cross the boundary column-major (n x nrhs); the helpers here
+accept torch tensors of shape (n,) or (n, nrhs) and transpose as needed.
+"""
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hfmm.h")
+
+HFMM_OK = 0
+HFMM_NOT_CONVERGED = 1
+FP64 = 0
+FP32 = 1
+
+_STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_OOM", -4: "ERR_STATE",
+           -5: "ERR_INTERNAL", -6: "ERR_NUMERIC"}
+
+
+class HFMMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("nrhs", ctypes.c_int32), ("rel_res_true", ctypes.c_double), ("rel_res_est", ctypes.c_double),
+                ("ms_precond", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_vp, _i32, _i64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "hfmm_last_error": ([], ctypes.c_char_p),
+    "hfmm_version": ([], _i32),
+    "hfmm_build_tree": ([_vp, _i64, _f64, _f64, _f64, _i32, _vp, ctypes.POINTER(_vp)], _i32),
+    "hfmm_tree_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                        ctypes.POINTER(_i32)], _i32),
+    "hfmm_tree_export": ([_vp, _vp, _vp, _vp], _i32),
+    "hfmm_tree_destroy": ([_vp], _i32),
+    "hfmm_fmm_apply": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_fd_helmholtz_matvec": ([_i32, _f64, _vp, _f64, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_solver_create": ([_i32, _f64, _vp, _f64, _f64, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)], _i32),
+    "hfmm_solver_set_k2": ([_vp, _vp, _f64, _vp], _i32),
+    "hfmm_precond_apply": ([_vp, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_fgmres_solve": ([_vp, _vp, _vp, _i32, _i32, _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "hfmm_fgmres_solve_batched": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _i32,
+                                   _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "hfmm_solver_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32)], _i32),
+    "hfmm_solver_destroy": ([_vp], _i32),
+}
+
+
+def lib():
+    """Load libhfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Entry-point names declared in include/hfmm.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hfmm_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status, allow_not_converged=False):
+    if status == HFMM_OK or (allow_not_converged and status == HFMM_NOT_CONVERGED):
+        return status
+    raise HFMMError(status, lib().hfmm_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_cuda(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+
+
+def _colmajor(x, dtype, name):
+    """(n,) or (n, nrhs) tensor -> contiguous (nrhs, n) tensor (column-major n x nrhs)."""
+    _require_cuda(x, dtype, name)
+    if x.dim() == 1:
+        return x.contiguous().view(1, -1), True
+    return x.t().contiguous(), False
+
+
+def _from_colmajor(y, squeeze):
+    return y.view(-1) if squeeze else y.t()
+
+
+# ---------------------------------------------------------------------- tree
+class Tree:
+    """Uniform quad-tree over points xy (n, 2) float64 on the device."""
+
+    def __init__(self, xy, x0=0.0, y0=0.0, side=1.0, leaf_size=64, stream=None):
+        _require_cuda(xy, torch.float64, "xy")
+        xy = xy.contiguous()
+        h = ctypes.c_void_p()
+        _check(lib().hfmm_build_tree(_ptr(xy), xy.shape[0], x0, y0, side, leaf_size, _stream(stream),
+                                     ctypes.byref(h)))
+        self.handle = h
+        self.n = xy.shape[0]
+        self.device = xy.device
+
+    def info(self):
+        L, n, nl, mx = _i32(), _i64(), _i64(), _i32()
+        _check(lib().hfmm_tree_info(self.handle, ctypes.byref(L), ctypes.byref(n), ctypes.byref(nl), ctypes.byref(mx)))
+        return {"levels": L.value, "n_points": n.value, "n_leaves": nl.value, "max_leaf_count": mx.value}
+
+    def export(self, stream=None):
+        inf = self.info()
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        off = torch.empty(inf["n_leaves"] + 1, dtype=torch.int32, device=self.device)
+        _check(lib().hfmm_tree_export(self.handle, _ptr(perm), _ptr(off), _stream(stream)))
+        return perm, off
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.hfmm_tree_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def hfmm_build_tree(xy, x0=0.0, y0=0.0, side=1.0, leaf_size=64, stream=None):
+    return Tree(xy, x0, y0, side, leaf_size, stream)
+
+
+def hfmm_fmm_apply(tree, k, p, q, prec=FP64, stream=None):
+    """phi = sum_{j != i} q_j (i/4) H0(k |x_i - x_j|); q is (n,) or (n, nrhs) complex."""
+    dtype = torch.complex128 if prec == FP64 else torch.complex64
+    qc, squeeze = _colmajor(q, dtype, "q")
+    if qc.shape[1] != tree.n:
+        raise ValueError("q has the wrong number of points")
+    phi = torch.empty_like(qc)
+    _check(lib().hfmm_fmm_apply(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), qc.shape[0],
+                                _stream(stream)))
+    return _from_colmajor(phi, squeeze)
+
+
+def hfmm_fd_helmholtz_matvec(n, h, x, k2=None, k2_const=0.0, stream=None):
+    """y = A x for the 5-point operator; x is (n*n,) or (n*n, nrhs) complex128."""
+    xc, squeeze = _colmajor(x, torch.complex128, "x")
+    if xc.shape[1] != n * n:
+        raise ValueError("x has the wrong length")
+    if k2 is not None:
+        _require_cuda(k2, torch.float64, "k2")
+        k2 = k2.contiguous()
+    y = torch.empty_like(xc)
+    _check(lib().hfmm_fd_helmholtz_matvec(n, h, _ptr(k2), float(k2_const), _ptr(xc), _ptr(y), xc.shape[0],
+                                          _stream(stream)))
+    return _from_colmajor(y, squeeze)
+
+
+# ---------------------------------------------------------------------- solver
+class Solver:
+    """FMM-BEM preconditioned FGMRES for the n x n FD Helmholtz system (h = 1/(n+1))."""
+
+    def __init__(self, n, k0, k2=None, k2_const=None, p=6, leaf_size=32, prec=FP64, nrhs=1, device="cuda",
+                 stream=None):
+        self.n, self.nrhs, self.prec, self.k0, self.p = n, nrhs, prec, k0, p
+        self.h = 1.0 / (n + 1)
+        self.device = torch.device(device)
+        if k2 is not None:
+            _require_cuda(k2, torch.float64, "k2")
+            k2 = k2.contiguous()
+        kc = float(k0 * k0 if k2_const is None else k2_const)
+        hdl = ctypes.c_void_p()
+        _check(lib().hfmm_solver_create(n, self.h, _ptr(k2), kc, float(k0), int(p), int(leaf_size), int(prec),
+                                        int(nrhs), _stream(stream), ctypes.byref(hdl)))
+        self.handle = hdl
+
+    def set_k2(self, k2=None, k2_const=0.0, stream=None):
+        if k2 is not None:
+            _require_cuda(k2, torch.float64, "k2")
+            k2 = k2.contiguous()
+        _check(lib().hfmm_solver_set_k2(self.handle, _ptr(k2), float(k2_const), _stream(stream)))
+
+    def precond_apply(self, r, stream=None):
+        rc, squeeze = _colmajor(r, torch.complex128, "r")
+        z = torch.empty_like(rc)
+        _check(lib().hfmm_precond_apply(self.handle, _ptr(rc), _ptr(z), rc.shape[0], _stream(stream)))
+        return _from_colmajor(z, squeeze)
+
+    def solve(self, b, x0=None, restart=30, maxit=5000, rtol=1e-6, transpose=False, stream=None, strict=False):
+        bc, squeeze = _colmajor(b, torch.complex128, "b")
+        x = torch.zeros_like(bc) if x0 is None else _colmajor(x0, torch.complex128, "x0")[0].clone()
+        info = SolveInfo()
+        st = lib().hfmm_fgmres_solve(self.handle, _ptr(bc), _ptr(x), int(restart), int(maxit), float(rtol),
+                                     1 if transpose else 0, ctypes.byref(info), _stream(stream))
+        _check(st, allow_not_converged=not strict)
+        return _from_colmajor(x, squeeze), info.as_dict()
+
+    def info(self):
+        ng, cond, L = _i32(), _f64(), _i32()
+        _check(lib().hfmm_solver_info(self.handle, ctypes.byref(ng), ctypes.byref(cond), ctypes.byref(L)))
+        return {"n_gamma": ng.value, "cond_S": cond.value, "levels": L.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.hfmm_solver_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def hfmm_solver_create(n, k0, **kw):
+    return Solver(n, k0, **kw)
+
+
+def hfmm_fgmres_solve(solver, b, **kw):
+    return solver.solve(b, **kw)
+
+
+def hfmm_precond_apply(solver, r, **kw):
+    return solver.precond_apply(r, **kw)
+
+
+def hfmm_fgmres_solve_batched(solvers, bs, restart=50, maxit=5000, rtol=1e-6, use_graph=True, stream=None):
+    """Solve every (solvers[i], bs[i]) together; returns (list of x, list of info dicts)."""
+    m = len(solvers)
+    cols = [_colmajor(b, torch.complex128, "b") for b in bs]
+    xs = [torch.zeros_like(c) for c, _ in cols]
+    hs = (ctypes.c_void_p * m)(*[s.handle.value for s in solvers])
+    bp = (ctypes.c_void_p * m)(*[c.data_ptr() for c, _ in cols])
+    xp = (ctypes.c_void_p * m)(*[x.data_ptr() for x in xs])
+    infos = (SolveInfo * m)()
+    st = lib().hfmm_fgmres_solve_batched(hs, m, bp, xp, int(restart), int(maxit), float(rtol), 1 if use_graph else 0,
+                                         infos, _stream(stream))
+    _check(st, allow_not_converged=True)
+    return [_from_colmajor(x, sq) for x, (_, sq) in zip(xs, cols)], [i.as_dict() for i in infos]
+
+
+def hfmm_last_error():
+    return lib().hfmm_last_error().decode()
+
+
+def hfmm_version():
+    return lib().hfmm_version()

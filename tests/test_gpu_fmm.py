@@ -1,0 +1,149 @@
+"""GPU parity of the tree build and the FMM apply (through the C-ABI)
+against the CPU oracle on the same seeded inputs."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fmm as ofmm
+from oracle import kernel
+from paper_1608_02461_amd import hfmm, workloads
+from gpu_util import rel, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "c2_reference.npz")
+
+
+def morton_np(ix, iy):
+    key = np.zeros_like(ix, dtype=np.int64)
+    for b in range(16):
+        key |= ((ix >> b) & 1) << (2 * b)
+        key |= ((iy >> b) & 1) << (2 * b + 1)
+    return key
+
+
+@pytest.mark.parametrize("N,leaf", [(1, 8), (17, 4), (1000, 16), (4356, 32), (70001, 32)])
+def test_tree_is_stable_morton_sort(N, leaf):
+    say(f"tree N={N} leaf={leaf}")
+    rng = np.random.default_rng(100 + N)
+    xy = rng.random((N, 2))
+    xy[: N // 10] = np.round(xy[: N // 10] * 8) / 8  # points on box edges, duplicates
+    t = hfmm.Tree(to_dev(xy), leaf_size=leaf)
+    info = t.info()
+    L = ofmm.tree_depth(N, leaf)
+    assert info["levels"] == L
+    perm, off = (to_np(a) for a in t.export())
+    nb = 2 ** L
+    ix = np.clip(np.floor(xy[:, 0] * nb).astype(np.int64), 0, nb - 1)
+    iy = np.clip(np.floor(xy[:, 1] * nb).astype(np.int64), 0, nb - 1)
+    key = morton_np(ix, iy)
+    ref = np.argsort(key, kind="stable")
+    assert np.array_equal(perm, ref)
+    counts = np.bincount(key, minlength=nb * nb)
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(counts)]))
+    assert info["max_leaf_count"] == counts.max()
+
+
+@pytest.mark.parametrize("k", [16.0, 100.0])
+@pytest.mark.parametrize("N", [1, 2, 17, 1000, 4356])
+def test_all_pairs_matches_direct_sum(N, k):
+    say(f"all-pairs N={N} k={k}")
+    xy, q = workloads.random_cloud(N, seed=N + int(k))
+    ref = kernel.direct_sum(xy, q[:, 0], k)
+    t = hfmm.Tree(to_dev(xy), leaf_size=0)
+    assert t.info()["levels"] == 0
+    f64 = to_np(hfmm.hfmm_fmm_apply(t, k, 6, to_dev(q[:, 0]), prec=hfmm.FP64))
+    f32 = to_np(hfmm.hfmm_fmm_apply(t, k, 6, to_dev(q[:, 0].astype(np.complex64)), prec=hfmm.FP32))
+    if N == 1:
+        assert f64[0] == 0 and f32[0] == 0
+        return
+    assert rel(f64, ref) <= 1e-12
+    assert rel(f32, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("N,leaf,k,p", [(1500, 16, 16.0, 6), (4356, 32, 16.0, 6), (3000, 16, 100.0, 4),
+                                        (3000, 16, 100.0, 12), (5000, 64, 60.0, 8)])
+def test_fmm_fp64_matches_oracle_fmm(N, leaf, k, p):
+    """Same mathematics as the oracle FMM: agreement far below the FMM error."""
+    say(f"fmm fp64 N={N} leaf={leaf} k={k} p={p}")
+    xy, q = workloads.random_cloud(N, seed=7 * N + p)
+    q = q[:, 0]
+    ref_fmm = ofmm.fmm(xy, q, k, p, leaf)
+    ref = kernel.direct_sum(xy, q, k)
+    eps_oracle = rel(ref_fmm, ref)
+    t = hfmm.Tree(to_dev(xy), leaf_size=leaf)
+    f = to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q), prec=hfmm.FP64))
+    assert rel(f, ref_fmm) <= 1e-10
+    assert rel(f, ref) <= eps_oracle + 1e-6
+
+
+@pytest.mark.parametrize("N,leaf,k,p", [(4356, 32, 16.0, 6), (3000, 16, 100.0, 4), (3000, 16, 100.0, 12)])
+def test_fmm_fp32_error(N, leaf, k, p):
+    say(f"fmm fp32 N={N} leaf={leaf} k={k} p={p}")
+    xy, q = workloads.random_cloud(N, seed=11 * N + p)
+    q = q[:, 0]
+    ref_fmm = ofmm.fmm(xy, q, k, p, leaf)
+    ref = kernel.direct_sum(xy, q, k)
+    eps_oracle = rel(ref_fmm, ref)
+    t = hfmm.Tree(to_dev(xy), leaf_size=leaf)
+    f = to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q.astype(np.complex64)), prec=hfmm.FP32))
+    say(f"  eps_oracle={eps_oracle:.3e} fp32 err={rel(f, ref):.3e} vs oracle fmm {rel(f, ref_fmm):.3e}")
+    assert rel(f, ref_fmm) <= 2e-5
+    assert rel(f, ref) <= eps_oracle + 2e-5
+
+
+@pytest.mark.parametrize("nrhs", [2, 3, 4, 7])
+def test_multi_rhs_equals_single(nrhs):
+    say(f"multi rhs {nrhs}")
+    xy, q = workloads.random_cloud(2000, seed=40 + nrhs, nrhs=nrhs)
+    t = hfmm.Tree(to_dev(xy), leaf_size=16)
+    for prec, dt, tol in [(hfmm.FP64, np.complex128, 1e-13), (hfmm.FP32, np.complex64, 1e-6)]:
+        qq = q.astype(dt)
+        full = to_np(hfmm.hfmm_fmm_apply(t, 30.0, 6, to_dev(qq), prec=prec))
+        for c in range(nrhs):
+            one = to_np(hfmm.hfmm_fmm_apply(t, 30.0, 6, to_dev(np.ascontiguousarray(qq[:, c])), prec=prec))
+            assert rel(full[:, c], one) <= tol
+
+
+def test_deterministic_repeat():
+    xy, q = workloads.random_cloud(3000, seed=5)
+    t = hfmm.Tree(to_dev(xy), leaf_size=16)
+    qd = to_dev(q[:, 0].astype(np.complex64))
+    a = to_np(hfmm.hfmm_fmm_apply(t, 50.0, 6, qd, prec=hfmm.FP32))
+    b = to_np(hfmm.hfmm_fmm_apply(t, 50.0, 6, qd, prec=hfmm.FP32))
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments():
+    xy, q = workloads.random_cloud(100, seed=1)
+    with pytest.raises(hfmm.HFMMError) as e:
+        hfmm.Tree(to_dev(xy * 2.0), leaf_size=8)  # outside the root box
+    assert e.value.status == -1
+    t = hfmm.Tree(to_dev(xy), leaf_size=8)
+    for k, p in [(0.0, 6), (-1.0, 6), (10.0, 0), (10.0, 41)]:
+        with pytest.raises(hfmm.HFMMError):
+            hfmm.hfmm_fmm_apply(t, k, p, to_dev(q[:, 0]))
+    with pytest.raises(hfmm.HFMMError):  # leaves too large for k
+        hfmm.hfmm_fmm_apply(t, 5000.0, 6, to_dev(q[:, 0]))
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD), reason="stored C2 reference missing")
+@pytest.mark.parametrize("p", [4, 8, 12])
+def test_c2_full_size_sampled(p):
+    """N = 2^20, k = 100, leaf 64: sampled targets against the stored direct sum."""
+    say(f"C2 full size p={p}")
+    g = np.load(GOLD)
+    w = workloads.fmm_c2()
+    samples = g["samples"]
+    assert np.array_equal(samples, w["samples"][: samples.size])
+    t = hfmm.Tree(to_dev(w["xy"]), leaf_size=w["leaf"])
+    assert t.info()["levels"] == 7
+    eps = float(g[f"eps_oracle_p{p}"])
+    f64 = to_np(hfmm.hfmm_fmm_apply(t, w["k"], p, to_dev(w["q"]), prec=hfmm.FP64))[samples]
+    f32 = to_np(hfmm.hfmm_fmm_apply(t, w["k"], p, to_dev(w["q"].astype(np.complex64)), prec=hfmm.FP32))[samples]
+    e64, e32 = rel(f64, g["direct"]), rel(f32, g["direct"])
+    say(f"  eps_oracle={eps:.3e} fp64={e64:.3e} fp32={e32:.3e}")
+    assert e64 <= eps + 1e-6
+    assert e32 <= eps + 2e-5
