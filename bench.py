@@ -1,0 +1,246 @@
+"""Benchmark: the 2-D Helmholtz FMM apply (and FMM-BEM preconditioned solves) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--p 8] [--no-extras] [--no-cpu]
+
+Headline workload (one step = one FMM apply, inputs resident in HBM, tree
+built beforehand and timed separately): N = 2^20 uniform points in the unit
+square, complex N(0,1) charges, k = 100, leaf 64, complex64 arithmetic, order
+p (default 8).  value = N / (time per apply) in Mpts/s.
+
+Also reported on the same JSON line:
+* the same apply in complex128 and at p = 4, 8, 12, with relative errors on
+  the 2048 seeded targets against the stored direct sum;
+* the mixed-precision (complex64 FMM inside FP64 FGMRES(50)) and all-FP64
+  solves of the 1024 x 1024 grid, k h = 0.3, Gaussian bump, to 1e-6;
+* the 64 x 64, k = 16, FP64 FGMRES(30) solve;
+* `roofline` for the dominant kernel of the timed apply, from per-stage
+  hipEvents recorded on the launch stream over the timed steps;
+* `cpu_baseline`: the CPU oracle's direct N-body sum on a bounded sample of
+  targets, scaled to Mpts/s of the full sum.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FMM-preconditioned Helmholtz solves/s to 1e-6 res; FMM Mpts/s FP32-mixed vs FP64"
+PEAK_FP32_ALU = 78.6   # TFLOP/s: 256 CU x 64 FP32 FMA lanes x 2 flop x 2.4 GHz (packed FP32 off)
+PEAK_FP64_ALU = 78.6
+PEAK_HBM = 8000.0       # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def p2p_flops_per_pair(deg, nrhs=1):
+    """FP32/FP64 fast-path P2P flops per pair, counted from the kernel source
+    (FMA = 2): dx, dy (2); t = fma(dx, dx, dy*dy) (3); u = fma (2); two
+    Horner chains of deg-1 FMAs (4 (deg-1)); Y = fma(J, fma(lg, c1, c0), Yh)
+    (4); 4 FMAs per right-hand side into the accumulators (8 nrhs).  The
+    log2 per pair is a transcendental and is not counted."""
+    return 2 + 3 + 2 + 4 * (deg - 1) + 4 + 8 * nrhs
+
+
+def m2l_flops(orders, L, nrhs=1):
+    """Algorithmic flops of the downward pass: 8 real flops per complex MAC,
+    M2L over each box's interaction list and L2L from its parent."""
+    tot = 0
+    for l in range(2, L + 1):
+        nb = 2 ** l
+        P = 2 * orders[l] + 1
+        # interaction-list sizes of every box at level l
+        b = np.arange(nb)
+        cnt = np.zeros((nb, nb), dtype=np.int64)
+        for ox in range(-3, 4):
+            for oy in range(-3, 4):
+                if max(abs(ox), abs(oy)) < 2:
+                    continue
+                sx, sy = b[:, None] + ox, b[None, :] + oy
+                ok = (sx >= 0) & (sx < nb) & (sy >= 0) & (sy < nb)
+                ok &= np.abs(sx // 2 - b[:, None] // 2) <= 1
+                ok &= np.abs(sy // 2 - b[None, :] // 2) <= 1
+                cnt += ok
+        tot += int(cnt.sum()) * P * P * 8 * nrhs
+        if l > 2:
+            tot += nb * nb * (2 * orders[l - 1] + 1) * P * 8 * nrhs
+    return tot
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1608_02461_amd import hfmm, workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.fmm_c2()
+    N, k, leaf, p = len(w["xy"]), w["k"], w["leaf"], args.p
+    xy = torch.from_numpy(w["xy"]).to(dev)
+    q32 = torch.from_numpy(w["q"].astype(np.complex64)).to(dev)
+    q64 = torch.from_numpy(w["q"]).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    tree = hfmm.Tree(xy, leaf_size=leaf)
+    torch.cuda.synchronize()
+    t_tree_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(5):
+        tree_b = hfmm.Tree(xy, leaf_size=leaf)
+    torch.cuda.synchronize()
+    t_tree = (time.perf_counter() - t0) / 5
+    del tree_b
+    plan = hfmm.hfmm_fmm_plan_info(tree, k, p, hfmm.FP32)
+    stream = torch.cuda.current_stream()
+
+    # ---------------- timed region: K FP32 applies
+    for _ in range(args.warmup):
+        phi = hfmm.hfmm_fmm_apply(tree, k, p, q32, prec=hfmm.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        phi = hfmm.hfmm_fmm_apply(tree, k, p, q32, prec=hfmm.FP32)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    value = N / (elapsed / args.steps) / 1e6
+
+    # ---------------- per-stage device times (hipEvents on the launch stream), same applies
+    stages = {s: 0.0 for s in hfmm.STAGES}
+    for _ in range(args.steps):
+        _, ms = hfmm.hfmm_fmm_apply_timed(tree, k, p, q32, prec=hfmm.FP32)
+        for s in stages:
+            stages[s] += ms[s] / args.steps
+    dominant = max(("p2p", "downward"), key=lambda s: stages[s])
+    if dominant == "p2p":
+        fl = plan["pairs"] * p2p_flops_per_pair(plan["near_deg"])
+        roof_kernel = f"k_p2p<float,1,{plan['near_deg']},true>"
+    else:
+        fl = m2l_flops(plan["orders"], tree.info()["levels"])
+        roof_kernel = "k_down<float,1> (M2L + L2L, one launch per level)"
+    achieved = fl / (stages[dominant] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": roof_kernel, "achieved": round(achieved, 3), "peak": PEAK_FP32_ALU,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ALU, 4), "traffic": None,
+                "algorithmic_flops_per_launch": fl, "ms_per_launch": round(stages[dominant], 5)}
+
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_reference.npz"))
+    smp = gold["samples"]
+    phi_np = phi.cpu().numpy()[smp]
+    err32 = float(np.linalg.norm(phi_np - gold["direct"]) / np.linalg.norm(gold["direct"]))
+
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"FMM apply, N=2^20 uniform points in the unit square, complex N(0,1) charges, "
+                               f"k=100, leaf 64, p={p}, complex64", "N": N, "k": k, "p": p, "leaf": leaf,
+                   "levels": tree.info()["levels"], "orders": plan["orders"]},
+        "stage_ms": {s: round(v, 5) for s, v in stages.items()},
+        "tree_build_ms": round(t_tree * 1e3, 4), "tree_build_first_ms": round(t_tree_first * 1e3, 3),
+        "rel_err_2048_samples": err32,
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        fmm_tab = {}
+        for pp in (4, 8, 12):
+            row = {"eps_oracle": float(gold[f"eps_oracle_p{pp}"])}
+            for name, q, prec in (("fp32", q32, hfmm.FP32), ("fp64", q64, hfmm.FP64)):
+                hfmm.hfmm_fmm_apply(tree, k, pp, q, prec=prec)
+                torch.cuda.synchronize()
+                reps = 5
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    out = hfmm.hfmm_fmm_apply(tree, k, pp, q, prec=prec)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                o = out.cpu().numpy()[smp]
+                row[name] = {"mpts_s": round(N / dt / 1e6, 2), "ms": round(dt * 1e3, 4),
+                             "rel_err": float(np.linalg.norm(o - gold["direct"]) / np.linalg.norm(gold["direct"]))}
+            fmm_tab[f"p{pp}"] = row
+            log(f"C2 p={pp}: {row}")
+        result["fmm_c2"] = fmm_tab
+
+        # 1024 x 1024 solve, mixed vs FP64
+        c3 = workloads.solve_c3()
+        f = torch.from_numpy(c3["f"]).to(dev)
+        solves = {}
+        for name, prec in (("mixed", hfmm.FP32), ("fp64", hfmm.FP64)):
+            t0 = time.perf_counter()
+            s = hfmm.Solver(c3["n"], c3["k"], p=6, leaf_size=c3["leaf"], prec=prec)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            s.solve(f, restart=50, rtol=1e-6)  # warm
+            torch.cuda.synchronize()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x, info = s.solve(f, restart=50, rtol=1e-6)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            solves[name] = {"solves_s": round(1 / dt, 4), "s_per_solve": round(dt, 4), "iters": info["iters"],
+                            "rel_res_true": info["rel_res_true"], "converged": info["converged"],
+                            "ms_precond_per_iter": round(info["ms_precond"] / max(1, info["iters"]), 4),
+                            "setup_s": round(setup, 3)}
+            log(f"C3 {name}: {solves[name]}")
+            del s
+        solves["mixed_over_fp64_speedup"] = round(solves["fp64"]["s_per_solve"] / solves["mixed"]["s_per_solve"], 3)
+        result["solve_1024"] = solves
+
+        c1 = workloads.solve_c1()
+        s = hfmm.Solver(c1["n"], c1["k"], p=6, leaf_size=32, prec=hfmm.FP64)
+        f1 = torch.from_numpy(c1["f"]).to(dev)
+        s.solve(f1, restart=30)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            x, info = s.solve(f1, restart=30, rtol=1e-6)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        result["solve_64"] = {"solves_s": round(1 / dt, 3), "iters": info["iters"],
+                              "rel_res_true": info["rel_res_true"]}
+        log(f"C1: {result['solve_64']}")
+
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import kernel
+
+        n_t = 24
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            kernel.direct_sum(w["xy"], w["q"], k, tgt=w["xy"][smp[:n_t]])
+            dt = time.perf_counter() - t0
+        # full N x N direct sum time by linearity in the number of targets
+        full = dt / n_t * N
+        result["cpu_baseline"] = {
+            "value": round(N / full / 1e6, 6), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle direct N-body sum (scipy hankel1, FP64) from all {N} sources to {n_t} of the "
+                      f"seeded targets ({dt:.1f} s, one thread); Mpts/s of the full N x N sum by linearity",
+            "pairs_per_s": round(n_t * N / dt, 1)}
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,23 @@ hfmm_status hfmm_tree_destroy(hfmm_tree t);
 hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
                            const void* d_q, void* d_phi, int32_t nrhs, hipStream_t stream);
 
+/* The same apply with hipEvents between its stages (tracing): ms_stages
+ * (host, 6 floats) receives the device time of [0] the gather to Morton
+ * order, [1] P2M + M2M, [2] M2L + L2L, [3] L2P, [4] P2P, [5] the scatter back.
+ * Synchronises `stream`. */
+hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
+                                 const void* d_q, void* d_phi, int32_t nrhs, float* ms_stages,
+                                 hipStream_t stream);
+
+/* Plan facts for a (k, p, prec) on a tree (builds the plan if needed).
+ * orders     host, levels+1 ints: p_l per level (levels < 2: only the near field).
+ * near_deg   coefficients of the near-field H0 polynomial (0 when the
+ *            full-range routine is used because the pair arguments exceed 12).
+ * pairs      near-field source-target pairs per column, self pairs excluded.
+ * Any output may be NULL. */
+hfmm_status hfmm_fmm_plan_info(hfmm_tree t, double k, int32_t p, hfmm_precision prec, int32_t* orders,
+                               int32_t* near_deg, int32_t* lanes_per_target, int64_t* pairs);
+
 /* ------------------------------------------------------------------------
  * 5-point FD Helmholtz operator (the sparse system A x = b of Sec. 2) on the
  * n x n interior grid of the unit square, zero Dirichlet ghosts:

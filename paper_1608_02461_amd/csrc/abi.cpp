@@ -108,6 +108,65 @@ hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec
   HFMM_GUARD_END
 }
 
+hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                                 void* d_phi, int32_t nrhs, float* ms_stages, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "fmm_apply_timed: NULL tree");
+  HFMM_REQUIRE(prec == HFMM_FP64 || prec == HFMM_FP32, "fmm_apply_timed: unknown precision");
+  HFMM_REQUIRE(nrhs >= 1 && nrhs <= 1024, "fmm_apply_timed: nrhs must be in [1, 1024]");
+  HFMM_REQUIRE(d_q != nullptr && d_phi != nullptr && ms_stages != nullptr, "fmm_apply_timed: NULL array");
+  hfmm::StageTimer tm;
+  if (prec == HFMM_FP64)
+    hfmm::fmm_apply<double>(*t->t, k, p, static_cast<const double2*>(d_q), static_cast<double2*>(d_phi), nrhs,
+                            stream, &tm);
+  else
+    hfmm::fmm_apply<float>(*t->t, k, p, static_cast<const float2*>(d_q), static_cast<float2*>(d_phi), nrhs, stream,
+                           &tm);
+  tm.collect(ms_stages, 6);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_fmm_plan_info(hfmm_tree t, double k, int32_t p, hfmm_precision prec, int32_t* orders,
+                               int32_t* near_deg, int32_t* lanes_per_target, int64_t* pairs) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "fmm_plan_info: NULL tree");
+  HFMM_REQUIRE(prec == HFMM_FP64 || prec == HFMM_FP32, "fmm_plan_info: unknown precision");
+  hfmm::Tree& tr = *t->t;
+  auto fill = [&](auto& pl) {
+    if (orders)
+      for (int l = 0; l <= tr.L; ++l) orders[l] = pl.lv[l].p;
+    if (near_deg) *near_deg = pl.near_fast ? pl.poly.deg : 0;
+    if (lanes_per_target) *lanes_per_target = pl.G;
+  };
+  if (prec == HFMM_FP64)
+    fill(hfmm::get_plan<double>(tr, k, p));
+  else
+    fill(hfmm::get_plan<float>(tr, k, p));
+  if (pairs) {
+    const int nb = 1 << tr.L;
+    int64_t s = 0;
+    for (int64_t b = 0; b < tr.nleaves; ++b) {
+      const int64_t cnt = tr.leaf_off_h[b + 1] - tr.leaf_off_h[b];
+      if (!cnt) continue;
+      int bx, by;
+      hfmm::demorton((uint32_t)b, bx, by);
+      int64_t src = 0;
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int sx = bx + dx, sy = by + dy;
+          if (sx < 0 || sy < 0 || sx >= nb || sy >= nb) continue;
+          const uint32_t sl = hfmm::morton((uint32_t)sx, (uint32_t)sy);
+          src += tr.leaf_off_h[sl + 1] - tr.leaf_off_h[sl];
+        }
+      s += cnt * (src - 1);
+    }
+    *pairs = s;
+  }
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
 hfmm_status hfmm_fd_helmholtz_matvec(int32_t n, double h, const double* d_k2, double k2_const, const double* d_x,
                                      double* d_y, int32_t nrhs, hipStream_t stream) {
   HFMM_GUARD_BEGIN

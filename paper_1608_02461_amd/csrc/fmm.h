@@ -60,6 +60,17 @@ struct FmmPlan : PlanBase {
 template <class T>
 FmmPlan<T>& get_plan(Tree& t, double k, int p);
 
+// Optional stage timing: hipEvents recorded on the launch stream at stage
+// boundaries; stage ids 0 gather, 1 upward (P2M+M2M), 2 downward (M2L+L2L),
+// 3 L2P, 4 P2P, 5 scatter.
+struct StageTimer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> stage;
+  ~StageTimer();
+  void mark(int s, hipStream_t st);  // closes stage s at this point
+  void collect(float* ms, int nstage);
+};
+
 // phi (+)= FMM(q) on sorted arrays (column-major N x nrhs).  `flags` (or
 // NULL for "every box") is a per-level array of 4^l bytes per level
 // (concatenated from level 0) marking boxes that hold sources; `accumulate`
@@ -67,13 +78,14 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p);
 // when it holds 0 every kernel of the call returns at once.
 template <class T>
 void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
-                bool accumulate, hipStream_t st, const int* alive = nullptr);
+                bool accumulate, hipStream_t st, const int* alive = nullptr, StageTimer* tm = nullptr);
 
 // Per-level source flags for the points whose caller index lies in [lo, hi).
 void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipStream_t st);
 
 // Public apply in caller order.
 template <class T>
-void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st);
+void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st,
+               StageTimer* tm = nullptr);
 
 }  // namespace hfmm

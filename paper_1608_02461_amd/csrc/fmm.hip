@@ -635,7 +635,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
 
 template <class T, int NR>
 void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
-              const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive) {
+              const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm) {
   const int L = t.L;
   const int64_t N = t.n;
   const cplx<T>* rel = rel_of<T>(t);
@@ -656,6 +656,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
                                                 flags ? flags + lp.box0 : nullptr, alive);
       HFMM_LAUNCH_CHECK();
     }
+    if (tm) tm->mark(1, st);
     for (int l = 2; l <= L; ++l) {
       const LevelInfo& li = pl.lv[l];
       const LevelInfo& lp = pl.lv[l - 1];
@@ -665,10 +666,12 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
                                                  nrhs, r0, flags ? flags + li.box0 : nullptr, alive);
       HFMM_LAUNCH_CHECK();
     }
+    if (tm) tm->mark(2, st);
     k_l2p<T, NR><<<(int)t.nleaves, 64, (size_t)NR * lf.P * sizeof(cplx<T>), st>>>(
         t.leaf_off.p, rel, Lc + lf.coef * nrhs, phi, N, nrhs, r0, lf.p, T(k / (2 * lf.s)), T(k * k / 4),
         pl.series.p, pl.K, accumulate ? 1 : 0, alive);
     HFMM_LAUNCH_CHECK();
+    if (tm) tm->mark(3, st);
   }
   P2PArgs<T> a{};
   a.leaf_off = t.leaf_off.p;
@@ -714,6 +717,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     }
   }
   HFMM_LAUNCH_CHECK();
+  if (tm) tm->mark(4, st);
 }
 
 }  // namespace
@@ -730,18 +734,18 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p) {
 
 template <class T>
 void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
-                bool accumulate, hipStream_t st, const int* alive) {
+                bool accumulate, hipStream_t st, const int* alive, StageTimer* tm) {
   pl.ensure_work(nrhs);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     if (left >= 4) {
-      run_cols<T, 4>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive);
+      run_cols<T, 4>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm);
       r0 += 4;
     } else if (left >= 2) {
-      run_cols<T, 2>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive);
+      run_cols<T, 2>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm);
       r0 += 2;
     } else {
-      run_cols<T, 1>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive);
+      run_cols<T, 1>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm);
       r0 += 1;
     }
   }
@@ -765,27 +769,54 @@ void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipSt
 }
 
 template <class T>
-void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st) {
+void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st,
+               StageTimer* tm) {
   HFMM_REQUIRE(nrhs >= 1, "fmm_apply: nrhs must be >= 1");
   HFMM_REQUIRE(q != nullptr && phi != nullptr, "fmm_apply: NULL array");
   FmmPlan<T>& pl = get_plan<T>(t, k, p);
   const int64_t total = t.n * nrhs;
   pl.qs.ensure(total);
   pl.phis.ensure(total);
+  if (tm) tm->mark(-1, st);
   k_gather<T><<<blocks_for(total), 256, 0, st>>>(q, pl.qs.p, t.perm.p, t.n, total);
   HFMM_LAUNCH_CHECK();
-  fmm_sorted<T>(t, pl, pl.qs.p, pl.phis.p, nrhs, nullptr, false, st);
+  if (tm) tm->mark(0, st);
+  fmm_sorted<T>(t, pl, pl.qs.p, pl.phis.p, nrhs, nullptr, false, st, nullptr, tm);
   k_scatter<T><<<blocks_for(total), 256, 0, st>>>(pl.phis.p, phi, t.perm.p, t.n, total);
   HFMM_LAUNCH_CHECK();
+  if (tm) tm->mark(5, st);
 }
 
 template FmmPlan<float>& get_plan<float>(Tree&, double, int);
 template FmmPlan<double>& get_plan<double>(Tree&, double, int);
 template void fmm_sorted<float>(const Tree&, FmmPlan<float>&, const float2*, float2*, int, const uint8_t*, bool,
-                                hipStream_t, const int*);
+                                hipStream_t, const int*, StageTimer*);
 template void fmm_sorted<double>(const Tree&, FmmPlan<double>&, const double2*, double2*, int, const uint8_t*, bool,
-                                 hipStream_t, const int*);
-template void fmm_apply<float>(Tree&, double, int, const float2*, float2*, int, hipStream_t);
-template void fmm_apply<double>(Tree&, double, int, const double2*, double2*, int, hipStream_t);
+                                 hipStream_t, const int*, StageTimer*);
+template void fmm_apply<float>(Tree&, double, int, const float2*, float2*, int, hipStream_t, StageTimer*);
+template void fmm_apply<double>(Tree&, double, int, const double2*, double2*, int, hipStream_t, StageTimer*);
+
+StageTimer::~StageTimer() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+void StageTimer::mark(int s, hipStream_t st) {
+  hipEvent_t e;
+  HFMM_HIP(hipEventCreate(&e));
+  ev.push_back(e);
+  stage.push_back(s);
+  HFMM_HIP(hipEventRecord(e, st));
+}
+
+void StageTimer::collect(float* ms, int nstage) {
+  for (int i = 0; i < nstage; ++i) ms[i] = 0;
+  if (ev.empty()) return;
+  HFMM_HIP(hipEventSynchronize(ev.back()));
+  for (size_t i = 1; i < ev.size(); ++i) {
+    float d = 0;
+    HFMM_HIP(hipEventElapsedTime(&d, ev[i - 1], ev[i]));
+    if (stage[i] >= 0 && stage[i] < nstage) ms[stage[i]] += d;
+  }
+}
 
 }  // namespace hfmm

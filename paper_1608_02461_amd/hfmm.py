@@ -54,6 +54,9 @@ _SIGS = {
     "hfmm_tree_export": ([_vp, _vp, _vp, _vp], _i32),
     "hfmm_tree_destroy": ([_vp], _i32),
     "hfmm_fmm_apply": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_fmm_apply_timed": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_float), _vp], _i32),
+    "hfmm_fmm_plan_info": ([_vp, _f64, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                            ctypes.POINTER(_i64)], _i32),
     "hfmm_fd_helmholtz_matvec": ([_i32, _f64, _vp, _f64, _vp, _vp, _i32, _vp], _i32),
     "hfmm_solver_create": ([_i32, _f64, _vp, _f64, _f64, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)], _i32),
     "hfmm_solver_set_k2": ([_vp, _vp, _f64, _vp], _i32),
@@ -170,6 +173,29 @@ def hfmm_fmm_apply(tree, k, p, q, prec=FP64, stream=None):
     _check(lib().hfmm_fmm_apply(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), qc.shape[0],
                                 _stream(stream)))
     return _from_colmajor(phi, squeeze)
+
+
+STAGES = ("gather", "upward", "downward", "l2p", "p2p", "scatter")
+
+
+def hfmm_fmm_apply_timed(tree, k, p, q, prec=FP64, stream=None):
+    """The FMM apply with per-stage device times; returns (phi, {stage: ms})."""
+    dtype = torch.complex128 if prec == FP64 else torch.complex64
+    qc, squeeze = _colmajor(q, dtype, "q")
+    phi = torch.empty_like(qc)
+    ms = (ctypes.c_float * 6)()
+    _check(lib().hfmm_fmm_apply_timed(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), qc.shape[0], ms,
+                                      _stream(stream)))
+    return _from_colmajor(phi, squeeze), dict(zip(STAGES, list(ms)))
+
+
+def hfmm_fmm_plan_info(tree, k, p, prec=FP64):
+    L = tree.info()["levels"]
+    orders = (_i32 * (L + 1))()
+    deg, g, pairs = _i32(), _i32(), _i64()
+    _check(lib().hfmm_fmm_plan_info(tree.handle, float(k), int(p), int(prec), orders, ctypes.byref(deg),
+                                    ctypes.byref(g), ctypes.byref(pairs)))
+    return {"orders": list(orders), "near_deg": deg.value, "lanes_per_target": g.value, "pairs": pairs.value}
 
 
 def hfmm_fd_helmholtz_matvec(n, h, x, k2=None, k2_const=0.0, stream=None):
