@@ -204,6 +204,21 @@ def main():
             log(f"C3 {name}: {solves[name]}")
             del s
         solves["mixed_over_fp64_speedup"] = round(solves["fp64"]["s_per_solve"] / solves["mixed"]["s_per_solve"], 3)
+        # stage times of one FMM pass on the same point set (interior nodes + boundary midpoints)
+        n3 = c3["n"]
+        h3 = 1.0 / (n3 + 1)
+        m = (np.arange(n3 + 1) + 0.5) * h3
+        z, o = np.zeros_like(m), np.ones_like(m)
+        pts = np.concatenate([workloads.interior_xy(n3), np.stack([m, z], 1), np.stack([o, m], 1),
+                              np.stack([m, o], 1), np.stack([z, m], 1)])
+        t3 = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=c3["leaf"])
+        qq = torch.ones(len(pts), dtype=torch.complex64, device=dev)
+        for name, prec, qv in (("fp32", hfmm.FP32, qq), ("fp64", hfmm.FP64, qq.to(torch.complex128))):
+            hfmm.hfmm_fmm_apply_timed(t3, c3["k"], 6, qv, prec=prec)
+            _, ms = hfmm.hfmm_fmm_apply_timed(t3, c3["k"], 6, qv, prec=prec)
+            solves[f"fmm_pass_stage_ms_{name}"] = {s_: round(v, 4) for s_, v in ms.items()}
+        solves["orders"] = hfmm.hfmm_fmm_plan_info(t3, c3["k"], 6, hfmm.FP32)["orders"]
+        log(f"C3 FMM stages: {solves['fmm_pass_stage_ms_fp32']}")
         result["solve_1024"] = solves
 
         c1 = workloads.solve_c1()

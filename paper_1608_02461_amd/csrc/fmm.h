@@ -27,6 +27,14 @@ struct LevelInfo {
   int64_t box0 = 0;    // offset of the level in the per-box flag array
 };
 
+// Launch shape of the MFMA downward pass at one level.
+struct MfmaLevel {
+  bool on = false;
+  int RT = 0, KS = 0, KSp = 0, KSc = 0, KPs = 0, tile = 0, gx = 0, gy = 0;
+  int64_t af = 0, wf = 0, mm = 0;  // offsets into the M2L / L2L / M2M fragment tables
+  size_t lds = 0;
+};
+
 template <class T>
 struct FmmPlan : PlanBase {
   double k = 0;
@@ -36,12 +44,15 @@ struct FmmPlan : PlanBase {
   int64_t flag_total = 0;   // sum over levels 0..L of 4^l
   DevBuf<cplx<T>> m2m, l2l, m2l;
   std::vector<int64_t> m2m_off, l2l_off, m2l_off;
+  std::vector<MfmaLevel> mf;   // per level
+  DevBuf<T> afrag, wfrag, mfrag;  // per-lane MFMA fragments of the M2L / L2L / M2M matrices
   DevBuf<T> series;         // (p_L + 1) x (K + 1): [n][0] = 1/(n+1), [n][j] = 1/(j (n+j))
   int K = 0;
   // near field
   bool near_fast = false;
   NearPoly poly;
   int G = 1;                // lanes per target in P2P
+  bool use_mfma = true;     // MFMA downward pass where the level's tables exist
   // work storage
   DevBuf<cplx<T>> M, Lc;
   int nrhs_cap = 0;

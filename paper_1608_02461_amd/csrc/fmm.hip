@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
+#include <string>
 #include <type_traits>
 
 #include "fmm.h"
@@ -203,6 +205,264 @@ __global__ __launch_bounds__(64) void k_down(const cplx<T>* __restrict__ M, cplx
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) Lc[((size_t)b * nrhs + r0 + r) * P + lo] = acc[r];
+  }
+}
+
+// ------------------------------------------------------------------ L2L + M2L on MFMA
+// Complex translations in real form: for an output coefficient m and input n,
+//   [Re L_m]   [ Re T  -Im T ] [Re M_n]
+//   [Im L_m] = [ Im T   Re T ] [Im M_n]
+// so each translation is a (2P x 2P) real matrix A.  One wave owns a 4 x 4
+// patch of target boxes = the 16 columns of a 16x16x4 MFMA; it walks the 40
+// offset classes (a column whose box does not have the offset in its
+// interaction list reads a zero) and the 4 L2L child positions (a column reads
+// its parent's local expansion only for its own position).  A comes from
+// tables already laid out per lane: frag[...][ks][lane] = A[16 rt + lane%16][4 ks + lane/16];
+// B comes from the source multipoles staged in LDS for the block's window.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <class T> struct Acc4;
+template <> struct Acc4<float> { typedef f32x4 type; };
+template <> struct Acc4<double> { typedef f64x4 type; };
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16x16 accumulator held in register q of a lane in group kq =
+// lane/16 (column = lane%16): 4 kq + q for the FP32 MFMA, 4 q + kq for FP64.
+template <class T> __device__ __forceinline__ int out_row(int kq, int q);
+template <> __device__ __forceinline__ int out_row<float>(int kq, int q) { return 4 * kq + q; }
+template <> __device__ __forceinline__ int out_row<double>(int kq, int q) { return 4 * q + kq; }
+
+constexpr int kMaxLev = 13;
+
+// the 40 M2L offset classes, o = (ox + 3) * 7 + (oy + 3), in increasing o
+__constant__ int kClassO[40] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 19, 20, 21, 22,
+                                26, 27, 28, 29, 33, 34, 35, 36, 37, 38, 39, 40, 41, 42, 43, 44, 45, 46, 47, 48};
+
+template <class T>
+struct M2LLevel {
+  const cplx<T>* M;
+  cplx<T>* Lc;
+  const T* Af;          // [49][RT][KS][64]
+  const uint8_t* fsrc;  // source flags of the level or NULL
+  int nb, P, RT, KS, KPs, tile, gx, block0;
+};
+
+template <class T>
+struct M2LAllArgs {
+  M2LLevel<T> lv[kMaxLev];
+  int nlev;
+  const int* alive;
+  int nrhs, r0, nr;
+};
+
+// M2L of every level in one launch (the levels are independent; L2L runs
+// afterwards, top down).  One block = a tile x tile patch of target boxes
+// (4 or 1 patches of 4 x 4) and one row tile.  Every wave owns all patches of
+// the block (one accumulator each, so one A fragment feeds up to 4 MFMAs)
+// and the offset classes whose index = wave (mod 4); the four partial sums
+// meet in LDS.
+template <class T>
+__global__ __launch_bounds__(256) void k_m2l_mfma(M2LAllArgs<T> args) {
+  typedef typename Acc4<T>::type V4;
+  extern __shared__ unsigned char smem_raw[];
+  T* Ms = reinterpret_cast<T*>(smem_raw);
+  T* red = Ms;  // the reduction reuses the window once the products are done
+  if (args.alive && !args.alive[0]) return;
+  int li = 0;
+  while (li + 1 < args.nlev && (int)blockIdx.x >= args.lv[li + 1].block0) ++li;
+  const M2LLevel<T>& a = args.lv[li];
+  const int lblock = (int)blockIdx.x - a.block0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nbt = a.nb / a.tile;
+  const int pb = lblock % a.gx, rt = lblock / a.gx;
+  const int bx0 = (pb % nbt) * a.tile, by0 = (pb / nbt) * a.tile;
+  const int wx0 = max(0, bx0 - 2), wy0 = max(0, by0 - 2);
+  const int WW = min(a.nb, bx0 + a.tile + 2) - wx0, WH = min(a.nb, by0 + a.tile + 2) - wy0;
+  const int pside = a.tile / 4;
+  const int np = pside * pside;  // 4 or 1
+  const int j = lane & 15, kq = lane >> 4;
+  int tx[4], ty[4];
+  uint32_t tbox[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int pp = p < np ? p : 0;
+    tx[p] = bx0 + (pp % pside) * 4 + (j & 3);
+    ty[p] = by0 + (pp / pside) * 4 + (j >> 2);
+    tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
+  }
+  const int P2 = 2 * a.P, KP = 4 * a.KS;
+  const int nchunk = (a.KS + 3) / 4;
+  for (int r = 0; r < args.nr; ++r) {
+    __syncthreads();
+    for (int idx = tid; idx < WW * WH * a.P; idx += 256) {
+      const int lb = idx / a.P, n = idx - lb * a.P;
+      const uint32_t gb = morton((uint32_t)(wx0 + lb % WW), (uint32_t)(wy0 + lb / WW));
+      cplx<T> v = mk<T>(0, 0);
+      if (!a.fsrc || a.fsrc[gb]) v = a.M[((size_t)gb * args.nrhs + args.r0 + r) * a.P + n];
+      Ms[lb * a.KPs + n] = v.x;
+      Ms[lb * a.KPs + a.P + n] = v.y;
+    }
+    const int padw = KP - P2;
+    for (int idx = tid; idx < WW * WH * padw; idx += 256) {
+      const int lb = idx / padw;
+      Ms[lb * a.KPs + P2 + (idx - lb * padw)] = T(0);
+    }
+    __syncthreads();
+    V4 acc[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[p] = V4{0, 0, 0, 0};
+    // this wave's 10 offset classes, (class index) = w (mod 4); the A
+    // fragments of the next chunk are loaded before the MFMAs of this one
+    const int nsteps = 10 * nchunk;
+    auto a_ptr = [&](int step) {
+      const int oi = step / nchunk, c = step - oi * nchunk;
+      return a.Af + ((size_t)(kClassO[4 * oi + w] * a.RT + rt) * a.KS + c * 4) * 64 + lane;
+    };
+    T an[4];
+    {
+      const T* A0 = a_ptr(0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) an[u] = A0[min(u, a.KS - 1) * 64];
+    }
+    bool v[4];
+    int lb[4];
+    for (int step = 0; step < nsteps; ++step) {
+      const int oi = step / nchunk, c = step - oi * nchunk;
+      T ac[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ac[u] = an[u];
+      if (step + 1 < nsteps) {
+        const int c1 = (step + 1) % nchunk;
+        const T* A1 = a_ptr(step + 1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) an[u] = A1[(min(c1 * 4 + u, a.KS - 1) - c1 * 4) * 64];
+      }
+      if (c == 0) {
+        const int o = kClassO[4 * oi + w];
+        const int ox = o / 7 - 3, oy = o % 7 - 3;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int sx = tx[p] + ox, sy = ty[p] + oy;
+          v[p] = p < np && sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb && abs((sx >> 1) - (tx[p] >> 1)) <= 1 &&
+                 abs((sy >> 1) - (ty[p] >> 1)) <= 1;
+          lb[p] = v[p] ? (sx - wx0) + (sy - wy0) * WW : 0;
+        }
+      }
+      T bv[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ks = min(c * 4 + u, a.KS - 1);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) bv[p][u] = v[p] ? Ms[lb[p] * a.KPs + ks * 4 + kq] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c * 4 + u < a.KS) {
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+            if (p < np) acc[p] = mfma16(ac[u], bv[p][u], acc[p]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (p < np) red[((w * 4 + p) * 4 + q) * 64 + lane] = acc[p][q];
+    __syncthreads();
+    if (w < np) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T s = red[((0 * 4 + w) * 4 + q) * 64 + lane] + red[((1 * 4 + w) * 4 + q) * 64 + lane] +
+                    red[((2 * 4 + w) * 4 + q) * 64 + lane] + red[((3 * 4 + w) * 4 + q) * 64 + lane];
+        const int i = rt * 16 + out_row<T>(kq, q);
+        if (i < P2) {
+          T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tbox[w] * args.nrhs + args.r0 + r) * a.P + (i < a.P ? i : i - a.P));
+          dst[i < a.P ? 0 : 1] = s;
+        }
+      }
+    }
+  }
+}
+
+// Level-to-level translation on MFMA.  One wave = 16 boxes of the output
+// level (columns) and one row tile (blockIdx.y):
+//   L2L (mode 0): child boxes 4 b + c of 16 consecutive parents b, one child
+//                 position c per wave; out += A_c * L_parent.
+//   M2M (mode 1): 16 consecutive parents; out = sum_c A_c * M_child(4 b + c).
+// Input columns read the real form [Re; Im] of the source coefficients.
+template <class T>
+struct TTArgs {
+  const cplx<T>* in;
+  cplx<T>* out;
+  const T* Wf;               // [4][RT][KS][64]
+  const uint8_t* fin;        // flags of the input level (M2M) or NULL
+  const uint8_t* fout;       // flags of the output level (M2M) or NULL
+  const int* alive;
+  int mode, nparents, Pin, Pout, RT, KS, nrhs, r0, nr;
+};
+
+template <class T>
+__global__ __launch_bounds__(64) void k_tt_mfma(TTArgs<T> a) {
+  typedef typename Acc4<T>::type V4;
+  if (a.alive && !a.alive[0]) return;
+  const int lane = threadIdx.x, j = lane & 15, kq = lane >> 4;
+  const int groups = (a.nparents + 15) / 16;
+  const int g = blockIdx.x % groups, cw = blockIdx.x / groups;  // cw: child position (L2L)
+  const int rt = blockIdx.y;
+  const int parent = g * 16 + j;
+  const bool colv = parent < a.nparents;
+  const int nchunk = (a.KS + 3) / 4;
+  for (int r = 0; r < a.nr; ++r) {
+    V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const int nterm = a.mode == 0 ? 1 : 4;
+    if (a.mode == 1 && a.fout && __ballot(colv && a.fout[parent]) == 0ull) return;
+    for (int term = 0; term < nterm; ++term) {
+      const int c = a.mode == 0 ? cw : term;
+      const int src = a.mode == 0 ? parent : 4 * parent + c;
+      const bool bvalid = colv && (a.mode == 0 || !a.fin || a.fin[src]);
+      const cplx<T>* col = a.in + ((size_t)(bvalid ? src : 0) * a.nrhs + a.r0 + r) * a.Pin;
+      const T* Wf = a.Wf + ((size_t)(c * a.RT + rt) * a.KS) * 64 + lane;
+      for (int ch = 0; ch < nchunk; ++ch) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ks = min(ch * 4 + u, a.KS - 1);
+          av[u] = Wf[ks * 64];
+          const int kk = ks * 4 + kq;
+          bv[u] = T(0);
+          if (bvalid && kk < 2 * a.Pin) {
+            const cplx<T> pv = col[kk < a.Pin ? kk : kk - a.Pin];
+            bv[u] = kk < a.Pin ? pv.x : pv.y;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ch * 4 + u < a.KS) {
+            if (u & 1)
+              acc1 = mfma16(av[u], bv[u], acc1);
+            else
+              acc0 = mfma16(av[u], bv[u], acc0);
+          }
+      }
+    }
+    if (!colv) continue;
+    const int obox = a.mode == 0 ? 4 * parent + cw : parent;
+    if (a.mode == 1 && a.fout && !a.fout[obox]) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = rt * 16 + out_row<T>(kq, q);
+      if (i < 2 * a.Pout) {
+        T* dst = reinterpret_cast<T*>(a.out + ((size_t)obox * a.nrhs + a.r0 + r) * a.Pout + (i < a.Pout ? i : i - a.Pout));
+        const T s = acc0[q] + acc1[q];
+        dst[i < a.Pout ? 0 : 1] = a.mode == 0 ? dst[i < a.Pout ? 0 : 1] + s : s;
+      }
+    }
   }
 }
 
@@ -528,6 +788,9 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   }
   pl->coef_total = coef;
   pl->flag_total = box0;
+  // HFMM_M2L=valu selects the VALU downward kernel at every level (ablation)
+  const char* m2l_env = std::getenv("HFMM_M2L");
+  pl->use_mfma = !(m2l_env && std::string(m2l_env) == "valu");
 
   // near field: pair arguments k r are bounded by the 3 x 3 leaf block
   const double lside = t.leaf_side();
@@ -629,6 +892,78 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
     pl->m2m.upload(hm2m);
     pl->l2l.upload(hl2l);
     pl->m2l.upload(hm2l);
+
+    // MFMA fragments: frag[..][rt][ks][lane] = A[16 rt + lane%16][4 ks + lane/16]
+    // with A the real form of a complex (P_out x P_in) block (see k_m2l_mfma)
+    auto embed = [](const cplx<T>& z, int i, int kk, int Pout, int Pin) -> T {
+      if (i >= 2 * Pout || kk >= 2 * Pin) return T(0);
+      const bool io = i >= Pout, ki = kk >= Pin;
+      if (!io && !ki) return z.x;
+      if (!io && ki) return -z.y;
+      if (io && !ki) return z.y;
+      return z.x;
+    };
+    pl->mf.assign(L + 1, MfmaLevel{});
+    std::vector<T> haf, hwf, hmf;
+    auto frag = [&](std::vector<T>& dst, int64_t base, int nterm, int RT, int KS, int Pout, int Pin,
+                    auto&& value) {  // value(term, m_out, n_in) -> complex entry
+      dst.resize(dst.size() + (size_t)nterm * RT * KS * 64, T(0));
+      for (int tm = 0; tm < nterm; ++tm)
+        for (int rt = 0; rt < RT; ++rt)
+          for (int ks = 0; ks < KS; ++ks)
+            for (int ln = 0; ln < 64; ++ln) {
+              const int i = rt * 16 + (ln & 15), kk = ks * 4 + (ln >> 4);
+              if (i < 2 * Pout && kk < 2 * Pin)
+                dst[base + (((size_t)tm * RT + rt) * KS + ks) * 64 + ln] = embed(value(tm, i % Pout, kk % Pin), i, kk, Pout, Pin);
+            }
+    };
+    for (int l = 2; l <= L; ++l) {
+      MfmaLevel& m = pl->mf[l];
+      const int P = pl->lv[l].P, nb = 1 << l;
+      m.RT = (2 * P + 15) / 16;
+      m.KS = (2 * P + 3) / 4;
+      m.KPs = 4 * m.KS + 1;
+      // M2L window: a tile of 8 x 8 targets when it fits in 64 KB of LDS, else 4 x 4
+      for (int tile : {8, 4}) {
+        m.tile = std::min(tile, nb);
+        const int win = std::min(nb, m.tile + 4);
+        m.lds = std::max((size_t)win * win * m.KPs, (size_t)4 * 4 * 4 * 64) * sizeof(T);
+        m.on = m.lds <= 65536;
+        if (m.on) break;
+      }
+      m.gx = (nb / m.tile) * (nb / m.tile);
+      m.gy = m.RT;
+      if (m.on) {
+        m.af = (int64_t)haf.size();
+        frag(haf, m.af, 49, m.RT, m.KS, P, P, [&](int o, int mo, int ni) -> cplx<T> {
+          const int ox = o / 7 - 3, oy = o % 7 - 3;
+          if (std::max(std::abs(ox), std::abs(oy)) < 2) return mk<T>(0, 0);
+          return hm2l[pl->m2l_off[l] + ((size_t)o * P + ni) * P + mo];
+        });
+      }
+      if (l > 2) {  // L2L into level l from its parent level
+        const int Pp = pl->lv[l - 1].P;
+        m.KSp = (2 * Pp + 3) / 4;
+        m.wf = (int64_t)hwf.size();
+        frag(hwf, m.wf, 4, m.RT, m.KSp, P, Pp, [&](int c, int mo, int ni) -> cplx<T> {
+          return hl2l[pl->l2l_off[l - 1] + ((size_t)c * Pp + ni) * P + mo];
+        });
+      }
+      if (l < L) {  // M2M into level l from its child level
+        const int Pc = pl->lv[l + 1].P;
+        m.KSc = (2 * Pc + 3) / 4;
+        m.mm = (int64_t)hmf.size();
+        frag(hmf, m.mm, 4, m.RT, m.KSc, P, Pc, [&](int c, int mo, int ni) -> cplx<T> {
+          return hm2m[pl->m2m_off[l] + ((size_t)c * Pc + ni) * P + mo];
+        });
+      }
+    }
+    if (haf.empty()) haf.resize(1);
+    if (hwf.empty()) hwf.resize(1);
+    if (hmf.empty()) hmf.resize(1);
+    pl->afrag.upload(haf);
+    pl->wfrag.upload(hwf);
+    pl->mfrag.upload(hmf);
   }
   return pl;
 }
@@ -649,22 +984,108 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
                                                  T(k / (2 * lf.s)), T(k * k / 4), pl.series.p, pl.K,
                                                  flags ? flags + lf.box0 : nullptr, alive);
     HFMM_LAUNCH_CHECK();
-    for (int l = L - 1; l >= 2; --l) {
-      const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
-      k_m2m<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + lc.coef * nrhs, M + lp.coef * nrhs, pl.m2m.p + pl.m2m_off[l],
-                                                lc.P, lp.P, nrhs, r0, flags ? flags + lc.box0 : nullptr,
-                                                flags ? flags + lp.box0 : nullptr, alive);
-      HFMM_LAUNCH_CHECK();
-    }
-    if (tm) tm->mark(1, st);
-    for (int l = 2; l <= L; ++l) {
-      const LevelInfo& li = pl.lv[l];
-      const LevelInfo& lp = pl.lv[l - 1];
-      k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs,
-                                                 l > 2 ? Lc + lp.coef * nrhs : nullptr, pl.m2l.p + pl.m2l_off[l],
-                                                 l > 2 ? pl.l2l.p + pl.l2l_off[l - 1] : nullptr, li.P, lp.P, l,
-                                                 nrhs, r0, flags ? flags + li.box0 : nullptr, alive);
-      HFMM_LAUNCH_CHECK();
+    if (pl.use_mfma) {
+      // upward: M2M on MFMA, levels L-1 .. 2
+      for (int l = L - 1; l >= 2; --l) {
+        const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
+        const MfmaLevel& mf = pl.mf[l];
+        TTArgs<T> ta{};
+        ta.in = M + lc.coef * nrhs;
+        ta.out = M + lp.coef * nrhs;
+        ta.Wf = pl.mfrag.p + mf.mm;
+        ta.fin = flags ? flags + lc.box0 : nullptr;
+        ta.fout = flags ? flags + lp.box0 : nullptr;
+        ta.alive = alive;
+        ta.mode = 1;
+        ta.nparents = 1 << (2 * l);
+        ta.Pin = lc.P;
+        ta.Pout = lp.P;
+        ta.RT = mf.RT;
+        ta.KS = mf.KSc;
+        ta.nrhs = nrhs;
+        ta.r0 = r0;
+        ta.nr = NR;
+        k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 64, 0, st>>>(ta);
+        HFMM_LAUNCH_CHECK();
+      }
+      if (tm) tm->mark(1, st);
+      // M2L of all levels in one launch (VALU for a level whose window does not fit)
+      M2LAllArgs<T> ma{};
+      ma.alive = alive;
+      ma.nrhs = nrhs;
+      ma.r0 = r0;
+      ma.nr = NR;
+      int blocks = 0;
+      size_t lds = 0;
+      for (int l = 2; l <= L; ++l) {
+        const LevelInfo& li = pl.lv[l];
+        const MfmaLevel& mf = pl.mf[l];
+        if (!mf.on) {
+          k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs, nullptr,
+                                                     pl.m2l.p + pl.m2l_off[l], nullptr, li.P, 1, l, nrhs, r0,
+                                                     flags ? flags + li.box0 : nullptr, alive);
+          HFMM_LAUNCH_CHECK();
+          continue;
+        }
+        M2LLevel<T>& v = ma.lv[ma.nlev++];
+        v.M = M + li.coef * nrhs;
+        v.Lc = Lc + li.coef * nrhs;
+        v.Af = pl.afrag.p + mf.af;
+        v.fsrc = flags ? flags + li.box0 : nullptr;
+        v.nb = 1 << l;
+        v.P = li.P;
+        v.RT = mf.RT;
+        v.KS = mf.KS;
+        v.KPs = mf.KPs;
+        v.tile = mf.tile;
+        v.gx = mf.gx;
+        v.block0 = blocks;
+        blocks += mf.gx * mf.gy;
+        lds = std::max(lds, mf.lds);
+      }
+      if (ma.nlev) {
+        k_m2l_mfma<T><<<blocks, 256, lds, st>>>(ma);
+        HFMM_LAUNCH_CHECK();
+      }
+      // L2L chain, levels 3 .. L
+      for (int l = 3; l <= L; ++l) {
+        const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
+        const MfmaLevel& mf = pl.mf[l];
+        TTArgs<T> ta{};
+        ta.in = Lc + lp.coef * nrhs;
+        ta.out = Lc + li.coef * nrhs;
+        ta.Wf = pl.wfrag.p + mf.wf;
+        ta.alive = alive;
+        ta.mode = 0;
+        ta.nparents = 1 << (2 * (l - 1));
+        ta.Pin = lp.P;
+        ta.Pout = li.P;
+        ta.RT = mf.RT;
+        ta.KS = mf.KSp;
+        ta.nrhs = nrhs;
+        ta.r0 = r0;
+        ta.nr = NR;
+        k_tt_mfma<T><<<dim3(4 * ((ta.nparents + 15) / 16), mf.RT), 64, 0, st>>>(ta);
+        HFMM_LAUNCH_CHECK();
+      }
+    } else {
+      for (int l = L - 1; l >= 2; --l) {
+        const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
+        k_m2m<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + lc.coef * nrhs, M + lp.coef * nrhs, pl.m2m.p + pl.m2m_off[l],
+                                                  lc.P, lp.P, nrhs, r0, flags ? flags + lc.box0 : nullptr,
+                                                  flags ? flags + lp.box0 : nullptr, alive);
+        HFMM_LAUNCH_CHECK();
+      }
+      if (tm) tm->mark(1, st);
+      for (int l = 2; l <= L; ++l) {
+        const LevelInfo& li = pl.lv[l];
+        const LevelInfo& lp = pl.lv[l - 1];
+        k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs,
+                                                   l > 2 ? Lc + lp.coef * nrhs : nullptr, pl.m2l.p + pl.m2l_off[l],
+                                                   l > 2 ? pl.l2l.p + pl.l2l_off[l - 1] : nullptr, li.P, lp.P, l,
+                                                   nrhs, r0, flags ? flags + li.box0 : nullptr, alive);
+        HFMM_LAUNCH_CHECK();
+      }
     }
     if (tm) tm->mark(2, st);
     k_l2p<T, NR><<<(int)t.nleaves, 64, (size_t)NR * lf.P * sizeof(cplx<T>), st>>>(

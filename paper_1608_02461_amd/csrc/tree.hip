@@ -46,28 +46,69 @@ __global__ __launch_bounds__(kThreads) void k_digit_hist(const uint32_t* __restr
   hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive prefix sum of a[0..m) in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ a, int64_t m) {
-  __shared__ uint32_t s[1024];
-  int t = threadIdx.x;
-  int64_t per = (m + 1023) / 1024;
-  int64_t lo = t * per, hi = lo + per < m ? lo + per : m;
-  uint32_t sum = 0;
-  for (int64_t i = lo; i < hi; ++i) sum += a[i];
-  s[t] = sum;
+// Exclusive prefix sum in three phases: per-block sums of 1024-element
+// chunks, a one-block scan of those sums, then a per-block scan with the
+// block's offset added.
+__device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* s, uint32_t& total) {
+  const int t = threadIdx.x;
+  s[t] = v;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = t >= off ? s[t - off] : 0u;
+    const uint32_t u = t >= off ? s[t - off] : 0u;
     __syncthreads();
-    s[t] += v;
+    s[t] += u;
     __syncthreads();
   }
-  uint32_t run = s[t] - sum;  // exclusive prefix of this segment
-  for (int64_t i = lo; i < hi; ++i) {
-    uint32_t v = a[i];
-    a[i] = run;
+  total = s[1023];
+  const uint32_t r = s[t] - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(const uint32_t* __restrict__ a, int64_t m,
+                                                    uint32_t* __restrict__ sums) {
+  __shared__ uint32_t s[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  uint32_t tot;
+  block_excl_scan_1024(i < m ? a[i] : 0u, s, tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of nb <= 1024 * per block sums, one block
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int nb) {
+  __shared__ uint32_t s[1024];
+  const int per = (nb + 1023) / 1024;
+  const int lo = threadIdx.x * per, hi = min(lo + per, nb);
+  uint32_t loc = 0;
+  for (int i = lo; i < hi; ++i) loc += sums[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan_1024(loc, s, tot);
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t v = sums[i];
+    sums[i] = run;
     run += v;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(uint32_t* __restrict__ a, int64_t m,
+                                                     const uint32_t* __restrict__ sums) {
+  __shared__ uint32_t s[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  uint32_t tot;
+  const uint32_t r = block_excl_scan_1024(i < m ? a[i] : 0u, s, tot);
+  if (i < m) a[i] = r + sums[blockIdx.x];
+}
+
+// Leaf offsets from the sorted keys: slot i opens every leaf in (key[i-1], key[i]].
+__global__ void k_leaf_bounds(const uint32_t* __restrict__ skeys, int n, int64_t nleaves,
+                              int32_t* __restrict__ off) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t k = skeys[i];
+  const int64_t prev = i > 0 ? (int64_t)skeys[i - 1] : -1;
+  for (int64_t b = prev + 1; b <= k; ++b) off[b] = i;
+  if (i == n - 1)
+    for (int64_t b = k + 1; b <= nleaves; ++b) off[b] = n;
 }
 
 __global__ __launch_bounds__(kThreads) void k_digit_scatter(const uint32_t* __restrict__ kin,
@@ -113,11 +154,6 @@ __global__ __launch_bounds__(kThreads) void k_digit_scatter(const uint32_t* __re
   }
 }
 
-__global__ void k_leaf_count(const uint32_t* __restrict__ keys, int n, uint32_t* __restrict__ cnt) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[keys[i]], 1u);
-}
-
 __global__ void k_finalize(const double* __restrict__ xy, const uint32_t* __restrict__ skeys,
                            const int32_t* __restrict__ perm, int n, double x0, double y0, double lside,
                            int32_t* __restrict__ iperm, double2* __restrict__ rel64, float2* __restrict__ rel32) {
@@ -133,6 +169,16 @@ __global__ void k_finalize(const double* __restrict__ xy, const uint32_t* __rest
   r.y = xy[2 * o + 1] - cy;
   rel64[i] = r;
   rel32[i] = make_float2((float)r.x, (float)r.y);
+}
+
+void scan_excl(uint32_t* a, int64_t m, DevBuf<uint32_t>& sums, hipStream_t st) {
+  const int nb = (int)((m + 1023) / 1024);
+  HFMM_REQUIRE(nb <= 1024 * 1024, "scan: too many elements");
+  sums.ensure(nb);
+  k_scan_sums<<<nb, 1024, 0, st>>>(a, m, sums.p);
+  k_scan_top<<<1, 1024, 0, st>>>(sums.p, nb);
+  k_scan_apply<<<nb, 1024, 0, st>>>(a, m, sums.p);
+  HFMM_LAUNCH_CHECK();
 }
 
 }  // namespace
@@ -177,25 +223,16 @@ std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, doubl
 
   // stable LSD radix sort of (key, index) over the 2L key bits
   const int ntiles = (N + kTile - 1) / kTile;
-  DevBuf<uint32_t> hist((size_t)256 * ntiles);
+  DevBuf<uint32_t> hist((size_t)256 * ntiles), sums;
   for (int shift = 0; shift < 2 * t->L; shift += 8) {
     k_digit_hist<<<ntiles, kThreads, 0, stream>>>(ka.p, N, shift, hist.p, ntiles);
     HFMM_LAUNCH_CHECK();
-    k_scan_excl<<<1, 1024, 0, stream>>>(hist.p, (int64_t)256 * ntiles);
-    HFMM_LAUNCH_CHECK();
+    scan_excl(hist.p, (int64_t)256 * ntiles, sums, stream);
     k_digit_scatter<<<ntiles, kThreads, 0, stream>>>(ka.p, va.p, kb.p, vb.p, N, shift, hist.p, ntiles);
     HFMM_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-
-  // leaf offsets: counts per key, exclusive scan over nleaves + 1 entries
-  DevBuf<uint32_t> cnt(t->nleaves + 1);
-  HFMM_HIP(hipMemsetAsync(cnt.p, 0, (t->nleaves + 1) * sizeof(uint32_t), stream));
-  k_leaf_count<<<blocks, 256, 0, stream>>>(ka.p, N, cnt.p);
-  HFMM_LAUNCH_CHECK();
-  k_scan_excl<<<1, 1024, 0, stream>>>(cnt.p, t->nleaves + 1);
-  HFMM_LAUNCH_CHECK();
 
   t->perm = std::move(va);
   t->iperm.alloc(N);
@@ -205,10 +242,10 @@ std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, doubl
                                          t->rel64.p, t->rel32.p);
   HFMM_LAUNCH_CHECK();
   t->leaf_off.alloc(t->nleaves + 1);
-  HFMM_HIP(hipMemcpyAsync(t->leaf_off.p, cnt.p, (t->nleaves + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                          stream));
+  k_leaf_bounds<<<blocks, 256, 0, stream>>>(ka.p, N, t->nleaves, t->leaf_off.p);
+  HFMM_LAUNCH_CHECK();
   t->leaf_off_h.resize(t->nleaves + 1);
-  HFMM_HIP(hipMemcpyAsync(t->leaf_off_h.data(), cnt.p, (t->nleaves + 1) * sizeof(int32_t),
+  HFMM_HIP(hipMemcpyAsync(t->leaf_off_h.data(), t->leaf_off.p, (t->nleaves + 1) * sizeof(int32_t),
                           hipMemcpyDeviceToHost, stream));
   HFMM_HIP(hipStreamSynchronize(stream));
   int mx = 0;

@@ -147,3 +147,21 @@ def test_c2_full_size_sampled(p):
     say(f"  eps_oracle={eps:.3e} fp64={e64:.3e} fp32={e32:.3e}")
     assert e64 <= eps + 1e-6
     assert e32 <= eps + 2e-5
+
+
+@pytest.mark.parametrize("N,leaf,k,p", [(4356, 32, 16.0, 6), (20000, 8, 300.0, 6), (3000, 16, 100.0, 12),
+                                        (70000, 16, 100.0, 8)])
+def test_mfma_downward_matches_valu(N, leaf, k, p, monkeypatch):
+    """The MFMA L2L+M2L kernel and the VALU one compute the same sums."""
+    say(f"mfma vs valu N={N} leaf={leaf} k={k} p={p}")
+    xy, q = workloads.random_cloud(N, seed=N + p)
+    q = q[:, 0]
+    out = {}
+    for mode in ("mfma", "valu"):
+        if mode == "valu":
+            monkeypatch.setenv("HFMM_M2L", "valu")
+        t = hfmm.Tree(to_dev(xy), leaf_size=leaf)
+        out[mode] = (to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q), prec=hfmm.FP64)),
+                     to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q.astype(np.complex64)), prec=hfmm.FP32)))
+    assert rel(out["mfma"][0], out["valu"][0]) <= 1e-12
+    assert rel(out["mfma"][1], out["valu"][1]) <= 3e-6
