@@ -13,6 +13,10 @@ Also reported on the same JSON line:
 * the mixed-precision (complex64 FMM inside FP64 FGMRES(50)) and all-FP64
   solves of the 1024 x 1024 grid, k h = 0.3, Gaussian bump, to 1e-6;
 * the 64 x 64, k = 16, FP64 FGMRES(30) solve;
+* the batched solve of 16 problems x 4 right-hand sides (k in [20, 300], n in
+  {128, 256, 384, 512}), one hipGraph-captured Arnoldi step vs eager;
+* forward + backward of the block-k^2 adjoint gradient on 256 x 256, checked
+  against the CPU oracle's sparse-direct adjoint gradient;
 * `roofline` for the dominant kernel of the timed apply, from per-stage
   hipEvents recorded on the launch stream over the timed steps;
 * `cpu_baseline`: the CPU oracle's direct N-body sum on a bounded sample of
@@ -184,9 +188,11 @@ def main():
         c3 = workloads.solve_c3()
         f = torch.from_numpy(c3["f"]).to(dev)
         solves = {}
-        for name, prec in (("mixed", hfmm.FP32), ("fp64", hfmm.FP64)):
+        k3m = hfmm.hfmm_matched_wavenumber(c3["k"], 1.0 / (c3["n"] + 1))
+        for name, prec, k0 in (("mixed", hfmm.FP32, c3["k"]), ("fp64", hfmm.FP64, c3["k"]),
+                               ("mixed_matched_k0", hfmm.FP32, k3m), ("fp64_matched_k0", hfmm.FP64, k3m)):
             t0 = time.perf_counter()
-            s = hfmm.Solver(c3["n"], c3["k"], p=6, leaf_size=c3["leaf"], prec=prec)
+            s = hfmm.Solver(c3["n"], k0, k2_const=c3["k"] ** 2, p=6, leaf_size=c3["leaf"], prec=prec)
             torch.cuda.synchronize()
             setup = time.perf_counter() - t0
             s.solve(f, restart=50, rtol=1e-6)  # warm
@@ -197,13 +203,16 @@ def main():
                 x, info = s.solve(f, restart=50, rtol=1e-6)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
-            solves[name] = {"solves_s": round(1 / dt, 4), "s_per_solve": round(dt, 4), "iters": info["iters"],
+            solves[name] = {"k0": round(k0, 4), "solves_s": round(1 / dt, 4), "s_per_solve": round(dt, 4),
+                            "iters": info["iters"],
                             "rel_res_true": info["rel_res_true"], "converged": info["converged"],
                             "ms_precond_per_iter": round(info["ms_precond"] / max(1, info["iters"]), 4),
                             "setup_s": round(setup, 3)}
             log(f"C3 {name}: {solves[name]}")
             del s
         solves["mixed_over_fp64_speedup"] = round(solves["fp64"]["s_per_solve"] / solves["mixed"]["s_per_solve"], 3)
+        solves["mixed_over_fp64_speedup_matched_k0"] = round(
+            solves["fp64_matched_k0"]["s_per_solve"] / solves["mixed_matched_k0"]["s_per_solve"], 3)
         # stage times of one FMM pass on the same point set (interior nodes + boundary midpoints)
         n3 = c3["n"]
         h3 = 1.0 / (n3 + 1)
@@ -220,6 +229,75 @@ def main():
         solves["orders"] = hfmm.hfmm_fmm_plan_info(t3, c3["k"], 6, hfmm.FP32)["orders"]
         log(f"C3 FMM stages: {solves['fmm_pass_stage_ms_fp32']}")
         result["solve_1024"] = solves
+
+        # batched: 16 problems x 4 right-hand sides, one captured Arnoldi step for all
+        c4 = workloads.batch_c4()
+        t0 = time.perf_counter()
+        solvers, bs = [], []
+        for pr in c4["problems"]:
+            k0 = hfmm.hfmm_matched_wavenumber(pr["k"], pr["h"])
+            solvers.append(hfmm.Solver(pr["n"], k0, k2_const=pr["k"] ** 2, p=c4["p"], leaf_size=c4["leaf"],
+                                       prec=hfmm.FP32, nrhs=4))
+            bs.append(torch.from_numpy(pr["f"].astype(np.complex128)).to(dev))
+        torch.cuda.synchronize()
+        setup4 = time.perf_counter() - t0
+        maxit4, restart4 = 3000, 200
+        batch = {"setup_s": round(setup4, 3), "k0": "matched", "maxit": maxit4, "restart": restart4,
+                 "problems": [(pr["n"], round(pr["k"], 2)) for pr in c4["problems"]]}
+        log(f"C4 setup {setup4:.2f} s")
+        for mode, graph in (("graph", True), ("eager", False)):
+            t0 = time.perf_counter()
+            xs, infos = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart4, rtol=c4["rtol"],
+                                                       maxit=maxit4, use_graph=graph)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            batch[mode] = {"solves_s": round(64 / dt, 3), "t_batch_s": round(dt, 4),
+                           "converged": sum(i["converged"] for i in infos),
+                           "iters": [i["iters"] for i in infos],
+                           "max_rel_res": max(i["rel_res_true"] for i in infos)}
+            log(f"C4 {mode}: {batch[mode]}")
+        result["batch_16x4"] = batch
+        del solvers, bs, xs
+
+        # adjoint: block k^2 field on 256 x 256, forward + backward through the autograd wrapper
+        from oracle import adjoint as oadj
+        from paper_1608_02461_amd.autograd import expand_blocks, helmholtz_solve
+        c5 = workloads.adjoint_c5()
+        n5 = c5["n"]
+        s5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
+        d5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
+        f5 = torch.from_numpy(c5["f"]).to(dev)
+        ud, _ = d5.solve(f5, restart=200, rtol=1e-10, strict=True)
+        P5 = torch.from_numpy(c5["P"]).to(dev)
+        dd = ud[P5]
+        del d5
+
+        def fwd_bwd(rtol):
+            kbt = torch.from_numpy(c5["kb"]).to(dev).requires_grad_(True)
+            u = helmholtz_solve(expand_blocks(kbt, n5), f5, s5, restart=200, rtol=rtol)
+            r = u[P5] - dd
+            J = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+            J.backward()
+            return J.item(), kbt.grad.cpu().numpy()
+
+        fwd_bwd(1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J5, g5 = fwd_bwd(1e-10)
+        torch.cuda.synchronize()
+        t_fb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        J6, g6 = fwd_bwd(1e-6)
+        torch.cuda.synchronize()
+        t_fb6 = time.perf_counter() - t0
+        Jo, Go, _, _ = oadj.gradient(n5, c5["kb"], c5["f"], c5["P"], dd.cpu().numpy())
+        result["adjoint_256"] = {
+            "fwd_bwd_s_rtol1e-10": round(t_fb, 4), "fwd_bwd_s_rtol1e-6": round(t_fb6, 4),
+            "grad_rel_err_vs_oracle_rtol1e-10": float(np.linalg.norm(g5 - Go) / np.linalg.norm(Go)),
+            "grad_rel_err_vs_oracle_rtol1e-6": float(np.linalg.norm(g6 - Go) / np.linalg.norm(Go)),
+            "J_rel_err": abs(J5 - Jo) / abs(Jo)}
+        log(f"C5: {result['adjoint_256']}")
+        del s5
 
         c1 = workloads.solve_c1()
         s = hfmm.Solver(c1["n"], c1["k"], p=6, leaf_size=32, prec=hfmm.FP64)

@@ -166,6 +166,14 @@ hfmm_status hfmm_solver_create(int32_t n, double h, const double* d_k2, double k
                                int32_t p, int32_t leaf_size, hfmm_precision precond_prec,
                                int32_t nrhs, hipStream_t stream, hfmm_solver* out);
 
+/* Preconditioner wavenumber matched to the 5-point stencil's dispersion: the
+ * mean of the discrete wavenumbers of a plane wave at k along a grid axis,
+ * (2/h) asin(k h/2), and along a diagonal, (2 sqrt2/h) asin(k h/(2 sqrt2)).
+ * The continuous Green's function of the preconditioner (Sec. 5.2) then keeps
+ * the phase of the discrete operator's waves; k0 = k is the paper's choice.
+ * Host only; ERR_ARG when k h >= 2 or an argument is not positive. */
+hfmm_status hfmm_matched_wavenumber(double k, double h, double* k0);
+
 /* Replace the operator's k^2 field (preconditioner unchanged).  Async. */
 hfmm_status hfmm_solver_set_k2(hfmm_solver s, const double* d_k2, double k2_const, hipStream_t stream);
 

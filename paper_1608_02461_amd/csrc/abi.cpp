@@ -191,6 +191,18 @@ hfmm_status hfmm_solver_create(int32_t n, double h, const double* d_k2, double k
   HFMM_GUARD_END
 }
 
+hfmm_status hfmm_matched_wavenumber(double k, double h, double* k0) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(k0 != nullptr, "matched_wavenumber: k0 is NULL");
+  HFMM_REQUIRE(std::isfinite(k) && std::isfinite(h) && k > 0 && h > 0 && k * h < 2.0,
+               "matched_wavenumber: need k > 0, h > 0 and k h < 2");
+  const double axis = 2.0 / h * std::asin(k * h / 2.0);
+  const double diag = 2.0 * std::sqrt(2.0) / h * std::asin(k * h / (2.0 * std::sqrt(2.0)));
+  *k0 = 0.5 * (axis + diag);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
 hfmm_status hfmm_solver_set_k2(hfmm_solver s, const double* d_k2, double k2_const, hipStream_t stream) {
   HFMM_GUARD_BEGIN
   HFMM_REQUIRE(s != nullptr && s->s, "set_k2: NULL solver");
@@ -244,6 +256,9 @@ hfmm_status hfmm_fgmres_solve_batched(hfmm_solver* s, int32_t nprob, const doubl
   hipStream_t st = stream;
   hipStream_t own = nullptr;
   if (use_graph && st == nullptr) {  // the legacy default stream cannot be captured
+    // work the caller queued on the default stream (its b and x) must be done
+    // first: a non-blocking stream is not ordered after it
+    HFMM_HIP(hipStreamSynchronize(nullptr));
     HFMM_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
     st = own;
   }

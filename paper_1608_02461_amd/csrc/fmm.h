@@ -32,7 +32,8 @@ struct MfmaLevel {
   bool on = false;
   int RT = 0, KS = 0, KSp = 0, KSc = 0, KPs = 0, tile = 0, gx = 0, gy = 0;
   int64_t af = 0, wf = 0, mm = 0;  // offsets into the M2L / L2L / M2M fragment tables
-  size_t lds = 0;
+  size_t lds = 0, lds4 = 0;        // LDS of the default tile and of the 4 x 4 tile
+  bool fit4 = false;
 };
 
 template <class T>
@@ -53,6 +54,8 @@ struct FmmPlan : PlanBase {
   NearPoly poly;
   int G = 1;                // lanes per target in P2P
   bool use_mfma = true;     // MFMA downward pass where the level's tables exist
+  bool m2l_small = false;   // M2L on 4 x 4 target tiles (autotuned)
+  float tune_ms[5] = {0, 0, 0, 0, 0};  // P2P with G = 1, 2, 4; M2L 8x8, 4x4 tiles
   // work storage
   DevBuf<cplx<T>> M, Lc;
   int nrhs_cap = 0;

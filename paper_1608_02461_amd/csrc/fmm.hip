@@ -706,6 +706,180 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   }
 }
 
+// P2P, one block per parent box: its 4 waves are the 4 sibling target
+// leaves, and the union of their 3 x 3 neighbourhoods (a 4 x 4 block of
+// leaves) is staged in LDS once, positions relative to the parent centre and
+// scaled by k.  In row-major leaf order each wave's sources are 3 contiguous
+// runs (one per row) and the own leaf splits the middle run: 4 unmasked
+// segments plus one masked.  G lanes share a target (template), each taking
+// every G-th source; a shuffle tree sums the G partial sums.
+template <class T, int NR>
+struct P2P4Cfg {
+  static constexpr int kBytes = 2 * (int)sizeof(T) * (1 + NR);
+  static constexpr int SCAP = (sizeof(T) == 4 ? 32768 : 49152) / kBytes;
+};
+
+template <class T, int D, bool FAST, bool MASK, int NR, int G>
+__device__ __forceinline__ void p2p_run(const P2PArgs<T>& a, const cplx<T>* __restrict__ spos,
+                                        const cplx<T> (*sq)[P2P4Cfg<T, NR>::SCAP], int lo, int hi, int g, T xt,
+                                        T yt, T (&A)[NR], T (&B)[NR]) {
+#pragma unroll 4
+  for (int j = lo + g; j < hi; j += G) {
+    const cplx<T> s = spos[j];
+    const T dx = xt - s.x, dy = yt - s.y;
+    const T t = fmaT(dx, dx, dy * dy);
+    T J, Y;
+    h0_pair<T, D, FAST, MASK>(a, t, J, Y);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const cplx<T> qq = sq[r][j];
+      A[r] = fmaT(qq.x, J, A[r]);
+      A[r] = fmaT(-qq.y, Y, A[r]);
+      B[r] = fmaT(qq.x, Y, B[r]);
+      B[r] = fmaT(qq.y, J, B[r]);
+    }
+  }
+}
+
+template <class T, int NR, int D, bool FAST, int G>
+__global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
+  constexpr int SCAP = P2P4Cfg<T, NR>::SCAP;
+  __shared__ cplx<T> spos[SCAP];
+  __shared__ cplx<T> sq[NR][SCAP];
+  __shared__ int s_pre[17], s_lo[16], s_rounds[4];
+  __shared__ T s_ox[16], s_oy[16];
+  if (a.alive && !a.alive[0]) return;
+  const int parent = blockIdx.x;
+  int px, py;
+  demorton((uint32_t)parent, px, py);
+  const int nb = 1 << a.L;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  if (tid < 16) {
+    const int rx = tid & 3, ry = tid >> 2;
+    const int lx = 2 * px - 1 + rx, ly = 2 * py - 1 + ry;
+    int cnt = 0, lo = 0;
+    if (lx >= 0 && ly >= 0 && lx < nb && ly < nb) {
+      const uint32_t sl = morton((uint32_t)lx, (uint32_t)ly);
+      if (!a.flags || a.flags[sl]) {
+        lo = a.leaf_off[sl];
+        cnt = a.leaf_off[sl + 1] - lo;
+      }
+    }
+    s_lo[tid] = lo;
+    s_pre[tid + 1] = cnt;
+    s_ox[tid] = T(rx - 1.5) * a.kls;
+    s_oy[tid] = T(ry - 1.5) * a.kls;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_pre[0] = 0;
+    for (int i = 1; i <= 16; ++i) s_pre[i] += s_pre[i - 1];
+  }
+  __syncthreads();
+  const int total = s_pre[16];
+  if (total == 0 && a.accumulate) return;
+  // this wave's target leaf (child position w of the parent) and its segments
+  const int cx = w & 1, cy = w >> 1;
+  const uint32_t tleaf = 4u * (uint32_t)parent + (uint32_t)w;
+  const int t0 = a.leaf_off[tleaf], t1 = a.leaf_off[tleaf + 1];
+  const T txo = T(cx - 0.5) * a.kls, tyo = T(cy - 0.5) * a.kls;
+  const int r0 = cy * 4 + cx, r1 = (cy + 1) * 4 + cx, r2 = (cy + 2) * 4 + cx, io = r1 + 1;
+  const int sg_lo[4] = {s_pre[r0], s_pre[r2], s_pre[r1], s_pre[io + 1]};
+  const int sg_hi[4] = {s_pre[r0 + 3], s_pre[r2 + 3], s_pre[io], s_pre[r1 + 3]};
+  const int own_lo = s_pre[io], own_hi = s_pre[io + 1];
+  constexpr int TPR = 64 / G;
+  const int g = lane & (G - 1), tl = lane / G;
+  auto stage = [&](int c0, int cnt) {
+    for (int idx = tid; idx < cnt; idx += 256) {
+      const int gi = c0 + idx;
+      int lf = 0;
+      while (lf < 15 && gi >= s_pre[lf + 1]) ++lf;
+      const int slot = s_lo[lf] + gi - s_pre[lf];
+      const cplx<T> d = a.rel[slot];
+      spos[idx] = mk<T>(fmaT(a.k, d.x, s_ox[lf]), fmaT(a.k, d.y, s_oy[lf]));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sq[r][idx] = a.q[(size_t)(a.r0 + r) * a.N + slot];
+    }
+  };
+  auto finish = [&](int ti, bool act, T (&A)[NR], T (&B)[NR]) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        A[r] += __shfl_xor(A[r], off);
+        B[r] += __shfl_xor(B[r], off);
+      }
+    }
+    if (g == 0 && act) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
+        cplx<T> v = mk<T>(T(-0.25) * B[r], T(0.25) * A[r]);
+        if (a.accumulate) {
+          const cplx<T> o = a.phi[idx];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        a.phi[idx] = v;
+      }
+    }
+  };
+  if (total <= SCAP) {
+    stage(0, total);
+    __syncthreads();
+    for (int rb = t0; rb < t1; rb += TPR) {
+      const int ti = rb + tl;
+      const bool act = ti < t1;
+      T xt = 0, yt = 0;
+      if (act) {
+        const cplx<T> d = a.rel[ti];
+        xt = fmaT(a.k, d.x, txo);
+        yt = fmaT(a.k, d.y, tyo);
+      }
+      T A[NR], B[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+#pragma unroll
+      for (int sgi = 0; sgi < 4; ++sgi)
+        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, A, B);
+      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, A, B);
+      finish(ti, act, A, B);
+    }
+  } else {
+    // the region does not fit: uniform rounds across the block, sources in chunks
+    if (lane == 0) s_rounds[w] = (t1 - t0 + TPR - 1) / TPR;
+    __syncthreads();
+    const int R = max(max(s_rounds[0], s_rounds[1]), max(s_rounds[2], s_rounds[3]));
+    for (int round = 0; round < R; ++round) {
+      const int ti = t0 + round * TPR + tl;
+      const bool act = ti < t1;
+      T xt = 0, yt = 0;
+      if (act) {
+        const cplx<T> d = a.rel[ti];
+        xt = fmaT(a.k, d.x, txo);
+        yt = fmaT(a.k, d.y, tyo);
+      }
+      T A[NR], B[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+      for (int c0 = 0; c0 < total; c0 += SCAP) {
+        const int cnt = min(SCAP, total - c0);
+        __syncthreads();
+        stage(c0, cnt);
+        __syncthreads();
+#pragma unroll
+        for (int sgi = 0; sgi < 4; ++sgi) {
+          const int lo = max(sg_lo[sgi], c0) - c0, hi = min(sg_hi[sgi], c0 + cnt) - c0;
+          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, A, B);
+        }
+        const int lo = max(own_lo, c0) - c0, hi = min(own_hi, c0 + cnt) - c0;
+        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, A, B);
+      }
+      finish(ti, act, A, B);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ misc
 template <class T>
 __global__ void k_gather(const cplx<T>* __restrict__ q, cplx<T>* __restrict__ qs, const int32_t* __restrict__ perm,
@@ -924,16 +1098,23 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       m.KS = (2 * P + 3) / 4;
       m.KPs = 4 * m.KS + 1;
       // M2L window: a tile of 8 x 8 targets when it fits in 64 KB of LDS, else 4 x 4
-      for (int tile : {8, 4}) {
-        m.tile = std::min(tile, nb);
-        const int win = std::min(nb, m.tile + 4);
-        m.lds = std::max((size_t)win * win * m.KPs, (size_t)4 * 4 * 4 * 64) * sizeof(T);
-        m.on = m.lds <= 65536;
-        if (m.on) break;
+      auto lds_for = [&](int tile) {
+        const int win = std::min(nb, std::min(tile, nb) + 4);
+        return std::max((size_t)win * win * m.KPs, (size_t)4 * 4 * 4 * 64) * sizeof(T);
+      };
+      m.lds4 = lds_for(4);
+      m.fit4 = m.lds4 <= 65536;
+      m.tile = std::min(8, nb);
+      m.lds = lds_for(8);
+      m.on = m.lds <= 65536;
+      if (!m.on && m.fit4) {
+        m.tile = 4;
+        m.lds = m.lds4;
+        m.on = true;
       }
       m.gx = (nb / m.tile) * (nb / m.tile);
       m.gy = m.RT;
-      if (m.on) {
+      if (m.on || m.fit4) {
         m.af = (int64_t)haf.size();
         frag(haf, m.af, 49, m.RT, m.KS, P, P, [&](int o, int mo, int ni) -> cplx<T> {
           const int ox = o / 7 - 3, oy = o % 7 - 3;
@@ -966,6 +1147,143 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
     pl->mfrag.upload(hmf);
   }
   return pl;
+}
+
+template <class T, int NR, int D, bool FAST>
+void launch_p2p4(int G, int grid, const P2PArgs<T>& a, hipStream_t st) {
+  switch (G) {
+    case 1: k_p2p4<T, NR, D, FAST, 1><<<grid, 256, 0, st>>>(a); break;
+    case 2: k_p2p4<T, NR, D, FAST, 2><<<grid, 256, 0, st>>>(a); break;
+    default: k_p2p4<T, NR, D, FAST, 4><<<grid, 256, 0, st>>>(a); break;
+  }
+}
+
+// Near field of one column group: the 4-sibling kernel for trees of depth >= 2,
+// the per-leaf kernel for a single leaf.
+template <class T, int NR>
+void launch_p2p(const Tree& t, const FmmPlan<T>& pl, const P2PArgs<T>& a, int G, hipStream_t st) {
+  const int deg = pl.poly.deg;
+  if (t.L < 2) {
+    const int grid = (int)t.nleaves;
+    if (!pl.near_fast) {
+      k_p2p<T, NR, 1, false><<<grid, 64, 0, st>>>(a);
+    } else if constexpr (std::is_same<T, float>::value) {
+      switch (deg) {
+        case 6: k_p2p<T, NR, 6, true><<<grid, 64, 0, st>>>(a); break;
+        case 8: k_p2p<T, NR, 8, true><<<grid, 64, 0, st>>>(a); break;
+        case 10: k_p2p<T, NR, 10, true><<<grid, 64, 0, st>>>(a); break;
+        case 12: k_p2p<T, NR, 12, true><<<grid, 64, 0, st>>>(a); break;
+        default: k_p2p<T, NR, 16, true><<<grid, 64, 0, st>>>(a); break;
+      }
+    } else {
+      switch (deg) {
+        case 12: k_p2p<T, NR, 12, true><<<grid, 64, 0, st>>>(a); break;
+        case 16: k_p2p<T, NR, 16, true><<<grid, 64, 0, st>>>(a); break;
+        case 20: k_p2p<T, NR, 20, true><<<grid, 64, 0, st>>>(a); break;
+        case 24: k_p2p<T, NR, 24, true><<<grid, 64, 0, st>>>(a); break;
+        default: k_p2p<T, NR, 28, true><<<grid, 64, 0, st>>>(a); break;
+      }
+    }
+    return;
+  }
+  const int grid = (int)(t.nleaves / 4);
+  if (!pl.near_fast) {
+    launch_p2p4<T, NR, 1, false>(G, grid, a, st);
+  } else if constexpr (std::is_same<T, float>::value) {
+    switch (deg) {
+      case 6: launch_p2p4<T, NR, 6, true>(G, grid, a, st); break;
+      case 8: launch_p2p4<T, NR, 8, true>(G, grid, a, st); break;
+      case 10: launch_p2p4<T, NR, 10, true>(G, grid, a, st); break;
+      case 12: launch_p2p4<T, NR, 12, true>(G, grid, a, st); break;
+      default: launch_p2p4<T, NR, 16, true>(G, grid, a, st); break;
+    }
+  } else {
+    switch (deg) {
+      case 12: launch_p2p4<T, NR, 12, true>(G, grid, a, st); break;
+      case 16: launch_p2p4<T, NR, 16, true>(G, grid, a, st); break;
+      case 20: launch_p2p4<T, NR, 20, true>(G, grid, a, st); break;
+      case 24: launch_p2p4<T, NR, 24, true>(G, grid, a, st); break;
+      default: launch_p2p4<T, NR, 28, true>(G, grid, a, st); break;
+    }
+  }
+}
+
+template <class T>
+P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
+                    const uint8_t* flags, bool accumulate, const int* alive) {
+  P2PArgs<T> a{};
+  a.leaf_off = t.leaf_off.p;
+  a.rel = rel_of<T>(t);
+  a.q = q;
+  a.phi = phi;
+  a.flags = flags ? flags + pl.lv[t.L].box0 : nullptr;
+  a.alive = alive;
+  a.N = t.n;
+  a.nrhs = nrhs;
+  a.r0 = r0;
+  a.L = t.L;
+  a.G = pl.G;
+  a.accumulate = (t.L >= 2 || accumulate) ? 1 : 0;
+  a.k = T(pl.k);
+  a.kls = T(pl.k * t.leaf_side());
+  const NearPoly& P = pl.poly;
+  for (int i = 0; i < 32; ++i) {
+    a.cJ[i] = T(P.cJ[i]);
+    a.cY[i] = T(P.cY[i]);
+  }
+  a.ua = T(P.ua);
+  a.ub = T(P.ub);
+  a.c1 = T(P.c1);
+  a.c0 = T(P.c0);
+  return a;
+}
+
+// M2L of all levels in one launch (the VALU kernel for a level whose LDS
+// window does not fit).  pl.m2l_small selects the 4 x 4 target tile.
+template <class T, int NR>
+void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, int nrhs, int r0,
+                const uint8_t* flags, const int* alive, hipStream_t st) {
+  const int L = t.L;
+  M2LAllArgs<T> ma{};
+  ma.alive = alive;
+  ma.nrhs = nrhs;
+  ma.r0 = r0;
+  ma.nr = NR;
+  int blocks = 0;
+  size_t lds = 0;
+  for (int l = 2; l <= L; ++l) {
+    const LevelInfo& li = pl.lv[l];
+    const MfmaLevel& mf = pl.mf[l];
+    const bool small = (pl.m2l_small && mf.fit4) || !mf.on;
+    const bool use = small ? mf.fit4 : mf.on;
+    if (!use) {
+      k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs, nullptr,
+                                                 pl.m2l.p + pl.m2l_off[l], nullptr, li.P, 1, l, nrhs, r0,
+                                                 flags ? flags + li.box0 : nullptr, alive);
+      HFMM_LAUNCH_CHECK();
+      continue;
+    }
+    const int tile = small ? std::min(4, 1 << l) : mf.tile;
+    M2LLevel<T>& v = ma.lv[ma.nlev++];
+    v.M = M + li.coef * nrhs;
+    v.Lc = Lc + li.coef * nrhs;
+    v.Af = pl.afrag.p + mf.af;
+    v.fsrc = flags ? flags + li.box0 : nullptr;
+    v.nb = 1 << l;
+    v.P = li.P;
+    v.RT = mf.RT;
+    v.KS = mf.KS;
+    v.KPs = mf.KPs;
+    v.tile = tile;
+    v.gx = ((1 << l) / tile) * ((1 << l) / tile);
+    v.block0 = blocks;
+    blocks += v.gx * mf.RT;
+    lds = std::max(lds, small ? mf.lds4 : mf.lds);
+  }
+  if (ma.nlev) {
+    k_m2l_mfma<T><<<blocks, 256, lds, st>>>(ma);
+    HFMM_LAUNCH_CHECK();
+  }
 }
 
 template <class T, int NR>
@@ -1009,44 +1327,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
         HFMM_LAUNCH_CHECK();
       }
       if (tm) tm->mark(1, st);
-      // M2L of all levels in one launch (VALU for a level whose window does not fit)
-      M2LAllArgs<T> ma{};
-      ma.alive = alive;
-      ma.nrhs = nrhs;
-      ma.r0 = r0;
-      ma.nr = NR;
-      int blocks = 0;
-      size_t lds = 0;
-      for (int l = 2; l <= L; ++l) {
-        const LevelInfo& li = pl.lv[l];
-        const MfmaLevel& mf = pl.mf[l];
-        if (!mf.on) {
-          k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs, nullptr,
-                                                     pl.m2l.p + pl.m2l_off[l], nullptr, li.P, 1, l, nrhs, r0,
-                                                     flags ? flags + li.box0 : nullptr, alive);
-          HFMM_LAUNCH_CHECK();
-          continue;
-        }
-        M2LLevel<T>& v = ma.lv[ma.nlev++];
-        v.M = M + li.coef * nrhs;
-        v.Lc = Lc + li.coef * nrhs;
-        v.Af = pl.afrag.p + mf.af;
-        v.fsrc = flags ? flags + li.box0 : nullptr;
-        v.nb = 1 << l;
-        v.P = li.P;
-        v.RT = mf.RT;
-        v.KS = mf.KS;
-        v.KPs = mf.KPs;
-        v.tile = mf.tile;
-        v.gx = mf.gx;
-        v.block0 = blocks;
-        blocks += mf.gx * mf.gy;
-        lds = std::max(lds, mf.lds);
-      }
-      if (ma.nlev) {
-        k_m2l_mfma<T><<<blocks, 256, lds, st>>>(ma);
-        HFMM_LAUNCH_CHECK();
-      }
+      launch_m2l<T, NR>(t, pl, M, Lc, nrhs, r0, flags, alive, st);
       // L2L chain, levels 3 .. L
       for (int l = 3; l <= L; ++l) {
         const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
@@ -1094,51 +1375,81 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     HFMM_LAUNCH_CHECK();
     if (tm) tm->mark(3, st);
   }
-  P2PArgs<T> a{};
-  a.leaf_off = t.leaf_off.p;
-  a.rel = rel;
-  a.q = q;
-  a.phi = phi;
-  a.flags = flags ? flags + pl.lv[L].box0 : nullptr;
-  a.alive = alive;
-  a.N = N;
-  a.nrhs = nrhs;
-  a.r0 = r0;
-  a.L = L;
-  a.G = pl.G;
-  a.accumulate = (L >= 2 || accumulate) ? 1 : 0;
-  a.k = T(k);
-  a.kls = T(k * t.leaf_side());
-  const NearPoly& P = pl.poly;
-  for (int i = 0; i < 32; ++i) {
-    a.cJ[i] = T(P.cJ[i]);
-    a.cY[i] = T(P.cY[i]);
-  }
-  a.ua = T(P.ua);
-  a.ub = T(P.ub);
-  a.c1 = T(P.c1);
-  a.c0 = T(P.c0);
-  const int grid = (int)t.nleaves;
-  if (!pl.near_fast) {
-    k_p2p<T, NR, 1, false><<<grid, 64, 0, st>>>(a);
-  } else {
-    switch (P.deg) {
-#define HFMM_P2P_CASE(DD) \
-  case DD: k_p2p<T, NR, DD, true><<<grid, 64, 0, st>>>(a); break;
-      HFMM_P2P_CASE(6)
-      HFMM_P2P_CASE(8)
-      HFMM_P2P_CASE(10)
-      HFMM_P2P_CASE(12)
-      HFMM_P2P_CASE(16)
-      HFMM_P2P_CASE(20)
-      HFMM_P2P_CASE(24)
-      HFMM_P2P_CASE(28)
-#undef HFMM_P2P_CASE
-      default: throw Error(HFMM_ERR_INTERNAL, "fmm: unexpected near-field degree");
-    }
-  }
+  const P2PArgs<T> a = p2p_args<T>(t, pl, q, phi, nrhs, r0, flags, accumulate, alive);
+  launch_p2p<T, NR>(t, pl, a, pl.G, st);
   HFMM_LAUNCH_CHECK();
   if (tm) tm->mark(4, st);
+}
+
+// Launch-shape autotuner, run once per plan on the tree it serves (the
+// kernels' cost does not depend on the charges, so zeros are used): the P2P
+// lanes per target G in {1, 2, 4} and the M2L target tile (8 x 8 or 4 x 4).
+// HFMM_TUNE=0 keeps the defaults.
+template <class T>
+void autotune(const Tree& t, FmmPlan<T>& pl) {
+  const char* e = std::getenv("HFMM_TUNE");
+  if ((e && std::string(e) == "0") || t.L < 2) return;
+  hipStream_t st;
+  HFMM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t e0, e1;
+  HFMM_HIP(hipEventCreate(&e0));
+  HFMM_HIP(hipEventCreate(&e1));
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+  };
+  try {
+    pl.ensure_work(1);
+    pl.qs.ensure(t.n);
+    pl.phis.ensure(t.n);
+    HFMM_HIP(hipMemsetAsync(pl.qs.p, 0, t.n * sizeof(cplx<T>), st));
+    HFMM_HIP(hipMemsetAsync(pl.M.p, 0, pl.coef_total * sizeof(cplx<T>), st));
+    auto timed = [&](auto&& fn) {
+      float best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HFMM_HIP(hipEventRecord(e0, st));
+        fn();
+        HFMM_HIP(hipEventRecord(e1, st));
+        HFMM_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      return best;
+    };
+    const P2PArgs<T> a = p2p_args<T>(t, pl, pl.qs.p, pl.phis.p, 1, 0, nullptr, false, nullptr);
+    int bestG = pl.G;
+    float bestms = 1e30f;
+    const int Gs[3] = {1, 2, 4};
+    for (int i = 0; i < 3; ++i) {
+      const float ms = timed([&] { launch_p2p<T, 1>(t, pl, a, Gs[i], st); });
+      pl.tune_ms[i] = ms;
+      if (ms < bestms) {
+        bestms = ms;
+        bestG = Gs[i];
+      }
+    }
+    pl.G = bestG;
+    if (pl.use_mfma) {
+      bool any_choice = false;
+      for (int l = 2; l <= t.L; ++l) any_choice = any_choice || (pl.mf[l].fit4 && pl.mf[l].tile == 8);
+      if (any_choice) {
+        pl.m2l_small = false;
+        const float big = timed([&] { launch_m2l<T, 1>(t, pl, pl.M.p, pl.Lc.p, 1, 0, nullptr, nullptr, st); });
+        pl.m2l_small = true;
+        const float small = timed([&] { launch_m2l<T, 1>(t, pl, pl.M.p, pl.Lc.p, 1, 0, nullptr, nullptr, st); });
+        pl.tune_ms[3] = big;
+        pl.tune_ms[4] = small;
+        pl.m2l_small = small < big;
+      }
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
 }
 
 }  // namespace
@@ -1149,7 +1460,11 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p) {
   HFMM_REQUIRE(p >= 1 && p <= 40, "fmm: p must be in [1, 40]");
   const auto key = std::make_tuple(k, p, std::is_same<T, float>::value ? 1 : 0);
   auto it = t.plans.find(key);
-  if (it == t.plans.end()) it = t.plans.emplace(key, make_plan<T>(t, k, p)).first;
+  if (it == t.plans.end()) {
+    auto pl = make_plan<T>(t, k, p);
+    autotune<T>(t, *pl);
+    it = t.plans.emplace(key, std::move(pl)).first;
+  }
   return *static_cast<FmmPlan<T>*>(it->second.get());
 }
 

@@ -745,7 +745,9 @@ void precond_apply(Solver& s, const double2* r, int64_t rs, double2* z, int64_t 
 
 namespace {
 
-void ensure_krylov(Solver& s, int m) {
+// Allocates the Krylov workspace for restart m; the zeroing is ordered on the
+// solve's stream (a non-blocking stream is not ordered after the NULL stream).
+void ensure_krylov(Solver& s, int m, hipStream_t st) {
   const int nr = s.nrhs;
   const int64_t nn = s.nn;
   if (m != s.m) {
@@ -768,9 +770,9 @@ void ensure_krylov(Solver& s, int m) {
     s.jj.alloc(nr);
     s.iters.alloc(nr);
     s.state.alloc(2);
-    HFMM_HIP(hipMemset(s.V.p, 0, s.V.n * sizeof(double2)));
-    HFMM_HIP(hipMemset(s.Z.p, 0, s.Z.n * sizeof(double2)));
-    HFMM_HIP(hipMemset(s.H.p, 0, s.H.n * sizeof(double2)));
+    HFMM_HIP(hipMemsetAsync(s.V.p, 0, s.V.n * sizeof(double2), st));
+    HFMM_HIP(hipMemsetAsync(s.Z.p, 0, s.Z.n * sizeof(double2), st));
+    HFMM_HIP(hipMemsetAsync(s.H.p, 0, s.H.n * sizeof(double2), st));
   }
 }
 
@@ -832,7 +834,7 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
   for (int q = 0; q < nprob; ++q) {
     HFMM_REQUIRE(S[q] != nullptr, "fgmres: NULL solver");
     HFMM_REQUIRE(b[q] != nullptr && x[q] != nullptr, "fgmres: NULL array");
-    ensure_krylov(*S[q], m);
+    ensure_krylov(*S[q], m, st);
   }
   double ms_prec = 0;
   // ||b||
@@ -868,112 +870,122 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
 
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  bool graph_ok = false;
+  std::vector<int> captured;  // problems whose Arnoldi step the current graph holds
+  auto drop_graph = [&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    captured.clear();
+  };
+  std::vector<int> alive(nprob, 0);
 
-  for (;;) {
-    // ---- cycle start: r = b - A x into V_0, beta = ||r||
-    bool any_active = false;
-    std::vector<std::vector<double>> beta(nprob);
-    for (int q = 0; q < nprob; ++q) {
-      Solver& s = *S[q];
-      if (ps[q].done) continue;
-      const int64_t vs = (int64_t)(s.m + 1) * s.nn;
-      k_fd<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(s.n, 1.0 / (s.h * s.h), s.field ? s.k2.p : nullptr, s.k2c,
-                                                         x[q], s.nn, s.V.p, vs, b[q], s.nn, s.nrhs, nullptr, nullptr);
-      HFMM_LAUNCH_CHECK();
-      col_norms(s, s.V.p, vs, s.rn.p, beta[q], st);
-    }
-    HFMM_HIP(hipStreamSynchronize(st));
-    for (int q = 0; q < nprob; ++q) {
-      Solver& s = *S[q];
-      ProbState& P = ps[q];
-      if (P.done) continue;
-      P.act.assign(s.nrhs, 0);
-      bool pa = false;
-      for (int c = 0; c < s.nrhs; ++c) {
-        if (!(P.bnorm[c] > 0)) continue;
-        if (!std::isfinite(beta[q][c])) P.numeric = true;
-        P.rel[c] = beta[q][c] / P.bnorm[c];
-        P.conv[c] = P.rel[c] <= rtol;
-        if (!P.conv[c] && P.iters[c] < maxit && std::isfinite(beta[q][c])) {
-          P.act[c] = 1;
-          pa = true;
+  try {
+    for (;;) {
+      // ---- cycle start: r = b - A x into V_0, beta = ||r||
+      bool any_active = false;
+      std::vector<std::vector<double>> beta(nprob);
+      for (int q = 0; q < nprob; ++q) {
+        Solver& s = *S[q];
+        if (ps[q].done) continue;
+        const int64_t vs = (int64_t)(s.m + 1) * s.nn;
+        k_fd<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(s.n, 1.0 / (s.h * s.h), s.field ? s.k2.p : nullptr, s.k2c,
+                                                           x[q], s.nn, s.V.p, vs, b[q], s.nn, s.nrhs, nullptr, nullptr);
+        HFMM_LAUNCH_CHECK();
+        col_norms(s, s.V.p, vs, s.rn.p, beta[q], st);
+      }
+      HFMM_HIP(hipStreamSynchronize(st));
+      for (int q = 0; q < nprob; ++q) {
+        Solver& s = *S[q];
+        ProbState& P = ps[q];
+        alive[q] = 0;
+        if (P.done) continue;
+        P.act.assign(s.nrhs, 0);
+        bool pa = false;
+        for (int c = 0; c < s.nrhs; ++c) {
+          if (!(P.bnorm[c] > 0)) continue;
+          if (!std::isfinite(beta[q][c])) P.numeric = true;
+          P.rel[c] = beta[q][c] / P.bnorm[c];
+          P.conv[c] = P.rel[c] <= rtol;
+          if (!P.conv[c] && P.iters[c] < maxit && std::isfinite(beta[q][c])) {
+            P.act[c] = 1;
+            pa = true;
+          }
+        }
+        if (!pa) {
+          P.done = true;
+          continue;
+        }
+        any_active = true;
+        alive[q] = 1;
+        int hstate[2] = {0, 1};
+        HFMM_HIP(hipMemcpyAsync(s.active.p, P.act.data(), s.nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+        HFMM_HIP(hipMemcpyAsync(s.state.p, hstate, 2 * sizeof(int), hipMemcpyHostToDevice, st));
+        k_cycle_init<<<1, 64, 0, st>>>(s.g.p, s.rn.p, s.jj.p, s.m, s.nrhs);
+        k_scale<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(s.V.p, (int64_t)(s.m + 1) * s.nn, s.nn, nullptr,
+                                                             s.active.p, s.rn.p);
+        HFMM_LAUNCH_CHECK();
+        HFMM_HIP(hipStreamSynchronize(st));  // host buffers above stay valid
+      }
+      if (!any_active) break;
+
+      // ---- Arnoldi steps
+      for (int step = 0; step < m; ++step) {
+        std::vector<int> live;
+        for (int q = 0; q < nprob; ++q)
+          if (!ps[q].done && alive[q]) live.push_back(q);
+        if (live.empty()) break;
+        const bool timed = (nprob == 1 && !use_graph);
+        if (timed) HFMM_HIP(hipEventRecord(S[0]->ev0, st));
+        if (use_graph) {
+          // one graph holds one step of every live problem; recapture when
+          // that set shrinks (plans and workspaces already exist, so the step
+          // allocates nothing)
+          if (live != captured) {
+            drop_graph();
+            HFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int q : live) arnoldi_step(*S[q], maxit, rtol, st);
+            HFMM_HIP(hipStreamEndCapture(st, &graph));
+            HFMM_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            captured = live;
+          }
+          HFMM_HIP(hipGraphLaunch(gexec, st));
+        } else {
+          for (int q : live) arnoldi_step(*S[q], maxit, rtol, st, timed ? S[q]->ev1 : nullptr);
+        }
+        for (int q : live) HFMM_HIP(hipMemcpyAsync(&alive[q], S[q]->state.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        HFMM_HIP(hipStreamSynchronize(st));
+        if (timed) {
+          float ms = 0;
+          HFMM_HIP(hipEventElapsedTime(&ms, S[0]->ev0, S[0]->ev1));
+          ms_prec += ms;
         }
       }
-      if (!pa) {
-        P.done = true;
-        continue;
-      }
-      any_active = true;
-      int hstate[2] = {0, 1};
-      HFMM_HIP(hipMemcpyAsync(s.active.p, P.act.data(), s.nrhs * sizeof(int), hipMemcpyHostToDevice, st));
-      HFMM_HIP(hipMemcpyAsync(s.state.p, hstate, 2 * sizeof(int), hipMemcpyHostToDevice, st));
-      k_cycle_init<<<1, 64, 0, st>>>(s.g.p, s.rn.p, s.jj.p, s.m, s.nrhs);
-      k_scale<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(s.V.p, (int64_t)(s.m + 1) * s.nn, s.nn, nullptr,
-                                                           s.active.p, s.rn.p);
-      HFMM_LAUNCH_CHECK();
-      HFMM_HIP(hipStreamSynchronize(st));  // host buffers above stay valid
-    }
-    if (!any_active) break;
-
-    // ---- Arnoldi steps
-    if (use_graph && !graph_ok) {
-      // all plans and workspaces exist by now (created above), so the step
-      // allocates nothing and can be captured
-      HFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int q = 0; q < nprob; ++q) arnoldi_step(*S[q], maxit, rtol, st);
-      HFMM_HIP(hipStreamEndCapture(st, &graph));
-      HFMM_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-      graph_ok = true;
-    }
-    for (int step = 0; step < m; ++step) {
-      const bool timed = (nprob == 1 && !use_graph);
-      if (timed) HFMM_HIP(hipEventRecord(S[0]->ev0, st));
-      if (graph_ok) {
-        HFMM_HIP(hipGraphLaunch(gexec, st));
-      } else {
-        for (int q = 0; q < nprob; ++q) {
-          if (ps[q].done) continue;
-          arnoldi_step(*S[q], maxit, rtol, st, timed ? S[q]->ev1 : nullptr);
+      // ---- end of cycle: x += Z R^{-1} g
+      for (int q = 0; q < nprob; ++q) {
+        Solver& s = *S[q];
+        if (ps[q].done) continue;
+        k_trisolve<<<1, 64, 0, st>>>(s.H.p, s.g.p, s.jj.p, s.y.p, s.m, s.nrhs);
+        k_xupdate<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(x[q], s.Z.p, (int64_t)s.m * s.nn, s.nn, s.jj.p, s.y.p,
+                                                              s.m);
+        HFMM_LAUNCH_CHECK();
+        std::vector<int> it(s.nrhs);
+        std::vector<double> es(s.nrhs);
+        HFMM_HIP(hipMemcpyAsync(it.data(), s.iters.p, s.nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+        HFMM_HIP(hipMemcpyAsync(es.data(), s.est.p, s.nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+        HFMM_HIP(hipStreamSynchronize(st));
+        ps[q].restarts += 1;
+        for (int c = 0; c < s.nrhs; ++c) {
+          if (ps[q].act[c]) ps[q].est[c] = es[c];
+          ps[q].iters[c] = it[c];
         }
       }
-      // host check: which problems still have running columns
-      std::vector<int> alive(nprob, 0);
-      for (int q = 0; q < nprob; ++q)
-        if (!ps[q].done)
-          HFMM_HIP(hipMemcpyAsync(&alive[q], S[q]->state.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-      HFMM_HIP(hipStreamSynchronize(st));
-      if (timed) {
-        float ms = 0;
-        HFMM_HIP(hipEventElapsedTime(&ms, S[0]->ev0, S[0]->ev1));
-        ms_prec += ms;
-      }
-      bool any = false;
-      for (int q = 0; q < nprob; ++q) any = any || (!ps[q].done && alive[q]);
-      if (!any) break;
     }
-    // ---- end of cycle: x += Z R^{-1} g
-    for (int q = 0; q < nprob; ++q) {
-      Solver& s = *S[q];
-      if (ps[q].done) continue;
-      k_trisolve<<<1, 64, 0, st>>>(s.H.p, s.g.p, s.jj.p, s.y.p, s.m, s.nrhs);
-      k_xupdate<<<dim3(nblocks(s.nn), s.nrhs), 256, 0, st>>>(x[q], s.Z.p, (int64_t)s.m * s.nn, s.nn, s.jj.p, s.y.p,
-                                                            s.m);
-      HFMM_LAUNCH_CHECK();
-      std::vector<int> it(s.nrhs);
-      std::vector<double> es(s.nrhs);
-      HFMM_HIP(hipMemcpyAsync(it.data(), s.iters.p, s.nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      HFMM_HIP(hipMemcpyAsync(es.data(), s.est.p, s.nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      HFMM_HIP(hipStreamSynchronize(st));
-      ps[q].restarts += 1;
-      for (int c = 0; c < s.nrhs; ++c) {
-        if (ps[q].act[c]) ps[q].est[c] = es[c];
-        ps[q].iters[c] = it[c];
-      }
-    }
+  } catch (...) {
+    drop_graph();
+    throw;
   }
-  if (gexec) (void)hipGraphExecDestroy(gexec);
-  if (graph) (void)hipGraphDestroy(graph);
+  drop_graph();
 
   const double ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -60,6 +60,7 @@ _SIGS = {
     "hfmm_fd_helmholtz_matvec": ([_i32, _f64, _vp, _f64, _vp, _vp, _i32, _vp], _i32),
     "hfmm_solver_create": ([_i32, _f64, _vp, _f64, _f64, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)], _i32),
     "hfmm_solver_set_k2": ([_vp, _vp, _f64, _vp], _i32),
+    "hfmm_matched_wavenumber": ([_f64, _f64, ctypes.POINTER(_f64)], _i32),
     "hfmm_precond_apply": ([_vp, _vp, _vp, _i32, _vp], _i32),
     "hfmm_fgmres_solve": ([_vp, _vp, _vp, _i32, _i32, _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
     "hfmm_fgmres_solve_batched": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _i32,
@@ -275,6 +276,13 @@ def hfmm_fgmres_solve(solver, b, **kw):
 
 def hfmm_precond_apply(solver, r, **kw):
     return solver.precond_apply(r, **kw)
+
+
+def hfmm_matched_wavenumber(k, h):
+    """Preconditioner wavenumber matched to the 5-point stencil's dispersion."""
+    out = _f64()
+    _check(lib().hfmm_matched_wavenumber(float(k), float(h), ctypes.byref(out)))
+    return out.value
 
 
 def hfmm_fgmres_solve_batched(solvers, bs, restart=50, maxit=5000, rtol=1e-6, use_graph=True, stream=None):

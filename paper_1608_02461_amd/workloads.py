@@ -70,7 +70,7 @@ def batch_c4(seed=4, n_problems=16, nrhs=4, sizes=(128, 256, 384, 512), kh_max=0
         n = int(rng.choice(ok))
         f = complex_normal(rng, (n * n, nrhs), np.complex64)
         probs.append({"n": n, "h": grid_h(n), "k": k, "f": f})
-    return {"problems": probs, "p": 6, "leaf": 32, "restart": 50, "rtol": 1e-6}
+    return {"problems": probs, "p": 6, "leaf": 32, "restart": 200, "rtol": 1e-6}
 
 
 def adjoint_c5(n=256, nb=16, k0=100.0, n_obs=512, seed=5):
@@ -79,7 +79,7 @@ def adjoint_c5(n=256, nb=16, k0=100.0, n_obs=512, seed=5):
     P = np.sort(rng.choice(n * n, n_obs, replace=False))
     f = complex_normal(rng, n * n)
     return {"n": n, "h": grid_h(n), "kb": kb, "P": P, "f": f, "k0": k0, "k2_ref": k0 * k0,
-            "p": 6, "leaf": 32, "restart": 50}
+            "p": 6, "leaf": 32, "restart": 200}
 
 
 def random_cloud(N, seed, nrhs=1, dtype=np.complex128):

@@ -178,3 +178,39 @@ def test_solver_invalid_arguments():
         k0 = kw.pop("k0")
         with pytest.raises(hfmm.HFMMError):
             hfmm.Solver(n, k0, **kw)
+
+
+def test_matched_wavenumber_and_fewer_iterations():
+    k, h = 100.0, 1.0 / 257
+    ref = 0.5 * (2 / h * np.arcsin(k * h / 2) + 2 * np.sqrt(2) / h * np.arcsin(k * h / (2 * np.sqrt(2))))
+    assert abs(hfmm.hfmm_matched_wavenumber(k, h) - ref) <= 1e-12 * ref
+    with pytest.raises(hfmm.HFMMError):
+        hfmm.hfmm_matched_wavenumber(600.0, 1.0 / 257)  # k h >= 2
+    n = 256
+    rng = np.random.default_rng(91)
+    b = workloads.complex_normal(rng, n * n)
+    its = {}
+    for name, k0 in (("k", k), ("matched", ref)):
+        s = hfmm.Solver(n, k0, k2_const=k * k, p=6, leaf_size=32, prec=hfmm.FP32)
+        x, info = s.solve(to_dev(b), restart=50, rtol=1e-6, maxit=2000)
+        A = fd.matrix(n, k * k)
+        assert np.linalg.norm(b - A @ to_np(x)) <= 1e-6 * np.linalg.norm(b)
+        its[name] = info["iters"]
+    say(f"  iterations k0=k: {its['k']}, matched: {its['matched']}")
+    assert its["matched"] < its["k"]
+
+
+def test_first_graph_solve_equals_eager():
+    """The first solve after creation (graph mode on a private stream) must see
+    a zeroed workspace and the caller's inputs: compare with a later eager solve."""
+    solvers, bs = [], []
+    for i, (n, k) in enumerate([(128, 60.0), (96, 40.0), (64, 30.0)]):
+        rng = np.random.default_rng(100 + i)
+        solvers.append(hfmm.Solver(n, hfmm.hfmm_matched_wavenumber(k, 1 / (n + 1)), k2_const=k * k, p=6,
+                                   leaf_size=32, prec=hfmm.FP32, nrhs=2))
+        bs.append(to_dev(workloads.complex_normal(rng, (n * n, 2))))
+    xg, ig = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=60, rtol=1e-6, use_graph=True)
+    xe, ie = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=60, rtol=1e-6, use_graph=False)
+    for a, b, p, q in zip(xg, xe, ig, ie):
+        assert p["iters"] == q["iters"]
+        assert np.array_equal(to_np(a), to_np(b))
