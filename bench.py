@@ -40,6 +40,30 @@ PEAK_FP64_ALU = 78.6
 PEAK_HBM = 8000.0       # GB/s
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "p2p_fmm_c2_n1m_k100_p8_fp32_pmc.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading on
+    a plain device copy of known size), or None when the summary is absent,
+    is for another kernel, or the near-field source has changed since."""
+    import hashlib
+    import re
+    try:
+        txt = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if rec["kernel"] != kernel or hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -86,6 +110,8 @@ def main():
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed applies, copy 512 MiB device to device once (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -128,6 +154,14 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     value = N / (elapsed / args.steps) / 1e6
 
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---------------- per-stage device times (hipEvents on the launch stream), same applies
     stages = {s: 0.0 for s in hfmm.STAGES}
     for _ in range(args.steps):
@@ -137,14 +171,18 @@ def main():
     dominant = max(("p2p", "downward"), key=lambda s: stages[s])
     if dominant == "p2p":
         fl = plan["pairs"] * p2p_flops_per_pair(plan["near_deg"])
-        roof_kernel = f"k_p2p<float,1,{plan['near_deg']},true>"
+        roof_kernel = f"k_p2p4<float,1,{plan['near_deg']},true,{plan['lanes_per_target']}>"
     else:
         fl = m2l_flops(plan["orders"], tree.info()["levels"])
         roof_kernel = "k_down<float,1> (M2L + L2L, one launch per level)"
     achieved = fl / (stages[dominant] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": roof_kernel, "achieved": round(achieved, 3), "peak": PEAK_FP32_ALU,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ALU, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ALU, 4),
+                "traffic": measured_traffic(roof_kernel) if dominant == "p2p" else None,
                 "algorithmic_flops_per_launch": fl, "ms_per_launch": round(stages[dominant], 5)}
+    if dominant == "p2p":
+        # positions, charges and the L2P partial potentials read once, potentials written once
+        roofline["algorithmic_bytes_per_launch"] = 32 * N
 
     gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_reference.npz"))
     smp = gold["samples"]
@@ -319,7 +357,7 @@ def main():
 
         from oracle import kernel
 
-        n_t = 24
+        n_t = 64
         with threadpool_limits(1):
             t0 = time.perf_counter()
             kernel.direct_sum(w["xy"], w["q"], k, tgt=w["xy"][smp[:n_t]])

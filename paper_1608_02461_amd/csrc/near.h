@@ -1,0 +1,369 @@
+// Near-field (P2P) kernels of the FMM: the direct sum of G(x - y) q(y) over
+// the sources in a target leaf's 3 x 3 leaf neighbourhood (Sec. 3, the near
+// part of the FMM sum), G = (i/4) H0^(1)(k r).  Included once, by fmm.hip,
+// inside its anonymous namespace, after the fmaT/log2T/cmac helpers; kept in
+// a file of its own so that its source identifies the measured kernel.
+#pragma once
+
+template <class T>
+struct P2PArgs {
+  const int32_t* leaf_off;
+  const cplx<T>* rel;
+  const cplx<T>* q;
+  cplx<T>* phi;
+  const uint8_t* flags;  // leaf-level source flags or NULL
+  const int* alive;      // device flag: 0 skips the launch's work, or NULL
+  int64_t N;
+  int nrhs, r0, L, G, accumulate;
+  T k, kls;  // k and k * leaf side
+  T cJ[32], cY[32];
+  T ua, ub, c1, c0;
+};
+
+template <class T, int NR>
+struct P2PCfg {
+  static constexpr int SCH = (2 * sizeof(T) * (1 + NR) * 512 <= 16384) ? 512 : 256;
+};
+
+// One pair: t = (k r)^2.  FAST uses the fitted polynomial (D coefficients),
+// otherwise the full-range FP64 routine.
+template <class T, int D, bool FAST, bool MASK>
+__device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y) {
+  bool valid = true;
+  if (MASK) {
+    valid = t > T(0);
+    t = valid ? t : T(1);
+  }
+  if constexpr (FAST) {
+    const T u = fmaT(t, a.ua, a.ub);
+    T j = a.cJ[D - 1], yh = a.cY[D - 1];
+#pragma unroll
+    for (int i = D - 2; i >= 0; --i) {
+      j = fmaT(j, u, a.cJ[i]);
+      yh = fmaT(yh, u, a.cY[i]);
+    }
+    const T lg = log2T(t);
+    Y = fmaT(j, fmaT(lg, a.c1, a.c0), yh);
+    J = j;
+  } else {
+    const double2 h = h0_general(sqrt((double)t));
+    J = (T)h.x;
+    Y = (T)h.y;
+  }
+  if (MASK) {
+    J = valid ? J : T(0);
+    Y = valid ? Y : T(0);
+  }
+}
+
+template <class T, int NR, int D, bool FAST>
+__global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
+  constexpr int SCH = P2PCfg<T, NR>::SCH;
+  __shared__ cplx<T> spos[SCH];
+  __shared__ cplx<T> sq[NR][SCH];
+  __shared__ int s_lo[9], s_pre[10], s_n, s_total, s_nonown;
+  __shared__ T s_ox[9], s_oy[9];
+  const int leaf = blockIdx.x;
+  if (a.alive && !a.alive[0]) return;
+  const int t0 = a.leaf_off[leaf], t1 = a.leaf_off[leaf + 1];
+  if (t0 == t1) return;
+  const int lane = threadIdx.x;
+  if (lane == 0) {
+    int bx, by;
+    demorton((uint32_t)leaf, bx, by);
+    const int nb = 1 << a.L;
+    int n = 0, pos = 0;
+    for (int pass = 0; pass < 2; ++pass) {  // neighbours first, own leaf last
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const bool own = (dx == 0 && dy == 0);
+          if (own != (pass == 1)) continue;
+          const int sx = bx + dx, sy = by + dy;
+          if (sx < 0 || sy < 0 || sx >= nb || sy >= nb) continue;
+          const uint32_t sl = morton((uint32_t)sx, (uint32_t)sy);
+          if (a.flags && !a.flags[sl]) continue;
+          const int lo = a.leaf_off[sl], hi = a.leaf_off[sl + 1];
+          if (lo == hi) continue;
+          s_lo[n] = lo;
+          s_pre[n] = pos;
+          s_ox[n] = T(dx) * a.kls;
+          s_oy[n] = T(dy) * a.kls;
+          pos += hi - lo;
+          ++n;
+        }
+      if (pass == 0) s_nonown = pos;
+    }
+    s_pre[n] = pos;
+    s_n = n;
+    s_total = pos;
+  }
+  __syncthreads();
+  const int total = s_total, nonown = s_nonown, nseg = s_n;
+  if (total == 0 && a.accumulate) return;
+  const int G = a.G, TPR = 64 / G;
+  const int g = lane & (G - 1), tl = lane / G;
+  for (int rb = t0; rb < t1; rb += TPR) {
+    const int ti = rb + tl;
+    const bool act = ti < t1;
+    T xt = 0, yt = 0;
+    if (act) {
+      const cplx<T> d = a.rel[ti];
+      xt = a.k * d.x;
+      yt = a.k * d.y;
+    }
+    T A[NR], B[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+    for (int c0 = 0; c0 < total; c0 += SCH) {
+      const int cnt = min(SCH, total - c0);
+      __syncthreads();
+      for (int idx = lane; idx < cnt; idx += 64) {
+        const int gi = c0 + idx;
+        int sg = 0;
+        while (sg + 1 < nseg && gi >= s_pre[sg + 1]) ++sg;
+        const int slot = s_lo[sg] + gi - s_pre[sg];
+        const cplx<T> d = a.rel[slot];
+        spos[idx] = mk<T>(fmaT(a.k, d.x, s_ox[sg]), fmaT(a.k, d.y, s_oy[sg]));
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sq[r][idx] = a.q[(size_t)(a.r0 + r) * a.N + slot];
+      }
+      __syncthreads();
+      const int split = min(max(nonown - c0, 0), cnt);
+#pragma unroll 2
+      for (int j = g; j < split; j += G) {
+        const cplx<T> s = spos[j];
+        const T dx = xt - s.x, dy = yt - s.y;
+        const T t = fmaT(dx, dx, dy * dy);
+        T J, Y;
+        h0_pair<T, D, FAST, false>(a, t, J, Y);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const cplx<T> qq = sq[r][j];
+          A[r] = fmaT(qq.x, J, A[r]);
+          A[r] = fmaT(-qq.y, Y, A[r]);
+          B[r] = fmaT(qq.x, Y, B[r]);
+          B[r] = fmaT(qq.y, J, B[r]);
+        }
+      }
+      for (int j = split + g; j < cnt; j += G) {
+        const cplx<T> s = spos[j];
+        const T dx = xt - s.x, dy = yt - s.y;
+        const T t = fmaT(dx, dx, dy * dy);
+        T J, Y;
+        h0_pair<T, D, FAST, true>(a, t, J, Y);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const cplx<T> qq = sq[r][j];
+          A[r] = fmaT(qq.x, J, A[r]);
+          A[r] = fmaT(-qq.y, Y, A[r]);
+          B[r] = fmaT(qq.x, Y, B[r]);
+          B[r] = fmaT(qq.y, J, B[r]);
+        }
+      }
+    }
+    for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        A[r] += __shfl_xor(A[r], off);
+        B[r] += __shfl_xor(B[r], off);
+      }
+    }
+    if (g == 0 && act) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
+        // q (i/4) H0 summed: (i/4)(A + iB) = (-B/4, A/4)
+        cplx<T> v = mk<T>(T(-0.25) * B[r], T(0.25) * A[r]);
+        if (a.accumulate) {
+          const cplx<T> o = a.phi[idx];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        a.phi[idx] = v;
+      }
+    }
+  }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
+// this maps hardware block b to a logical block so that every XCD walks one
+// contiguous range of the Morton order, and neighbouring blocks, which read
+// the same leaves, share an L2.  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ int xcd_swizzle(int b, int n) {
+  if (n & 7) return b;
+  return (b & 7) * (n >> 3) + (b >> 3);
+}
+
+// P2P, one block per parent box: its 4 waves are the 4 sibling target
+// leaves, and the union of their 3 x 3 neighbourhoods (a 4 x 4 block of
+// leaves) is staged in LDS once, positions relative to the parent centre and
+// scaled by k.  In row-major leaf order each wave's sources are 3 contiguous
+// runs (one per row) and the own leaf splits the middle run: 4 unmasked
+// segments plus one masked.  G lanes share a target (template), each taking
+// every G-th source; a shuffle tree sums the G partial sums.
+template <class T, int NR>
+struct P2P4Cfg {
+  static constexpr int kBytes = 2 * (int)sizeof(T) * (1 + NR);
+  static constexpr int SCAP = (sizeof(T) == 4 ? 32768 : 49152) / kBytes;
+};
+
+template <class T, int D, bool FAST, bool MASK, int NR, int G>
+__device__ __forceinline__ void p2p_run(const P2PArgs<T>& a, const cplx<T>* __restrict__ spos,
+                                        const cplx<T> (*sq)[P2P4Cfg<T, NR>::SCAP], int lo, int hi, int g, T xt,
+                                        T yt, T (&A)[NR], T (&B)[NR]) {
+#pragma unroll 4
+  for (int j = lo + g; j < hi; j += G) {
+    const cplx<T> s = spos[j];
+    const T dx = xt - s.x, dy = yt - s.y;
+    const T t = fmaT(dx, dx, dy * dy);
+    T J, Y;
+    h0_pair<T, D, FAST, MASK>(a, t, J, Y);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const cplx<T> qq = sq[r][j];
+      A[r] = fmaT(qq.x, J, A[r]);
+      A[r] = fmaT(-qq.y, Y, A[r]);
+      B[r] = fmaT(qq.x, Y, B[r]);
+      B[r] = fmaT(qq.y, J, B[r]);
+    }
+  }
+}
+
+template <class T, int NR, int D, bool FAST, int G>
+__global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
+  constexpr int SCAP = P2P4Cfg<T, NR>::SCAP;
+  __shared__ cplx<T> spos[SCAP];
+  __shared__ cplx<T> sq[NR][SCAP];
+  __shared__ int s_pre[17], s_lo[16], s_rounds[4];
+  __shared__ T s_ox[16], s_oy[16];
+  if (a.alive && !a.alive[0]) return;
+  const int parent = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+  int px, py;
+  demorton((uint32_t)parent, px, py);
+  const int nb = 1 << a.L;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  if (tid < 16) {
+    const int rx = tid & 3, ry = tid >> 2;
+    const int lx = 2 * px - 1 + rx, ly = 2 * py - 1 + ry;
+    int cnt = 0, lo = 0;
+    if (lx >= 0 && ly >= 0 && lx < nb && ly < nb) {
+      const uint32_t sl = morton((uint32_t)lx, (uint32_t)ly);
+      if (!a.flags || a.flags[sl]) {
+        lo = a.leaf_off[sl];
+        cnt = a.leaf_off[sl + 1] - lo;
+      }
+    }
+    s_lo[tid] = lo;
+    s_pre[tid + 1] = cnt;
+    s_ox[tid] = T(rx - 1.5) * a.kls;
+    s_oy[tid] = T(ry - 1.5) * a.kls;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_pre[0] = 0;
+    for (int i = 1; i <= 16; ++i) s_pre[i] += s_pre[i - 1];
+  }
+  __syncthreads();
+  const int total = s_pre[16];
+  if (total == 0 && a.accumulate) return;
+  // this wave's target leaf (child position w of the parent) and its segments
+  const int cx = w & 1, cy = w >> 1;
+  const uint32_t tleaf = 4u * (uint32_t)parent + (uint32_t)w;
+  const int t0 = a.leaf_off[tleaf], t1 = a.leaf_off[tleaf + 1];
+  const T txo = T(cx - 0.5) * a.kls, tyo = T(cy - 0.5) * a.kls;
+  const int r0 = cy * 4 + cx, r1 = (cy + 1) * 4 + cx, r2 = (cy + 2) * 4 + cx, io = r1 + 1;
+  const int sg_lo[4] = {s_pre[r0], s_pre[r2], s_pre[r1], s_pre[io + 1]};
+  const int sg_hi[4] = {s_pre[r0 + 3], s_pre[r2 + 3], s_pre[io], s_pre[r1 + 3]};
+  const int own_lo = s_pre[io], own_hi = s_pre[io + 1];
+  constexpr int TPR = 64 / G;
+  const int g = lane & (G - 1), tl = lane / G;
+  auto stage = [&](int c0, int cnt) {
+    for (int idx = tid; idx < cnt; idx += 256) {
+      const int gi = c0 + idx;
+      int lf = 0;
+      while (lf < 15 && gi >= s_pre[lf + 1]) ++lf;
+      const int slot = s_lo[lf] + gi - s_pre[lf];
+      const cplx<T> d = a.rel[slot];
+      spos[idx] = mk<T>(fmaT(a.k, d.x, s_ox[lf]), fmaT(a.k, d.y, s_oy[lf]));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sq[r][idx] = a.q[(size_t)(a.r0 + r) * a.N + slot];
+    }
+  };
+  auto finish = [&](int ti, bool act, T (&A)[NR], T (&B)[NR]) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        A[r] += __shfl_xor(A[r], off);
+        B[r] += __shfl_xor(B[r], off);
+      }
+    }
+    if (g == 0 && act) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
+        cplx<T> v = mk<T>(T(-0.25) * B[r], T(0.25) * A[r]);
+        if (a.accumulate) {
+          const cplx<T> o = a.phi[idx];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        a.phi[idx] = v;
+      }
+    }
+  };
+  if (total <= SCAP) {
+    stage(0, total);
+    __syncthreads();
+    for (int rb = t0; rb < t1; rb += TPR) {
+      const int ti = rb + tl;
+      const bool act = ti < t1;
+      T xt = 0, yt = 0;
+      if (act) {
+        const cplx<T> d = a.rel[ti];
+        xt = fmaT(a.k, d.x, txo);
+        yt = fmaT(a.k, d.y, tyo);
+      }
+      T A[NR], B[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+#pragma unroll
+      for (int sgi = 0; sgi < 4; ++sgi)
+        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, A, B);
+      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, A, B);
+      finish(ti, act, A, B);
+    }
+  } else {
+    // the region does not fit: uniform rounds across the block, sources in chunks
+    if (lane == 0) s_rounds[w] = (t1 - t0 + TPR - 1) / TPR;
+    __syncthreads();
+    const int R = max(max(s_rounds[0], s_rounds[1]), max(s_rounds[2], s_rounds[3]));
+    for (int round = 0; round < R; ++round) {
+      const int ti = t0 + round * TPR + tl;
+      const bool act = ti < t1;
+      T xt = 0, yt = 0;
+      if (act) {
+        const cplx<T> d = a.rel[ti];
+        xt = fmaT(a.k, d.x, txo);
+        yt = fmaT(a.k, d.y, tyo);
+      }
+      T A[NR], B[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+      for (int c0 = 0; c0 < total; c0 += SCAP) {
+        const int cnt = min(SCAP, total - c0);
+        __syncthreads();
+        stage(c0, cnt);
+        __syncthreads();
+#pragma unroll
+        for (int sgi = 0; sgi < 4; ++sgi) {
+          const int lo = max(sg_lo[sgi], c0) - c0, hi = min(sg_hi[sgi], c0 + cnt) - c0;
+          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, A, B);
+        }
+        const int lo = max(own_lo, c0) - c0, hi = min(own_hi, c0 + cnt) - c0;
+        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, A, B);
+      }
+      finish(ti, act, A, B);
+    }
+  }
+}
