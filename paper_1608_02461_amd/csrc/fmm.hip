@@ -77,6 +77,7 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
   cplx<T>* sq = sb + (pL + 1) * 64;                     // [NR][64]
   const int lane = threadIdx.x;
   const int P = 2 * pL + 1;
+  const int G = 64 / (pL + 1), g = lane / (pL + 1), n = lane - g * (pL + 1);
   const int t0 = leaf_off[leaf], t1 = leaf_off[leaf + 1];
   cplx<T> accP[NR], accN[NR];
 #pragma unroll
@@ -88,10 +89,10 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
       const T wr = wscale * d.x, wi = -wscale * d.y;  // w = (k / 2s) (dx - i dy)
       const T y = yscale * (d.x * d.x + d.y * d.y);   // (k rho)^2 / 4
       T ur = T(1), ui = T(0);
-      for (int n = 0; n <= pL; ++n) {
-        const T* sr = series + n * (K + 1);
+      for (int m = 0; m <= pL; ++m) {
+        const T* sr = series + m * (K + 1);
         const T S = jseries(sr, K, y);
-        sb[n * 64 + lane] = mk<T>(ur * S, ui * S);
+        sb[m * 64 + lane] = mk<T>(ur * S, ui * S);
         const T inv = sr[0];
         const T nr = (ur * wr - ui * wi) * inv, ni = (ur * wi + ui * wr) * inv;
         ur = nr;
@@ -101,9 +102,10 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
       for (int r = 0; r < NR; ++r) sq[r * 64 + lane] = q[(size_t)(r0 + r) * N + c0 + lane];
     }
     __syncthreads();
-    if (lane <= pL) {
-      for (int j = 0; j < cnt; ++j) {
-        const cplx<T> b = sb[lane * 64 + j];
+    // lane = (group g, order n): the G groups split the points of the chunk
+    if (g < G) {
+      for (int j = g; j < cnt; j += G) {
+        const cplx<T> b = sb[n * 64 + j];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const cplx<T> qq = sq[r * 64 + j];
@@ -114,14 +116,33 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
     }
     __syncthreads();
   }
+  // sum the G partial sums of each order (sb is free again)
+  cplx<T>* red = sb;  // [NR][2][64]
+  if (g < G) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      red[(r * 2 + 0) * 64 + lane] = accP[r];
+      red[(r * 2 + 1) * 64 + lane] = accN[r];
+    }
+  }
+  __syncthreads();
   if (lane <= pL) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
+      cplx<T> sp = accP[r], sn = accN[r];
+      for (int gg = 1; gg < G; ++gg) {
+        const cplx<T> a = red[(r * 2 + 0) * 64 + gg * (pL + 1) + lane];
+        const cplx<T> b = red[(r * 2 + 1) * 64 + gg * (pL + 1) + lane];
+        sp.x += a.x;
+        sp.y += a.y;
+        sn.x += b.x;
+        sn.y += b.y;
+      }
       const size_t base = ((size_t)leaf * nrhs + r0 + r) * P;
-      Mout[base + pL + lane] = accP[r];
+      Mout[base + pL + lane] = sp;
       if (lane > 0) {
         const T sg = (lane & 1) ? T(-1) : T(1);
-        Mout[base + pL - lane] = mk<T>(sg * accN[r].x, sg * accN[r].y);
+        Mout[base + pL - lane] = mk<T>(sg * sn.x, sg * sn.y);
       }
     }
   }
@@ -390,12 +411,15 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(M2LAllArgs<T> args) {
   }
 }
 
-// Level-to-level translation on MFMA.  One wave = 16 boxes of the output
-// level (columns) and one row tile (blockIdx.y):
-//   L2L (mode 0): child boxes 4 b + c of 16 consecutive parents b, one child
-//                 position c per wave; out += A_c * L_parent.
-//   M2M (mode 1): 16 consecutive parents; out = sum_c A_c * M_child(4 b + c).
-// Input columns read the real form [Re; Im] of the source coefficients.
+// Level-to-level translation on MFMA.  A block of 4 waves covers 16 boxes of
+// the output level (columns) and one 16-row tile (blockIdx.y):
+//   L2L (mode 0): child boxes 4 b + c of 16 consecutive parents b; wave c
+//                 takes child position c; out += A_c * L_parent.
+//   M2M (mode 1): 16 consecutive parents; wave c forms A_c * M_child(4 b + c)
+//                 and the 4 partial products are summed in LDS.
+// Input columns read the real form [Re; Im] of the source coefficients.  The
+// k steps run in chunks of 16 whose loads are all issued before the chunk's
+// MFMAs, so a wave waits for memory once per chunk, not once per step.
 template <class T>
 struct TTArgs {
   const cplx<T>* in;
@@ -407,60 +431,80 @@ struct TTArgs {
   int mode, nparents, Pin, Pout, RT, KS, nrhs, r0, nr;
 };
 
+constexpr int kTTChunk = 16;
+
 template <class T>
-__global__ __launch_bounds__(64) void k_tt_mfma(TTArgs<T> a) {
+__global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
   typedef typename Acc4<T>::type V4;
+  __shared__ T red[3][4][64];
   if (a.alive && !a.alive[0]) return;
-  const int lane = threadIdx.x, j = lane & 15, kq = lane >> 4;
-  const int groups = (a.nparents + 15) / 16;
-  const int g = blockIdx.x % groups, cw = blockIdx.x / groups;  // cw: child position (L2L)
-  const int rt = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, kq = lane >> 4;
+  const int g = blockIdx.x, rt = blockIdx.y;
   const int parent = g * 16 + j;
   const bool colv = parent < a.nparents;
-  const int nchunk = (a.KS + 3) / 4;
+  if (a.mode == 1 && a.fout) {
+    // block-uniform: every wave sees the same 16 parents
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    if (wave == 0 && colv && a.fout[parent]) any = 1;
+    __syncthreads();
+    if (!any) return;
+  }
+  const int c = wave;
+  const int src = a.mode == 0 ? parent : 4 * parent + c;
+  const bool bvalid = colv && (a.mode == 0 || !a.fin || a.fin[src]);
+  const T* Wf = a.Wf + ((size_t)(c * a.RT + rt) * a.KS) * 64 + lane;
   for (int r = 0; r < a.nr; ++r) {
     V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    const int nterm = a.mode == 0 ? 1 : 4;
-    if (a.mode == 1 && a.fout && __ballot(colv && a.fout[parent]) == 0ull) return;
-    for (int term = 0; term < nterm; ++term) {
-      const int c = a.mode == 0 ? cw : term;
-      const int src = a.mode == 0 ? parent : 4 * parent + c;
-      const bool bvalid = colv && (a.mode == 0 || !a.fin || a.fin[src]);
-      const cplx<T>* col = a.in + ((size_t)(bvalid ? src : 0) * a.nrhs + a.r0 + r) * a.Pin;
-      const T* Wf = a.Wf + ((size_t)(c * a.RT + rt) * a.KS) * 64 + lane;
-      for (int ch = 0; ch < nchunk; ++ch) {
-        T av[4], bv[4];
+    const cplx<T>* col = a.in + ((size_t)(bvalid ? src : 0) * a.nrhs + a.r0 + r) * a.Pin;
+    for (int k0 = 0; k0 < a.KS; k0 += kTTChunk) {
+      T av[kTTChunk], bv[kTTChunk];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ks = min(ch * 4 + u, a.KS - 1);
-          av[u] = Wf[ks * 64];
-          const int kk = ks * 4 + kq;
-          bv[u] = T(0);
-          if (bvalid && kk < 2 * a.Pin) {
-            const cplx<T> pv = col[kk < a.Pin ? kk : kk - a.Pin];
-            bv[u] = kk < a.Pin ? pv.x : pv.y;
-          }
+      for (int u = 0; u < kTTChunk; ++u) {
+        const int ks = min(k0 + u, a.KS - 1);
+        av[u] = Wf[ks * 64];
+        const int kk = ks * 4 + kq;
+        bv[u] = T(0);
+        if (bvalid && k0 + u < a.KS && kk < 2 * a.Pin) {
+          const cplx<T> pv = col[kk < a.Pin ? kk : kk - a.Pin];
+          bv[u] = kk < a.Pin ? pv.x : pv.y;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (ch * 4 + u < a.KS) {
-            if (u & 1)
-              acc1 = mfma16(av[u], bv[u], acc1);
-            else
-              acc0 = mfma16(av[u], bv[u], acc0);
-          }
       }
+#pragma unroll
+      for (int u = 0; u < kTTChunk; ++u)
+        if (k0 + u < a.KS) {
+          if (u & 1)
+            acc1 = mfma16(av[u], bv[u], acc1);
+          else
+            acc0 = mfma16(av[u], bv[u], acc0);
+        }
+    }
+    T s[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = acc0[q] + acc1[q];
+    if (a.mode == 1) {
+      if (wave > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wave - 1][q][lane] = s[q];
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += red[0][q][lane] + red[1][q][lane] + red[2][q][lane];
+      }
+      __syncthreads();
+      if (wave > 0) continue;
     }
     if (!colv) continue;
-    const int obox = a.mode == 0 ? 4 * parent + cw : parent;
+    const int obox = a.mode == 0 ? 4 * parent + c : parent;
     if (a.mode == 1 && a.fout && !a.fout[obox]) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = rt * 16 + out_row<T>(kq, q);
       if (i < 2 * a.Pout) {
         T* dst = reinterpret_cast<T*>(a.out + ((size_t)obox * a.nrhs + a.r0 + r) * a.Pout + (i < a.Pout ? i : i - a.Pout));
-        const T s = acc0[q] + acc1[q];
-        dst[i < a.Pout ? 0 : 1] = a.mode == 0 ? dst[i < a.Pout ? 0 : 1] + s : s;
+        dst[i < a.Pout ? 0 : 1] = a.mode == 0 ? dst[i < a.Pout ? 0 : 1] + s[q] : s[q];
       }
     }
   }
@@ -944,7 +988,8 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
   const double k = pl.k;
   if (L >= 2) {
     const LevelInfo& lf = pl.lv[L];
-    const size_t sh = (size_t)(lf.p + 1 + NR) * 64 * sizeof(cplx<T>);
+    // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
+    const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
     k_p2m<T, NR><<<(int)t.nleaves, 64, sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, M + lf.coef * nrhs, lf.p,
                                                  T(k / (2 * lf.s)), T(k * k / 4), pl.series.p, pl.K,
                                                  flags ? flags + lf.box0 : nullptr, alive);
@@ -970,7 +1015,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
         ta.nrhs = nrhs;
         ta.r0 = r0;
         ta.nr = NR;
-        k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 64, 0, st>>>(ta);
+        k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
         HFMM_LAUNCH_CHECK();
       }
       if (tm) tm->mark(1, st);
@@ -993,7 +1038,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
         ta.nrhs = nrhs;
         ta.r0 = r0;
         ta.nr = NR;
-        k_tt_mfma<T><<<dim3(4 * ((ta.nparents + 15) / 16), mf.RT), 64, 0, st>>>(ta);
+        k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
         HFMM_LAUNCH_CHECK();
       }
     } else {
