@@ -29,7 +29,9 @@ namespace {
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float log2T(float x) { return __log2f(x); }
+// v_log_f32 without the denormal-input rescaling: every argument here is
+// (k r)^2 of two distinct FP32 positions, far above the denormal range.
+__device__ __forceinline__ float log2T(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ double log2T(double x) { return log2(x); }
 
 // acc += a * b (complex; V is float2 or double2)
@@ -283,132 +285,167 @@ struct M2LAllArgs {
 
 // M2L of every level in one launch (the levels are independent; L2L runs
 // afterwards, top down).  One block = a tile x tile patch of target boxes
-// (4 or 1 patches of 4 x 4) and one row tile.  Every wave owns all patches of
-// the block (one accumulator each, so one A fragment feeds up to 4 MFMAs)
-// and the offset classes whose index = wave (mod 4); the four partial sums
-// meet in LDS.
-template <class T>
-__global__ __launch_bounds__(256) void k_m2l_mfma(M2LAllArgs<T> args) {
+// (4 or 1 patches of 4 x 4) and one row tile.  The block stages the source
+// window (the targets' boxes plus a 2-box margin, clipped to the grid) in LDS
+// as real columns [Re; Im; 0 pad] of stride KPs, followed by one all-zero box
+// that stands in for sources outside the grid or not adjacent to the
+// target's parent, so every operand read is unconditional.  The k steps are
+// padded with zeros to whole chunks of 4.  Each of the 8 waves owns all
+// patches of the block (one accumulator each, so one A fragment feeds up to 4
+// MFMAs) and the offset classes whose index = wave (mod 8); the eight partial
+// sums meet in LDS.  KPs = 2 m with m odd: the 16 columns of a patch
+// times 2 rows then fall in distinct LDS banks (32 of 4 bytes) when the
+// window is 12 boxes wide.
+template <class T, int NP>
+__device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int lblock, T* Ms) {
   typedef typename Acc4<T>::type V4;
-  extern __shared__ unsigned char smem_raw[];
-  T* Ms = reinterpret_cast<T*>(smem_raw);
   T* red = Ms;  // the reduction reuses the window once the products are done
-  if (args.alive && !args.alive[0]) return;
-  int li = 0;
-  while (li + 1 < args.nlev && (int)blockIdx.x >= args.lv[li + 1].block0) ++li;
-  const M2LLevel<T>& a = args.lv[li];
-  const int lblock = (int)blockIdx.x - a.block0;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nbt = a.nb / a.tile;
   const int pb = lblock % a.gx, rt = lblock / a.gx;
   const int bx0 = (pb % nbt) * a.tile, by0 = (pb / nbt) * a.tile;
   const int wx0 = max(0, bx0 - 2), wy0 = max(0, by0 - 2);
   const int WW = min(a.nb, bx0 + a.tile + 2) - wx0, WH = min(a.nb, by0 + a.tile + 2) - wy0;
-  const int pside = a.tile / 4;
-  const int np = pside * pside;  // 4 or 1
+  const int zb = WW * WH;  // the zero box
+  const int KPs = a.KPs, P = a.P, KS = a.KS;
+  constexpr int pside = NP == 4 ? 2 : 1;
   const int j = lane & 15, kq = lane >> 4;
-  int tx[4], ty[4];
-  uint32_t tbox[4];
+  int tx[NP], ty[NP];
+  uint32_t tbox[NP];
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int pp = p < np ? p : 0;
-    tx[p] = bx0 + (pp % pside) * 4 + (j & 3);
-    ty[p] = by0 + (pp / pside) * 4 + (j >> 2);
+  for (int p = 0; p < NP; ++p) {
+    tx[p] = bx0 + (p % pside) * 4 + (j & 3);
+    ty[p] = by0 + (p / pside) * 4 + (j >> 2);
     tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
   }
-  const int P2 = 2 * a.P, KP = 4 * a.KS;
-  const int nchunk = (a.KS + 3) / 4;
+  const int nch = KS >> 2;  // KS is a multiple of 4
+  const size_t cstride = (size_t)a.RT * KS * 64;
+  const T* Abase = a.Af + (size_t)rt * KS * 64 + lane;
   for (int r = 0; r < args.nr; ++r) {
     __syncthreads();
-    for (int idx = tid; idx < WW * WH * a.P; idx += 256) {
-      const int lb = idx / a.P, n = idx - lb * a.P;
-      const uint32_t gb = morton((uint32_t)(wx0 + lb % WW), (uint32_t)(wy0 + lb / WW));
-      cplx<T> v = mk<T>(0, 0);
-      if (!a.fsrc || a.fsrc[gb]) v = a.M[((size_t)gb * args.nrhs + args.r0 + r) * a.P + n];
-      Ms[lb * a.KPs + n] = v.x;
-      Ms[lb * a.KPs + a.P + n] = v.y;
-    }
-    const int padw = KP - P2;
-    for (int idx = tid; idx < WW * WH * padw; idx += 256) {
-      const int lb = idx / padw;
-      Ms[lb * a.KPs + P2 + (idx - lb * padw)] = T(0);
-    }
+    // stage the window: wave w takes boxes w, w + 8, ... of the window in
+    // row order, lanes run along the box's column; wave 0 also clears the
+    // zero box
+    for (int y = 0; y < WH; ++y)
+      for (int x = (w + y * 3) & 7; x < WW; x += 8) {
+        const uint32_t gb = morton((uint32_t)(wx0 + x), (uint32_t)(wy0 + y));
+        const bool on = !a.fsrc || a.fsrc[gb];
+        const cplx<T>* src = a.M + ((size_t)gb * args.nrhs + args.r0 + r) * P;
+        T* dst = Ms + (y * WW + x) * KPs;
+        for (int n = lane; n < KPs; n += 64) {
+          T v = T(0);
+          if (on && n < 2 * P) {
+            const cplx<T> c = src[n < P ? n : n - P];
+            v = n < P ? c.x : c.y;
+          }
+          dst[n] = v;
+        }
+      }
+    if (w == 0)
+      for (int n = lane; n < KPs; n += 64) Ms[zb * KPs + n] = T(0);
     __syncthreads();
-    V4 acc[4];
+    V4 acc[NP];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) acc[p] = V4{0, 0, 0, 0};
-    // this wave's 10 offset classes, (class index) = w (mod 4); the A
-    // fragments of the next chunk are loaded before the MFMAs of this one
-    const int nsteps = 10 * nchunk;
-    auto a_ptr = [&](int step) {
-      const int oi = step / nchunk, c = step - oi * nchunk;
-      return a.Af + ((size_t)(kClassO[4 * oi + w] * a.RT + rt) * a.KS + c * 4) * 64 + lane;
-    };
+    for (int p = 0; p < NP; ++p) acc[p] = V4{0, 0, 0, 0};
+    // this wave's 5 offset classes (class index = wave mod 8); the A
+    // fragments of the next chunk, also across classes, load one chunk ahead
     T an[4];
     {
-      const T* A0 = a_ptr(0);
+      const T* A0 = Abase + (size_t)kClassO[w] * cstride;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) an[u] = A0[min(u, a.KS - 1) * 64];
+      for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
     }
-    bool v[4];
-    int lb[4];
-    for (int step = 0; step < nsteps; ++step) {
-      const int oi = step / nchunk, c = step - oi * nchunk;
-      T ac[4];
+    for (int oi = 0; oi < 5; ++oi) {
+      const int o = kClassO[8 * oi + w];
+      const int ox = o / 7 - 3, oy = o % 7 - 3;
+      int base[NP];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) ac[u] = an[u];
-      if (step + 1 < nsteps) {
-        const int c1 = (step + 1) % nchunk;
-        const T* A1 = a_ptr(step + 1);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) an[u] = A1[(min(c1 * 4 + u, a.KS - 1) - c1 * 4) * 64];
+      for (int p = 0; p < NP; ++p) {
+        const int sx = tx[p] + ox, sy = ty[p] + oy;
+        const bool v = sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb && abs((sx >> 1) - (tx[p] >> 1)) <= 1 &&
+                       abs((sy >> 1) - (ty[p] >> 1)) <= 1;
+        base[p] = (v ? (sx - wx0) + (sy - wy0) * WW : zb) * KPs + kq;
       }
-      if (c == 0) {
-        const int o = kClassO[4 * oi + w];
-        const int ox = o / 7 - 3, oy = o % 7 - 3;
+      const T* A = Abase + (size_t)o * cstride;
+      const T* An = oi + 1 < 5 ? Abase + (size_t)kClassO[8 * (oi + 1) + w] * cstride : A;
+      for (int c = 0; c < nch; ++c) {
+        T av[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const int sx = tx[p] + ox, sy = ty[p] + oy;
-          v[p] = p < np && sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb && abs((sx >> 1) - (tx[p] >> 1)) <= 1 &&
-                 abs((sy >> 1) - (ty[p] >> 1)) <= 1;
-          lb[p] = v[p] ? (sx - wx0) + (sy - wy0) * WW : 0;
+        for (int u = 0; u < 4; ++u) av[u] = an[u];
+        if (c + 1 < nch) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
+        } else if (oi + 1 < 5) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
         }
+        T bv[NP][4];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
       }
-      T bv[4][4];
+    }
+    // sum the 8 waves' partial products: waves 4..7 into 0..3, then 0..3
+    __syncthreads();
+    if (w >= 4) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ks = min(c * 4 + u, a.KS - 1);
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int p = 0; p < 4; ++p) bv[p][u] = v[p] ? Ms[lb[p] * a.KPs + ks * 4 + kq] : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (c * 4 + u < a.KS) {
-#pragma unroll
-          for (int p = 0; p < 4; ++p)
-            if (p < np) acc[p] = mfma16(ac[u], bv[p][u], acc[p]);
-        }
+        for (int q = 0; q < 4; ++q) red[(((w - 4) * NP + p) * 4 + q) * 64 + lane] = acc[p][q];
     }
     __syncthreads();
+    if (w < 4) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (p < np) red[((w * 4 + p) * 4 + q) * 64 + lane] = acc[p][q];
+        for (int q = 0; q < 4; ++q) acc[p][q] += red[((w * NP + p) * 4 + q) * 64 + lane];
+    }
     __syncthreads();
-    if (w < np) {
+    if (w < 4) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[((w * NP + p) * 4 + q) * 64 + lane] = acc[p][q];
+    }
+    __syncthreads();
+    if (w < NP) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const T s = red[((0 * 4 + w) * 4 + q) * 64 + lane] + red[((1 * 4 + w) * 4 + q) * 64 + lane] +
-                    red[((2 * 4 + w) * 4 + q) * 64 + lane] + red[((3 * 4 + w) * 4 + q) * 64 + lane];
+        const T s = red[((0 * NP + w) * 4 + q) * 64 + lane] + red[((1 * NP + w) * 4 + q) * 64 + lane] +
+                    red[((2 * NP + w) * 4 + q) * 64 + lane] + red[((3 * NP + w) * 4 + q) * 64 + lane];
         const int i = rt * 16 + out_row<T>(kq, q);
-        if (i < P2) {
-          T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tbox[w] * args.nrhs + args.r0 + r) * a.P + (i < a.P ? i : i - a.P));
-          dst[i < a.P ? 0 : 1] = s;
+        if (i < 2 * P) {
+          uint32_t tb = tbox[0];
+#pragma unroll
+          for (int p = 1; p < NP; ++p)
+            if (w == p) tb = tbox[p];
+          T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tb * args.nrhs + args.r0 + r) * P + (i < P ? i : i - P));
+          dst[i < P ? 0 : 1] = s;
         }
       }
     }
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(512) void k_m2l_mfma(M2LAllArgs<T> args) {
+  extern __shared__ unsigned char smem_raw[];
+  T* Ms = reinterpret_cast<T*>(smem_raw);
+  if (args.alive && !args.alive[0]) return;
+  int li = 0;
+  while (li + 1 < args.nlev && (int)blockIdx.x >= args.lv[li + 1].block0) ++li;
+  const M2LLevel<T>& a = args.lv[li];
+  const int lblock = (int)blockIdx.x - a.block0;
+  if (a.tile == 8)
+    m2l_block<T, 4>(args, a, lblock, Ms);
+  else
+    m2l_block<T, 1>(args, a, lblock, Ms);
 }
 
 // Level-to-level translation on MFMA.  A block of 4 waves covers 16 boxes of
@@ -786,12 +823,14 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       MfmaLevel& m = pl->mf[l];
       const int P = pl->lv[l].P, nb = 1 << l;
       m.RT = (2 * P + 15) / 16;
-      m.KS = (2 * P + 3) / 4;
-      m.KPs = 4 * m.KS + 1;
-      // M2L window: a tile of 8 x 8 targets when it fits in 64 KB of LDS, else 4 x 4
+      m.KS = 4 * ((2 * P + 15) / 16);  // whole chunks of 4 k steps; the padding is zero
+      m.KPs = 4 * m.KS + 2;            // 2 x odd (see k_m2l_mfma)
+      // M2L window: a tile of 8 x 8 targets when it fits in 64 KB of LDS, else
+      // 4 x 4; the window plus one zero box, or the partial sums of 4 waves
       auto lds_for = [&](int tile) {
         const int win = std::min(nb, std::min(tile, nb) + 4);
-        return std::max((size_t)win * win * m.KPs, (size_t)4 * 4 * 4 * 64) * sizeof(T);
+        const int np = tile >= 8 && nb >= 8 ? 4 : 1;
+        return std::max((size_t)(win * win + 1) * m.KPs, (size_t)4 * np * 4 * 64) * sizeof(T);
       };
       m.lds4 = lds_for(4);
       m.fit4 = m.lds4 <= 65536;
@@ -925,7 +964,7 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.ua = T(P.ua);
   a.ub = T(P.ub);
   a.c1 = T(P.c1);
-  a.c0 = T(P.c0);
+  a.jinv = T(1.0 / P.c1);
   return a;
 }
 
@@ -972,7 +1011,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
     lds = std::max(lds, small ? mf.lds4 : mf.lds);
   }
   if (ma.nlev) {
-    k_m2l_mfma<T><<<blocks, 256, lds, st>>>(ma);
+    k_m2l_mfma<T><<<blocks, 512, lds, st>>>(ma);
     HFMM_LAUNCH_CHECK();
   }
 }

@@ -17,7 +17,43 @@ struct P2PArgs {
   int nrhs, r0, L, G, accumulate;
   T k, kls;  // k and k * leaf side
   T cJ[32], cY[32];
-  T ua, ub, c1, c0;
+  T ua, ub;  // centred polynomial variable u = ua t + ub
+  T c1, jinv;  // J0 is carried as Jc = c1 J0; jinv = 1 / c1
+};
+
+// Running sums of q (J0 + i Y0) over one target's sources, J0 carried as
+// Jc = c1 J0:  Re = sum (qx J0 - qy Y0) = jinv aj - ay,
+//              Im = sum (qx Y0 + qy J0) = by + jinv bj.
+template <class T, int NR>
+struct PairSum {
+  T aj[NR], ay[NR], by[NR], bj[NR];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) aj[r] = ay[r] = by[r] = bj[r] = T(0);
+  }
+  __device__ __forceinline__ void add(int r, cplx<T> q, T Jc, T Y) {
+    aj[r] = fmaT(q.x, Jc, aj[r]);
+    ay[r] = fmaT(q.y, Y, ay[r]);
+    by[r] = fmaT(q.x, Y, by[r]);
+    bj[r] = fmaT(q.y, Jc, bj[r]);
+  }
+  // sum over the G lanes (a power of two) that share a target
+  __device__ __forceinline__ void reduce(int G) {
+    for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        aj[r] += __shfl_xor(aj[r], off);
+        ay[r] += __shfl_xor(ay[r], off);
+        by[r] += __shfl_xor(by[r], off);
+        bj[r] += __shfl_xor(bj[r], off);
+      }
+    }
+  }
+  // (i/4) times the sum: (i/4)(Re + i Im) = (-Im/4, Re/4)
+  __device__ __forceinline__ cplx<T> phi(int r, T jinv) const {
+    const T re = fmaT(jinv, aj[r], -ay[r]), im = fmaT(jinv, bj[r], by[r]);
+    return mk<T>(T(-0.25) * im, T(0.25) * re);
+  }
 };
 
 template <class T, int NR>
@@ -25,8 +61,10 @@ struct P2PCfg {
   static constexpr int SCH = (2 * sizeof(T) * (1 + NR) * 512 <= 16384) ? 512 : 256;
 };
 
-// One pair: t = (k r)^2.  FAST uses the fitted polynomial (D coefficients),
-// otherwise the full-range FP64 routine.
+// One pair: t = (k r)^2; returns Jc = c1 J0(sqrt t) and Y = Y0(sqrt t).
+// FAST uses the fitted polynomials (D coefficients each), otherwise the
+// full-range FP64 routine.  MASK zeroes the pair at t = 0 (a point with
+// itself, or a coincident point).
 template <class T, int D, bool FAST, bool MASK>
 __device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y) {
   bool valid = true;
@@ -42,12 +80,11 @@ __device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y) {
       j = fmaT(j, u, a.cJ[i]);
       yh = fmaT(yh, u, a.cY[i]);
     }
-    const T lg = log2T(t);
-    Y = fmaT(j, fmaT(lg, a.c1, a.c0), yh);
+    Y = fmaT(j, log2T(t), yh);
     J = j;
   } else {
     const double2 h = h0_general(sqrt((double)t));
-    J = (T)h.x;
+    J = (T)h.x * a.c1;
     Y = (T)h.y;
   }
   if (MASK) {
@@ -111,9 +148,8 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
       xt = a.k * d.x;
       yt = a.k * d.y;
     }
-    T A[NR], B[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+    PairSum<T, NR> acc;
+    acc.zero();
     for (int c0 = 0; c0 < total; c0 += SCH) {
       const int cnt = min(SCH, total - c0);
       __syncthreads();
@@ -137,13 +173,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         T J, Y;
         h0_pair<T, D, FAST, false>(a, t, J, Y);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const cplx<T> qq = sq[r][j];
-          A[r] = fmaT(qq.x, J, A[r]);
-          A[r] = fmaT(-qq.y, Y, A[r]);
-          B[r] = fmaT(qq.x, Y, B[r]);
-          B[r] = fmaT(qq.y, J, B[r]);
-        }
+        for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
       }
       for (int j = split + g; j < cnt; j += G) {
         const cplx<T> s = spos[j];
@@ -152,28 +182,15 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         T J, Y;
         h0_pair<T, D, FAST, true>(a, t, J, Y);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const cplx<T> qq = sq[r][j];
-          A[r] = fmaT(qq.x, J, A[r]);
-          A[r] = fmaT(-qq.y, Y, A[r]);
-          B[r] = fmaT(qq.x, Y, B[r]);
-          B[r] = fmaT(qq.y, J, B[r]);
-        }
+        for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
       }
     }
-    for (int off = 1; off < G; off <<= 1) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        A[r] += __shfl_xor(A[r], off);
-        B[r] += __shfl_xor(B[r], off);
-      }
-    }
+    acc.reduce(G);
     if (g == 0 && act) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
-        // q (i/4) H0 summed: (i/4)(A + iB) = (-B/4, A/4)
-        cplx<T> v = mk<T>(T(-0.25) * B[r], T(0.25) * A[r]);
+        cplx<T> v = acc.phi(r, a.jinv);
         if (a.accumulate) {
           const cplx<T> o = a.phi[idx];
           v.x += o.x;
@@ -210,7 +227,7 @@ struct P2P4Cfg {
 template <class T, int D, bool FAST, bool MASK, int NR, int G>
 __device__ __forceinline__ void p2p_run(const P2PArgs<T>& a, const cplx<T>* __restrict__ spos,
                                         const cplx<T> (*sq)[P2P4Cfg<T, NR>::SCAP], int lo, int hi, int g, T xt,
-                                        T yt, T (&A)[NR], T (&B)[NR]) {
+                                        T yt, PairSum<T, NR>& acc) {
 #pragma unroll 4
   for (int j = lo + g; j < hi; j += G) {
     const cplx<T> s = spos[j];
@@ -219,13 +236,7 @@ __device__ __forceinline__ void p2p_run(const P2PArgs<T>& a, const cplx<T>* __re
     T J, Y;
     h0_pair<T, D, FAST, MASK>(a, t, J, Y);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const cplx<T> qq = sq[r][j];
-      A[r] = fmaT(qq.x, J, A[r]);
-      A[r] = fmaT(-qq.y, Y, A[r]);
-      B[r] = fmaT(qq.x, Y, B[r]);
-      B[r] = fmaT(qq.y, J, B[r]);
-    }
+    for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
   }
 }
 
@@ -289,20 +300,13 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       for (int r = 0; r < NR; ++r) sq[r][idx] = a.q[(size_t)(a.r0 + r) * a.N + slot];
     }
   };
-  auto finish = [&](int ti, bool act, T (&A)[NR], T (&B)[NR]) {
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        A[r] += __shfl_xor(A[r], off);
-        B[r] += __shfl_xor(B[r], off);
-      }
-    }
+  auto finish = [&](int ti, bool act, PairSum<T, NR>& acc) {
+    acc.reduce(G);
     if (g == 0 && act) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
-        cplx<T> v = mk<T>(T(-0.25) * B[r], T(0.25) * A[r]);
+        cplx<T> v = acc.phi(r, a.jinv);
         if (a.accumulate) {
           const cplx<T> o = a.phi[idx];
           v.x += o.x;
@@ -324,14 +328,13 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
         xt = fmaT(a.k, d.x, txo);
         yt = fmaT(a.k, d.y, tyo);
       }
-      T A[NR], B[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+      PairSum<T, NR> acc;
+      acc.zero();
 #pragma unroll
       for (int sgi = 0; sgi < 4; ++sgi)
-        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, A, B);
-      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, A, B);
-      finish(ti, act, A, B);
+        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, acc);
+      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, acc);
+      finish(ti, act, acc);
     }
   } else {
     // the region does not fit: uniform rounds across the block, sources in chunks
@@ -347,9 +350,8 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
         xt = fmaT(a.k, d.x, txo);
         yt = fmaT(a.k, d.y, tyo);
       }
-      T A[NR], B[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) A[r] = B[r] = T(0);
+      PairSum<T, NR> acc;
+      acc.zero();
       for (int c0 = 0; c0 < total; c0 += SCAP) {
         const int cnt = min(SCAP, total - c0);
         __syncthreads();
@@ -358,12 +360,12 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
 #pragma unroll
         for (int sgi = 0; sgi < 4; ++sgi) {
           const int lo = max(sg_lo[sgi], c0) - c0, hi = min(sg_hi[sgi], c0 + cnt) - c0;
-          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, A, B);
+          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc);
         }
         const int lo = max(own_lo, c0) - c0, hi = min(own_hi, c0 + cnt) - c0;
-        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, A, B);
+        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc);
       }
-      finish(ti, act, A, B);
+      finish(ti, act, acc);
     }
   }
 }

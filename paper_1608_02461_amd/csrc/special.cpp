@@ -98,19 +98,23 @@ bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, double to
     }
     NearPoly P;
     P.deg = n;
-    cheb_to_mono(fJ, n, P.cJ);
-    cheb_to_mono(fY, n, P.cY);
+    double mJ[32], mY[32];
+    cheb_to_mono(fJ, n, mJ);
+    cheb_to_mono(fY, n, mY);
     P.ua = 2.0 / tmax;
     P.ub = -1.0;
-    P.c1 = kLn2 / kPi;
-    P.c0 = (2.0 / kPi) * (kEulerGamma - kLn2);
+    for (int i = 0; i < n; ++i) {
+      P.cJ[i] = P.c1 * mJ[i];
+      P.cY[i] = mY[i] + P.c0 * mJ[i];
+    }
     double err = 0;
     for (int s = 1; s < nsamp; ++s) {
       double t = tmax * s / (nsamp - 1);
       double u = t * P.ua + P.ub;
-      double J = fp32 ? horner<float>(P.cJ, n, u) : horner<double>(P.cJ, n, u);
-      double Y = fp32 ? horner<float>(P.cY, n, u) : horner<double>(P.cY, n, u);
-      err = std::max(err, std::max(std::fabs(J - (double)tJ[s]), std::fabs(Y - (double)tY[s])));
+      double Jc = fp32 ? horner<float>(P.cJ, n, u) : horner<double>(P.cJ, n, u);
+      double Yf = fp32 ? horner<float>(P.cY, n, u) : horner<double>(P.cY, n, u);
+      const double J = (double)tJ[s], Yt = (double)tY[s] + P.c0 * J;
+      err = std::max(err, std::max(std::fabs(Jc / P.c1 - J), std::fabs(Yf - Yt)));
     }
     P.max_err = err;
     out = P;

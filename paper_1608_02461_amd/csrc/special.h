@@ -93,15 +93,27 @@ void hankel_seq(int nmax, double x, std::vector<std::complex<double>>& H);
 // Near-field polynomial: on t = (k r)^2 in [0, tmax],
 //   J0(sqrt t) ~ sum cJ[i] u^i,  Yhat(sqrt t) ~ sum cY[i] u^i,  u = t*ua + ub,
 //   Y0 = J0 (c1 log2 t + c0) + Yhat.
+// Near-field H0 on t = (k r)^2 in [0, tmax], in the form the pair kernels
+// evaluate with u = ua t + ub:
+//   Jc(u) = c1 J0(sqrt t)                      (coefficients cJ)
+//   Yf(u) = Yhat(sqrt t) + c0 J0(sqrt t)       (coefficients cY)
+//   Y0    = Jc log2(t) + Yf,   J0 = Jc / c1,
+// where Yhat = Y0 - (2/pi)(ln(sqrt(t)/2) + gamma_E) J0, c1 = ln2/pi and
+// c0 = (2/pi)(gamma_E - ln 2).  Folding c0 into Yf and c1 into Jc leaves one
+// FMA per pair between the two polynomials, the log2 and the accumulation.
 struct NearPoly {
   int deg = 0;  // number of coefficients
   double cJ[32] = {0}, cY[32] = {0};
-  double ua = 0, ub = 0, c1 = 0, c0 = 0;
-  double max_err = 0;  // measured max |error| of H0 over the interval
+  double ua = 0, ub = 0;
+  // set whether or not a fit is found: the general routine's J0 is scaled by c1 too
+  double c1 = 0.69314718055994530942 / 3.14159265358979323846;
+  double c0 = (2.0 / 3.14159265358979323846) * (0.57721566490153286061 - 0.69314718055994530942);
+  double max_err = 0;  // measured max |error| of J0 and of Yf over the interval
 };
 // Picks the smallest of the candidate coefficient counts whose error, with
-// Horner evaluated in `fp32 ? float : double`, is below tol; returns false if
-// none is (then the general routine must be used).
+// Horner evaluated in `fp32 ? float : double` on coefficients rounded to it,
+// is below tol; returns false if none is (then the general routine must be
+// used).
 bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, double tol, NearPoly& out);
 
 // Exact integral of G over an h x h cell centred on the node:
