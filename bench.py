@@ -71,10 +71,11 @@ def log(*a):
 def p2p_flops_per_pair(deg, nrhs=1):
     """FP32/FP64 fast-path P2P flops per pair, counted from the kernel source
     (FMA = 2): dx, dy (2); t = fma(dx, dx, dy*dy) (3); u = fma (2); two
-    Horner chains of deg-1 FMAs (4 (deg-1)); Y = fma(J, fma(lg, c1, c0), Yh)
-    (4); 4 FMAs per right-hand side into the accumulators (8 nrhs).  The
-    log2 per pair is a transcendental and is not counted."""
-    return 2 + 3 + 2 + 4 * (deg - 1) + 4 + 8 * nrhs
+    Horner chains of deg-1 FMAs (4 (deg-1)); Y = fma(Jc, log2 t, Yf) (2); 4
+    FMAs per right-hand side into the accumulators (8 nrhs).  The log2 per
+    pair is a transcendental and is not counted, nor is the L2P that the
+    same kernel evaluates once per target (under 2% of its flops here)."""
+    return 2 + 3 + 2 + 4 * (deg - 1) + 2 + 8 * nrhs
 
 
 def m2l_flops(orders, L, nrhs=1):
@@ -181,8 +182,10 @@ def main():
                 "traffic": measured_traffic(roof_kernel) if dominant == "p2p" else None,
                 "algorithmic_flops_per_launch": fl, "ms_per_launch": round(stages[dominant], 5)}
     if dominant == "p2p":
-        # positions, charges and the L2P partial potentials read once, potentials written once
-        roofline["algorithmic_bytes_per_launch"] = 32 * N
+        # positions, sorted charges and the output permutation read once, the
+        # leaf local expansions read once, potentials written once
+        L = tree.info()["levels"]
+        roofline["algorithmic_bytes_per_launch"] = (8 + 8 + 4 + 8) * N + 4 ** L * (2 * plan["orders"][L] + 1) * 8
 
     gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_reference.npz"))
     smp = gold["samples"]

@@ -47,7 +47,6 @@ struct FmmPlan : PlanBase {
   std::vector<int64_t> m2m_off, l2l_off, m2l_off;
   std::vector<MfmaLevel> mf;   // per level
   DevBuf<T> afrag, wfrag, mfrag;  // per-lane MFMA fragments of the M2L / L2L / M2M matrices
-  DevBuf<T> series;         // (p_L + 1) x (K + 1): [n][0] = 1/(n+1), [n][j] = 1/(j (n+j))
   int K = 0;
   // near field
   bool near_fast = false;
@@ -89,10 +88,13 @@ struct StageTimer {
 // NULL for "every box") is a per-level array of 4^l bytes per level
 // (concatenated from level 0) marking boxes that hold sources; `accumulate`
 // adds into phi instead of overwriting.  `alive` (device int or NULL):
-// when it holds 0 every kernel of the call returns at once.
+// when it holds 0 every kernel of the call returns at once.  With `perm`
+// (the tree's sorted -> caller permutation; depth >= 2, no flags) q and phi
+// are in caller order instead and `qs` (N x nrhs) receives the sorted charges.
 template <class T>
 void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
-                bool accumulate, hipStream_t st, const int* alive = nullptr, StageTimer* tm = nullptr);
+                bool accumulate, hipStream_t st, const int* alive = nullptr, StageTimer* tm = nullptr,
+                const int32_t* perm = nullptr, cplx<T>* qs = nullptr);
 
 // Per-level source flags for the points whose caller index lies in [lo, hi).
 void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipStream_t st);

@@ -55,22 +55,35 @@ template <class T> const cplx<T>* rel_of(const Tree& t);
 template <> const float2* rel_of<float>(const Tree& t) { return t.rel32.p; }
 template <> const double2* rel_of<double>(const Tree& t) { return t.rel64.p; }
 
-// Series S_n(y) = sum_j (-y)^j n! / (j! (n+j)!) by Horner, so that
-// J_n(x) = (x/2)^n / n! * S_n(x^2/4).
+__device__ __forceinline__ float rcpT(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcpT(double x) { return 1.0 / x; }
+
+// Bessel functions of order n at x through J_n(x) = (x/2)^n / n! S_n(x^2/4),
+// S_n(y) = sum_j (-y)^j n! / (j! (n+j)!) (DLMF 10.2.2), which has no
+// division by x:
+//   sseries: S_n(y) from its first K + 1 terms by Horner, with the term
+//            ratios -y / (j (n + j)) formed in registers (no table loads);
+//   sdown:   S_{n-1} = S_n - y S_{n+1} / (n (n + 1)), the three-term
+//            recurrence J_{n-1} + J_{n+1} = (2n/x) J_n in this scaling, run
+//            downward (the stable direction) from two series values.
 template <class T>
-__device__ __forceinline__ T jseries(const T* __restrict__ sr, int K, T y) {
+__device__ __forceinline__ T sseries(int n, int K, T y) {
   T S = T(1);
-  for (int j = K; j >= 1; --j) S = fmaT(-y * sr[j], S, T(1));
+  for (int j = K; j >= 1; --j) S = fmaT(-y * rcpT(T(j) * T(n + j)), S, T(1));
   return S;
+}
+template <class T>
+__device__ __forceinline__ T sdown(int n, T y, T Sn, T Sn1) {
+  return fmaT(-y * rcpT(T(n) * T(n + 1)), Sn1, Sn);
 }
 
 // ------------------------------------------------------------------ P2M
 template <class T, int NR>
 __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
                                             const cplx<T>* __restrict__ q, int64_t N, int nrhs, int r0,
-                                            cplx<T>* __restrict__ Mout, int pL, T wscale, T yscale,
-                                            const T* __restrict__ series, int K, const uint8_t* __restrict__ flags,
-                                            const int* __restrict__ alive) {
+                                            cplx<T>* __restrict__ Mout, int pL, T wscale, T yscale, int K,
+                                            const uint8_t* __restrict__ flags, const int* __restrict__ alive,
+                                            const int32_t* __restrict__ gperm, cplx<T>* __restrict__ qs_out) {
   extern __shared__ unsigned char smem_raw[];
   const int leaf = blockIdx.x;
   if (alive && !alive[0]) return;
@@ -90,18 +103,35 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
       const cplx<T> d = rel[c0 + lane];
       const T wr = wscale * d.x, wi = -wscale * d.y;  // w = (k / 2s) (dx - i dy)
       const T y = yscale * (d.x * d.x + d.y * d.y);   // (k rho)^2 / 4
+      // S_n downward into the lane's column, then times w^n / n! upward
+      T s1 = sseries(pL + 1, K, y), s0 = sseries(pL, K, y);
+      for (int m = pL; m >= 0; --m) {
+        sb[m * 64 + lane].x = s0;
+        if (m > 0) {
+          const T sm = sdown(m, y, s0, s1);
+          s1 = s0;
+          s0 = sm;
+        }
+      }
       T ur = T(1), ui = T(0);
       for (int m = 0; m <= pL; ++m) {
-        const T* sr = series + m * (K + 1);
-        const T S = jseries(sr, K, y);
+        const T S = sb[m * 64 + lane].x;
         sb[m * 64 + lane] = mk<T>(ur * S, ui * S);
-        const T inv = sr[0];
+        const T inv = rcpT(T(m + 1));
         const T nr = (ur * wr - ui * wi) * inv, ni = (ur * wi + ui * wr) * inv;
         ur = nr;
         ui = ni;
       }
+      // charges in Morton order; with gperm, q is in caller order and the
+      // sorted copy is written to qs_out for the near field
+      const int j = c0 + lane;
+      const int src = gperm ? gperm[j] : j;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) sq[r * 64 + lane] = q[(size_t)(r0 + r) * N + c0 + lane];
+      for (int r = 0; r < NR; ++r) {
+        const cplx<T> v = q[(size_t)(r0 + r) * N + src];
+        sq[r * 64 + lane] = v;
+        if (gperm) qs_out[(size_t)(r0 + r) * N + j] = v;
+      }
     }
     __syncthreads();
     // lane = (group g, order n): the G groups split the points of the chunk
@@ -547,84 +577,25 @@ __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
   }
 }
 
-// ------------------------------------------------------------------ L2P
-template <class T, int NR>
-__global__ __launch_bounds__(64) void k_l2p(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
-                                            const cplx<T>* __restrict__ Lc, cplx<T>* __restrict__ phi, int64_t N,
-                                            int nrhs, int r0, int pL, T wscale, T yscale,
-                                            const T* __restrict__ series, int K, int accumulate,
-                                            const int* __restrict__ alive) {
-  extern __shared__ unsigned char smem_raw[];
-  cplx<T>* sL = reinterpret_cast<cplx<T>*>(smem_raw);  // [NR][P]
-  const int leaf = blockIdx.x;
-  if (alive && !alive[0]) return;
-  const int t0 = leaf_off[leaf], t1 = leaf_off[leaf + 1];
-  if (t0 == t1) return;
-  const int P = 2 * pL + 1;
-  for (int i = threadIdx.x; i < NR * P; i += 64) {
-    const int r = i / P, n = i - r * P;
-    sL[i] = Lc[((size_t)leaf * nrhs + r0 + r) * P + n];
-  }
-  __syncthreads();
-  for (int i = t0 + (int)threadIdx.x; i < t1; i += 64) {
-    const cplx<T> d = rel[i];
-    const T wr = wscale * d.x, wi = wscale * d.y;  // (k / 2s)(dx + i dy)
-    const T y = yscale * (d.x * d.x + d.y * d.y);
-    cplx<T> acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = mk<T>(0, 0);
-    T ur = T(1), ui = T(0);
-    for (int n = 0; n <= pL; ++n) {
-      const T* sr = series + n * (K + 1);
-      const T S = jseries(sr, K, y);
-      const cplx<T> c = mk<T>(ur * S, ui * S);
-      const T sg = (n & 1) ? T(-1) : T(1);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        cmac(acc[r], sL[r * P + pL + n], c);
-        if (n > 0) {
-          const cplx<T> lm = sL[r * P + pL - n];
-          cmacc(acc[r], mk<T>(sg * lm.x, sg * lm.y), c);
-        }
-      }
-      const T inv = sr[0];
-      const T nr = (ur * wr - ui * wi) * inv, ni = (ur * wi + ui * wr) * inv;
-      ur = nr;
-      ui = ni;
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const size_t idx = (size_t)(r0 + r) * N + i;
-      cplx<T> v = mk<T>(T(-0.25) * acc[r].y, T(0.25) * acc[r].x);
-      if (accumulate) {
-        const cplx<T> o = phi[idx];
-        v.x += o.x;
-        v.y += o.y;
-      }
-      phi[idx] = v;
-    }
-  }
-}
-
 #include "near.h"
 
 // ------------------------------------------------------------------ misc
 template <class T>
 __global__ void k_gather(const cplx<T>* __restrict__ q, cplx<T>* __restrict__ qs, const int32_t* __restrict__ perm,
-                         int64_t N, int64_t total) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int64_t r = i / N, j = i - r * N;
-  qs[i] = q[r * N + perm[j]];
+                         int64_t N) {  // grid: (points, columns)
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const size_t col = (size_t)blockIdx.y * N;
+  qs[col + j] = q[col + perm[j]];
 }
 
 template <class T>
 __global__ void k_scatter(const cplx<T>* __restrict__ phis, cplx<T>* __restrict__ phi,
-                          const int32_t* __restrict__ perm, int64_t N, int64_t total) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int64_t r = i / N, j = i - r * N;
-  phi[r * N + perm[j]] = phis[i];
+                          const int32_t* __restrict__ perm, int64_t N) {  // grid: (points, columns)
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const size_t col = (size_t)blockIdx.y * N;
+  phi[col + perm[j]] = phis[col + j];
 }
 
 __global__ void k_leaf_flags(const int32_t* __restrict__ leaf_off, const int32_t* __restrict__ perm,
@@ -719,12 +690,6 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       term *= y / (double(K) * K);
     }
     pl->K = K;
-    std::vector<T> ser((size_t)(lf.p + 1) * (K + 1));
-    for (int n = 0; n <= lf.p; ++n) {
-      ser[(size_t)n * (K + 1)] = T(1.0 / (n + 1));
-      for (int j = 1; j <= K; ++j) ser[(size_t)n * (K + 1) + j] = T(1.0 / (double(j) * (n + j)));
-    }
-    pl->series.upload(ser);
 
     double maxabs = 0;
     auto put = [&](std::vector<cplx<T>>& v, size_t i, std::complex<double> z) {
@@ -940,8 +905,9 @@ void launch_p2p(const Tree& t, const FmmPlan<T>& pl, const P2PArgs<T>& a, int G,
 
 template <class T>
 P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
-                    const uint8_t* flags, bool accumulate, const int* alive) {
+                    const uint8_t* flags, bool accumulate, const int* alive, const int32_t* operm = nullptr) {
   P2PArgs<T> a{};
+  a.operm = operm;
   a.leaf_off = t.leaf_off.p;
   a.rel = rel_of<T>(t);
   a.q = q;
@@ -953,7 +919,7 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.r0 = r0;
   a.L = t.L;
   a.G = pl.G;
-  a.accumulate = (t.L >= 2 || accumulate) ? 1 : 0;
+  a.accumulate = accumulate ? 1 : 0;
   a.k = T(pl.k);
   a.kls = T(pl.k * t.leaf_side());
   const NearPoly& P = pl.poly;
@@ -965,6 +931,15 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.ub = T(P.ub);
   a.c1 = T(P.c1);
   a.jinv = T(1.0 / P.c1);
+  a.Lc = nullptr;
+  if (t.L >= 2) {  // the leaf level's local expansions are evaluated by the near-field kernel
+    const LevelInfo& lf = pl.lv[t.L];
+    a.Lc = pl.Lc.p + lf.coef * nrhs;
+    a.pL = lf.p;
+    a.K = pl.K;
+    a.wscale = T(pl.k / (2 * lf.s));
+    a.yscale = T(pl.k * pl.k / 4);
+  }
   return a;
 }
 
@@ -1018,7 +993,8 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
 
 template <class T, int NR>
 void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
-              const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm) {
+              const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm,
+              const int32_t* perm, cplx<T>* qs) {
   const int L = t.L;
   const int64_t N = t.n;
   const cplx<T>* rel = rel_of<T>(t);
@@ -1030,8 +1006,8 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
     const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
     k_p2m<T, NR><<<(int)t.nleaves, 64, sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, M + lf.coef * nrhs, lf.p,
-                                                 T(k / (2 * lf.s)), T(k * k / 4), pl.series.p, pl.K,
-                                                 flags ? flags + lf.box0 : nullptr, alive);
+                                                 T(k / (2 * lf.s)), T(k * k / 4), pl.K,
+                                                 flags ? flags + lf.box0 : nullptr, alive, perm, qs);
     HFMM_LAUNCH_CHECK();
     if (pl.use_mfma) {
       // upward: M2M on MFMA, levels L-1 .. 2
@@ -1099,14 +1075,11 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
         HFMM_LAUNCH_CHECK();
       }
     }
+    // L2P runs inside the near-field kernel (its stage time is that kernel's)
     if (tm) tm->mark(2, st);
-    k_l2p<T, NR><<<(int)t.nleaves, 64, (size_t)NR * lf.P * sizeof(cplx<T>), st>>>(
-        t.leaf_off.p, rel, Lc + lf.coef * nrhs, phi, N, nrhs, r0, lf.p, T(k / (2 * lf.s)), T(k * k / 4),
-        pl.series.p, pl.K, accumulate ? 1 : 0, alive);
-    HFMM_LAUNCH_CHECK();
     if (tm) tm->mark(3, st);
   }
-  const P2PArgs<T> a = p2p_args<T>(t, pl, q, phi, nrhs, r0, flags, accumulate, alive);
+  const P2PArgs<T> a = p2p_args<T>(t, pl, perm ? qs : q, phi, nrhs, r0, flags, accumulate, alive, perm);
   launch_p2p<T, NR>(t, pl, a, pl.G, st);
   HFMM_LAUNCH_CHECK();
   if (tm) tm->mark(4, st);
@@ -1201,18 +1174,20 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p) {
 
 template <class T>
 void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
-                bool accumulate, hipStream_t st, const int* alive, StageTimer* tm) {
+                bool accumulate, hipStream_t st, const int* alive, StageTimer* tm, const int32_t* perm,
+                cplx<T>* qs) {
+  HFMM_REQUIRE(!perm || (t.L >= 2 && qs && !flags), "fmm: internal: permuted I/O needs a tree of depth >= 2");
   pl.ensure_work(nrhs);
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     if (left >= 4) {
-      run_cols<T, 4>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm);
+      run_cols<T, 4>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs);
       r0 += 4;
     } else if (left >= 2) {
-      run_cols<T, 2>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm);
+      run_cols<T, 2>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs);
       r0 += 2;
     } else {
-      run_cols<T, 1>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm);
+      run_cols<T, 1>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs);
       r0 += 1;
     }
   }
@@ -1245,21 +1220,28 @@ void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrh
   pl.qs.ensure(total);
   pl.phis.ensure(total);
   if (tm) tm->mark(-1, st);
-  k_gather<T><<<blocks_for(total), 256, 0, st>>>(q, pl.qs.p, t.perm.p, t.n, total);
-  HFMM_LAUNCH_CHECK();
-  if (tm) tm->mark(0, st);
-  fmm_sorted<T>(t, pl, pl.qs.p, pl.phis.p, nrhs, nullptr, false, st, nullptr, tm);
-  k_scatter<T><<<blocks_for(total), 256, 0, st>>>(pl.phis.p, phi, t.perm.p, t.n, total);
-  HFMM_LAUNCH_CHECK();
+  if (t.L >= 2) {
+    // the P2M kernel gathers the charges into Morton order and the near-field
+    // kernel writes the potentials back in caller order
+    if (tm) tm->mark(0, st);
+    fmm_sorted<T>(t, pl, q, phi, nrhs, nullptr, false, st, nullptr, tm, t.perm.p, pl.qs.p);
+  } else {
+    k_gather<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(q, pl.qs.p, t.perm.p, t.n);
+    HFMM_LAUNCH_CHECK();
+    if (tm) tm->mark(0, st);
+    fmm_sorted<T>(t, pl, pl.qs.p, pl.phis.p, nrhs, nullptr, false, st, nullptr, tm);
+    k_scatter<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(pl.phis.p, phi, t.perm.p, t.n);
+    HFMM_LAUNCH_CHECK();
+  }
   if (tm) tm->mark(5, st);
 }
 
 template FmmPlan<float>& get_plan<float>(Tree&, double, int);
 template FmmPlan<double>& get_plan<double>(Tree&, double, int);
 template void fmm_sorted<float>(const Tree&, FmmPlan<float>&, const float2*, float2*, int, const uint8_t*, bool,
-                                hipStream_t, const int*, StageTimer*);
+                                hipStream_t, const int*, StageTimer*, const int32_t*, float2*);
 template void fmm_sorted<double>(const Tree&, FmmPlan<double>&, const double2*, double2*, int, const uint8_t*, bool,
-                                 hipStream_t, const int*, StageTimer*);
+                                 hipStream_t, const int*, StageTimer*, const int32_t*, double2*);
 template void fmm_apply<float>(Tree&, double, int, const float2*, float2*, int, hipStream_t, StageTimer*);
 template void fmm_apply<double>(Tree&, double, int, const double2*, double2*, int, hipStream_t, StageTimer*);
 

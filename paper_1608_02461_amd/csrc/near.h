@@ -13,13 +13,77 @@ struct P2PArgs {
   cplx<T>* phi;
   const uint8_t* flags;  // leaf-level source flags or NULL
   const int* alive;      // device flag: 0 skips the launch's work, or NULL
+  const int32_t* operm;  // NULL: phi in Morton order; else phi[operm[i]] (caller order)
   int64_t N;
   int nrhs, r0, L, G, accumulate;
   T k, kls;  // k and k * leaf side
   T cJ[32], cY[32];
   T ua, ub;  // centred polynomial variable u = ua t + ub
   T c1, jinv;  // J0 is carried as Jc = c1 J0; jinv = 1 / c1
+  // far field (L2P) of the target leaves, or Lc = NULL for none: local
+  // expansions [leaf][nrhs][2 pL + 1] of the leaf level, the Bessel series
+  // length and the scales (as in P2M)
+  const cplx<T>* Lc;
+  int pL, K;
+  T wscale, yscale;
 };
+
+// L2P at one target, d = position relative to its leaf centre: the local
+// expansion sum_m L_m J_m(k rho) e^{i m theta} of the leaf (Sec. 5.1.2), for
+// every column.  With w = (k/2)(dx + i dy) (in the level's scaling) and
+// J_m e^{i m theta} = w^m / m! S_m, the positive orders are a Horner sum in
+// w and the negative ones, J_{-m} e^{-i m theta} = (-1)^m conj(w)^m / m! S_m,
+// one in conj(w); S_m runs downward alongside (sseries, sdown).
+template <class T, int NR>
+__device__ __forceinline__ void far_field(const P2PArgs<T>& a, uint32_t leaf, cplx<T> d, cplx<T> (&F)[NR]) {
+  const int pL = a.pL, P = 2 * pL + 1;
+  const cplx<T>* Lf = a.Lc + ((size_t)leaf * a.nrhs + a.r0) * P + pL;  // Lf[r P + m], m in [-pL, pL]
+  const T wr = a.wscale * d.x, wi = a.wscale * d.y;
+  const T y = a.yscale * (d.x * d.x + d.y * d.y);
+  T s1 = sseries(pL + 1, a.K, y), s0 = sseries(pL, a.K, y);
+  cplx<T> A[NR], B[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) A[r] = B[r] = mk<T>(0, 0);
+  cplx<T> lp[NR], lm[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    lp[r] = Lf[r * P + pL];
+    lm[r] = Lf[r * P - pL];
+  }
+  for (int n = pL; n >= 0; --n) {
+    // s0 = S_n, s1 = S_{n+1}; lp, lm = L_n, L_{-n}; the next pair loads ahead
+    cplx<T> lpn[NR], lmn[NR];
+    const int n1 = n > 0 ? n - 1 : 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      lpn[r] = Lf[r * P + n1];
+      lmn[r] = Lf[r * P - n1];
+    }
+    const T inv = rcpT(T(n + 1));
+    const T sgs = (n & 1) ? -s0 : s0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      // A <- S_n L_n + (w / (n+1)) A;  B <- (-1)^n S_n L_{-n} + (conj(w) / (n+1)) B  (n >= 1)
+      const T ar = (A[r].x * wr - A[r].y * wi) * inv, ai = (A[r].x * wi + A[r].y * wr) * inv;
+      A[r] = mk<T>(fmaT(s0, lp[r].x, ar), fmaT(s0, lp[r].y, ai));
+      if (n > 0) {
+        const T br = (B[r].x * wr + B[r].y * wi) * inv, bi = (B[r].y * wr - B[r].x * wi) * inv;
+        B[r] = mk<T>(fmaT(sgs, lm[r].x, br), fmaT(sgs, lm[r].y, bi));
+      }
+      lp[r] = lpn[r];
+      lm[r] = lmn[r];
+    }
+    if (n > 0) {
+      const T sm = sdown(n, y, s0, s1);
+      s1 = s0;
+      s0 = sm;
+    }
+  }
+  // F = A_0 + conj(w) B_1
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    F[r] = mk<T>(A[r].x + wr * B[r].x + wi * B[r].y, A[r].y + wr * B[r].y - wi * B[r].x);
+}
 
 // Running sums of q (J0 + i Y0) over one target's sources, J0 carried as
 // Jc = c1 J0:  Re = sum (qx J0 - qy Y0) = jinv aj - ay,
@@ -48,6 +112,11 @@ struct PairSum {
         bj[r] += __shfl_xor(bj[r], off);
       }
     }
+  }
+  // add F to the sum (counted once over the G lanes: lane g = 0 only)
+  __device__ __forceinline__ void add_far(int r, cplx<T> F) {
+    ay[r] -= F.x;
+    by[r] += F.y;
   }
   // (i/4) times the sum: (i/4)(Re + i Im) = (-Im/4, Re/4)
   __device__ __forceinline__ cplx<T> phi(int r, T jinv) const {
@@ -189,7 +258,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
     if (g == 0 && act) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
+        const size_t idx = (size_t)(a.r0 + r) * a.N + (a.operm ? a.operm[ti] : ti);
         cplx<T> v = acc.phi(r, a.jinv);
         if (a.accumulate) {
           const cplx<T> o = a.phi[idx];
@@ -217,7 +286,9 @@ __device__ __forceinline__ int xcd_swizzle(int b, int n) {
 // scaled by k.  In row-major leaf order each wave's sources are 3 contiguous
 // runs (one per row) and the own leaf splits the middle run: 4 unmasked
 // segments plus one masked.  G lanes share a target (template), each taking
-// every G-th source; a shuffle tree sums the G partial sums.
+// every G-th source; a shuffle tree sums the G partial sums.  With a.Lc set
+// the kernel also evaluates the target leaves' local expansions (L2P) and
+// writes far + near field.
 template <class T, int NR>
 struct P2P4Cfg {
   static constexpr int kBytes = 2 * (int)sizeof(T) * (1 + NR);
@@ -276,7 +347,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
   }
   __syncthreads();
   const int total = s_pre[16];
-  if (total == 0 && a.accumulate) return;
+  if (total == 0 && a.accumulate && !a.Lc) return;
   // this wave's target leaf (child position w of the parent) and its segments
   const int cx = w & 1, cy = w >> 1;
   const uint32_t tleaf = 4u * (uint32_t)parent + (uint32_t)w;
@@ -305,7 +376,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
     if (g == 0 && act) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const size_t idx = (size_t)(a.r0 + r) * a.N + ti;
+        const size_t idx = (size_t)(a.r0 + r) * a.N + (a.operm ? a.operm[ti] : ti);
         cplx<T> v = acc.phi(r, a.jinv);
         if (a.accumulate) {
           const cplx<T> o = a.phi[idx];
@@ -316,10 +387,30 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       }
     }
   };
+  // far field: lane l evaluates target (batch start + l) once per 64
+  // targets; each round picks its targets' values with a shuffle
+  cplx<T> far[NR];
+  auto far_batch = [&](int rb) {
+    if (((rb - t0) & 63) != 0 || !a.Lc) return;
+    const int tf = rb + lane;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) far[r] = mk<T>(0, 0);
+    if (tf < t1) far_field<T, NR>(a, tleaf, a.rel[tf], far);
+  };
+  auto add_far = [&](int ti, PairSum<T, NR>& acc) {
+    if (!a.Lc) return;
+    const int src = (ti - t0) & 63;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const cplx<T> f = mk<T>(__shfl(far[r].x, src), __shfl(far[r].y, src));
+      if (g == 0) acc.add_far(r, f);
+    }
+  };
   if (total <= SCAP) {
     stage(0, total);
     __syncthreads();
     for (int rb = t0; rb < t1; rb += TPR) {
+      far_batch(rb);
       const int ti = rb + tl;
       const bool act = ti < t1;
       T xt = 0, yt = 0;
@@ -330,6 +421,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       }
       PairSum<T, NR> acc;
       acc.zero();
+      add_far(ti, acc);
 #pragma unroll
       for (int sgi = 0; sgi < 4; ++sgi)
         p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, acc);
@@ -342,6 +434,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
     __syncthreads();
     const int R = max(max(s_rounds[0], s_rounds[1]), max(s_rounds[2], s_rounds[3]));
     for (int round = 0; round < R; ++round) {
+      far_batch(t0 + round * TPR);
       const int ti = t0 + round * TPR + tl;
       const bool act = ti < t1;
       T xt = 0, yt = 0;
@@ -352,6 +445,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       }
       PairSum<T, NR> acc;
       acc.zero();
+      add_far(ti, acc);
       for (int c0 = 0; c0 < total; c0 += SCAP) {
         const int cnt = min(SCAP, total - c0);
         __syncthreads();
