@@ -302,7 +302,7 @@ struct M2LLevel {
   cplx<T>* Lc;
   const T* Af;          // [49][RT][KS][64]
   const uint8_t* fsrc;  // source flags of the level or NULL
-  int nb, P, RT, KS, KPs, tile, gx, block0;
+  int nb, P, RT, KS, KSL, tile, gx, block0;  // KSL: k steps per LDS slice (a multiple of 4)
 };
 
 template <class T>
@@ -323,9 +323,11 @@ struct M2LAllArgs {
 // padded with zeros to whole chunks of 4.  Each of the 8 waves owns all
 // patches of the block (one accumulator each, so one A fragment feeds up to 4
 // MFMAs) and the offset classes whose index = wave (mod 8); the eight partial
-// sums meet in LDS.  KPs = 2 m with m odd: the 16 columns of a patch
-// times 2 rows then fall in distinct LDS banks (32 of 4 bytes) when the
-// window is 12 boxes wide.
+// sums meet in LDS.  A level whose window does not fit is staged in slices
+// of KSL k steps (the products of each slice accumulate).  The LDS stride of
+// a box, 4 KSL + 2 = 2 m with m odd, puts the 16 columns of a patch times 2
+// rows in distinct LDS banks (32 of 4 bytes) when the window is 12 boxes
+// wide.
 template <class T, int NP>
 __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int lblock, T* Ms) {
   typedef typename Acc4<T>::type V4;
@@ -338,7 +340,8 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
   const int wx0 = max(0, bx0 - 2), wy0 = max(0, by0 - 2);
   const int WW = min(a.nb, bx0 + a.tile + 2) - wx0, WH = min(a.nb, by0 + a.tile + 2) - wy0;
   const int zb = WW * WH;  // the zero box
-  const int KPs = a.KPs, P = a.P, KS = a.KS;
+  const int P = a.P, KS = a.KS, KSL = a.KSL;
+  const int KPs = 4 * KSL + 2;  // LDS stride of one box's slice
   constexpr int pside = NP == 4 ? 2 : 1;
   const int j = lane & 15, kq = lane >> 4;
   int tx[NP], ty[NP];
@@ -349,76 +352,136 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
     ty[p] = by0 + (p / pside) * 4 + (j >> 2);
     tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
   }
-  const int nch = KS >> 2;  // KS is a multiple of 4
   const size_t cstride = (size_t)a.RT * KS * 64;
   const T* Abase = a.Af + (size_t)rt * KS * 64 + lane;
+  // LDS position of the source box of class o for patch p (the zero box when
+  // it is outside the grid or not adjacent to the target's parent)
+  auto src_base = [&](int o, int p) {
+    const int ox = o / 7 - 3, oy = o % 7 - 3;
+    const int sx = tx[p] + ox, sy = ty[p] + oy;
+    const bool v = sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb && abs((sx >> 1) - (tx[p] >> 1)) <= 1 &&
+                   abs((sy >> 1) - (ty[p] >> 1)) <= 1;
+    return (v ? (sx - wx0) + (sy - wy0) * WW : zb) * KPs + kq;
+  };
   for (int r = 0; r < args.nr; ++r) {
-    __syncthreads();
-    // stage the window: wave w takes boxes w, w + 8, ... of the window in
-    // row order, lanes run along the box's column; wave 0 also clears the
-    // zero box
-    for (int y = 0; y < WH; ++y)
-      for (int x = (w + y * 3) & 7; x < WW; x += 8) {
-        const uint32_t gb = morton((uint32_t)(wx0 + x), (uint32_t)(wy0 + y));
-        const bool on = !a.fsrc || a.fsrc[gb];
-        const cplx<T>* src = a.M + ((size_t)gb * args.nrhs + args.r0 + r) * P;
-        T* dst = Ms + (y * WW + x) * KPs;
-        for (int n = lane; n < KPs; n += 64) {
-          T v = T(0);
-          if (on && n < 2 * P) {
-            const cplx<T> c = src[n < P ? n : n - P];
-            v = n < P ? c.x : c.y;
-          }
-          dst[n] = v;
-        }
-      }
-    if (w == 0)
-      for (int n = lane; n < KPs; n += 64) Ms[zb * KPs + n] = T(0);
-    __syncthreads();
     V4 acc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = V4{0, 0, 0, 0};
-    // this wave's 5 offset classes (class index = wave mod 8); the A
-    // fragments of the next chunk, also across classes, load one chunk ahead
-    T an[4];
-    {
-      const T* A0 = Abase + (size_t)kClassO[w] * cstride;
+    for (int k0 = 0; k0 < KS; k0 += KSL) {
+      const int nch = min(KSL, KS - k0) >> 2;  // whole chunks of 4 k steps
+      __syncthreads();
+      // stage the slice [4 k0, 4 k0 + 4 KSL) of the real columns of the
+      // window: a flat (box, element) index over the block, with the loads
+      // of 4 elements issued before their LDS stores
+      {
+        const int nel = zb * KPs;
+        const uint32_t mK = 0xffffffffu / (uint32_t)KPs + 1u, mW = 0xffffffffu / (uint32_t)WW + 1u;
+        for (int i0 = tid; i0 < nel; i0 += 4 * 512) {
+          T v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
-    }
-    for (int oi = 0; oi < 5; ++oi) {
-      const int o = kClassO[8 * oi + w];
-      const int ox = o / 7 - 3, oy = o % 7 - 3;
-      int base[NP];
+          for (int u = 0; u < 4; ++u) {
+            const int idx = i0 + u * 512;
+            v[u] = T(0);
+            const int box = (int)__umulhi((uint32_t)idx, mK);
+            const int n = idx - box * KPs, nn = 4 * k0 + n;
+            if (idx < nel && n < 4 * KSL && nn < 2 * P) {
+              const int by = (int)__umulhi((uint32_t)box, mW), bx = box - by * WW;
+              const uint32_t gb = morton((uint32_t)(wx0 + bx), (uint32_t)(wy0 + by));
+              const T* src = reinterpret_cast<const T*>(a.M + ((size_t)gb * args.nrhs + args.r0 + r) * P);
+              const T x = src[nn < P ? 2 * nn : 2 * (nn - P) + 1];
+              v[u] = (!a.fsrc || a.fsrc[gb]) ? x : T(0);
+            }
+          }
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int sx = tx[p] + ox, sy = ty[p] + oy;
-        const bool v = sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb && abs((sx >> 1) - (tx[p] >> 1)) <= 1 &&
-                       abs((sy >> 1) - (ty[p] >> 1)) <= 1;
-        base[p] = (v ? (sx - wx0) + (sy - wy0) * WW : zb) * KPs + kq;
-      }
-      const T* A = Abase + (size_t)o * cstride;
-      const T* An = oi + 1 < 5 ? Abase + (size_t)kClassO[8 * (oi + 1) + w] * cstride : A;
-      for (int c = 0; c < nch; ++c) {
-        T av[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) av[u] = an[u];
-        if (c + 1 < nch) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
-        } else if (oi + 1 < 5) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
+          for (int u = 0; u < 4; ++u)
+            if (i0 + u * 512 < nel) Ms[i0 + u * 512] = v[u];
         }
-        T bv[NP][4];
+      }
+      if (w == 0)
+        for (int n = lane; n < KPs; n += 64) Ms[zb * KPs + n] = T(0);
+      __syncthreads();
+      const T* Ab = Abase + (size_t)k0 * 64;  // this slice's k steps
+      // this wave's 5 offset classes (class index = wave mod 8)
+      if constexpr (NP == 1) {
+        // one patch: the 5 classes run side by side (5 accumulators, 20
+        // independent MFMAs per chunk, the next chunk's A loaded ahead) and
+        // are summed at the end
+        int b5[5];
+        const T* A5[5];
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int oi = 0; oi < 5; ++oi) {
+          const int o = kClassO[8 * oi + w];
+          b5[oi] = src_base(o, 0);
+          A5[oi] = Ab + (size_t)o * cstride;
+        }
+        V4 acc5[5];
+        T an[5][4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];
+        for (int oi = 0; oi < 5; ++oi) {
+          acc5[oi] = V4{0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 4; ++u) an[oi][u] = A5[oi][u * 64];
+        }
+        for (int c = 0; c < nch; ++c) {
+          T av[5][4], bv[5][4];
 #pragma unroll
-          for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
+          for (int oi = 0; oi < 5; ++oi)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              av[oi][u] = an[oi][u];
+              bv[oi][u] = Ms[b5[oi] + (c * 4 + u) * 4];
+            }
+          if (c + 1 < nch) {
+#pragma unroll
+            for (int oi = 0; oi < 5; ++oi)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) an[oi][u] = A5[oi][(c * 4 + 4 + u) * 64];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int oi = 0; oi < 5; ++oi) acc5[oi] = mfma16(av[oi][u], bv[oi][u], acc5[oi]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[0][q] += acc5[0][q] + acc5[1][q] + acc5[2][q] + acc5[3][q] + acc5[4][q];
+      } else {
+        // the A fragments of the next chunk, also across classes, load one
+        // chunk ahead
+        T an[4];
+        {
+          const T* A0 = Ab + (size_t)kClassO[w] * cstride;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
+        }
+        for (int oi = 0; oi < 5; ++oi) {
+          const int o = kClassO[8 * oi + w];
+          int base[NP];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
+          const T* A = Ab + (size_t)o * cstride;
+          const T* An = oi + 1 < 5 ? Ab + (size_t)kClassO[8 * (oi + 1) + w] * cstride : A;
+          for (int c = 0; c < nch; ++c) {
+            T av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = an[u];
+            if (c + 1 < nch) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
+            } else if (oi + 1 < 5) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
+            }
+            T bv[NP][4];
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
+          }
+        }
       }
     }
     // sum the 8 waves' partial products: waves 4..7 into 0..3, then 0..3
@@ -499,6 +562,8 @@ struct TTArgs {
 };
 
 constexpr int kTTChunk = 16;
+// LDS budget of one M2L block (the launch takes the largest over its levels)
+constexpr size_t kM2LLds = 40 * 1024;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
@@ -789,21 +854,30 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       const int P = pl->lv[l].P, nb = 1 << l;
       m.RT = (2 * P + 15) / 16;
       m.KS = 4 * ((2 * P + 15) / 16);  // whole chunks of 4 k steps; the padding is zero
-      m.KPs = 4 * m.KS + 2;            // 2 x odd (see k_m2l_mfma)
-      // M2L window: a tile of 8 x 8 targets when it fits in 64 KB of LDS, else
-      // 4 x 4; the window plus one zero box, or the partial sums of 4 waves
-      auto lds_for = [&](int tile) {
+      // M2L window: a tile of 8 x 8 targets (4 x 4 on a 4 x 4 grid, or by
+      // the autotuner), the window plus one zero box (or the partial sums of
+      // 4 waves) in at most kM2LLds bytes of LDS; when the whole k range does
+      // not fit, the kernel stages it in slices of KSL k steps
+      auto lds_for = [&](int tile, int ksl) {
         const int win = std::min(nb, std::min(tile, nb) + 4);
         const int np = tile >= 8 && nb >= 8 ? 4 : 1;
-        return std::max((size_t)(win * win + 1) * m.KPs, (size_t)4 * np * 4 * 64) * sizeof(T);
+        return std::max((size_t)(win * win + 1) * (4 * ksl + 2), (size_t)4 * np * 4 * 64) * sizeof(T);
       };
-      m.lds4 = lds_for(4);
-      m.fit4 = m.lds4 <= 65536;
+      auto slice = [&](int tile) {
+        int ksl = m.KS;
+        while (ksl > 4 && lds_for(tile, ksl) > kM2LLds) ksl = std::max(4, (ksl / 2 + 3) / 4 * 4);
+        return ksl;
+      };
       m.tile = std::min(8, nb);
-      m.lds = lds_for(8);
+      m.KSL = slice(m.tile);
+      m.lds = lds_for(m.tile, m.KSL);
+      m.KSL4 = slice(4);
+      m.lds4 = lds_for(4, m.KSL4);
       m.on = m.lds <= 65536;
+      m.fit4 = m.lds4 <= 65536;
       if (!m.on && m.fit4) {
         m.tile = 4;
+        m.KSL = m.KSL4;
         m.lds = m.lds4;
         m.on = true;
       }
@@ -978,7 +1052,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
     v.P = li.P;
     v.RT = mf.RT;
     v.KS = mf.KS;
-    v.KPs = mf.KPs;
+    v.KSL = small ? mf.KSL4 : mf.KSL;
     v.tile = tile;
     v.gx = ((1 << l) / tile) * ((1 << l) / tile);
     v.block0 = blocks;
