@@ -733,9 +733,11 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   // near field: pair arguments k r are bounded by the 3 x 3 leaf block
   const double lside = t.leaf_side();
   const double X = (L == 0) ? k * std::sqrt(2.0) * t.side : k * 2.0 * std::sqrt(2.0) * lside;
-  static const int candF[] = {6, 8, 10, 12, 16};
-  static const int candD[] = {12, 16, 20, 24, 28};
-  pl->near_fast = fit_near_poly(X * X * (1 + 1e-9), F32, F32 ? candF : candD, 5, F32 ? 5e-7 : 2e-13, pl->poly);
+  // FP32: 1e-6 absolute on J0 and Yf, below the rounding of a complex64 sum
+  // over the few hundred pairs of a leaf neighbourhood
+  static const int candF[] = {5, 7, 9, 12, 16};
+  static const int candD[] = {8, 10, 12, 16, 24};  // (both lists match the launch_p2p switches)
+  pl->near_fast = fit_near_poly(X * X * (1 + 1e-9), F32, F32 ? candF : candD, 5, F32 ? 1e-6 : 2e-13, pl->poly);
   const double mean = double(t.n) / double(t.nleaves);
   pl->G = mean >= 40 ? 1 : (mean >= 20 ? 2 : 4);
 
@@ -938,19 +940,19 @@ void launch_p2p(const Tree& t, const FmmPlan<T>& pl, const P2PArgs<T>& a, int G,
       k_p2p<T, NR, 1, false><<<grid, 64, 0, st>>>(a);
     } else if constexpr (std::is_same<T, float>::value) {
       switch (deg) {
-        case 6: k_p2p<T, NR, 6, true><<<grid, 64, 0, st>>>(a); break;
-        case 8: k_p2p<T, NR, 8, true><<<grid, 64, 0, st>>>(a); break;
-        case 10: k_p2p<T, NR, 10, true><<<grid, 64, 0, st>>>(a); break;
+        case 5: k_p2p<T, NR, 5, true><<<grid, 64, 0, st>>>(a); break;
+        case 7: k_p2p<T, NR, 7, true><<<grid, 64, 0, st>>>(a); break;
+        case 9: k_p2p<T, NR, 9, true><<<grid, 64, 0, st>>>(a); break;
         case 12: k_p2p<T, NR, 12, true><<<grid, 64, 0, st>>>(a); break;
         default: k_p2p<T, NR, 16, true><<<grid, 64, 0, st>>>(a); break;
       }
     } else {
       switch (deg) {
+        case 8: k_p2p<T, NR, 8, true><<<grid, 64, 0, st>>>(a); break;
+        case 10: k_p2p<T, NR, 10, true><<<grid, 64, 0, st>>>(a); break;
         case 12: k_p2p<T, NR, 12, true><<<grid, 64, 0, st>>>(a); break;
         case 16: k_p2p<T, NR, 16, true><<<grid, 64, 0, st>>>(a); break;
-        case 20: k_p2p<T, NR, 20, true><<<grid, 64, 0, st>>>(a); break;
-        case 24: k_p2p<T, NR, 24, true><<<grid, 64, 0, st>>>(a); break;
-        default: k_p2p<T, NR, 28, true><<<grid, 64, 0, st>>>(a); break;
+        default: k_p2p<T, NR, 24, true><<<grid, 64, 0, st>>>(a); break;
       }
     }
     return;
@@ -960,19 +962,19 @@ void launch_p2p(const Tree& t, const FmmPlan<T>& pl, const P2PArgs<T>& a, int G,
     launch_p2p4<T, NR, 1, false>(G, grid, a, st);
   } else if constexpr (std::is_same<T, float>::value) {
     switch (deg) {
-      case 6: launch_p2p4<T, NR, 6, true>(G, grid, a, st); break;
-      case 8: launch_p2p4<T, NR, 8, true>(G, grid, a, st); break;
-      case 10: launch_p2p4<T, NR, 10, true>(G, grid, a, st); break;
+      case 5: launch_p2p4<T, NR, 5, true>(G, grid, a, st); break;
+      case 7: launch_p2p4<T, NR, 7, true>(G, grid, a, st); break;
+      case 9: launch_p2p4<T, NR, 9, true>(G, grid, a, st); break;
       case 12: launch_p2p4<T, NR, 12, true>(G, grid, a, st); break;
       default: launch_p2p4<T, NR, 16, true>(G, grid, a, st); break;
     }
   } else {
     switch (deg) {
+      case 8: launch_p2p4<T, NR, 8, true>(G, grid, a, st); break;
+      case 10: launch_p2p4<T, NR, 10, true>(G, grid, a, st); break;
       case 12: launch_p2p4<T, NR, 12, true>(G, grid, a, st); break;
       case 16: launch_p2p4<T, NR, 16, true>(G, grid, a, st); break;
-      case 20: launch_p2p4<T, NR, 20, true>(G, grid, a, st); break;
-      case 24: launch_p2p4<T, NR, 24, true>(G, grid, a, st); break;
-      default: launch_p2p4<T, NR, 28, true>(G, grid, a, st); break;
+      default: launch_p2p4<T, NR, 24, true>(G, grid, a, st); break;
     }
   }
 }
