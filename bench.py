@@ -68,14 +68,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def p2p_flops_per_pair(deg, nrhs=1):
-    """FP32/FP64 fast-path P2P flops per pair, counted from the kernel source
-    (FMA = 2): dx, dy (2); t = fma(dx, dx, dy*dy) (3); u = fma (2); two
-    Horner chains of deg-1 FMAs (4 (deg-1)); Y = fma(Jc, log2 t, Yf) (2); 4
-    FMAs per right-hand side into the accumulators (8 nrhs).  The log2 per
-    pair is a transcendental and is not counted, nor is the L2P that the
-    same kernel evaluates once per target (under 2% of its flops here)."""
-    return 2 + 3 + 2 + 4 * (deg - 1) + 2 + 8 * nrhs
+def p2p_flops_per_pair(deg, nrhs=1, plain_below=9):
+    """FP32 fast-path P2P flops per pair, counted from the kernel source
+    (FMA = 2): dx, dy (2); t = fma(dx, dx, dy*dy) (3); the centred variable
+    u = fma(t, ua, ub) (2), only for coefficient counts of 9 and more (the
+    lower ones are polynomials in t itself); two Horner chains of deg-1 FMAs
+    (4 (deg-1)); Y = fma(Jc, log2 t, Yf) (2); 4 FMAs per right-hand side into
+    the accumulators (8 nrhs).  The log2 per pair is a transcendental and is
+    not counted, nor is the L2P that the same kernel evaluates once per
+    target (under 2% of its flops here)."""
+    return 2 + 3 + (0 if deg < plain_below else 2) + 4 * (deg - 1) + 2 + 8 * nrhs
 
 
 def m2l_flops(orders, L, nrhs=1):

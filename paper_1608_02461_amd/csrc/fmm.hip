@@ -737,7 +737,8 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   // over the few hundred pairs of a leaf neighbourhood
   static const int candF[] = {5, 7, 9, 12, 16};
   static const int candD[] = {8, 10, 12, 16, 24};  // (both lists match the launch_p2p switches)
-  pl->near_fast = fit_near_poly(X * X * (1 + 1e-9), F32, F32 ? candF : candD, 5, F32 ? 1e-6 : 2e-13, pl->poly);
+  // the first two candidates of each are polynomials in t itself (kPlainDeg)
+  pl->near_fast = fit_near_poly(X * X * (1 + 1e-9), F32, F32 ? candF : candD, 5, 2, F32 ? 1e-6 : 2e-13, pl->poly);
   const double mean = double(t.n) / double(t.nleaves);
   pl->G = mean >= 40 ? 1 : (mean >= 20 ? 2 : 4);
 

@@ -130,6 +130,12 @@ struct P2PCfg {
   static constexpr int SCH = (2 * sizeof(T) * (1 + NR) * 512 <= 16384) ? 512 : 256;
 };
 
+// Coefficient counts below this are fitted as polynomials in t itself (the
+// first two candidates of each precision's list).
+template <class T> struct kPlainDeg;
+template <> struct kPlainDeg<float> { static constexpr int below = 9; };
+template <> struct kPlainDeg<double> { static constexpr int below = 12; };
+
 // One pair: t = (k r)^2; returns Jc = c1 J0(sqrt t) and Y = Y0(sqrt t).
 // FAST uses the fitted polynomials (D coefficients each), otherwise the
 // full-range FP64 routine.  MASK zeroes the pair at t = 0 (a point with
@@ -142,7 +148,8 @@ __device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y) {
     t = valid ? t : T(1);
   }
   if constexpr (FAST) {
-    const T u = fmaT(t, a.ua, a.ub);
+    // the low degrees are polynomials in t itself, the others in u = ua t + ub
+    const T u = D < kPlainDeg<T>::below ? t : fmaT(t, a.ua, a.ub);
     T j = a.cJ[D - 1], yh = a.cY[D - 1];
 #pragma unroll
     for (int i = D - 2; i >= 0; --i) {

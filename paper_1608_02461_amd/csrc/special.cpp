@@ -81,7 +81,7 @@ void cheb_to_mono(const std::vector<double>& fvals, int n, double* mono) {
 
 }  // namespace
 
-bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, double tol, NearPoly& out) {
+bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, int nplain, double tol, NearPoly& out) {
   if (!(tmax > 0) || tmax > 144.0) return false;
   const int nsamp = 4001;
   std::vector<long double> tJ(nsamp), tY(nsamp);
@@ -103,6 +103,26 @@ bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, double to
     cheb_to_mono(fY, n, mY);
     P.ua = 2.0 / tmax;
     P.ub = -1.0;
+    if (ci < nplain) {
+      // in t itself: expand sum_k m_k (ua t + ub)^k (exact binomial sums in long double)
+      long double a[32] = {0}, b[32] = {0};
+      for (int k = 0; k < n; ++k) {
+        long double binom = 1, ap = 1;  // C(k, j) ua^j for j = 0 .. k
+        for (int j = 0; j <= k; ++j) {
+          const long double bp = std::pow((long double)P.ub, (long double)(k - j));
+          a[j] += (long double)mJ[k] * binom * ap * bp;
+          b[j] += (long double)mY[k] * binom * ap * bp;
+          binom = binom * (k - j) / (j + 1);
+          ap *= (long double)P.ua;
+        }
+      }
+      for (int j = 0; j < n; ++j) {
+        mJ[j] = (double)a[j];
+        mY[j] = (double)b[j];
+      }
+      P.ua = 1.0;
+      P.ub = 0.0;
+    }
     for (int i = 0; i < n; ++i) {
       P.cJ[i] = P.c1 * mJ[i];
       P.cY[i] = mY[i] + P.c0 * mJ[i];

@@ -94,7 +94,7 @@ void hankel_seq(int nmax, double x, std::vector<std::complex<double>>& H);
 //   J0(sqrt t) ~ sum cJ[i] u^i,  Yhat(sqrt t) ~ sum cY[i] u^i,  u = t*ua + ub,
 //   Y0 = J0 (c1 log2 t + c0) + Yhat.
 // Near-field H0 on t = (k r)^2 in [0, tmax], in the form the pair kernels
-// evaluate with u = ua t + ub:
+// evaluate with u = ua t + ub (u = t for the low-degree, plain forms):
 //   Jc(u) = c1 J0(sqrt t)                      (coefficients cJ)
 //   Yf(u) = Yhat(sqrt t) + c0 J0(sqrt t)       (coefficients cY)
 //   Y0    = Jc log2(t) + Yf,   J0 = Jc / c1,
@@ -113,8 +113,10 @@ struct NearPoly {
 // Picks the smallest of the candidate coefficient counts whose error, with
 // Horner evaluated in `fp32 ? float : double` on coefficients rounded to it,
 // is below tol; returns false if none is (then the general routine must be
-// used).
-bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, double tol, NearPoly& out);
+// used).  The first `nplain` candidates are polynomials in t itself (ua = 1,
+// ub = 0: one FMA less per pair, accurate on short intervals), the others in
+// the centred variable u = 2 t / tmax - 1.
+bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, int nplain, double tol, NearPoly& out);
 
 // Exact integral of G over an h x h cell centred on the node:
 // (i/4) int H0(k|x|) dA = (i/4) 8 int_0^{pi/4} [R H1(kR)/k + 2i/(pi k^2)] dtheta, R = h/(2 cos theta).
