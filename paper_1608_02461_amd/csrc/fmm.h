@@ -62,10 +62,12 @@ struct FmmPlan : PlanBase {
   DevBuf<cplx<T>> qs, phis;  // sorted scratch for the public apply
   double max_table = 0;
 
+  int64_t npts = 0;  // points of the tree
   void ensure_work(int nrhs) {
     if (nrhs > nrhs_cap) {
       M.alloc((size_t)coef_total * nrhs);
       Lc.alloc((size_t)coef_total * nrhs);
+      phis.ensure((size_t)npts * nrhs);  // near field of the overlapped pass
       nrhs_cap = nrhs;
     }
   }

@@ -705,6 +705,7 @@ template <class T>
 std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   constexpr bool F32 = std::is_same<T, float>::value;
   auto pl = std::make_unique<FmmPlan<T>>();
+  pl->npts = t.n;
   pl->k = k;
   pl->p = p;
   pl->L = t.L;
@@ -713,7 +714,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   int64_t coef = 0, box0 = 0;
   for (int l = 0; l <= L; ++l) {
     LevelInfo& li = pl->lv[l];
-    const double sl = t.side / double(1 << l);
+    const double sl = t.side_len / double(1 << l);
     li.p = p + (int)std::floor(k * std::sqrt(2.0) * sl / 2.0);
     li.P = 2 * li.p + 1;
     li.s = std::min(1.0, k * sl);
@@ -732,7 +733,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
 
   // near field: pair arguments k r are bounded by the 3 x 3 leaf block
   const double lside = t.leaf_side();
-  const double X = (L == 0) ? k * std::sqrt(2.0) * t.side : k * 2.0 * std::sqrt(2.0) * lside;
+  const double X = (L == 0) ? k * std::sqrt(2.0) * t.side_len : k * 2.0 * std::sqrt(2.0) * lside;
   // FP32: 1e-6 absolute on J0 and Yf, below the rounding of a complex64 sum
   // over the few hundred pairs of a leaf neighbourhood
   static const int candF[] = {5, 7, 9, 12, 16};
@@ -771,7 +772,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
     std::vector<double> J;
     for (int l = 2; l < L; ++l) {
       const LevelInfo &lp = pl->lv[l], &lc = pl->lv[l + 1];
-      const double sch = t.side / double(1 << (l + 1));
+      const double sch = t.side_len / double(1 << (l + 1));
       pl->m2m_off[l] = hm2m.size();
       pl->l2l_off[l] = hl2l.size();
       hm2m.resize(hm2m.size() + (size_t)4 * lp.P * lc.P);
@@ -803,7 +804,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
     for (int l = 2; l <= L; ++l) {
       const LevelInfo& li = pl->lv[l];
       const int P = li.P, pp = li.p;
-      const double sl = t.side / double(1 << l);
+      const double sl = t.side_len / double(1 << l);
       pl->m2l_off[l] = hm2l.size();
       hm2l.resize(hm2l.size() + (size_t)49 * P * P, mk<T>(0, 0));
       for (int ox = -3; ox <= 3; ++ox)
@@ -1068,6 +1069,88 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
   }
 }
 
+// Far-field chain of one column group: M2M levels L-1 .. 2, M2L of every
+// level, L2L levels 3 .. L (MFMA kernels, or the VALU ones for the ablation).
+template <class T, int NR>
+void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* flags, hipStream_t st,
+               const int* alive, StageTimer* tm) {
+  const int L = t.L;
+  cplx<T>* M = pl.M.p;
+  cplx<T>* Lc = pl.Lc.p;
+  if (pl.use_mfma) {
+    for (int l = L - 1; l >= 2; --l) {
+      const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
+      const MfmaLevel& mf = pl.mf[l];
+      TTArgs<T> ta{};
+      ta.in = M + lc.coef * nrhs;
+      ta.out = M + lp.coef * nrhs;
+      ta.Wf = pl.mfrag.p + mf.mm;
+      ta.fin = flags ? flags + lc.box0 : nullptr;
+      ta.fout = flags ? flags + lp.box0 : nullptr;
+      ta.alive = alive;
+      ta.mode = 1;
+      ta.nparents = 1 << (2 * l);
+      ta.Pin = lc.P;
+      ta.Pout = lp.P;
+      ta.RT = mf.RT;
+      ta.KS = mf.KSc;
+      ta.nrhs = nrhs;
+      ta.r0 = r0;
+      ta.nr = NR;
+      k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
+      HFMM_LAUNCH_CHECK();
+    }
+    if (tm) tm->mark(1, st);
+    launch_m2l<T, NR>(t, pl, M, Lc, nrhs, r0, flags, alive, st);
+    for (int l = 3; l <= L; ++l) {
+      const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
+      const MfmaLevel& mf = pl.mf[l];
+      TTArgs<T> ta{};
+      ta.in = Lc + lp.coef * nrhs;
+      ta.out = Lc + li.coef * nrhs;
+      ta.Wf = pl.wfrag.p + mf.wf;
+      ta.alive = alive;
+      ta.mode = 0;
+      ta.nparents = 1 << (2 * (l - 1));
+      ta.Pin = lp.P;
+      ta.Pout = li.P;
+      ta.RT = mf.RT;
+      ta.KS = mf.KSp;
+      ta.nrhs = nrhs;
+      ta.r0 = r0;
+      ta.nr = NR;
+      k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
+      HFMM_LAUNCH_CHECK();
+    }
+  } else {
+    for (int l = L - 1; l >= 2; --l) {
+      const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
+      k_m2m<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + lc.coef * nrhs, M + lp.coef * nrhs, pl.m2m.p + pl.m2m_off[l],
+                                                lc.P, lp.P, nrhs, r0, flags ? flags + lc.box0 : nullptr,
+                                                flags ? flags + lp.box0 : nullptr, alive);
+      HFMM_LAUNCH_CHECK();
+    }
+    if (tm) tm->mark(1, st);
+    for (int l = 2; l <= L; ++l) {
+      const LevelInfo& li = pl.lv[l];
+      const LevelInfo& lp = pl.lv[l - 1];
+      k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs,
+                                                 l > 2 ? Lc + lp.coef * nrhs : nullptr, pl.m2l.p + pl.m2l_off[l],
+                                                 l > 2 ? pl.l2l.p + pl.l2l_off[l - 1] : nullptr, li.P, lp.P, l,
+                                                 nrhs, r0, flags ? flags + li.box0 : nullptr, alive);
+      HFMM_LAUNCH_CHECK();
+    }
+  }
+}
+
+// One column group (NR columns from r0).  P2M (which also gathers the
+// charges into Morton order when `perm` is given) comes first.  Then, on a
+// tree of depth >= 2 and without stage timing, the far-field chain runs on
+// the tree's side stream while the near field runs on `st` into the sorted
+// scratch; a last kernel adds the L2P of the finished local expansions and
+// writes the result (through `perm` when given).  With stage timing the
+// stages run one after another and the near-field kernel evaluates the L2P
+// itself.
 template <class T, int NR>
 void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
               const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm,
@@ -1075,88 +1158,37 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
   const int L = t.L;
   const int64_t N = t.n;
   const cplx<T>* rel = rel_of<T>(t);
-  cplx<T>* M = pl.M.p;
-  cplx<T>* Lc = pl.Lc.p;
   const double k = pl.k;
+  const cplx<T>* qnear = perm ? qs : q;
   if (L >= 2) {
     const LevelInfo& lf = pl.lv[L];
     // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
     const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
-    k_p2m<T, NR><<<(int)t.nleaves, 64, sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, M + lf.coef * nrhs, lf.p,
+    k_p2m<T, NR><<<(int)t.nleaves, 64, sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, pl.M.p + lf.coef * nrhs, lf.p,
                                                  T(k / (2 * lf.s)), T(k * k / 4), pl.K,
                                                  flags ? flags + lf.box0 : nullptr, alive, perm, qs);
     HFMM_LAUNCH_CHECK();
-    if (pl.use_mfma) {
-      // upward: M2M on MFMA, levels L-1 .. 2
-      for (int l = L - 1; l >= 2; --l) {
-        const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
-        const MfmaLevel& mf = pl.mf[l];
-        TTArgs<T> ta{};
-        ta.in = M + lc.coef * nrhs;
-        ta.out = M + lp.coef * nrhs;
-        ta.Wf = pl.mfrag.p + mf.mm;
-        ta.fin = flags ? flags + lc.box0 : nullptr;
-        ta.fout = flags ? flags + lp.box0 : nullptr;
-        ta.alive = alive;
-        ta.mode = 1;
-        ta.nparents = 1 << (2 * l);
-        ta.Pin = lc.P;
-        ta.Pout = lp.P;
-        ta.RT = mf.RT;
-        ta.KS = mf.KSc;
-        ta.nrhs = nrhs;
-        ta.r0 = r0;
-        ta.nr = NR;
-        k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
-        HFMM_LAUNCH_CHECK();
-      }
-      if (tm) tm->mark(1, st);
-      launch_m2l<T, NR>(t, pl, M, Lc, nrhs, r0, flags, alive, st);
-      // L2L chain, levels 3 .. L
-      for (int l = 3; l <= L; ++l) {
-        const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
-        const MfmaLevel& mf = pl.mf[l];
-        TTArgs<T> ta{};
-        ta.in = Lc + lp.coef * nrhs;
-        ta.out = Lc + li.coef * nrhs;
-        ta.Wf = pl.wfrag.p + mf.wf;
-        ta.alive = alive;
-        ta.mode = 0;
-        ta.nparents = 1 << (2 * (l - 1));
-        ta.Pin = lp.P;
-        ta.Pout = li.P;
-        ta.RT = mf.RT;
-        ta.KS = mf.KSp;
-        ta.nrhs = nrhs;
-        ta.r0 = r0;
-        ta.nr = NR;
-        k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
-        HFMM_LAUNCH_CHECK();
-      }
-    } else {
-      for (int l = L - 1; l >= 2; --l) {
-        const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
-        k_m2m<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + lc.coef * nrhs, M + lp.coef * nrhs, pl.m2m.p + pl.m2m_off[l],
-                                                  lc.P, lp.P, nrhs, r0, flags ? flags + lc.box0 : nullptr,
-                                                  flags ? flags + lp.box0 : nullptr, alive);
-        HFMM_LAUNCH_CHECK();
-      }
-      if (tm) tm->mark(1, st);
-      for (int l = 2; l <= L; ++l) {
-        const LevelInfo& li = pl.lv[l];
-        const LevelInfo& lp = pl.lv[l - 1];
-        k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs,
-                                                   l > 2 ? Lc + lp.coef * nrhs : nullptr, pl.m2l.p + pl.m2l_off[l],
-                                                   l > 2 ? pl.l2l.p + pl.l2l_off[l - 1] : nullptr, li.P, lp.P, l,
-                                                   nrhs, r0, flags ? flags + li.box0 : nullptr, alive);
-        HFMM_LAUNCH_CHECK();
-      }
+    if (!tm && t.side) {
+      HFMM_HIP(hipEventRecord(t.fork, st));
+      HFMM_HIP(hipStreamWaitEvent(t.side, t.fork, 0));
+      far_chain<T, NR>(t, pl, nrhs, r0, flags, t.side, alive, nullptr);
+      HFMM_HIP(hipEventRecord(t.join, t.side));
+      P2PArgs<T> a = p2p_args<T>(t, pl, qnear, pl.phis.p, nrhs, r0, flags, false, alive);
+      a.Lc = nullptr;
+      launch_p2p<T, NR>(t, pl, a, pl.G, st);
+      HFMM_LAUNCH_CHECK();
+      HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
+      const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
+      k_l2p<T, NR><<<(int)t.nleaves, 64, 0, st>>>(b, pl.phis.p);
+      HFMM_LAUNCH_CHECK();
+      return;
     }
+    far_chain<T, NR>(t, pl, nrhs, r0, flags, st, alive, tm);
     // L2P runs inside the near-field kernel (its stage time is that kernel's)
     if (tm) tm->mark(2, st);
     if (tm) tm->mark(3, st);
   }
-  const P2PArgs<T> a = p2p_args<T>(t, pl, perm ? qs : q, phi, nrhs, r0, flags, accumulate, alive, perm);
+  const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
   launch_p2p<T, NR>(t, pl, a, pl.G, st);
   HFMM_LAUNCH_CHECK();
   if (tm) tm->mark(4, st);

@@ -85,6 +85,33 @@ __device__ __forceinline__ void far_field(const P2PArgs<T>& a, uint32_t leaf, cp
     F[r] = mk<T>(A[r].x + wr * B[r].x + wi * B[r].y, A[r].y + wr * B[r].y - wi * B[r].x);
 }
 
+// L2P and output for the overlapped pass: one wave per leaf, one lane per
+// point; phi (+)= phis + (i/4) (far field), written through a.operm when set
+// (phis holds the near field in Morton order).
+template <class T, int NR>
+__global__ __launch_bounds__(64) void k_l2p(P2PArgs<T> a, const cplx<T>* __restrict__ phis) {
+  if (a.alive && !a.alive[0]) return;
+  const int leaf = blockIdx.x;
+  const int t0 = a.leaf_off[leaf], t1 = a.leaf_off[leaf + 1];
+  for (int i = t0 + (int)threadIdx.x; i < t1; i += 64) {
+    cplx<T> F[NR];
+    far_field<T, NR>(a, (uint32_t)leaf, a.rel[i], F);
+    const int o = a.operm ? a.operm[i] : i;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const size_t col = (size_t)(a.r0 + r) * a.N;
+      const cplx<T> nf = phis[col + i];
+      cplx<T> v = mk<T>(nf.x - T(0.25) * F[r].y, nf.y + T(0.25) * F[r].x);
+      if (a.accumulate) {
+        const cplx<T> old = a.phi[col + o];
+        v.x += old.x;
+        v.y += old.y;
+      }
+      a.phi[col + o] = v;
+    }
+  }
+}
+
 // Running sums of q (J0 + i Y0) over one target's sources, J0 carried as
 // Jc = c1 J0:  Re = sum (qx J0 - qy Y0) = jinv aj - ay,
 //              Im = sum (qx Y0 + qy J0) = by + jinv bj.

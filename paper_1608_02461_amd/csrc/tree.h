@@ -17,7 +17,7 @@ struct PlanBase {
 struct Tree {
   int64_t n = 0;          // points
   int L = 0;              // depth; 4^L leaves
-  double x0 = 0, y0 = 0, side = 1;
+  double x0 = 0, y0 = 0, side_len = 1;  // root box corner and side
   int leaf_size = 0;
   int64_t nleaves = 1;
   int max_leaf = 0;
@@ -29,8 +29,18 @@ struct Tree {
   std::vector<int32_t> leaf_off_h;
   // translation plans, keyed by (k, p, precision)
   std::map<std::tuple<double, int, int>, std::unique_ptr<PlanBase>> plans;
+  // a second stream (default priority, non-blocking) on which the far-field
+  // chain runs beside the near field, and the events that fork and join it;
+  // created with the tree (depth >= 2) so that no call under graph capture
+  // creates them
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 
-  double leaf_side() const { return side / double(1u << L); }
+  Tree() = default;
+  Tree(const Tree&) = delete;
+  Tree& operator=(const Tree&) = delete;
+  ~Tree();
+  double leaf_side() const { return side_len / double(1u << L); }
 };
 
 // Depth rule: 0 for leaf_size <= 0, else max(2, smallest L with leaf*4^L >= n).

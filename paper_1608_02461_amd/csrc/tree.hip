@@ -204,7 +204,7 @@ std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, doubl
   HFMM_REQUIRE(t->L <= 12, "build_tree: depth above 12 (raise leaf_size)");
   t->x0 = x0;
   t->y0 = y0;
-  t->side = side;
+  t->side_len = side;
   t->leaf_size = leaf_size;
   t->nleaves = int64_t(1) << (2 * t->L);
   const int N = (int)n;
@@ -252,7 +252,21 @@ std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, doubl
   for (int64_t b = 0; b < t->nleaves; ++b) mx = std::max(mx, t->leaf_off_h[b + 1] - t->leaf_off_h[b]);
   t->max_leaf = mx;
   if (t->leaf_off_h[t->nleaves] != N) throw Error(HFMM_ERR_INTERNAL, "build_tree: leaf offsets do not sum to n");
+  if (t->L >= 2) {
+    HFMM_HIP(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+    HFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
+    HFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
+  }
   return t;
+}
+
+Tree::~Tree() {
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
 }
 
 }  // namespace hfmm
