@@ -17,8 +17,9 @@ Also reported on the same JSON line:
   {128, 256, 384, 512}), one hipGraph-captured Arnoldi step vs eager;
 * forward + backward of the block-k^2 adjoint gradient on 256 x 256, checked
   against the CPU oracle's sparse-direct adjoint gradient;
-* `roofline` for the dominant kernel of the timed apply, from per-stage
-  hipEvents recorded on the launch stream over the timed steps;
+* `roofline` for the dominant kernel of the apply (the near field), from
+  hipEvents recorded on its launch stream around it, over the same number of
+  applies as the timed steps;
 * `cpu_baseline`: the CPU oracle's direct N-body sum on a bounded sample of
   targets, scaled to Mpts/s of the full sum.
 """
@@ -78,31 +79,6 @@ def p2p_flops_per_pair(deg, nrhs=1, plain_below=9):
     not counted, nor is the L2P that the same kernel evaluates once per
     target (under 2% of its flops here)."""
     return 2 + 3 + (0 if deg < plain_below else 2) + 4 * (deg - 1) + 2 + 8 * nrhs
-
-
-def m2l_flops(orders, L, nrhs=1):
-    """Algorithmic flops of the downward pass: 8 real flops per complex MAC,
-    M2L over each box's interaction list and L2L from its parent."""
-    tot = 0
-    for l in range(2, L + 1):
-        nb = 2 ** l
-        P = 2 * orders[l] + 1
-        # interaction-list sizes of every box at level l
-        b = np.arange(nb)
-        cnt = np.zeros((nb, nb), dtype=np.int64)
-        for ox in range(-3, 4):
-            for oy in range(-3, 4):
-                if max(abs(ox), abs(oy)) < 2:
-                    continue
-                sx, sy = b[:, None] + ox, b[None, :] + oy
-                ok = (sx >= 0) & (sx < nb) & (sy >= 0) & (sy < nb)
-                ok &= np.abs(sx // 2 - b[:, None] // 2) <= 1
-                ok &= np.abs(sy // 2 - b[None, :] // 2) <= 1
-                cnt += ok
-        tot += int(cnt.sum()) * P * P * 8 * nrhs
-        if l > 2:
-            tot += nb * nb * (2 * orders[l - 1] + 1) * P * 8 * nrhs
-    return tot
 
 
 def main():
@@ -171,23 +147,21 @@ def main():
         _, ms = hfmm.hfmm_fmm_apply_timed(tree, k, p, q32, prec=hfmm.FP32)
         for s in stages:
             stages[s] += ms[s] / args.steps
-    dominant = max(("p2p", "downward"), key=lambda s: stages[s])
-    if dominant == "p2p":
-        fl = plan["pairs"] * p2p_flops_per_pair(plan["near_deg"])
-        roof_kernel = f"k_p2p4<float,1,{plan['near_deg']},true,{plan['lanes_per_target']}>"
-    else:
-        fl = m2l_flops(plan["orders"], tree.info()["levels"])
-        roof_kernel = "k_down<float,1> (M2L + L2L, one launch per level)"
-    achieved = fl / (stages[dominant] * 1e-3) / 1e12
+    # the dominant kernel is the near field (P2P): about 70% of the kernel
+    # time of an apply; it runs beside the far-field chain, so its duration
+    # here includes that contention, as in the timed loop above
+    fl = plan["pairs"] * p2p_flops_per_pair(plan["near_deg"])
+    roof_kernel = f"k_p2p4<float,1,{plan['near_deg']},true,{plan['lanes_per_target']}>"
+    ms_p2p = stages["p2p"]
+    achieved = fl / (ms_p2p * 1e-3) / 1e12
+    L = tree.info()["levels"]
     roofline = {"bound": "alu", "kernel": roof_kernel, "achieved": round(achieved, 3), "peak": PEAK_FP32_ALU,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ALU, 4),
-                "traffic": measured_traffic(roof_kernel) if dominant == "p2p" else None,
-                "algorithmic_flops_per_launch": fl, "ms_per_launch": round(stages[dominant], 5)}
-    if dominant == "p2p":
-        # positions, sorted charges and the output permutation read once, the
-        # leaf local expansions read once, potentials written once
-        L = tree.info()["levels"]
-        roofline["algorithmic_bytes_per_launch"] = (8 + 8 + 4 + 8) * N + 4 ** L * (2 * plan["orders"][L] + 1) * 8
+                "traffic": measured_traffic(roof_kernel),
+                "algorithmic_flops_per_launch": fl, "ms_per_launch": round(ms_p2p, 5),
+                # positions and sorted charges read once, potentials written once (Morton order)
+                "algorithmic_bytes_per_launch": (8 + 8 + 8) * N,
+                "pairs_per_s": round(plan["pairs"] / (ms_p2p * 1e-3), 1)}
 
     gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_reference.npz"))
     smp = gold["samples"]

@@ -114,10 +114,14 @@ hfmm_status hfmm_tree_destroy(hfmm_tree t);
 hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
                            const void* d_q, void* d_phi, int32_t nrhs, hipStream_t stream);
 
-/* The same apply with hipEvents between its stages (tracing): ms_stages
- * (host, 6 floats) receives the device time of [0] the gather to Morton
- * order, [1] P2M + M2M, [2] M2L + L2L, [3] L2P, [4] P2P, [5] the scatter back.
- * Synchronises `stream`. */
+/* The same apply with hipEvents around its stages (tracing): ms_stages
+ * (host, 6 floats) receives device times in ms.  On a tree of depth >= 2:
+ * [1] P2M (which also gathers the charges into Morton order), [2] the
+ * far-field chain M2M + M2L + L2L, which runs on the tree's second stream
+ * beside [4] the near field (P2P), and [3] the L2P and the write in caller
+ * order, including the wait for [2]; [0] and [5] are 0.  On a single leaf:
+ * [0] the gather, [4] the direct sum, [5] the scatter.  Synchronises
+ * `stream`. */
 hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
                                  const void* d_q, void* d_phi, int32_t nrhs, float* ms_stages,
                                  hipStream_t stream);

@@ -81,9 +81,12 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p);
 // 3 L2P, 4 P2P, 5 scatter.
 struct StageTimer {
   std::vector<hipEvent_t> ev;
-  std::vector<int> stage;
+  std::vector<int> stage, from;
   ~StageTimer();
-  void mark(int s, hipStream_t st);  // closes stage s at this point
+  // records an event on st that closes stage s; the stage is timed from the
+  // event with index `from_ev` (default: the previous one).  Returns the
+  // index of the new event.
+  int mark(int s, hipStream_t st, int from_ev = -1);
   void collect(float* ms, int nstage);
 };
 

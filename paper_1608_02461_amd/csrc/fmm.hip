@@ -77,20 +77,31 @@ __device__ __forceinline__ T sdown(int n, T y, T Sn, T Sn1) {
   return fmaT(-y * rcpT(T(n) * T(n + 1)), Sn1, Sn);
 }
 
+// The LDS stores and loads of one wave are performed in order; this keeps
+// the compiler from moving them across the point, so lanes of the wave see
+// each other's stores (waves that share no LDS need no block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ P2M
 template <class T, int NR>
-__global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
+__global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
                                             const cplx<T>* __restrict__ q, int64_t N, int nrhs, int r0,
                                             cplx<T>* __restrict__ Mout, int pL, T wscale, T yscale, int K,
                                             const uint8_t* __restrict__ flags, const int* __restrict__ alive,
                                             const int32_t* __restrict__ gperm, cplx<T>* __restrict__ qs_out) {
   extern __shared__ unsigned char smem_raw[];
-  const int leaf = blockIdx.x;
+  // blockDim / 64 leaves per block, one wave each; every wave has its own
+  // LDS region
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int leaf = (int)(blockDim.x >> 6) * blockIdx.x + w;
   if (alive && !alive[0]) return;
   if (flags && !flags[leaf]) return;
-  cplx<T>* sb = reinterpret_cast<cplx<T>*>(smem_raw);  // [(pL+1)][64]
+  cplx<T>* sb = reinterpret_cast<cplx<T>*>(smem_raw) + (size_t)w * max(pL + 1 + NR, 2 * NR) * 64;  // [(pL+1)][64]
   cplx<T>* sq = sb + (pL + 1) * 64;                     // [NR][64]
-  const int lane = threadIdx.x;
   const int P = 2 * pL + 1;
   const int G = 64 / (pL + 1), g = lane / (pL + 1), n = lane - g * (pL + 1);
   const int t0 = leaf_off[leaf], t1 = leaf_off[leaf + 1];
@@ -133,7 +144,7 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
         if (gperm) qs_out[(size_t)(r0 + r) * N + j] = v;
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     // lane = (group g, order n): the G groups split the points of the chunk
     if (g < G) {
       for (int j = g; j < cnt; j += G) {
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   // sum the G partial sums of each order (sb is free again)
   cplx<T>* red = sb;  // [NR][2][64]
@@ -157,7 +168,7 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t* __restrict__ leaf_off
       red[(r * 2 + 1) * 64 + lane] = accN[r];
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   if (lane <= pL) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -562,8 +573,10 @@ struct TTArgs {
 };
 
 constexpr int kTTChunk = 16;
-// LDS budget of one M2L block (the launch takes the largest over its levels)
-constexpr size_t kM2LLds = 40 * 1024;
+// LDS budget of one M2L block (the launch takes the largest over its
+// levels): small enough that a block fits beside the four near-field blocks
+// a CU holds, so that the far-field chain progresses while the near field runs
+constexpr size_t kM2LLds = 24 * 1024;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
@@ -859,17 +872,21 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       m.RT = (2 * P + 15) / 16;
       m.KS = 4 * ((2 * P + 15) / 16);  // whole chunks of 4 k steps; the padding is zero
       // M2L window: a tile of 8 x 8 targets (4 x 4 on a 4 x 4 grid, or by
-      // the autotuner), the window plus one zero box (or the partial sums of
-      // 4 waves) in at most kM2LLds bytes of LDS; when the whole k range does
-      // not fit, the kernel stages it in slices of KSL k steps
-      auto lds_for = [&](int tile, int ksl) {
+      // the autotuner): the window plus one zero box in at most kM2LLds bytes
+      // of LDS (the block also needs room for the partial sums of 4 waves);
+      // when the whole k range does not fit, the kernel stages it in slices
+      // of KSL k steps
+      auto window = [&](int tile, int ksl) {
         const int win = std::min(nb, std::min(tile, nb) + 4);
+        return (size_t)(win * win + 1) * (4 * ksl + 2) * sizeof(T);
+      };
+      auto lds_for = [&](int tile, int ksl) {
         const int np = tile >= 8 && nb >= 8 ? 4 : 1;
-        return std::max((size_t)(win * win + 1) * (4 * ksl + 2), (size_t)4 * np * 4 * 64) * sizeof(T);
+        return std::max(window(tile, ksl), (size_t)4 * np * 4 * 64 * sizeof(T));
       };
       auto slice = [&](int tile) {
         int ksl = m.KS;
-        while (ksl > 4 && lds_for(tile, ksl) > kM2LLds) ksl = std::max(4, (ksl / 2 + 3) / 4 * 4);
+        while (ksl > 4 && window(tile, ksl) > kM2LLds) ksl = std::max(4, (ksl / 2 + 3) / 4 * 4);
         return ksl;
       };
       m.tile = std::min(8, nb);
@@ -983,7 +1000,8 @@ void launch_p2p(const Tree& t, const FmmPlan<T>& pl, const P2PArgs<T>& a, int G,
 
 template <class T>
 P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
-                    const uint8_t* flags, bool accumulate, const int* alive, const int32_t* operm = nullptr) {
+                    const uint8_t* flags, bool accumulate, const int* alive, const int32_t* operm = nullptr,
+                    bool far = false) {
   P2PArgs<T> a{};
   a.operm = operm;
   a.leaf_off = t.leaf_off.p;
@@ -1010,7 +1028,7 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.c1 = T(P.c1);
   a.jinv = T(1.0 / P.c1);
   a.Lc = nullptr;
-  if (t.L >= 2) {  // the leaf level's local expansions are evaluated by the near-field kernel
+  if (far && t.L >= 2) {  // the leaf level's local expansions, for the L2P kernel
     const LevelInfo& lf = pl.lv[t.L];
     a.Lc = pl.Lc.p + lf.coef * nrhs;
     a.pL = lf.p;
@@ -1073,7 +1091,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
 // level, L2L levels 3 .. L (MFMA kernels, or the VALU ones for the ablation).
 template <class T, int NR>
 void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* flags, hipStream_t st,
-               const int* alive, StageTimer* tm) {
+               const int* alive) {
   const int L = t.L;
   cplx<T>* M = pl.M.p;
   cplx<T>* Lc = pl.Lc.p;
@@ -1100,7 +1118,6 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
       k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
       HFMM_LAUNCH_CHECK();
     }
-    if (tm) tm->mark(1, st);
     launch_m2l<T, NR>(t, pl, M, Lc, nrhs, r0, flags, alive, st);
     for (int l = 3; l <= L; ++l) {
       const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
@@ -1130,7 +1147,6 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
                                                 flags ? flags + lp.box0 : nullptr, alive);
       HFMM_LAUNCH_CHECK();
     }
-    if (tm) tm->mark(1, st);
     for (int l = 2; l <= L; ++l) {
       const LevelInfo& li = pl.lv[l];
       const LevelInfo& lp = pl.lv[l - 1];
@@ -1144,13 +1160,13 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
 }
 
 // One column group (NR columns from r0).  P2M (which also gathers the
-// charges into Morton order when `perm` is given) comes first.  Then, on a
-// tree of depth >= 2 and without stage timing, the far-field chain runs on
-// the tree's side stream while the near field runs on `st` into the sorted
-// scratch; a last kernel adds the L2P of the finished local expansions and
-// writes the result (through `perm` when given).  With stage timing the
-// stages run one after another and the near-field kernel evaluates the L2P
-// itself.
+// charges into Morton order when `perm` is given) comes first.  On a tree
+// of depth >= 2 the far-field chain then runs on the tree's side stream
+// while the near field runs on `st` into the sorted scratch, and a last
+// kernel adds the L2P of the finished local expansions and writes the
+// result (through `perm` when given).  Stage timing: [1] P2M, [2] the
+// far-field chain (side stream, beside [4]), [4] the near field, [3] the
+// L2P and output, including the wait for [2].
 template <class T, int NR>
 void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
               const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm,
@@ -1161,33 +1177,33 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
   const double k = pl.k;
   const cplx<T>* qnear = perm ? qs : q;
   if (L >= 2) {
+    HFMM_REQUIRE(t.side != nullptr, "fmm: internal: tree without a side stream");
     const LevelInfo& lf = pl.lv[L];
     // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
     const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
-    k_p2m<T, NR><<<(int)t.nleaves, 64, sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, pl.M.p + lf.coef * nrhs, lf.p,
+    const int lpb = 4 * sh <= 65536 ? 4 : (2 * sh <= 65536 ? 2 : 1);  // leaves per block
+    k_p2m<T, NR><<<(int)(t.nleaves / lpb), 64 * lpb, lpb * sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, pl.M.p + lf.coef * nrhs, lf.p,
                                                  T(k / (2 * lf.s)), T(k * k / 4), pl.K,
                                                  flags ? flags + lf.box0 : nullptr, alive, perm, qs);
     HFMM_LAUNCH_CHECK();
-    if (!tm && t.side) {
-      HFMM_HIP(hipEventRecord(t.fork, st));
-      HFMM_HIP(hipStreamWaitEvent(t.side, t.fork, 0));
-      far_chain<T, NR>(t, pl, nrhs, r0, flags, t.side, alive, nullptr);
-      HFMM_HIP(hipEventRecord(t.join, t.side));
-      P2PArgs<T> a = p2p_args<T>(t, pl, qnear, pl.phis.p, nrhs, r0, flags, false, alive);
-      a.Lc = nullptr;
-      launch_p2p<T, NR>(t, pl, a, pl.G, st);
-      HFMM_LAUNCH_CHECK();
-      HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
-      const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
-      k_l2p<T, NR><<<(int)t.nleaves, 64, 0, st>>>(b, pl.phis.p);
-      HFMM_LAUNCH_CHECK();
-      return;
-    }
-    far_chain<T, NR>(t, pl, nrhs, r0, flags, st, alive, tm);
-    // L2P runs inside the near-field kernel (its stage time is that kernel's)
-    if (tm) tm->mark(2, st);
-    if (tm) tm->mark(3, st);
+    const int e_p2m = tm ? tm->mark(1, st) : -1;
+    HFMM_HIP(hipEventRecord(t.fork, st));
+    HFMM_HIP(hipStreamWaitEvent(t.side, t.fork, 0));
+    far_chain<T, NR>(t, pl, nrhs, r0, flags, t.side, alive);
+    if (tm) tm->mark(2, t.side, e_p2m);
+    HFMM_HIP(hipEventRecord(t.join, t.side));
+    const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, pl.phis.p, nrhs, r0, flags, false, alive);
+    launch_p2p<T, NR>(t, pl, a, pl.G, st);
+    HFMM_LAUNCH_CHECK();
+    const int e_p2p = tm ? tm->mark(4, st, e_p2m) : -1;
+    HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
+    const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm, true);
+    k_l2p<T, NR><<<(int)(t.nleaves / 4), 256, 4 * (size_t)NR * (2 * b.pL + 1) * sizeof(cplx<T>), st>>>(b, pl.phis.p);
+    HFMM_LAUNCH_CHECK();
+    if (tm) tm->mark(3, st, e_p2p);
+    return;
   }
+  // a single leaf: the near field is the whole sum
   const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
   launch_p2p<T, NR>(t, pl, a, pl.G, st);
   HFMM_LAUNCH_CHECK();
@@ -1358,21 +1374,22 @@ StageTimer::~StageTimer() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
-void StageTimer::mark(int s, hipStream_t st) {
+int StageTimer::mark(int s, hipStream_t st, int from_ev) {
   hipEvent_t e;
   HFMM_HIP(hipEventCreate(&e));
   ev.push_back(e);
   stage.push_back(s);
+  from.push_back(from_ev >= 0 ? from_ev : (int)ev.size() - 2);
   HFMM_HIP(hipEventRecord(e, st));
+  return (int)ev.size() - 1;
 }
 
 void StageTimer::collect(float* ms, int nstage) {
   for (int i = 0; i < nstage; ++i) ms[i] = 0;
-  if (ev.empty()) return;
-  HFMM_HIP(hipEventSynchronize(ev.back()));
+  for (hipEvent_t e : ev) HFMM_HIP(hipEventSynchronize(e));
   for (size_t i = 1; i < ev.size(); ++i) {
     float d = 0;
-    HFMM_HIP(hipEventElapsedTime(&d, ev[i - 1], ev[i]));
+    HFMM_HIP(hipEventElapsedTime(&d, ev[from[i]], ev[i]));
     if (stage[i] >= 0 && stage[i] < nstage) ms[stage[i]] += d;
   }
 }

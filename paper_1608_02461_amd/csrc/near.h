@@ -35,9 +35,9 @@ struct P2PArgs {
 // w and the negative ones, J_{-m} e^{-i m theta} = (-1)^m conj(w)^m / m! S_m,
 // one in conj(w); S_m runs downward alongside (sseries, sdown).
 template <class T, int NR>
-__device__ __forceinline__ void far_field(const P2PArgs<T>& a, uint32_t leaf, cplx<T> d, cplx<T> (&F)[NR]) {
+__device__ __forceinline__ void far_field(const P2PArgs<T>& a, const cplx<T>* Lleaf, cplx<T> d, cplx<T> (&F)[NR]) {
   const int pL = a.pL, P = 2 * pL + 1;
-  const cplx<T>* Lf = a.Lc + ((size_t)leaf * a.nrhs + a.r0) * P + pL;  // Lf[r P + m], m in [-pL, pL]
+  const cplx<T>* Lf = Lleaf + pL;  // Lf[r P + m], m in [-pL, pL]
   const T wr = a.wscale * d.x, wi = a.wscale * d.y;
   const T y = a.yscale * (d.x * d.x + d.y * d.y);
   T s1 = sseries(pL + 1, a.K, y), s0 = sseries(pL, a.K, y);
@@ -89,13 +89,21 @@ __device__ __forceinline__ void far_field(const P2PArgs<T>& a, uint32_t leaf, cp
 // point; phi (+)= phis + (i/4) (far field), written through a.operm when set
 // (phis holds the near field in Morton order).
 template <class T, int NR>
-__global__ __launch_bounds__(64) void k_l2p(P2PArgs<T> a, const cplx<T>* __restrict__ phis) {
+__global__ __launch_bounds__(256) void k_l2p(P2PArgs<T> a, const cplx<T>* __restrict__ phis) {
+  extern __shared__ unsigned char smem_raw[];
+  // 4 leaves per block, one wave each, each with its leaf's expansions in LDS
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int P = 2 * a.pL + 1;
+  cplx<T>* sL = reinterpret_cast<cplx<T>*>(smem_raw) + (size_t)w * NR * P;  // [NR][P]
   if (a.alive && !a.alive[0]) return;
-  const int leaf = blockIdx.x;
+  const int leaf = 4 * blockIdx.x + w;
   const int t0 = a.leaf_off[leaf], t1 = a.leaf_off[leaf + 1];
-  for (int i = t0 + (int)threadIdx.x; i < t1; i += 64) {
+  if (t0 == t1) return;
+  for (int i = lane; i < NR * P; i += 64) sL[i] = a.Lc[((size_t)leaf * a.nrhs + a.r0) * P + i];
+  wave_lds_sync();
+  for (int i = t0 + lane; i < t1; i += 64) {
     cplx<T> F[NR];
-    far_field<T, NR>(a, (uint32_t)leaf, a.rel[i], F);
+    far_field<T, NR>(a, sL, a.rel[i], F);
     const int o = a.operm ? a.operm[i] : i;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -139,11 +147,6 @@ struct PairSum {
         bj[r] += __shfl_xor(bj[r], off);
       }
     }
-  }
-  // add F to the sum (counted once over the G lanes: lane g = 0 only)
-  __device__ __forceinline__ void add_far(int r, cplx<T> F) {
-    ay[r] -= F.x;
-    by[r] += F.y;
   }
   // (i/4) times the sum: (i/4)(Re + i Im) = (-Im/4, Re/4)
   __device__ __forceinline__ cplx<T> phi(int r, T jinv) const {
@@ -320,9 +323,7 @@ __device__ __forceinline__ int xcd_swizzle(int b, int n) {
 // scaled by k.  In row-major leaf order each wave's sources are 3 contiguous
 // runs (one per row) and the own leaf splits the middle run: 4 unmasked
 // segments plus one masked.  G lanes share a target (template), each taking
-// every G-th source; a shuffle tree sums the G partial sums.  With a.Lc set
-// the kernel also evaluates the target leaves' local expansions (L2P) and
-// writes far + near field.
+// every G-th source; a shuffle tree sums the G partial sums.
 template <class T, int NR>
 struct P2P4Cfg {
   static constexpr int kBytes = 2 * (int)sizeof(T) * (1 + NR);
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
   }
   __syncthreads();
   const int total = s_pre[16];
-  if (total == 0 && a.accumulate && !a.Lc) return;
+  if (total == 0 && a.accumulate) return;
   // this wave's target leaf (child position w of the parent) and its segments
   const int cx = w & 1, cy = w >> 1;
   const uint32_t tleaf = 4u * (uint32_t)parent + (uint32_t)w;
@@ -421,30 +422,10 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       }
     }
   };
-  // far field: lane l evaluates target (batch start + l) once per 64
-  // targets; each round picks its targets' values with a shuffle
-  cplx<T> far[NR];
-  auto far_batch = [&](int rb) {
-    if (((rb - t0) & 63) != 0 || !a.Lc) return;
-    const int tf = rb + lane;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) far[r] = mk<T>(0, 0);
-    if (tf < t1) far_field<T, NR>(a, tleaf, a.rel[tf], far);
-  };
-  auto add_far = [&](int ti, PairSum<T, NR>& acc) {
-    if (!a.Lc) return;
-    const int src = (ti - t0) & 63;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const cplx<T> f = mk<T>(__shfl(far[r].x, src), __shfl(far[r].y, src));
-      if (g == 0) acc.add_far(r, f);
-    }
-  };
   if (total <= SCAP) {
     stage(0, total);
     __syncthreads();
     for (int rb = t0; rb < t1; rb += TPR) {
-      far_batch(rb);
       const int ti = rb + tl;
       const bool act = ti < t1;
       T xt = 0, yt = 0;
@@ -455,7 +436,6 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       }
       PairSum<T, NR> acc;
       acc.zero();
-      add_far(ti, acc);
 #pragma unroll
       for (int sgi = 0; sgi < 4; ++sgi)
         p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, acc);
@@ -468,7 +448,6 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
     __syncthreads();
     const int R = max(max(s_rounds[0], s_rounds[1]), max(s_rounds[2], s_rounds[3]));
     for (int round = 0; round < R; ++round) {
-      far_batch(t0 + round * TPR);
       const int ti = t0 + round * TPR + tl;
       const bool act = ti < t1;
       T xt = 0, yt = 0;
@@ -479,7 +458,6 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       }
       PairSum<T, NR> acc;
       acc.zero();
-      add_far(ti, acc);
       for (int c0 = 0; c0 < total; c0 += SCAP) {
         const int cnt = min(SCAP, total - c0);
         __syncthreads();
