@@ -1161,8 +1161,9 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
 
 // One column group (NR columns from r0).  P2M (which also gathers the
 // charges into Morton order when `perm` is given) comes first.  On a tree
-// of depth >= 2 the far-field chain then runs on the tree's side stream
-// while the near field runs on `st` into the sorted scratch, and a last
+// of depth >= 2 (and 2^18 points or more) the far-field chain then runs on
+// the tree's side stream while the near field runs on `st` into the sorted
+// scratch (smaller trees run both on `st`, near field first), and a last
 // kernel adds the L2P of the finished local expansions and writes the
 // result (through `perm` when given).  Stage timing: [1] P2M, [2] the
 // far-field chain (side stream, beside [4]), [4] the near field, [3] the
@@ -1178,6 +1179,10 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
   const cplx<T>* qnear = perm ? qs : q;
   if (L >= 2) {
     HFMM_REQUIRE(t.side != nullptr, "fmm: internal: tree without a side stream");
+    // small trees: the chain on `st` itself (two events would cost more
+    // than the overlap gains)
+    const bool overlap = t.n >= (int64_t(1) << 18);
+    hipStream_t cs = overlap ? t.side : st;
     const LevelInfo& lf = pl.lv[L];
     // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
     const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
@@ -1187,20 +1192,26 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
                                                  flags ? flags + lf.box0 : nullptr, alive, perm, qs);
     HFMM_LAUNCH_CHECK();
     const int e_p2m = tm ? tm->mark(1, st) : -1;
-    HFMM_HIP(hipEventRecord(t.fork, st));
-    HFMM_HIP(hipStreamWaitEvent(t.side, t.fork, 0));
-    far_chain<T, NR>(t, pl, nrhs, r0, flags, t.side, alive);
-    if (tm) tm->mark(2, t.side, e_p2m);
-    HFMM_HIP(hipEventRecord(t.join, t.side));
+    if (overlap) {
+      HFMM_HIP(hipEventRecord(t.fork, st));
+      HFMM_HIP(hipStreamWaitEvent(t.side, t.fork, 0));
+    }
+    // the near field is queued first: when the host is not ahead of the
+    // device, the chain's many launches would otherwise delay its start
     const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, pl.phis.p, nrhs, r0, flags, false, alive);
     launch_p2p<T, NR>(t, pl, a, pl.G, st);
     HFMM_LAUNCH_CHECK();
     const int e_p2p = tm ? tm->mark(4, st, e_p2m) : -1;
-    HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
+    far_chain<T, NR>(t, pl, nrhs, r0, flags, cs, alive);
+    if (tm) tm->mark(2, cs, overlap ? e_p2m : e_p2p);
+    if (overlap) {
+      HFMM_HIP(hipEventRecord(t.join, t.side));
+      HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
+    }
     const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm, true);
     k_l2p<T, NR><<<(int)(t.nleaves / 4), 256, 4 * (size_t)NR * (2 * b.pL + 1) * sizeof(cplx<T>), st>>>(b, pl.phis.p);
     HFMM_LAUNCH_CHECK();
-    if (tm) tm->mark(3, st, e_p2p);
+    if (tm) tm->mark(3, st, overlap ? e_p2p : -1);
     return;
   }
   // a single leaf: the near field is the whole sum
