@@ -166,12 +166,23 @@ template <class T> struct kPlainDeg;
 template <> struct kPlainDeg<float> { static constexpr int below = 9; };
 template <> struct kPlainDeg<double> { static constexpr int below = 12; };
 
+// A wave-uniform value held in a VGPR for the whole kernel: the first Horner
+// step has two constant operands and one of them must sit in a VGPR; pinned
+// once here, the compiler does not copy it into one inside every loop trip.
+__device__ __forceinline__ float pin_vgpr(float x) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+__device__ __forceinline__ double pin_vgpr(double x) { return x; }
+
 // One pair: t = (k r)^2; returns Jc = c1 J0(sqrt t) and Y = Y0(sqrt t).
 // FAST uses the fitted polynomials (D coefficients each), otherwise the
 // full-range FP64 routine.  MASK zeroes the pair at t = 0 (a point with
 // itself, or a coincident point).
 template <class T, int D, bool FAST, bool MASK>
-__device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y) {
+__device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y, T cj2, T cy2) {
+  // cj2, cy2: a.cJ[D - 2], a.cY[D - 2] (pinned in VGPRs by the caller)
   bool valid = true;
   if (MASK) {
     valid = t > T(0);
@@ -180,9 +191,9 @@ __device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y) {
   if constexpr (FAST) {
     // the low degrees are polynomials in t itself, the others in u = ua t + ub
     const T u = D < kPlainDeg<T>::below ? t : fmaT(t, a.ua, a.ub);
-    T j = a.cJ[D - 1], yh = a.cY[D - 1];
+    T j = fmaT(a.cJ[D - 1], u, cj2), yh = fmaT(a.cY[D - 1], u, cy2);
 #pragma unroll
-    for (int i = D - 2; i >= 0; --i) {
+    for (int i = D - 3; i >= 0; --i) {
       j = fmaT(j, u, a.cJ[i]);
       yh = fmaT(yh, u, a.cY[i]);
     }
@@ -277,7 +288,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         const T dx = xt - s.x, dy = yt - s.y;
         const T t = fmaT(dx, dx, dy * dy);
         T J, Y;
-        h0_pair<T, D, FAST, false>(a, t, J, Y);
+        h0_pair<T, D, FAST, false>(a, t, J, Y, a.cJ[D >= 2 ? D - 2 : 0], a.cY[D >= 2 ? D - 2 : 0]);
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
       }
@@ -286,7 +297,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         const T dx = xt - s.x, dy = yt - s.y;
         const T t = fmaT(dx, dx, dy * dy);
         T J, Y;
-        h0_pair<T, D, FAST, true>(a, t, J, Y);
+        h0_pair<T, D, FAST, true>(a, t, J, Y, a.cJ[D >= 2 ? D - 2 : 0], a.cY[D >= 2 ? D - 2 : 0]);
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
       }
@@ -333,14 +344,14 @@ struct P2P4Cfg {
 template <class T, int D, bool FAST, bool MASK, int NR, int G>
 __device__ __forceinline__ void p2p_run(const P2PArgs<T>& a, const cplx<T>* __restrict__ spos,
                                         const cplx<T> (*sq)[P2P4Cfg<T, NR>::SCAP], int lo, int hi, int g, T xt,
-                                        T yt, PairSum<T, NR>& acc) {
+                                        T yt, PairSum<T, NR>& acc, T cj2, T cy2) {
 #pragma unroll 4
   for (int j = lo + g; j < hi; j += G) {
     const cplx<T> s = spos[j];
     const T dx = xt - s.x, dy = yt - s.y;
     const T t = fmaT(dx, dx, dy * dy);
     T J, Y;
-    h0_pair<T, D, FAST, MASK>(a, t, J, Y);
+    h0_pair<T, D, FAST, MASK>(a, t, J, Y, cj2, cy2);
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
   }
@@ -394,6 +405,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
   const int own_lo = s_pre[io], own_hi = s_pre[io + 1];
   constexpr int TPR = 64 / G;
   const int g = lane & (G - 1), tl = lane / G;
+  const T cj2 = pin_vgpr(a.cJ[D >= 2 ? D - 2 : 0]), cy2 = pin_vgpr(a.cY[D >= 2 ? D - 2 : 0]);
   auto stage = [&](int c0, int cnt) {
     for (int idx = tid; idx < cnt; idx += 256) {
       const int gi = c0 + idx;
@@ -404,6 +416,19 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       spos[idx] = mk<T>(fmaT(a.k, d.x, s_ox[lf]), fmaT(a.k, d.y, s_oy[lf]));
 #pragma unroll
       for (int r = 0; r < NR; ++r) sq[r][idx] = a.q[(size_t)(a.r0 + r) * a.N + slot];
+    }
+  };
+  // whole region: 16 threads per leaf of the 4 x 4 block, no search
+  auto stage_all = [&]() {
+    const int lf = tid >> 4, sub = tid & 15;
+    const int lo = s_lo[lf], dst = s_pre[lf], n = s_pre[lf + 1] - dst;
+    const T ox = s_ox[lf], oy = s_oy[lf];
+#pragma unroll 2
+    for (int i = sub; i < n; i += 16) {
+      const cplx<T> d = a.rel[lo + i];
+      spos[dst + i] = mk<T>(fmaT(a.k, d.x, ox), fmaT(a.k, d.y, oy));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sq[r][dst + i] = a.q[(size_t)(a.r0 + r) * a.N + lo + i];
     }
   };
   auto finish = [&](int ti, bool act, PairSum<T, NR>& acc) {
@@ -423,7 +448,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
     }
   };
   if (total <= SCAP) {
-    stage(0, total);
+    stage_all();
     __syncthreads();
     for (int rb = t0; rb < t1; rb += TPR) {
       const int ti = rb + tl;
@@ -438,8 +463,8 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       acc.zero();
 #pragma unroll
       for (int sgi = 0; sgi < 4; ++sgi)
-        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, acc);
-      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, acc);
+        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, acc, cj2, cy2);
+      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, acc, cj2, cy2);
       finish(ti, act, acc);
     }
   } else {
@@ -466,10 +491,10 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
 #pragma unroll
         for (int sgi = 0; sgi < 4; ++sgi) {
           const int lo = max(sg_lo[sgi], c0) - c0, hi = min(sg_hi[sgi], c0 + cnt) - c0;
-          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc);
+          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2);
         }
         const int lo = max(own_lo, c0) - c0, hi = min(own_hi, c0 + cnt) - c0;
-        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc);
+        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2);
       }
       finish(ti, act, acc);
     }
