@@ -117,9 +117,9 @@ hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec
 /* The same apply with hipEvents around its stages (tracing): ms_stages
  * (host, 6 floats) receives device times in ms.  On a tree of depth >= 2:
  * [1] P2M (which also gathers the charges into Morton order), [2] the
- * far-field chain M2M + M2L + L2L, which runs on the tree's second stream
- * beside [4] the near field (P2P) on trees of 2^18 points or more (after it
- * on smaller ones), and [3] the L2P and the write in caller
+ * far-field chain M2M + M2L + L2L + L2P, which runs on the tree's second
+ * stream beside [4] the near field (P2P) on trees of 2^18 points or more
+ * (after it on smaller ones), and [3] the sum of both written in caller
  * order, including the wait for [2]; [0] and [5] are 0.  On a single leaf:
  * [0] the gather, [4] the direct sum, [5] the scatter.  Synchronises
  * `stream`. */

@@ -60,6 +60,7 @@ struct FmmPlan : PlanBase {
   DevBuf<cplx<T>> M, Lc;
   int nrhs_cap = 0;
   DevBuf<cplx<T>> qs, phis;  // sorted scratch for the public apply
+  DevBuf<cplx<T>> far;        // far field of a pass, in the output's point order
   double max_table = 0;
 
   int64_t npts = 0;  // points of the tree
@@ -67,7 +68,7 @@ struct FmmPlan : PlanBase {
     if (nrhs > nrhs_cap) {
       M.alloc((size_t)coef_total * nrhs);
       Lc.alloc((size_t)coef_total * nrhs);
-      phis.ensure((size_t)npts * nrhs);  // near field of the overlapped pass
+      far.ensure((size_t)npts * nrhs);  // far field of a pass
       nrhs_cap = nrhs;
     }
   }

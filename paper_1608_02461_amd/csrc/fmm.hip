@@ -1088,11 +1088,15 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
 }
 
 // Far-field chain of one column group: M2M levels L-1 .. 2, M2L of every
-// level, L2L levels 3 .. L (MFMA kernels, or the VALU ones for the ablation).
+// level, L2L levels 3 .. r (MFMA kernels, or the VALU ones for the
+// ablation), then k_down_tree: L2L of the last levels r+1 .. L and the L2P
+// into pl.far (Morton order), r = max(2, L - 2).  `fa` carries the points
+// and far-field scales.
 template <class T, int NR>
 void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* flags, hipStream_t st,
-               const int* alive) {
+               const int* alive, const P2PArgs<T>& fa) {
   const int L = t.L;
+  const int rl = std::max(2, L - 2);  // the down tree starts below this level
   cplx<T>* M = pl.M.p;
   cplx<T>* Lc = pl.Lc.p;
   if (pl.use_mfma) {
@@ -1119,7 +1123,7 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
       HFMM_LAUNCH_CHECK();
     }
     launch_m2l<T, NR>(t, pl, M, Lc, nrhs, r0, flags, alive, st);
-    for (int l = 3; l <= L; ++l) {
+    for (int l = 3; l <= rl; ++l) {
       const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
       const MfmaLevel& mf = pl.mf[l];
       TTArgs<T> ta{};
@@ -1151,23 +1155,44 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
       const LevelInfo& li = pl.lv[l];
       const LevelInfo& lp = pl.lv[l - 1];
       k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs,
-                                                 l > 2 ? Lc + lp.coef * nrhs : nullptr, pl.m2l.p + pl.m2l_off[l],
-                                                 l > 2 ? pl.l2l.p + pl.l2l_off[l - 1] : nullptr, li.P, lp.P, l,
+                                                 l > 2 && l <= rl ? Lc + lp.coef * nrhs : nullptr, pl.m2l.p + pl.m2l_off[l],
+                                                 l > 2 && l <= rl ? pl.l2l.p + pl.l2l_off[l - 1] : nullptr, li.P, lp.P, l,
                                                  nrhs, r0, flags ? flags + li.box0 : nullptr, alive);
       HFMM_LAUNCH_CHECK();
     }
   }
+  // the last levels and the L2P
+  DownTreeArgs<T> g{};
+  g.a = fa;
+  g.d = L - rl;
+  g.Lr = Lc + pl.lv[rl].coef * nrhs;
+  g.P0 = pl.lv[rl].P;
+  if (g.d >= 1) {
+    g.L1 = Lc + pl.lv[rl + 1].coef * nrhs;
+    g.W1 = pl.l2l.p + pl.l2l_off[rl];
+    g.P1 = pl.lv[rl + 1].P;
+  }
+  if (g.d == 2) {
+    g.L2 = Lc + pl.lv[rl + 2].coef * nrhs;
+    g.W2 = pl.l2l.p + pl.l2l_off[rl + 1];
+    g.P2 = pl.lv[rl + 2].P;
+  }
+  g.far = pl.far.p;
+  const size_t sh = (size_t)(4 * NR * g.P1 + 16 * NR * g.P2) * sizeof(cplx<T>);
+  k_down_tree<T, NR><<<1 << (2 * rl), 256, sh, st>>>(g);
+  HFMM_LAUNCH_CHECK();
 }
 
 // One column group (NR columns from r0).  P2M (which also gathers the
 // charges into Morton order when `perm` is given) comes first.  On a tree
 // of depth >= 2 (and 2^18 points or more) the far-field chain then runs on
-// the tree's side stream while the near field runs on `st` into the sorted
-// scratch (smaller trees run both on `st`, near field first), and a last
-// kernel adds the L2P of the finished local expansions and writes the
-// result (through `perm` when given).  Stage timing: [1] P2M, [2] the
-// far-field chain (side stream, beside [4]), [4] the near field, [3] the
-// L2P and output, including the wait for [2].
+// the tree's side stream while the near field runs on `st` (smaller trees
+// run both on `st`, near field first).  The near field writes (or adds to)
+// phi, the chain ends with the L2P into the far-field scratch pl.far, both
+// through `perm` when given, and a last streaming kernel adds the far
+// field to phi.  Stage timing: [1] P2M, [2] the far-field chain including
+// the L2P (side stream, beside [4]), [4] the near field, [3] the sum,
+// including the wait for [2].
 template <class T, int NR>
 void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
               const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm,
@@ -1198,18 +1223,18 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     }
     // the near field is queued first: when the host is not ahead of the
     // device, the chain's many launches would otherwise delay its start
-    const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, pl.phis.p, nrhs, r0, flags, false, alive);
+    const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
     launch_p2p<T, NR>(t, pl, a, pl.G, st);
     HFMM_LAUNCH_CHECK();
     const int e_p2p = tm ? tm->mark(4, st, e_p2m) : -1;
-    far_chain<T, NR>(t, pl, nrhs, r0, flags, cs, alive);
+    const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, false, alive, perm, true);
+    far_chain<T, NR>(t, pl, nrhs, r0, flags, cs, alive, b);
     if (tm) tm->mark(2, cs, overlap ? e_p2m : e_p2p);
     if (overlap) {
       HFMM_HIP(hipEventRecord(t.join, t.side));
       HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
     }
-    const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm, true);
-    k_l2p<T, NR><<<(int)(t.nleaves / 4), 256, 4 * (size_t)NR * (2 * b.pL + 1) * sizeof(cplx<T>), st>>>(b, pl.phis.p);
+    k_combine<T, NR><<<(int)((N + 255) / 256), 256, 0, st>>>(phi, pl.far.p, N, r0, alive);
     HFMM_LAUNCH_CHECK();
     if (tm) tm->mark(3, st, overlap ? e_p2p : -1);
     return;

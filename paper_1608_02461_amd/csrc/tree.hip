@@ -254,8 +254,8 @@ std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, doubl
   if (t->leaf_off_h[t->nleaves] != N) throw Error(HFMM_ERR_INTERNAL, "build_tree: leaf offsets do not sum to n");
   if (t->L >= 2) {
     HFMM_HIP(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
-    HFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
-    HFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
+    HFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming | hipEventDisableSystemFence));
+    HFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming | hipEventDisableSystemFence));
   }
   return t;
 }

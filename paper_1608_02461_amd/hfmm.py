@@ -177,8 +177,8 @@ def hfmm_fmm_apply(tree, k, p, q, prec=FP64, stream=None):
 
 
 # stage names of hfmm_fmm_apply_timed; on a tree of depth >= 2 "upward" is
-# P2M, "downward" the far-field chain (M2M + M2L + L2L) on the tree's second
-# stream beside "p2p", and "l2p" the L2P and output (see include/hfmm.h)
+# P2M, "downward" the far-field chain (M2M + M2L + L2L + L2P) on the tree's
+# second stream beside "p2p", and "l2p" the output (see include/hfmm.h)
 STAGES = ("gather", "upward", "downward", "l2p", "p2p", "scatter")
 
 
