@@ -76,8 +76,7 @@ def p2p_flops_per_pair(deg, nrhs=1, plain_below=9):
     lower ones are polynomials in t itself); two Horner chains of deg-1 FMAs
     (4 (deg-1)); Y = fma(Jc, log2 t, Yf) (2); 4 FMAs per right-hand side into
     the accumulators (8 nrhs).  The log2 per pair is a transcendental and is
-    not counted, nor is the L2P that the same kernel evaluates once per
-    target (under 2% of its flops here)."""
+    not counted."""
     return 2 + 3 + (0 if deg < plain_below else 2) + 4 * (deg - 1) + 2 + 8 * nrhs
 
 

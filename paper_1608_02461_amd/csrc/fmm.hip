@@ -86,6 +86,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The far-field chain runs beside the near field, whose waves keep every
+// SIMD busy.  Its kernels raise their waves' issue priority so that the
+// chain, which is short of parallelism, advances at close to its own speed
+// while the near field takes the issue slots it leaves.
+__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // ------------------------------------------------------------------ P2M
 template <class T, int NR>
 __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
@@ -339,6 +345,10 @@ struct M2LAllArgs {
 // a box, 4 KSL + 2 = 2 m with m odd, puts the 16 columns of a patch times 2
 // rows in distinct LDS banks (32 of 4 bytes) when the window is 12 boxes
 // wide.
+// 4 waves (one per SIMD), so that a block fits in the registers the
+// near-field blocks leave free on a CU and the chain runs beside them
+constexpr int kM2LThreads = 256;
+
 template <class T, int NP>
 __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int lblock, T* Ms) {
   typedef typename Acc4<T>::type V4;
@@ -387,11 +397,11 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
       {
         const int nel = zb * KPs;
         const uint32_t mK = 0xffffffffu / (uint32_t)KPs + 1u, mW = 0xffffffffu / (uint32_t)WW + 1u;
-        for (int i0 = tid; i0 < nel; i0 += 4 * 512) {
+        for (int i0 = tid; i0 < nel; i0 += 4 * kM2LThreads) {
           T v[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int idx = i0 + u * 512;
+            const int idx = i0 + u * kM2LThreads;
             v[u] = T(0);
             const int box = (int)__umulhi((uint32_t)idx, mK);
             const int n = idx - box * KPs, nn = 4 * k0 + n;
@@ -405,7 +415,7 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (i0 + u * 512 < nel) Ms[i0 + u * 512] = v[u];
+            if (i0 + u * kM2LThreads < nel) Ms[i0 + u * kM2LThreads] = v[u];
         }
       }
       if (w == 0)
@@ -414,14 +424,16 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
       const T* Ab = Abase + (size_t)k0 * 64;  // this slice's k steps
       // this wave's 5 offset classes (class index = wave mod 8)
       if constexpr (NP == 1) {
-        // one patch: the 5 classes run side by side (5 accumulators, 20
-        // independent MFMAs per chunk, the next chunk's A loaded ahead) and
-        // are summed at the end
+        // one patch: each group of 5 classes runs side by side (5
+        // accumulators, 20 independent MFMAs per chunk, the next chunk's A
+        // loaded ahead) and is summed at the end
+#pragma unroll 1
+        for (int g = 0; g < 2; ++g) {
         int b5[5];
         const T* A5[5];
 #pragma unroll
         for (int oi = 0; oi < 5; ++oi) {
-          const int o = kClassO[8 * oi + w];
+          const int o = kClassO[8 * oi + w + 4 * g];
           b5[oi] = src_base(o, 0);
           A5[oi] = Ab + (size_t)o * cstride;
         }
@@ -455,22 +467,26 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[0][q] += acc5[0][q] + acc5[1][q] + acc5[2][q] + acc5[3][q] + acc5[4][q];
+        }
       } else {
         // the A fragments of the next chunk, also across classes, load one
         // chunk ahead
+        // the wave's 10 classes: index = wave (mod 4)
+        auto cls = [&](int i) { return kClassO[8 * (i % 5) + w + 4 * (i / 5)]; };
         T an[4];
         {
-          const T* A0 = Ab + (size_t)kClassO[w] * cstride;
+          const T* A0 = Ab + (size_t)cls(0) * cstride;
 #pragma unroll
           for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
         }
-        for (int oi = 0; oi < 5; ++oi) {
-          const int o = kClassO[8 * oi + w];
+#pragma unroll 1
+        for (int oi = 0; oi < 10; ++oi) {
+          const int o = cls(oi);
           int base[NP];
 #pragma unroll
           for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
           const T* A = Ab + (size_t)o * cstride;
-          const T* An = oi + 1 < 5 ? Ab + (size_t)kClassO[8 * (oi + 1) + w] * cstride : A;
+          const T* An = oi + 1 < 10 ? Ab + (size_t)cls(oi + 1) * cstride : A;
           for (int c = 0; c < nch; ++c) {
             T av[4];
 #pragma unroll
@@ -478,7 +494,7 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
             if (c + 1 < nch) {
 #pragma unroll
               for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
-            } else if (oi + 1 < 5) {
+            } else if (oi + 1 < 10) {
 #pragma unroll
               for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
             }
@@ -495,28 +511,12 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
         }
       }
     }
-    // sum the 8 waves' partial products: waves 4..7 into 0..3, then 0..3
+    // sum the 4 waves' partial products in LDS
     __syncthreads();
-    if (w >= 4) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[(((w - 4) * NP + p) * 4 + q) * 64 + lane] = acc[p][q];
-    }
-    __syncthreads();
-    if (w < 4) {
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += red[((w * NP + p) * 4 + q) * 64 + lane];
-    }
-    __syncthreads();
-    if (w < 4) {
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) red[((w * NP + p) * 4 + q) * 64 + lane] = acc[p][q];
-    }
+      for (int q = 0; q < 4; ++q) red[((w * NP + p) * 4 + q) * 64 + lane] = acc[p][q];
     __syncthreads();
     if (w < NP) {
 #pragma unroll
@@ -538,13 +538,17 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
 }
 
 template <class T>
-__global__ __launch_bounds__(512) void k_m2l_mfma(M2LAllArgs<T> args) {
+__global__ __launch_bounds__(kM2LThreads) void k_m2l_mfma(M2LAllArgs<T> args) {
   extern __shared__ unsigned char smem_raw[];
+  chain_priority();
   T* Ms = reinterpret_cast<T*>(smem_raw);
   if (args.alive && !args.alive[0]) return;
-  int li = 0;
-  while (li + 1 < args.nlev && (int)blockIdx.x >= args.lv[li + 1].block0) ++li;
-  const M2LLevel<T>& a = args.lv[li];
+  // the block's level, selected by constant indices (a runtime index into
+  // the argument array would copy the array to registers)
+  M2LLevel<T> a = args.lv[0];
+#pragma unroll
+  for (int i = 1; i < kMaxLev; ++i)
+    if (i < args.nlev && (int)blockIdx.x >= args.lv[i].block0) a = args.lv[i];
   const int lblock = (int)blockIdx.x - a.block0;
   if (a.tile == 8)
     m2l_block<T, 4>(args, a, lblock, Ms);
@@ -582,6 +586,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
   typedef typename Acc4<T>::type V4;
   __shared__ T red[3][4][64];
+  chain_priority();
   if (a.alive && !a.alive[0]) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, kq = lane >> 4;
   const int g = blockIdx.x, rt = blockIdx.y;
@@ -1082,7 +1087,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
     lds = std::max(lds, small ? mf.lds4 : mf.lds);
   }
   if (ma.nlev) {
-    k_m2l_mfma<T><<<blocks, 512, lds, st>>>(ma);
+    k_m2l_mfma<T><<<blocks, kM2LThreads, lds, st>>>(ma);
     HFMM_LAUNCH_CHECK();
   }
 }

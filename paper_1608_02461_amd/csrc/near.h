@@ -106,6 +106,7 @@ struct DownTreeArgs {
 template <class T, int NR>
 __global__ __launch_bounds__(256) void k_down_tree(DownTreeArgs<T> g) {
   extern __shared__ unsigned char smem_raw[];
+  chain_priority();
   const P2PArgs<T>& a = g.a;
   if (a.alive && !a.alive[0]) return;
   const int b = blockIdx.x, tid = threadIdx.x;
