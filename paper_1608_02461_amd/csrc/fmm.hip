@@ -392,30 +392,57 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
       const int nch = min(KSL, KS - k0) >> 2;  // whole chunks of 4 k steps
       __syncthreads();
       // stage the slice [4 k0, 4 k0 + 4 KSL) of the real columns of the
-      // window: a flat (box, element) index over the block, with the loads
-      // of 4 elements issued before their LDS stores
+      // window.  Lanes in groups of P take one complex coefficient each of
+      // gpw boxes per wave step (lanes loop over coefficients when P > 64);
+      // the loads of 4 steps are issued before their LDS stores.  The
+      // columns past 2 P that the slice's whole MFMA chunks read are zeroed
+      // apart.
       {
-        const int nel = zb * KPs;
-        const uint32_t mK = 0xffffffffu / (uint32_t)KPs + 1u, mW = 0xffffffffu / (uint32_t)WW + 1u;
-        for (int i0 = tid; i0 < nel; i0 += 4 * kM2LThreads) {
-          T v[4];
+        const int gpw = P <= 64 ? 64 / P : 1;  // boxes per wave step
+        const int g = P <= 64 ? lane / P : 0, m0 = P <= 64 ? lane - g * P : lane;
+        const int lo = 4 * k0, hi = 4 * (k0 + KSL);  // real columns of the slice
+        const uint32_t mW = 0xffffffffu / (uint32_t)WW + 1u;
+        const bool on = g < gpw;
+        const uint8_t* fl = a.fsrc;
+        const size_t bstride = (size_t)args.nrhs * P;  // between boxes
+        for (int m = m0; m < P; m += 64) {
+          const cplx<T>* Mm = a.M + (size_t)(args.r0 + r) * P + m;
+          for (int b0 = w * gpw; b0 < zb; b0 += 4 * 4 * gpw) {
+            cplx<T> v[4];
+            uint8_t f[4];
+            int lb[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int idx = i0 + u * kM2LThreads;
-            v[u] = T(0);
-            const int box = (int)__umulhi((uint32_t)idx, mK);
-            const int n = idx - box * KPs, nn = 4 * k0 + n;
-            if (idx < nel && n < 4 * KSL && nn < 2 * P) {
-              const int by = (int)__umulhi((uint32_t)box, mW), bx = box - by * WW;
-              const uint32_t gb = morton((uint32_t)(wx0 + bx), (uint32_t)(wy0 + by));
-              const T* src = reinterpret_cast<const T*>(a.M + ((size_t)gb * args.nrhs + args.r0 + r) * P);
-              const T x = src[nn < P ? 2 * nn : 2 * (nn - P) + 1];
-              v[u] = (!a.fsrc || a.fsrc[gb]) ? x : T(0);
+            for (int u = 0; u < 4; ++u) {
+              const int box = b0 + u * 4 * gpw + g;
+              lb[u] = on && box < zb ? box : -1;
+              v[u] = mk<T>(0, 0);
+              f[u] = 1;
+              if (lb[u] >= 0) {
+                const int by = (int)__umulhi((uint32_t)box, mW), bx = box - by * WW;
+                const uint32_t gb = morton((uint32_t)(wx0 + bx), (uint32_t)(wy0 + by));
+                v[u] = Mm[gb * bstride];
+                if (fl) f[u] = fl[gb];
+              }
             }
-          }
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (i0 + u * kM2LThreads < nel) Ms[i0 + u * kM2LThreads] = v[u];
+            for (int u = 0; u < 4; ++u)
+              if (lb[u] >= 0) {
+                T* row = Ms + (size_t)lb[u] * KPs - lo;
+                const T re = f[u] ? v[u].x : T(0), im = f[u] ? v[u].y : T(0);
+                if (m >= lo && m < hi) row[m] = re;
+                if (m + P >= lo && m + P < hi) row[m + P] = im;
+              }
+          }
+        }
+        // zero padding: columns [2 P, 4 (k0 + min(KSL, KS - k0))) of every box
+        const int z0 = max(2 * P, lo), z1 = 4 * (k0 + min(KSL, KS - k0));
+        if (z1 > z0) {
+          const int nz = z1 - z0;
+          const uint32_t mZ = 0xffffffffu / (uint32_t)nz + 1u;
+          for (int i = tid; i < zb * nz; i += kM2LThreads) {
+            const int box = (int)__umulhi((uint32_t)i, mZ);
+            Ms[(size_t)box * KPs + z0 - lo + (i - box * nz)] = T(0);
+          }
         }
       }
       if (w == 0)
