@@ -345,7 +345,7 @@ struct M2LAllArgs {
 // a box, 4 KSL + 2 = 2 m with m odd, puts the 16 columns of a patch times 2
 // rows in distinct LDS banks (32 of 4 bytes) when the window is 12 boxes
 // wide.
-// 4 waves (one per SIMD), so that a block fits in the registers the
+// 4 waves (one per SIMD), so that blocks fit in the registers the
 // near-field blocks leave free on a CU and the chain runs beside them
 constexpr int kM2LThreads = 256;
 
@@ -449,92 +449,44 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
         for (int n = lane; n < KPs; n += 64) Ms[zb * KPs + n] = T(0);
       __syncthreads();
       const T* Ab = Abase + (size_t)k0 * 64;  // this slice's k steps
-      // this wave's 5 offset classes (class index = wave mod 8)
-      if constexpr (NP == 1) {
-        // one patch: each group of 5 classes runs side by side (5
-        // accumulators, 20 independent MFMAs per chunk, the next chunk's A
-        // loaded ahead) and is summed at the end
+      // the wave's 10 offset classes (class index = wave mod 4) one after
+      // another; the A fragments of the next chunk, also across classes,
+      // load one chunk ahead
+      auto cls = [&](int i) { return kClassO[8 * (i % 5) + w + 4 * (i / 5)]; };
+      T an[4];
+      {
+        const T* A0 = Ab + (size_t)cls(0) * cstride;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
+      }
 #pragma unroll 1
-        for (int g = 0; g < 2; ++g) {
-        int b5[5];
-        const T* A5[5];
+      for (int oi = 0; oi < 10; ++oi) {
+        const int o = cls(oi);
+        int base[NP];
 #pragma unroll
-        for (int oi = 0; oi < 5; ++oi) {
-          const int o = kClassO[8 * oi + w + 4 * g];
-          b5[oi] = src_base(o, 0);
-          A5[oi] = Ab + (size_t)o * cstride;
-        }
-        V4 acc5[5];
-        T an[5][4];
-#pragma unroll
-        for (int oi = 0; oi < 5; ++oi) {
-          acc5[oi] = V4{0, 0, 0, 0};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) an[oi][u] = A5[oi][u * 64];
-        }
+        for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
+        const T* A = Ab + (size_t)o * cstride;
+        const T* An = oi + 1 < 10 ? Ab + (size_t)cls(oi + 1) * cstride : A;
         for (int c = 0; c < nch; ++c) {
-          T av[5][4], bv[5][4];
+          T av[4];
 #pragma unroll
-          for (int oi = 0; oi < 5; ++oi)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              av[oi][u] = an[oi][u];
-              bv[oi][u] = Ms[b5[oi] + (c * 4 + u) * 4];
-            }
+          for (int u = 0; u < 4; ++u) av[u] = an[u];
           if (c + 1 < nch) {
 #pragma unroll
-            for (int oi = 0; oi < 5; ++oi)
+            for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
+          } else if (oi + 1 < 10) {
 #pragma unroll
-              for (int u = 0; u < 4; ++u) an[oi][u] = A5[oi][(c * 4 + 4 + u) * 64];
+            for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
           }
+          T bv[NP][4];
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];
 #pragma unroll
           for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int oi = 0; oi < 5; ++oi) acc5[oi] = mfma16(av[oi][u], bv[oi][u], acc5[oi]);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[0][q] += acc5[0][q] + acc5[1][q] + acc5[2][q] + acc5[3][q] + acc5[4][q];
-        }
-      } else {
-        // the A fragments of the next chunk, also across classes, load one
-        // chunk ahead
-        // the wave's 10 classes: index = wave (mod 4)
-        auto cls = [&](int i) { return kClassO[8 * (i % 5) + w + 4 * (i / 5)]; };
-        T an[4];
-        {
-          const T* A0 = Ab + (size_t)cls(0) * cstride;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
-        }
-#pragma unroll 1
-        for (int oi = 0; oi < 10; ++oi) {
-          const int o = cls(oi);
-          int base[NP];
-#pragma unroll
-          for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
-          const T* A = Ab + (size_t)o * cstride;
-          const T* An = oi + 1 < 10 ? Ab + (size_t)cls(oi + 1) * cstride : A;
-          for (int c = 0; c < nch; ++c) {
-            T av[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = an[u];
-            if (c + 1 < nch) {
-#pragma unroll
-              for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
-            } else if (oi + 1 < 10) {
-#pragma unroll
-              for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
-            }
-            T bv[NP][4];
-#pragma unroll
-            for (int p = 0; p < NP; ++p)
-#pragma unroll
-              for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
-          }
+            for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
         }
       }
     }
