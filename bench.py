@@ -158,8 +158,9 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ALU, 4),
                 "traffic": measured_traffic(roof_kernel),
                 "algorithmic_flops_per_launch": fl, "ms_per_launch": round(ms_p2p, 5),
-                # positions and sorted charges read once, potentials written once (Morton order)
-                "algorithmic_bytes_per_launch": (8 + 8 + 8) * N,
+                # positions, sorted charges and the permutation read once, potentials
+                # written once (in caller order)
+                "algorithmic_bytes_per_launch": (8 + 8 + 4 + 8) * N,
                 "pairs_per_s": round(plan["pairs"] / (ms_p2p * 1e-3), 1)}
 
     gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_reference.npz"))
