@@ -477,9 +477,9 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       for (int r = 0; r < NR; ++r) sq[r][dst + i] = a.q[(size_t)(a.r0 + r) * a.N + lo + i];
     }
   };
-  auto finish = [&](int ti, bool act, PairSum<T, NR>& acc) {
-    acc.reduce(G);
-    if (g == 0 && act) {
+  auto finish = [&](int ti, bool act, PairSum<T, NR>& acc, int gw, int gl) {
+    acc.reduce(gw);
+    if (gl == 0 && act) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const size_t idx = (size_t)(a.r0 + r) * a.N + (a.operm ? a.operm[ti] : ti);
@@ -496,8 +496,12 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
   if (total <= SCAP) {
     stage_all();
     __syncthreads();
-    for (int rb = t0; rb < t1; rb += TPR) {
-      const int ti = rb + tl;
+    // one pass = 64 / GG targets, GG lanes each; the last pass of a leaf
+    // widens GG to 2 G or 4 G when few targets are left, so that fewer
+    // lanes idle
+    auto pass = [&](auto gc, int rb) {
+      constexpr int GG = decltype(gc)::value;
+      const int gl = lane & (GG - 1), ti = rb + lane / GG;
       const bool act = ti < t1;
       T xt = 0, yt = 0;
       if (act) {
@@ -509,9 +513,19 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       acc.zero();
 #pragma unroll
       for (int sgi = 0; sgi < 4; ++sgi)
-        p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], g, xt, yt, acc, cj2, cy2);
-      p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, own_lo, own_hi, g, xt, yt, acc, cj2, cy2);
-      finish(ti, act, acc);
+        p2p_run<T, D, FAST, false, NR, GG>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], gl, xt, yt, acc, cj2, cy2);
+      p2p_run<T, D, FAST, true, NR, GG>(a, spos, sq, own_lo, own_hi, gl, xt, yt, acc, cj2, cy2);
+      finish(ti, act, acc, GG, gl);
+      return 64 / GG;
+    };
+    for (int rb = t0; rb < t1;) {
+      const int rem = t1 - rb;
+      if (rem <= TPR / 4)
+        rb += pass(std::integral_constant<int, 4 * G>{}, rb);
+      else if (rem <= TPR / 2)
+        rb += pass(std::integral_constant<int, 2 * G>{}, rb);
+      else
+        rb += pass(std::integral_constant<int, G>{}, rb);
     }
   } else {
     // the region does not fit: uniform rounds across the block, sources in chunks
@@ -542,7 +556,7 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
         const int lo = max(own_lo, c0) - c0, hi = min(own_hi, c0 + cnt) - c0;
         p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2);
       }
-      finish(ti, act, acc);
+      finish(ti, act, acc, G, g);
     }
   }
 }
