@@ -589,16 +589,15 @@ __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
     const cplx<T>* col = a.in + ((size_t)(bvalid ? src : 0) * a.nrhs + a.r0 + r) * a.Pin;
     for (int k0 = 0; k0 < a.KS; k0 += kTTChunk) {
       T av[kTTChunk], bv[kTTChunk];
+      // every load is issued (clamped to a valid element) before any is
+      // used, so a chunk waits for memory once
 #pragma unroll
       for (int u = 0; u < kTTChunk; ++u) {
         const int ks = min(k0 + u, a.KS - 1);
         av[u] = Wf[ks * 64];
-        const int kk = ks * 4 + kq;
-        bv[u] = T(0);
-        if (bvalid && k0 + u < a.KS && kk < 2 * a.Pin) {
-          const cplx<T> pv = col[kk < a.Pin ? kk : kk - a.Pin];
-          bv[u] = kk < a.Pin ? pv.x : pv.y;
-        }
+        const int kk = ks * 4 + kq, kc = min(kk, 2 * a.Pin - 1);
+        const cplx<T> pv = col[kc < a.Pin ? kc : kc - a.Pin];
+        bv[u] = bvalid && k0 + u < a.KS && kk < 2 * a.Pin ? (kk < a.Pin ? pv.x : pv.y) : T(0);
       }
 #pragma unroll
       for (int u = 0; u < kTTChunk; ++u)
@@ -628,14 +627,19 @@ __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
     if (!colv) continue;
     const int obox = a.mode == 0 ? 4 * parent + c : parent;
     if (a.mode == 1 && a.fout && !a.fout[obox]) continue;
+    // L2L adds to the M2L part already there: the 4 old values load together
+    T* dst[4];
+    T old[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = rt * 16 + out_row<T>(kq, q);
-      if (i < 2 * a.Pout) {
-        T* dst = reinterpret_cast<T*>(a.out + ((size_t)obox * a.nrhs + a.r0 + r) * a.Pout + (i < a.Pout ? i : i - a.Pout));
-        dst[i < a.Pout ? 0 : 1] = a.mode == 0 ? dst[i < a.Pout ? 0 : 1] + s[q] : s[q];
-      }
+      const int i = min(rt * 16 + out_row<T>(kq, q), 2 * a.Pout - 1);
+      dst[q] = reinterpret_cast<T*>(a.out + ((size_t)obox * a.nrhs + a.r0 + r) * a.Pout + (i < a.Pout ? i : i - a.Pout)) +
+               (i < a.Pout ? 0 : 1);
+      old[q] = a.mode == 0 ? *dst[q] : T(0);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (rt * 16 + out_row<T>(kq, q) < 2 * a.Pout) *dst[q] = old[q] + s[q];
   }
 }
 
