@@ -30,7 +30,7 @@ struct LevelInfo {
 // Launch shape of the MFMA downward pass at one level.
 struct MfmaLevel {
   bool on = false;
-  int RT = 0, KS = 0, KSp = 0, KSc = 0, tile = 0, gx = 0, gy = 0;
+  int RT = 0, KS = 0, KSA = 0, KSp = 0, KSc = 0, tile = 0, gx = 0, gy = 0;
   int KSL = 0, KSL4 = 0;           // M2L k steps per LDS slice (8 x 8 and 4 x 4 tiles)
   int64_t af = 0, wf = 0, mm = 0;  // offsets into the M2L / L2L / M2M fragment tables
   size_t lds = 0, lds4 = 0;        // LDS of the default tile and of the 4 x 4 tile

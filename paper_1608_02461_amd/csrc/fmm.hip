@@ -317,9 +317,12 @@ template <class T>
 struct M2LLevel {
   const cplx<T>* M;
   cplx<T>* Lc;
-  const T* Af;          // [49][RT][KS][64]
+  const T* Af;          // [49][RT][KSA][64]
   const uint8_t* fsrc;  // source flags of the level or NULL
-  int nb, P, RT, KS, KSL, tile, gx, block0;  // KSL: k steps per LDS slice (a multiple of 4)
+  // KS = ceil(2 P / 4) k steps; KSA = KS rounded up to 4 (the table's
+  // stride, zero beyond KS); KSL: k steps per LDS slice (all KS, or a
+  // multiple of 4)
+  int nb, P, RT, KS, KSA, KSL, tile, gx, block0;
 };
 
 template <class T>
@@ -362,19 +365,18 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
   const int WW = min(a.nb, bx0 + a.tile + 2) - wx0, WH = min(a.nb, by0 + a.tile + 2) - wy0;
   const int zb = WW * WH;  // the zero box
   const int P = a.P, KS = a.KS, KSL = a.KSL;
-  const int KPs = 4 * KSL + 2;  // LDS stride of one box's slice
-  constexpr int pside = NP == 4 ? 2 : 1;
+  const int KPs = 4 * ((KSL + 3) & ~3) + 2;  // LDS stride of one box's slice (whole chunks)
   const int j = lane & 15, kq = lane >> 4;
   int tx[NP], ty[NP];
   uint32_t tbox[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    tx[p] = bx0 + (p % pside) * 4 + (j & 3);
-    ty[p] = by0 + (p / pside) * 4 + (j >> 2);
+    tx[p] = bx0 + (p & 1) * 4 + (j & 3);
+    ty[p] = by0 + (p >> 1) * 4 + (j >> 2);
     tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
   }
-  const size_t cstride = (size_t)a.RT * KS * 64;
-  const T* Abase = a.Af + (size_t)rt * KS * 64 + lane;
+  const size_t cstride = (size_t)a.RT * a.KSA * 64;
+  const T* Abase = a.Af + (size_t)rt * a.KSA * 64 + lane;
   // LDS position of the source box of class o for patch p (the zero box when
   // it is outside the grid or not adjacent to the target's parent)
   auto src_base = [&](int o, int p) {
@@ -389,7 +391,6 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = V4{0, 0, 0, 0};
     for (int k0 = 0; k0 < KS; k0 += KSL) {
-      const int nch = min(KSL, KS - k0) >> 2;  // whole chunks of 4 k steps
       __syncthreads();
       // stage the slice [4 k0, 4 k0 + 4 KSL) of the real columns of the
       // window.  Lanes in groups of P take one complex coefficient each of
@@ -451,8 +452,11 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
       const T* Ab = Abase + (size_t)k0 * 64;  // this slice's k steps
       // the wave's 10 offset classes (class index = wave mod 4) one after
       // another; the A fragments of the next chunk, also across classes,
-      // load one chunk ahead
+      // load one chunk ahead.  The last chunk of a slice may have fewer than
+      // 4 k steps (ns).
       auto cls = [&](int i) { return kClassO[8 * (i % 5) + w + 4 * (i / 5)]; };
+      const int nst = min(KSL, KS - k0);
+      const int nch = (nst + 3) >> 2;
       T an[4];
       {
         const T* A0 = Ab + (size_t)cls(0) * cstride;
@@ -478,15 +482,17 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
 #pragma unroll
             for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
           }
+          const int ns = min(4, nst - 4 * c);
           T bv[NP][4];
 #pragma unroll
           for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];
+            for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];  // in the box's stride
 #pragma unroll
           for (int u = 0; u < 4; ++u)
+            if (u < ns)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
+              for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
         }
       }
     }
@@ -516,8 +522,13 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
   }
 }
 
+// FP32: at most 96 registers per lane (88 used), so that a block fits
+// beside four near-field blocks on a CU
+template <class T> struct M2LWaves { static constexpr int value = sizeof(T) == 4 ? 5 : 1; };
+
 template <class T>
-__global__ __launch_bounds__(kM2LThreads) void k_m2l_mfma(M2LAllArgs<T> args) {
+__global__ __launch_bounds__(kM2LThreads) __attribute__((amdgpu_waves_per_eu(M2LWaves<T>::value)))
+void k_m2l_mfma(M2LAllArgs<T> args) {
   extern __shared__ unsigned char smem_raw[];
   chain_priority();
   T* Ms = reinterpret_cast<T*>(smem_raw);
@@ -858,7 +869,8 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       MfmaLevel& m = pl->mf[l];
       const int P = pl->lv[l].P, nb = 1 << l;
       m.RT = (2 * P + 15) / 16;
-      m.KS = 4 * ((2 * P + 15) / 16);  // whole chunks of 4 k steps; the padding is zero
+      m.KS = (2 * P + 3) / 4;      // k steps of 4 (the padding is zero)
+      m.KSA = (m.KS + 3) / 4 * 4;  // table stride: whole chunks of 4 k steps
       // M2L window: a tile of 8 x 8 targets (4 x 4 on a 4 x 4 grid, or by
       // the autotuner): the window plus one zero box in at most kM2LLds bytes
       // of LDS (the block also needs room for the partial sums of 4 waves);
@@ -866,7 +878,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       // of KSL k steps
       auto window = [&](int tile, int ksl) {
         const int win = std::min(nb, std::min(tile, nb) + 4);
-        return (size_t)(win * win + 1) * (4 * ksl + 2) * sizeof(T);
+        return (size_t)(win * win + 1) * (4 * ((ksl + 3) / 4 * 4) + 2) * sizeof(T);
       };
       auto lds_for = [&](int tile, int ksl) {
         const int np = tile >= 8 && nb >= 8 ? 4 : 1;
@@ -894,7 +906,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
       m.gy = m.RT;
       if (m.on || m.fit4) {
         m.af = (int64_t)haf.size();
-        frag(haf, m.af, 49, m.RT, m.KS, P, P, [&](int o, int mo, int ni) -> cplx<T> {
+        frag(haf, m.af, 49, m.RT, m.KSA, P, P, [&](int o, int mo, int ni) -> cplx<T> {
           const int ox = o / 7 - 3, oy = o % 7 - 3;
           if (std::max(std::abs(ox), std::abs(oy)) < 2) return mk<T>(0, 0);
           return hm2l[pl->m2l_off[l] + ((size_t)o * P + ni) * P + mo];
@@ -1063,6 +1075,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
     v.RT = mf.RT;
     v.KS = mf.KS;
     v.KSL = small ? mf.KSL4 : mf.KSL;
+    v.KSA = mf.KSA;
     v.tile = tile;
     v.gx = ((1 << l) / tile) * ((1 << l) / tile);
     v.block0 = blocks;
