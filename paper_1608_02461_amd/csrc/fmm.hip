@@ -1286,17 +1286,15 @@ void autotune(const Tree& t, FmmPlan<T>& pl) {
       return best;
     };
     const P2PArgs<T> a = p2p_args<T>(t, pl, pl.qs.p, pl.phis.p, 1, 0, nullptr, false, nullptr);
+    // the fastest G; a larger G within 5 % of it wins (the choice stays
+    // the same from one plan to the next when two are that close)
     int bestG = pl.G;
     float bestms = 1e30f;
     const int Gs[3] = {1, 2, 4};
-    for (int i = 0; i < 3; ++i) {
-      const float ms = timed([&] { launch_p2p<T, 1>(t, pl, a, Gs[i], st); });
-      pl.tune_ms[i] = ms;
-      if (ms < bestms) {
-        bestms = ms;
-        bestG = Gs[i];
-      }
-    }
+    for (int i = 0; i < 3; ++i) pl.tune_ms[i] = timed([&] { launch_p2p<T, 1>(t, pl, a, Gs[i], st); });
+    for (int i = 0; i < 3; ++i) bestms = std::min(bestms, pl.tune_ms[i]);
+    for (int i = 0; i < 3; ++i)
+      if (pl.tune_ms[i] <= 1.05f * bestms) bestG = Gs[i];
     pl.G = bestG;
     if (pl.use_mfma) {
       bool any_choice = false;
