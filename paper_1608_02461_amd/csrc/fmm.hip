@@ -93,24 +93,30 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
 
 // ------------------------------------------------------------------ P2M
-template <class T, int NR>
+template <class T, int NR, int LPW>
 __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
                                             const cplx<T>* __restrict__ q, int64_t N, int nrhs, int r0,
                                             cplx<T>* __restrict__ Mout, int pL, T wscale, T yscale, int K,
                                             const uint8_t* __restrict__ flags, const int* __restrict__ alive,
                                             const int32_t* __restrict__ gperm, cplx<T>* __restrict__ qs_out) {
   extern __shared__ unsigned char smem_raw[];
-  // blockDim / 64 leaves per block, one wave each; every wave has its own
-  // LDS region
+  // blockDim / 64 waves per block, LPW consecutive leaves per wave (small
+  // leaves share a wave so that its lanes stay busy); every wave has its own
+  // LDS region.  The basis of a chunk of 64 points is leaf-independent (the
+  // positions are relative to their own leaf); the sums then take lanes
+  // (leaf l, group g, order n).
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int leaf = (int)(blockDim.x >> 6) * blockIdx.x + w;
+  const int leaf0 = ((int)(blockDim.x >> 6) * blockIdx.x + w) * LPW;
   if (alive && !alive[0]) return;
-  if (flags && !flags[leaf]) return;
+  if (LPW == 1 && flags && !flags[leaf0]) return;
   cplx<T>* sb = reinterpret_cast<cplx<T>*>(smem_raw) + (size_t)w * max(pL + 1 + NR, 2 * NR) * 64;  // [(pL+1)][64]
   cplx<T>* sq = sb + (pL + 1) * 64;                     // [NR][64]
   const int P = 2 * pL + 1;
-  const int G = 64 / (pL + 1), g = lane / (pL + 1), n = lane - g * (pL + 1);
-  const int t0 = leaf_off[leaf], t1 = leaf_off[leaf + 1];
+  const int per = pL + 1, G = 64 / (LPW * per);  // groups per (leaf, order)
+  const int l = lane / (G * per), lr = lane - l * G * per, g = lr / per, n = lr - g * per;
+  const bool accl = l < LPW;
+  const int t0 = leaf_off[leaf0], t1 = leaf_off[leaf0 + LPW];
+  const int lo_l = accl ? leaf_off[leaf0 + l] : 0, hi_l = accl ? leaf_off[leaf0 + l + 1] : 0;
   cplx<T> accP[NR], accN[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) accP[r] = accN[r] = mk<T>(0, 0);
@@ -151,9 +157,11 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
       }
     }
     wave_lds_sync();
-    // lane = (group g, order n): the G groups split the points of the chunk
-    if (g < G) {
-      for (int j = g; j < cnt; j += G) {
+    // lane = (leaf l, group g, order n): the G groups split the chunk's
+    // points of leaf l
+    if (accl) {
+      const int jl = max(lo_l, c0) - c0, jh = min(hi_l, c0 + cnt) - c0;
+      for (int j = jl + g; j < jh; j += G) {
         const cplx<T> b = sb[n * 64 + j];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -165,9 +173,9 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
     }
     wave_lds_sync();
   }
-  // sum the G partial sums of each order (sb is free again)
+  // sum the G partial sums of each (leaf, order) (sb is free again)
   cplx<T>* red = sb;  // [NR][2][64]
-  if (g < G) {
+  if (accl) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       red[(r * 2 + 0) * 64 + lane] = accP[r];
@@ -175,23 +183,24 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
     }
   }
   wave_lds_sync();
-  if (lane <= pL) {
+  const int leaf = leaf0 + l;
+  if (accl && g == 0 && (LPW == 1 || !flags || flags[leaf])) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       cplx<T> sp = accP[r], sn = accN[r];
       for (int gg = 1; gg < G; ++gg) {
-        const cplx<T> a = red[(r * 2 + 0) * 64 + gg * (pL + 1) + lane];
-        const cplx<T> b = red[(r * 2 + 1) * 64 + gg * (pL + 1) + lane];
+        const cplx<T> a = red[(r * 2 + 0) * 64 + lane + gg * per];
+        const cplx<T> b = red[(r * 2 + 1) * 64 + lane + gg * per];
         sp.x += a.x;
         sp.y += a.y;
         sn.x += b.x;
         sn.y += b.y;
       }
       const size_t base = ((size_t)leaf * nrhs + r0 + r) * P;
-      Mout[base + pL + lane] = sp;
-      if (lane > 0) {
-        const T sg = (lane & 1) ? T(-1) : T(1);
-        Mout[base + pL - lane] = mk<T>(sg * sn.x, sg * sn.y);
+      Mout[base + pL + n] = sp;
+      if (n > 0) {
+        const T sg = (n & 1) ? T(-1) : T(1);
+        Mout[base + pL - n] = mk<T>(sg * sn.x, sg * sn.y);
       }
     }
   }
@@ -1212,10 +1221,22 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     const LevelInfo& lf = pl.lv[L];
     // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
     const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
-    const int lpb = 4 * sh <= 65536 ? 4 : (2 * sh <= 65536 ? 2 : 1);  // leaves per block
-    k_p2m<T, NR><<<(int)(t.nleaves / lpb), 64 * lpb, lpb * sh, st>>>(t.leaf_off.p, rel, q, N, nrhs, r0, pl.M.p + lf.coef * nrhs, lf.p,
-                                                 T(k / (2 * lf.s)), T(k * k / 4), pl.K,
-                                                 flags ? flags + lf.box0 : nullptr, alive, perm, qs);
+    const int lpb = 4 * sh <= 65536 ? 4 : (2 * sh <= 65536 ? 2 : 1);  // waves per block
+    // leaves per wave: small leaves share a wave
+    const double mean = double(N) / double(t.nleaves);
+    const int lpw = (mean <= 20 && 4 * (lf.p + 1) <= 64) ? 4 : ((mean <= 40 && 2 * (lf.p + 1) <= 64) ? 2 : 1);
+    auto p2m = [&](auto lc) {
+      constexpr int LPW = decltype(lc)::value;
+      k_p2m<T, NR, LPW><<<(int)(t.nleaves / (lpb * LPW)), 64 * lpb, lpb * sh, st>>>(
+          t.leaf_off.p, rel, q, N, nrhs, r0, pl.M.p + lf.coef * nrhs, lf.p, T(k / (2 * lf.s)), T(k * k / 4), pl.K,
+          flags ? flags + lf.box0 : nullptr, alive, perm, qs);
+    };
+    if (lpw == 4)
+      p2m(std::integral_constant<int, 4>{});
+    else if (lpw == 2)
+      p2m(std::integral_constant<int, 2>{});
+    else
+      p2m(std::integral_constant<int, 1>{});
     HFMM_LAUNCH_CHECK();
     const int e_p2m = tm ? tm->mark(1, st) : -1;
     if (overlap) {
