@@ -204,7 +204,7 @@ __global__ void k_vg_gather(const cplx<T>* __restrict__ phi, const int32_t* __re
 }
 
 // q2[boundary slot a] = sum_b B[a][b] vg[b]; one wave per row, up to 8 columns.
-template <class T>
+template <class T, int NC>
 __global__ __launch_bounds__(256) void k_bgemv(const cplx<T>* __restrict__ B, const cplx<T>* __restrict__ vg, int ng,
                                                const int32_t* __restrict__ iperm, int64_t nn, int64_t N,
                                                cplx<T>* __restrict__ q2, int nrhs, const int* __restrict__ alive) {
@@ -212,23 +212,28 @@ __global__ __launch_bounds__(256) void k_bgemv(const cplx<T>* __restrict__ B, co
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (a >= ng) return;
-  for (int c0 = 0; c0 < nrhs; c0 += 8) {
-    T ar[8], ai[8];
+  for (int c0 = 0; c0 < nrhs; c0 += NC) {
+    // NC columns per pass; a column past nrhs repeats the last one and is
+    // not written, so every load is unconditional and several row loads
+    // stay in flight (the kernel streams B)
+    const cplx<T>* vc[NC];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) ar[c] = ai[c] = T(0);
+    for (int c = 0; c < NC; ++c) vc[c] = vg + (int64_t)min(c0 + c, nrhs - 1) * ng;
+    T ar[NC], ai[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ar[c] = ai[c] = T(0);
+#pragma unroll 8
     for (int b = lane; b < ng; b += 64) {
       const cplx<T> m = B[(int64_t)a * ng + b];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c0 + c < nrhs) {
-          const cplx<T> v = vg[(int64_t)(c0 + c) * ng + b];
-          ar[c] += m.x * v.x - m.y * v.y;
-          ai[c] += m.x * v.y + m.y * v.x;
-        }
+      for (int c = 0; c < NC; ++c) {
+        const cplx<T> v = vc[c][b];
+        ar[c] += m.x * v.x - m.y * v.y;
+        ai[c] += m.x * v.y + m.y * v.x;
       }
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < NC; ++c) {
       for (int off = 32; off > 0; off >>= 1) {
         ar[c] += __shfl_xor(ar[c], off);
         ai[c] += __shfl_xor(ai[c], off);
@@ -237,7 +242,7 @@ __global__ __launch_bounds__(256) void k_bgemv(const cplx<T>* __restrict__ B, co
     if (lane == 0) {
       const int64_t slot = iperm[nn + a];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
+      for (int c = 0; c < NC; ++c)
         if (c0 + c < nrhs) q2[(int64_t)(c0 + c) * N + slot] = mk<T>(ar[c], ai[c]);
     }
   }
@@ -575,7 +580,10 @@ void precond_impl(Solver& s, const double2* r, int64_t rs, double2* z, int64_t z
   fmm_sorted<T>(t, pl, q1, phi, nr, s.flags1.p, false, st, alive);
   k_vg_gather<T><<<nblocks(s.ng * nr), 256, 0, st>>>(phi, t.iperm.p, s.nn, (int)s.ng, N, vg, nr, alive);
   HFMM_LAUNCH_CHECK();
-  k_bgemv<T><<<(int)((s.ng + 3) / 4), 256, 0, st>>>(B_of<T>(s).p, vg, (int)s.ng, t.iperm.p, s.nn, N, q2, nr, alive);
+  if (nr == 1)
+    k_bgemv<T, 1><<<(int)((s.ng + 3) / 4), 256, 0, st>>>(B_of<T>(s).p, vg, (int)s.ng, t.iperm.p, s.nn, N, q2, nr, alive);
+  else
+    k_bgemv<T, 4><<<(int)((s.ng + 3) / 4), 256, 0, st>>>(B_of<T>(s).p, vg, (int)s.ng, t.iperm.p, s.nn, N, q2, nr, alive);
   HFMM_LAUNCH_CHECK();
   fmm_sorted<T>(t, pl, q2, phi, nr, s.flags2.p, true, st, alive);
   const double2 sv = make_double2(s.svol.real(), s.svol.imag());
