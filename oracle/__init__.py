@@ -10,22 +10,25 @@ Preconditioner for the Helmholtz Equation based on the Fast Multipole
 Method"), in plain numpy/scipy FP64, with no blocking or fusion beyond what
 the definitions state:
 
-* ``kernel``   -- the 2-D free-space kernel G = (i/4) H0(k r) (Sec. 5.2, the
-                  2-D Green's function) and the direct N-body sum (Sec. 5.1,
-                  the N-body sum equation).
+* ``kernel``   -- the 2-D free-space kernel G = (i/4) H0(k r) and its normal
+                  derivative dG/dn (Sec. 5.2) and the direct N-body sums
+                  (Sec. 5.1, the N-body sum equation).
 * ``fmm``      -- a reference FMM (Sec. 5.1.2: P2M, M2M, M2L, L2L, L2P, P2P on
                   the quad-tree of Sec. 5.1.1) written with Graf's addition
                   theorem, so that "the oracle's own FMM error at order p" has
                   a meaning.
 * ``bem``      -- the dense BEM preconditioner of Sec. 5.2-5.3 (Dirichlet
                   boundary equation, interior equation, constant elements and
-                  the analytic singular diagonal).
+                  the analytic singular diagonal), and the solution with
+                  inhomogeneous Dirichlet data (double layer and 1/2 delta).
 * ``fd``       -- the 5-point finite-difference Helmholtz matrix.
 * ``fgmres``   -- right-preconditioned restarted flexible GMRES (Sec. 3-4).
+* ``bicgstab`` -- right-preconditioned BiCGSTAB, the short-recurrence
+                  alternative of Sec. 3.
 * ``adjoint``  -- the adjoint gradient dJ/dk^2 by sparse direct solves.
 
 Every function names the passage it follows.  Readings of passages where the
 paper is silent or ambiguous are stated at the function.
 """
 
-from . import kernel, fmm, bem, fd, fgmres, adjoint  # noqa: F401
+from . import kernel, fmm, bem, fd, fgmres, bicgstab, adjoint  # noqa: F401

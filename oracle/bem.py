@@ -125,12 +125,28 @@ def precond_apply(n, k, r):
     return v_omega + w * (Gog @ q)
 
 
-def precond_apply_fmm(n, k, r, p, leaf):
-    """The same preconditioner with the two N-body sums done by the reference FMM.
+def boundary_normals(n):
+    """Outward unit normals of the elements, in the order of boundary_nodes."""
+    m = n + 1
+    return np.concatenate([np.tile([0.0, -1.0], (m, 1)), np.tile([1.0, 0.0], (m, 1)),
+                           np.tile([0.0, 1.0], (m, 1)), np.tile([-1.0, 0.0], (m, 1))])
+
+
+def precond_apply_fmm(n, k, r, p, leaf, targets=None, g=None):
+    """The same preconditioner with the N-body sums done by the reference FMM.
 
     Pass 1: sources h^2 r at the interior nodes, targets all nodes (the tree is
     built over interior and boundary nodes together).  Boundary solve.  Pass 2:
     sources w q at the boundary nodes, targets the interior nodes.
+
+    targets : optional interior node indices; z is then computed only there
+              (pass 1 at the boundary nodes and those targets, pass 2 at the
+              targets), which keeps large grids cheap.
+    g       : optional Dirichlet data at the boundary midpoints (Sec. 5.2 with
+              u = g on Gamma): pass 1 also carries the double layer
+              -w sum_b g_b dG/dn_b, the boundary equation takes the 1/2 delta
+              term, S q = g/2 + D_Gamma - V_Gamma, and the interior equation
+              keeps -D_Omega (see dirichlet_solve).
     """
     from .fmm import fmm
 
@@ -138,21 +154,76 @@ def precond_apply_fmm(n, k, r, p, leaf):
     w = h
     xo, xg = interior_nodes(n), boundary_nodes(n)
     pts = np.concatenate([xo, xg])
-    no = xo.shape[0]
+    no, ng = xo.shape[0], xg.shape[0]
     r = np.asarray(r, dtype=np.complex128)
     squeeze = r.ndim == 1
     if squeeze:
         r = r[:, None]
+    tg = np.arange(no) if targets is None else np.asarray(targets, dtype=np.int64)
+    t1 = np.concatenate([tg, no + np.arange(ng)])
     src1 = np.zeros((pts.shape[0], r.shape[1]), dtype=np.complex128)
     src1[:no] = h * h * r
-    phi1 = fmm(pts, src1, k, p, leaf)
-    v_omega = phi1[:no] + volume_self(k, h) * r
-    v_gamma = phi1[no:]
+    phi1 = fmm(pts, src1, k, p, leaf, targets=t1)
+    if g is not None:
+        g = np.asarray(g, dtype=np.complex128).reshape(ng, -1)
+        nrm = np.zeros((pts.shape[0], 2))
+        nrm[no:] = boundary_normals(n)
+        srcd = np.zeros_like(src1)
+        srcd[no:] = -w * g
+        phi1 = phi1 + fmm(pts, srcd, k, p, leaf, targets=t1, normals=nrm)
+    v_omega = phi1[:tg.size] + volume_self(k, h) * r[tg]
+    v_gamma = phi1[tg.size:]
     Sw = _pair_matrix(xg, xg, k)
     Sw[np.diag_indices_from(Sw)] = boundary_self(k, w) / w
-    q = -np.linalg.solve(w * Sw, v_gamma)
+    rhs = -v_gamma if g is None else 0.5 * g - v_gamma
+    q = np.linalg.solve(w * Sw, rhs)
     src2 = np.zeros_like(src1)
     src2[no:] = w * q
-    phi2 = fmm(pts, src2, k, p, leaf)
-    z = v_omega + phi2[:no]
+    phi2 = fmm(pts, src2, k, p, leaf, targets=tg)
+    z = v_omega + phi2
     return z[:, 0] if squeeze else z
+
+
+def double_layer_blocks(n, k):
+    """D_OG[i, b] = dG/dn_b(x_i, y_b) and D_GG[a, b] = dG/dn_b(y_a, y_b) (a != b).
+
+    The diagonal of D_GG is zero: on a flat constant element (x - y).n = 0
+    for every y of the element, so the element exerts no double-layer field
+    on its own midpoint (one-point quadrature elsewhere, as for G).
+    """
+    from .kernel import dgreen_dn
+
+    xo, xg, nrm = interior_nodes(n), boundary_nodes(n), boundary_normals(n)
+    Dog = dgreen_dn(xo[:, None, :], xg[None, :, :], nrm[None, :, :], k)
+    X = np.broadcast_to(xg[:, None, :], (xg.shape[0], xg.shape[0], 2))
+    Y = np.broadcast_to(xg[None, :, :], X.shape)
+    Nn = np.broadcast_to(nrm[None, :, :], X.shape)
+    Dgg = np.zeros(X.shape[:2], dtype=np.complex128)
+    off = ~np.eye(xg.shape[0], dtype=bool)
+    Dgg[off] = dgreen_dn(X[off], Y[off], Nn[off], k)
+    return Dog, Dgg
+
+
+def dirichlet_solve(n, k, f, g):
+    """Boundary-element solution with source f and Dirichlet data g (Sec. 5.2), dense.
+
+    Green's representation with the Cauchy factor (1/2 on the smooth boundary
+    points, 1 inside) for -Laplace(u) - k^2 u = f:
+        eta u = int_Omega f G + int_Gamma (du/dn) G - int_Gamma u dG/dn.
+    On the boundary (eq. ubound) the unknown q = du/dn solves
+        S q = g/2 + w D_GG g - V_Gamma,     S = w G_GG (analytic diagonal),
+    and inside (eq. uinter)
+        u = V_Omega + w G_OG q - w D_OG g,
+    with V = h^2 G f the volume potential (midpoint rule, exact self cell).
+    f : (n*n,) interior values; g : (4(n+1),) values at the element midpoints.
+    """
+    h = 1.0 / (n + 1)
+    w = h
+    Goo, Gog, Sw = blocks(n, k)
+    Dog, Dgg = double_layer_blocks(n, k)
+    f = np.asarray(f, dtype=np.complex128)
+    g = np.asarray(g, dtype=np.complex128)
+    v_omega = h * h * (Goo @ f)
+    v_gamma = h * h * (Gog.T @ f)
+    q = np.linalg.solve(w * Sw, 0.5 * g + w * (Dgg @ g) - v_gamma)
+    return v_omega + w * (Gog @ q) - w * (Dog @ g)

@@ -34,7 +34,7 @@ import math
 import numpy as np
 from scipy.special import hankel1, jv
 
-from .kernel import green
+from .kernel import dgreen_dn, green
 
 
 def tree_depth(n_points, leaf):
@@ -74,17 +74,28 @@ def box_center(l, bx, by, root):
     return (x0 + (bx + 0.5) * s) + 1j * (y0 + (by + 0.5) * s)
 
 
-def fmm(xy, q, k, p, leaf, root=(0.0, 0.0, 1.0), targets=None, return_stages=False):
+def fmm(xy, q, k, p, leaf, root=(0.0, 0.0, 1.0), targets=None, return_stages=False, normals=None):
     """Reference FMM: phi_i ~ sum_{j != i} q_j (i/4) H0(k |x_i - x_j|).
 
     xy : (N, 2) float64 points (sources = targets).  q : (N,) or (N, nrhs).
     targets : optional integer indices; only those potentials are computed
               (the downward pass runs only on their ancestors).
+    normals : optional (N, 2) unit normals; the sources are then dipoles and
+              the sum is phi_i ~ sum_j q_j dG/dn_j(x_i, x_j) (the double layer
+              of Sec. 5.2).  Only P2M and P2P change: the multipole of a
+              dipole is the derivative of the monopole's along n at the source,
+                  M_n = q (n . grad_y) [J_n(k rho) e^{-i n phi}]
+                      = q (k/2) [conj(nu) b_{n-1} - nu b_{n+1}],
+              b_m = J_m(k rho) e^{-i m phi}, nu = n_x + i n_y, which follows
+              from the ladder relations (d/dx +- i d/dy) of the cylinder
+              functions (DLMF 10.6.2).
     Returns phi for the targets (all points by default) and, if asked, a dict
     with the per-level orders and the multipole/local arrays.
     """
     xy = np.asarray(xy, dtype=np.float64)
     q = np.asarray(q, dtype=np.complex128)
+    if normals is not None:
+        normals = np.asarray(normals, dtype=np.float64)
     squeeze = q.ndim == 1
     if squeeze:
         q = q[:, None]
@@ -105,7 +116,14 @@ def fmm(xy, q, k, p, leaf, root=(0.0, 0.0, 1.0), targets=None, return_stages=Fal
         n = np.arange(-P, P + 1)
         c = box_center(L, ix, iy, root)
         rel = pts - c
-        terms = jv(n[None, :], k * np.abs(rel)[:, None]) * np.exp(-1j * n[None, :] * np.angle(rel)[:, None])
+        def b(m):
+            return jv(m[None, :], k * np.abs(rel)[:, None]) * np.exp(-1j * m[None, :] * np.angle(rel)[:, None])
+
+        if normals is None:
+            terms = b(n)
+        else:
+            nu = (normals[:, 0] + 1j * normals[:, 1])[:, None]
+            terms = 0.5 * k * (np.conj(nu) * b(n - 1) - nu * b(n + 1))
         M = {L: np.zeros((2 ** L, 2 ** L, 2 * P + 1, nrhs), dtype=np.complex128)}
         np.add.at(M[L], (ix, iy), terms[:, :, None] * q[:, None, :])
 
@@ -196,7 +214,13 @@ def fmm(xy, q, k, p, leaf, root=(0.0, 0.0, 1.0), targets=None, return_stages=Fal
         r = np.abs(pts[tidx[rows]][:, None] - pts[src][None, :])
         g = np.zeros(r.shape, dtype=np.complex128)
         use = r > 0
-        g[use] = green(r[use], k)
+        if normals is None:
+            g[use] = green(r[use], k)
+        else:
+            X = np.broadcast_to(xy[tidx[rows]][:, None, :], r.shape + (2,))
+            Y = np.broadcast_to(xy[src][None, :, :], r.shape + (2,))
+            Nn = np.broadcast_to(normals[src][None, :, :], r.shape + (2,))
+            g[use] = dgreen_dn(X[use], Y[use], Nn[use], k)
         phi[rows] += g @ q[src]
 
     phi = phi[:, 0] if squeeze else phi

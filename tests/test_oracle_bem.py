@@ -109,3 +109,73 @@ def test_fmm_form_converges_to_dense():
     ref = bem.precond_apply(n, k, r)
     e = [np.linalg.norm(bem.precond_apply_fmm(n, k, r, p, 8) - ref) / np.linalg.norm(ref) for p in (3, 6, 20)]
     assert e[0] > e[1] > e[2] and e[2] < 1e-10
+
+
+def _helm2(mu):
+    """The paper's inhomogeneous-Dirichlet problem (Sec. 6, eq. helm2) with
+    kappa = mu sqrt(2), in the sign convention -Laplace(u) - k^2 u = f (the
+    paper's right-hand side negated): exact u = x^2 sin(mu x) cos(mu y)."""
+    def u(P):
+        return P[:, 0] ** 2 * np.sin(mu * P[:, 0]) * np.cos(mu * P[:, 1])
+
+    def f(P):
+        return -(2 * np.sin(mu * P[:, 0]) * np.cos(mu * P[:, 1]) + 4 * mu * P[:, 0] * np.cos(mu * P[:, 0]) *
+                 np.cos(mu * P[:, 1]))
+    return mu * math.sqrt(2.0), u, f
+
+
+@pytest.mark.parametrize("mu", [1.0, 4.0])
+def test_dirichlet_solve_reproduces_helm2(mu):
+    """With f and the boundary values of the exact solution, the boundary
+    equation (1/2 delta and double layer) and the interior equation give u
+    with an error that falls with h; a wrong sign or a missing double layer
+    leaves an O(1) error."""
+    k, u, f = _helm2(mu)
+    errs = []
+    for n in (15, 31):
+        xo, xg = bem.interior_nodes(n), bem.boundary_nodes(n)
+        us = bem.dirichlet_solve(n, k, f(xo), u(xg))
+        errs.append(np.linalg.norm(us - u(xo)) / np.linalg.norm(u(xo)))
+    assert errs[1] < 0.5 * errs[0]
+    assert errs[1] < (5e-3 if mu == 1.0 else 2e-2)
+
+
+def test_dirichlet_solve_plane_wave_and_zero_data():
+    """f = 0 with the boundary values of a plane wave reproduces the wave
+    inside (error falling with h); g = 0 is the preconditioner apply."""
+    k, a = 10.0, 0.3
+    errs = []
+    for n in (15, 31):
+        xo, xg = bem.interior_nodes(n), bem.boundary_nodes(n)
+        pw = lambda P: np.exp(1j * k * (P[:, 0] * math.cos(a) + P[:, 1] * math.sin(a)))
+        us = bem.dirichlet_solve(n, k, np.zeros(n * n), pw(xg))
+        errs.append(np.linalg.norm(us - pw(xo)) / np.linalg.norm(pw(xo)))
+    assert errs[1] < 0.5 * errs[0] and errs[1] < 0.2
+    n = 12
+    r = np.random.default_rng(3).standard_normal(n * n) + 0j
+    assert np.allclose(bem.dirichlet_solve(n, 9.0, r, np.zeros(4 * (n + 1))), bem.precond_apply(n, 9.0, r),
+                       rtol=1e-12, atol=1e-14)
+
+
+def test_boundary_normals_are_outward():
+    n = 7
+    xg, nrm = bem.boundary_nodes(n), bem.boundary_normals(n)
+    out = xg + 1e-3 * nrm
+    assert np.all(((out < 0) | (out > 1)).any(axis=1))
+
+
+def test_fmm_form_targets_and_dirichlet_data():
+    """The FMM form at a subset of targets equals the full FMM form there, and
+    with Dirichlet data it converges to the dense solution as p grows."""
+    n, k, leaf = 20, 14.0, 8
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
+    g = rng.standard_normal(4 * (n + 1)) + 1j * rng.standard_normal(4 * (n + 1))
+    tg = np.sort(rng.choice(n * n, 37, replace=False))
+    full = bem.precond_apply_fmm(n, k, r, 10, leaf)
+    part = bem.precond_apply_fmm(n, k, r, 10, leaf, targets=tg)
+    assert np.allclose(part, full[tg], rtol=1e-12, atol=1e-14)
+    dense = bem.dirichlet_solve(n, k, r, g)
+    errs = [np.linalg.norm(bem.precond_apply_fmm(n, k, r, p, leaf, g=g) - dense) / np.linalg.norm(dense)
+            for p in (4, 10, 30)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-12

@@ -95,3 +95,25 @@ def test_all_pairs_mode_is_direct(cloud):
     f = fmm.fmm(xy[:200], q[:200], 50.0, 4, leaf=0)
     ref = kernel.direct_sum(xy[:200], q[:200], 50.0)
     assert np.allclose(f, ref, rtol=1e-13)
+
+
+@pytest.mark.parametrize("k", [16.0, 60.0])
+def test_dipole_error_falls_with_p(cloud, k):
+    """Dipole sources (the double layer): the P2M of a dipole is the exact
+    derivative of the monopole expansion, so the FMM error against the direct
+    dG/dn sum falls with p to round-off, as for G."""
+    xy, q = cloud
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0, 2 * np.pi, xy.shape[0])
+    nrm = np.stack([np.cos(a), np.sin(a)], 1)
+    ref = kernel.direct_sum_dipole(xy, q, nrm, k)
+    errs = []
+    for p in (2, 4, 8, 14, 24):
+        f = fmm.fmm(xy, q, k, p, leaf=16, normals=nrm)
+        errs.append(np.linalg.norm(f - ref) / np.linalg.norm(ref))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-11
+    # targets give the same values
+    t = np.arange(0, xy.shape[0], 7)
+    ft = fmm.fmm(xy, q, k, 14, leaf=16, normals=nrm, targets=t)
+    assert np.allclose(ft, fmm.fmm(xy, q, k, 14, leaf=16, normals=nrm)[t], rtol=1e-13, atol=1e-13)
