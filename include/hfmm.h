@@ -56,8 +56,12 @@ typedef struct {
   int32_t nrhs;
   double rel_res_true;    /* max over columns of ||b - A x|| / ||b|| at exit */
   double rel_res_est;     /* max over columns of the Givens estimate at exit */
-  double ms_precond;      /* device time in preconditioner applies (ms) */
+  double ms_precond;      /* device time in preconditioner applies (ms); 0 when not
+                             measured (batched solves) */
+  double ms_krylov;       /* device time of the rest of the Arnoldi steps: FD matvec,
+                             CGS2, norms, Givens (ms); 0 when not measured */
   double ms_total;        /* wall time of the solve call (ms) */
+  double ms_setup;        /* wall time of hfmm_solver_create for this solver (ms) */
 } hfmm_solve_info;
 
 /* Thread-local text of the last non-OK status on this thread ("" if none). */
@@ -93,6 +97,17 @@ hfmm_status hfmm_tree_info(hfmm_tree t, int32_t* levels, int64_t* n_points, int6
 hfmm_status hfmm_tree_export(hfmm_tree t, int32_t* d_perm, int32_t* d_leaf_off, hipStream_t stream);
 
 hfmm_status hfmm_tree_destroy(hfmm_tree t);
+
+/* Options of the plans made on this tree from now on (cached plans are
+ * dropped, so the next apply rebuilds them):
+ * m2l_valu   0: M2M, M2L and L2L on the matrix cores (MFMA, the default);
+ *            1: the same translations on the vector units (a reference path
+ *               for checking the MFMA kernels, and an ablation).
+ * autotune   1: time the near-field lanes per target and the M2L target tile
+ *               on this tree when a plan is made (the default); 0: use the
+ *               tuning cache if it has the plan's key, else fixed defaults.
+ * Errors: values other than 0 and 1. */
+hfmm_status hfmm_tree_set_options(hfmm_tree t, int32_t m2l_valu, int32_t autotune);
 
 /* ------------------------------------------------------------------------
  * N-body sum (Sec. 5.1, the N-body sum) with the 2-D Helmholtz kernel
@@ -135,6 +150,29 @@ hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precisio
  * Any output may be NULL. */
 hfmm_status hfmm_fmm_plan_info(hfmm_tree t, double k, int32_t p, hfmm_precision prec, int32_t* orders,
                                int32_t* near_deg, int32_t* lanes_per_target, int64_t* pairs);
+
+/* Double-layer sum (the dG/dn kernel of Sec. 5.2, 2-D form) by the same FMM:
+ *   phi[i, c] = sum_{j : |x_i - x_j| > 0} q[j, c] dG/dn_j(x_i, x_j),
+ *   dG/dn_j(x, y) = (i k / 4) H1^(1)(k r) (x - y).n_j / r,  r = |x - y|,
+ * the derivative of G(x, y) at the source y along its unit normal n_j.  The
+ * sources become dipoles in P2M (exact in the expansion order) and in the
+ * near field; M2M, M2L, L2L and L2P are the single-layer ones.
+ * d_normals  n x 2 FP64 (n_x, n_y) per point, caller order, device.
+ * Other arguments and errors as hfmm_fmm_apply.  Async. */
+hfmm_status hfmm_fmm_apply_dipole(hfmm_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                                  const double* d_normals, void* d_phi, int32_t nrhs, hipStream_t stream);
+
+/* Tuning cache (process-wide): the launch shapes the autotuner chose,
+ * keyed by the device architecture, precision, tree depth, mean leaf
+ * occupancy, level orders, near-field polynomial and column-group width.
+ * save writes it to a text file; load adds a file's entries (count in
+ * *n_loaded, may be NULL), which later plans with the same key take without
+ * timing.  size returns the number of entries; clear empties the cache.
+ * Errors: unreadable/unwritable file, malformed line. */
+hfmm_status hfmm_tune_cache_save(const char* path);
+hfmm_status hfmm_tune_cache_load(const char* path, int32_t* n_loaded);
+int32_t hfmm_tune_cache_size(void);
+hfmm_status hfmm_tune_cache_clear(void);
 
 /* ------------------------------------------------------------------------
  * 5-point FD Helmholtz operator (the sparse system A x = b of Sec. 2) on the
@@ -182,6 +220,22 @@ hfmm_status hfmm_matched_wavenumber(double k, double h, double* k0);
 /* Replace the operator's k^2 field (preconditioner unchanged).  Async. */
 hfmm_status hfmm_solver_set_k2(hfmm_solver s, const double* d_k2, double k2_const, hipStream_t stream);
 
+/* Replace the operator's k^2 field by one constant on nb x nb square blocks
+ * of (n/nb)^2 nodes each: d_kb is nb*nb FP64, row-major, block row index
+ * following y (node (i, j) takes d_kb[(j / (n/nb)) nb + i / (n/nb)]).  The
+ * library expands it on the device.  Errors: nb < 1 or nb not dividing n.
+ * Async. */
+hfmm_status hfmm_solver_set_k2_blocks(hfmm_solver s, const double* d_kb, int32_t nb, hipStream_t stream);
+
+/* Gradient product of the adjoint method: with u the solution of A u = f and
+ * mu the solution of A^H mu = dJ/du (both n*n complex128, device), dA/dk^2_x
+ * = -e_x e_x^T gives dJ/dk^2_x = Re(conj(mu_x) u_x) = -Re(lambda_x u_x) for
+ * lambda = -conj(mu).  d_grad (nb*nb FP64, device) receives the sums over the
+ * nb x nb blocks of set_k2_blocks (nb = n: one value per node).  Blocks are
+ * summed row by row in a fixed order (deterministic).  Async. */
+hfmm_status hfmm_k2_gradient(int32_t n, const double* d_u, const double* d_mu, int32_t nb, double* d_grad,
+                             hipStream_t stream);
+
 /* z = M^{-1} r for nrhs columns (complex128 n*n x nrhs in and out).  Async. */
 hfmm_status hfmm_precond_apply(hfmm_solver s, const double* d_r, double* d_z, int32_t nrhs,
                                hipStream_t stream);
@@ -207,6 +261,38 @@ hfmm_status hfmm_fgmres_solve(hfmm_solver s, const double* d_b, double* d_x, int
 hfmm_status hfmm_fgmres_solve_batched(hfmm_solver* s, int32_t nprob, const double* const* d_b,
                                       double* const* d_x, int32_t restart, int32_t maxit, double rtol,
                                       int32_t use_graph, hfmm_solve_info* info, hipStream_t stream);
+
+/* The boundary-element solution with inhomogeneous Dirichlet data (Sec. 5.2,
+ * the boundary equation with its 1/2 delta and double-layer terms, then the
+ * interior equation; constant elements and the analytic diagonal of Sec. 5.3):
+ *   boundary  S q = g/2 + D[g] - V     at the element midpoints,
+ *   interior  u = V + S_vol f + sum_b w G q_b - D[g]   at the interior nodes,
+ * with V the volume potential of f (h^2 weights), D[g] the double layer
+ * sum_b w g_b dG/dn_b, w = h, all sums by the solver's FMM (wavenumber k0,
+ * precision as created).  With g = 0 this is hfmm_precond_apply.
+ * d_f  n*n x nrhs complex128 source.  d_g  4(n+1) x nrhs complex128 values
+ * at the element midpoints in the order of hfmm_solver_boundary_nodes.
+ * d_u  n*n x nrhs complex128, overwritten.  nrhs as created.  Async. */
+hfmm_status hfmm_dirichlet_apply(hfmm_solver s, const double* d_f, const double* d_g, double* d_u, int32_t nrhs,
+                                 hipStream_t stream);
+
+/* The 4(n+1) boundary element midpoints, (x, y) interleaved FP64 into d_xy
+ * (device): bottom side (y = 0), right (x = 1), top (y = 1), left (x = 0),
+ * each with the free coordinate (m + 1/2) h, m = 0..n.  Async. */
+hfmm_status hfmm_solver_boundary_nodes(hfmm_solver s, double* d_xy, hipStream_t stream);
+
+/* Right-preconditioned BiCGSTAB (van der Vorst's method, the short-recurrence
+ * alternative of Sec. 3) with the solver's operator and FMM-BEM
+ * preconditioner: two preconditioner applies and two matvecs per iteration,
+ * FP64 vectors and scalars on the device, conj(a).b inner products.  Stops
+ * when ||b - A x|| / ||b|| <= rtol for every column (recursive residual,
+ * the true residual is computed at exit and decides info->converged), or
+ * after maxit iterations, or on breakdown of a column (a zero denominator).
+ * d_b, d_x as hfmm_fgmres_solve (x0 read from d_x).  info->iters counts
+ * BiCGSTAB iterations.  Returns HFMM_OK, HFMM_NOT_CONVERGED or an error.
+ * Synchronises `stream`. */
+hfmm_status hfmm_bicgstab_solve(hfmm_solver s, const double* d_b, double* d_x, int32_t maxit, double rtol,
+                                hfmm_solve_info* info, hipStream_t stream);
 
 /* Boundary-matrix diagnostics of a solver: N_Gamma and the 1-norm condition
  * estimate ||S||_1 ||S^{-1}||_1 (host outputs, may be NULL). */

@@ -18,7 +18,12 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhfmm.so")
 
-SOURCES = ["tree.hip", "fmm.hip", "solver.hip", "special.cpp", "abi.cpp"]
+# (source, object name, extra flags): near.hip is built once per precision and
+# column-group width so that its kernel instances compile in parallel
+SOURCES = [("tree.hip", "tree", []), ("fmm.hip", "fmm", []), ("solver.hip", "solver", []),
+           ("special.cpp", "special", []), ("abi.cpp", "abi", [])] + [
+    ("near.hip", f"near_{t}_{nr}", [f"-DNEAR_T={t}", f"-DNEAR_NR={nr}"])
+    for t in ("float", "double") for nr in (1, 2, 4)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -32,9 +37,10 @@ CFLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(entry):
+    src, name, extra = entry
+    obj = os.path.join(OBJDIR, name + ".o")
+    cmd = [HIPCC, *CFLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -43,7 +49,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(OBJDIR, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, (os.cpu_count() or 4)))
+    jobs = min(len(SOURCES), max(1, min(16, os.cpu_count() or 4)))
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

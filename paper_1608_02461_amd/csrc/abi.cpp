@@ -3,6 +3,7 @@
 // message; nothing throws across the interface.
 #include <new>
 #include <string>
+#include <vector>
 
 #include "solver.h"
 
@@ -108,6 +109,65 @@ hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec
   HFMM_GUARD_END
 }
 
+hfmm_status hfmm_tree_set_options(hfmm_tree t, int32_t m2l_valu, int32_t autotune) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "tree_set_options: NULL tree");
+  HFMM_REQUIRE((m2l_valu == 0 || m2l_valu == 1) && (autotune == 0 || autotune == 1),
+               "tree_set_options: options must be 0 or 1");
+  hfmm::Tree& tr = *t->t;
+  if (tr.side) HFMM_HIP(hipStreamSynchronize(tr.side));
+  tr.m2l_valu = m2l_valu != 0;
+  tr.autotune = autotune != 0;
+  tr.plans.clear();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_fmm_apply_dipole(hfmm_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                                  const double* d_normals, void* d_phi, int32_t nrhs, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "fmm_apply_dipole: NULL tree");
+  HFMM_REQUIRE(prec == HFMM_FP64 || prec == HFMM_FP32, "fmm_apply_dipole: unknown precision");
+  HFMM_REQUIRE(nrhs >= 1 && nrhs <= 1024, "fmm_apply_dipole: nrhs must be in [1, 1024]");
+  HFMM_REQUIRE(std::isfinite(k) && k > 0, "fmm_apply_dipole: k must be finite and > 0");
+  HFMM_REQUIRE(p >= 1 && p <= 40, "fmm_apply_dipole: p must be in [1, 40]");
+  HFMM_REQUIRE(d_q != nullptr && d_phi != nullptr && d_normals != nullptr, "fmm_apply_dipole: NULL array");
+  if (prec == HFMM_FP64)
+    hfmm::fmm_apply_dipole<double>(*t->t, k, p, static_cast<const double2*>(d_q), d_normals,
+                                   static_cast<double2*>(d_phi), nrhs, stream);
+  else
+    hfmm::fmm_apply_dipole<float>(*t->t, k, p, static_cast<const float2*>(d_q), d_normals,
+                                  static_cast<float2*>(d_phi), nrhs, stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_tune_cache_save(const char* path) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(path != nullptr, "tune_cache_save: NULL path");
+  hfmm::tune_cache_save(path);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_tune_cache_load(const char* path, int32_t* n_loaded) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(path != nullptr, "tune_cache_load: NULL path");
+  const int n = hfmm::tune_cache_load(path);
+  if (n_loaded) *n_loaded = n;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+int32_t hfmm_tune_cache_size(void) { return hfmm::tune_cache_size(); }
+
+hfmm_status hfmm_tune_cache_clear(void) {
+  HFMM_GUARD_BEGIN
+  hfmm::tune_cache_clear();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
 hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
                                  void* d_phi, int32_t nrhs, float* ms_stages, hipStream_t stream) {
   HFMM_GUARD_BEGIN
@@ -137,7 +197,7 @@ hfmm_status hfmm_fmm_plan_info(hfmm_tree t, double k, int32_t p, hfmm_precision 
     if (orders)
       for (int l = 0; l <= tr.L; ++l) orders[l] = pl.lv[l].p;
     if (near_deg) *near_deg = pl.near_fast ? pl.poly.deg : 0;
-    if (lanes_per_target) *lanes_per_target = pl.G;
+    if (lanes_per_target) *lanes_per_target = pl.G[0];
   };
   if (prec == HFMM_FP64)
     fill(hfmm::get_plan<double>(tr, k, p));
@@ -208,6 +268,64 @@ hfmm_status hfmm_solver_set_k2(hfmm_solver s, const double* d_k2, double k2_cons
   HFMM_REQUIRE(s != nullptr && s->s, "set_k2: NULL solver");
   hfmm::solver_set_k2(*s->s, d_k2, k2_const, stream);
   return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_set_k2_blocks(hfmm_solver s, const double* d_kb, int32_t nb, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "set_k2_blocks: NULL solver");
+  hfmm::solver_set_k2_blocks(*s->s, d_kb, nb, stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_k2_gradient(int32_t n, const double* d_u, const double* d_mu, int32_t nb, double* d_grad,
+                             hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  hfmm::k2_gradient(n, reinterpret_cast<const double2*>(d_u), reinterpret_cast<const double2*>(d_mu), nb, d_grad,
+                    stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_dirichlet_apply(hfmm_solver s, const double* d_f, const double* d_g, double* d_u, int32_t nrhs,
+                                 hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "dirichlet_apply: NULL solver");
+  HFMM_REQUIRE(nrhs == s->s->nrhs, "dirichlet_apply: nrhs differs from the solver's");
+  hfmm::dirichlet_apply(*s->s, reinterpret_cast<const double2*>(d_f), reinterpret_cast<const double2*>(d_g),
+                        reinterpret_cast<double2*>(d_u), stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_boundary_nodes(hfmm_solver s, double* d_xy, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "solver_boundary_nodes: NULL solver");
+  HFMM_REQUIRE(d_xy != nullptr, "solver_boundary_nodes: NULL array");
+  const hfmm::Solver& sv = *s->s;
+  std::vector<double> xy(2 * sv.ng);
+  const int n = sv.n;
+  for (int m = 0; m <= n; ++m) {
+    const double t = (m + 0.5) * sv.h;
+    const double pts[4][2] = {{t, 0.0}, {1.0, t}, {t, 1.0}, {0.0, t}};
+    for (int side = 0; side < 4; ++side) {
+      xy[2 * (side * (n + 1) + m)] = pts[side][0];
+      xy[2 * (side * (n + 1) + m) + 1] = pts[side][1];
+    }
+  }
+  HFMM_HIP(hipMemcpyAsync(d_xy, xy.data(), xy.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HFMM_HIP(hipStreamSynchronize(stream));  // the host buffer goes out of scope
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_bicgstab_solve(hfmm_solver s, const double* d_b, double* d_x, int32_t maxit, double rtol,
+                                hfmm_solve_info* info, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "bicgstab_solve: NULL solver");
+  return hfmm::bicgstab(*s->s, reinterpret_cast<const double2*>(d_b), reinterpret_cast<double2*>(d_x), maxit, rtol,
+                        info, stream);
   HFMM_GUARD_END
 }
 

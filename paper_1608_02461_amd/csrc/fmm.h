@@ -17,6 +17,8 @@
 #include "special.h"
 #include "tree.h"
 
+#include <string>
+
 namespace hfmm {
 
 struct LevelInfo {
@@ -52,15 +54,21 @@ struct FmmPlan : PlanBase {
   // near field
   bool near_fast = false;
   NearPoly poly;
-  int G = 1;                // lanes per target in P2P
+  // lanes per target in P2P, per column-group width (1, 2, 4 columns);
+  // tuned[g] once the autotuner (or its cache) has chosen G[g]
+  int G[3] = {1, 1, 1};
+  bool tuned[3] = {false, false, false};
   bool use_mfma = true;     // MFMA downward pass where the level's tables exist
   bool m2l_small = false;   // M2L on 4 x 4 target tiles (autotuned)
-  float tune_ms[5] = {0, 0, 0, 0, 0};  // P2P with G = 1, 2, 4; M2L 8x8, 4x4 tiles
+  float tune_ms[5] = {0, 0, 0, 0, 0};  // P2P with G = 1, 2, 4 (one column); M2L 8x8, 4x4 tiles
+  int tune_source = 0;      // 0 defaults, 1 timed on this device, 2 from the tuning cache
+  std::string tune_key;     // the cache key of this plan (without the column-group width)
   // work storage
   DevBuf<cplx<T>> M, Lc;
   int nrhs_cap = 0;
   DevBuf<cplx<T>> qs, phis;  // sorted scratch for the public apply
   DevBuf<cplx<T>> far;        // far field of a pass, in the output's point order
+  DevBuf<cplx<T>> dns;        // sorted unit normals of a double-layer apply
   double max_table = 0;
 
   int64_t npts = 0;  // points of the tree
@@ -74,8 +82,37 @@ struct FmmPlan : PlanBase {
   }
 };
 
+// Work arrays of one FMM pass: multipole and local expansions of every
+// level (coef_total x nrhs each) and the far field at the points (N x nrhs).
+template <class T>
+struct FmmWork {
+  cplx<T>* M = nullptr;
+  cplx<T>* Lc = nullptr;
+  cplx<T>* far = nullptr;
+};
+
+// Column-group index of a group width (1, 2, 4 columns -> 0, 1, 2).
+inline int nr_group(int nr) { return nr >= 4 ? 2 : (nr >= 2 ? 1 : 0); }
+
 template <class T>
 FmmPlan<T>& get_plan(Tree& t, double k, int p);
+// The cached plan of (k, p) or NULL (creates nothing).
+template <class T>
+FmmPlan<T>* find_plan(Tree& t, double k, int p);
+// Chooses the near-field lanes per target for the column-group widths that
+// nrhs columns use (timed on the tree, or taken from the tuning cache).
+// Not callable under stream capture.
+template <class T>
+void ensure_tuned(Tree& t, FmmPlan<T>& pl, int nrhs);
+
+// Process-wide tuning cache: launch shapes chosen by the autotuner, keyed by
+// the device architecture, the precision, the tree's depth and mean leaf
+// occupancy, the level orders, the near-field polynomial and the column-group
+// width.  Saved to / loaded from a text file so that later processes reuse it.
+void tune_cache_save(const std::string& path);
+int tune_cache_load(const std::string& path);
+int tune_cache_size();
+void tune_cache_clear();
 
 // Optional stage timing: hipEvents recorded on the launch stream at stage
 // boundaries; stage ids 0 gather, 1 upward (P2M+M2M), 2 downward (M2L+L2L),
@@ -98,10 +135,16 @@ struct StageTimer {
 // when it holds 0 every kernel of the call returns at once.  With `perm`
 // (the tree's sorted -> caller permutation; depth >= 2, no flags) q and phi
 // are in caller order instead and `qs` (N x nrhs) receives the sorted charges.
+//
+// `w` (or NULL for the plan's own arrays, grown as needed) supplies the work
+// arrays.  `dn` (sorted order, or NULL) turns the sources into dipoles with
+// unit normals dn: the pass then sums q_j dG/dn_j (the double-layer kernel
+// of Sec. 5.2) instead of q_j G.
 template <class T>
 void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
                 bool accumulate, hipStream_t st, const int* alive = nullptr, StageTimer* tm = nullptr,
-                const int32_t* perm = nullptr, cplx<T>* qs = nullptr);
+                const int32_t* perm = nullptr, cplx<T>* qs = nullptr, const FmmWork<T>* w = nullptr,
+                const cplx<T>* dn = nullptr);
 
 // Per-level source flags for the points whose caller index lies in [lo, hi).
 void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipStream_t st);
@@ -110,5 +153,19 @@ void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipSt
 template <class T>
 void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st,
                StageTimer* tm = nullptr);
+
+// Double-layer apply in caller order: phi_i = sum_j q_j dG/dn_j(x_i, x_j)
+// with unit normals `normals` (n x 2 FP64, caller order).
+template <class T>
+void fmm_apply_dipole(Tree& t, double k, int p, const cplx<T>* q, const double* normals, cplx<T>* phi, int nrhs,
+                      hipStream_t st);
+
+// The public apply on caller-provided work memory (`scratch`, `bytes`): no
+// device allocation.  The plan of (k, p) must exist and be tuned for nrhs.
+// Returns the bytes needed when they exceed `bytes` (nothing is launched
+// then), else 0.
+template <class T>
+size_t fmm_apply_scratch(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, void* scratch,
+                         size_t bytes, hipStream_t st);
 
 }  // namespace hfmm

@@ -17,88 +17,45 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <type_traits>
 
+#include "devutil.h"
 #include "fmm.h"
+#include "p2p.h"
 
 namespace hfmm {
 
 namespace {
 
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-// v_log_f32 without the denormal-input rescaling: every argument here is
-// (k r)^2 of two distinct FP32 positions, far above the denormal range.
-__device__ __forceinline__ float log2T(float x) { return __builtin_amdgcn_logf(x); }
-__device__ __forceinline__ double log2T(double x) { return log2(x); }
-
-// acc += a * b (complex; V is float2 or double2)
-template <class V>
-__device__ __forceinline__ void cmac(V& acc, V a, V b) {
-  acc.x = fmaT(a.x, b.x, acc.x);
-  acc.x = fmaT(-a.y, b.y, acc.x);
-  acc.y = fmaT(a.x, b.y, acc.y);
-  acc.y = fmaT(a.y, b.x, acc.y);
-}
-// acc += a * conj(b)
-template <class V>
-__device__ __forceinline__ void cmacc(V& acc, V a, V b) {
-  acc.x = fmaT(a.x, b.x, acc.x);
-  acc.x = fmaT(a.y, b.y, acc.x);
-  acc.y = fmaT(a.y, b.x, acc.y);
-  acc.y = fmaT(-a.x, b.y, acc.y);
-}
-
 template <class T> const cplx<T>* rel_of(const Tree& t);
 template <> const float2* rel_of<float>(const Tree& t) { return t.rel32.p; }
 template <> const double2* rel_of<double>(const Tree& t) { return t.rel64.p; }
 
-__device__ __forceinline__ float rcpT(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcpT(double x) { return 1.0 / x; }
-
-// Bessel functions of order n at x through J_n(x) = (x/2)^n / n! S_n(x^2/4),
-// S_n(y) = sum_j (-y)^j n! / (j! (n+j)!) (DLMF 10.2.2), which has no
-// division by x:
-//   sseries: S_n(y) from its first K + 1 terms by Horner, with the term
-//            ratios -y / (j (n + j)) formed in registers (no table loads);
-//   sdown:   S_{n-1} = S_n - y S_{n+1} / (n (n + 1)), the three-term
-//            recurrence J_{n-1} + J_{n+1} = (2n/x) J_n in this scaling, run
-//            downward (the stable direction) from two series values.
-template <class T>
-__device__ __forceinline__ T sseries(int n, int K, T y) {
-  T S = T(1);
-  for (int j = K; j >= 1; --j) S = fmaT(-y * rcpT(T(j) * T(n + j)), S, T(1));
-  return S;
-}
-template <class T>
-__device__ __forceinline__ T sdown(int n, T y, T Sn, T Sn1) {
-  return fmaT(-y * rcpT(T(n) * T(n + 1)), Sn1, Sn);
-}
-
-// The LDS stores and loads of one wave are performed in order; this keeps
-// the compiler from moving them across the point, so lanes of the wave see
-// each other's stores (waves that share no LDS need no block barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// The far-field chain runs beside the near field, whose waves keep every
-// SIMD busy.  Its kernels raise their waves' issue priority so that the
-// chain, which is short of parallelism, advances at close to its own speed
-// while the near field takes the issue slots it leaves.
-__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
-
 // ------------------------------------------------------------------ P2M
-template <class T, int NR, int LPW>
+// DIP: the sources are dipoles with unit normals dn (sorted order) and
+// density q, whose field is q dG/dn_y (the double layer of Sec. 5.2).  With
+// c_m = J_m(k rho) e^{-i m phi} / s^m the scaled basis and n = nx + i ny,
+// the directional derivative of J_m e^{-i m phi} along n at the source,
+// (k/2)[conj(n) J_{m-1} e^{-i(m-1)phi} - n J_{m+1} e^{-i(m+1)phi}] (the
+// ladder relations of the cylinder functions, DLMF 10.6.2), gives
+//   Mt_m     += q (k/2)[conj(n) c_{m-1} / s - n c_{m+1} s],
+//   Mt_{-m}  += (-1)^m q (-(k/2))[conj(n) conj(c_{m+1}) s - n conj(c_{m-1}) / s]
+// (from J_{-j} e^{i j phi} = (-1)^j conj(J_j e^{-i j phi})),
+// with c_{-1} = -conj(c_1) s^2 (J_{-1} = -J_1).
+template <class T, int NR, int LPW, bool DIP>
 __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_off, const cplx<T>* __restrict__ rel,
                                             const cplx<T>* __restrict__ q, int64_t N, int nrhs, int r0,
                                             cplx<T>* __restrict__ Mout, int pL, T wscale, T yscale, int K,
                                             const uint8_t* __restrict__ flags, const int* __restrict__ alive,
-                                            const int32_t* __restrict__ gperm, cplx<T>* __restrict__ qs_out) {
+                                            const int32_t* __restrict__ gperm, cplx<T>* __restrict__ qs_out,
+                                            const cplx<T>* __restrict__ dn, T hk, T sl) {
   extern __shared__ unsigned char smem_raw[];
   // blockDim / 64 waves per block, LPW consecutive leaves per wave (small
   // leaves share a wave so that its lanes stay busy); every wave has its own
@@ -109,8 +66,10 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
   const int leaf0 = ((int)(blockDim.x >> 6) * blockIdx.x + w) * LPW;
   if (alive && !alive[0]) return;
   if (LPW == 1 && flags && !flags[leaf0]) return;
-  cplx<T>* sb = reinterpret_cast<cplx<T>*>(smem_raw) + (size_t)w * max(pL + 1 + NR, 2 * NR) * 64;  // [(pL+1)][64]
-  cplx<T>* sq = sb + (pL + 1) * 64;                     // [NR][64]
+  constexpr int NB = DIP ? 2 : 1;  // basis arrays: c_m, or the dipole's positive and negative orders
+  cplx<T>* sb = reinterpret_cast<cplx<T>*>(smem_raw) + (size_t)w * max(NB * (pL + 1) + NR, 2 * NR) * 64;  // [(pL+1)][64]
+  cplx<T>* sbn = sb + (pL + 1) * 64;                    // DIP: [(pL+1)][64]
+  cplx<T>* sq = sb + NB * (pL + 1) * 64;                // [NR][64]
   const int P = 2 * pL + 1;
   const int per = pL + 1, G = 64 / (LPW * per);  // groups per (leaf, order)
   const int l = lane / (G * per), lr = lane - l * G * per, g = lr / per, n = lr - g * per;
@@ -128,6 +87,7 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
       const T y = yscale * (d.x * d.x + d.y * d.y);   // (k rho)^2 / 4
       // S_n downward into the lane's column, then times w^n / n! upward
       T s1 = sseries(pL + 1, K, y), s0 = sseries(pL, K, y);
+      const T stop = s1;  // S_{pL+1}
       for (int m = pL; m >= 0; --m) {
         sb[m * 64 + lane].x = s0;
         if (m > 0) {
@@ -144,6 +104,26 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
         const T nr = (ur * wr - ui * wi) * inv, ni = (ur * wi + ui * wr) * inv;
         ur = nr;
         ui = ni;
+      }
+      if constexpr (DIP) {
+        // (ur, ui) = w^{pL+1} / (pL+1)!, so c_{pL+1} = (ur, ui) S_{pL+1}
+        const cplx<T> nv = dn[c0 + lane];
+        const T isl = rcpT(sl);
+        const cplx<T> c1 = pL >= 1 ? sb[64 + lane] : mk<T>(ur * stop, ui * stop);
+        cplx<T> cp = mk<T>(-c1.x * sl * sl, c1.y * sl * sl);  // c_{-1}
+        for (int m = 0; m <= pL; ++m) {
+          const cplx<T> cm = sb[m * 64 + lane];
+          const cplx<T> cn = m < pL ? sb[(m + 1) * 64 + lane] : mk<T>(ur * stop, ui * stop);
+          // conj(n) c_{m-1} / s - n c_{m+1} s
+          const T ar = (nv.x * cp.x + nv.y * cp.y) * isl, ai = (nv.x * cp.y - nv.y * cp.x) * isl;
+          const T br = (nv.x * cn.x - nv.y * cn.y) * sl, bi = (nv.x * cn.y + nv.y * cn.x) * sl;
+          sb[m * 64 + lane] = mk<T>(hk * (ar - br), hk * (ai - bi));
+          // -(conj(n) conj(c_{m+1}) s - n conj(c_{m-1}) / s)
+          const T er = (nv.x * cn.x - nv.y * cn.y) * sl, ei = -(nv.x * cn.y + nv.y * cn.x) * sl;
+          const T fr = (nv.x * cp.x + nv.y * cp.y) * isl, fi = (nv.y * cp.x - nv.x * cp.y) * isl;
+          sbn[m * 64 + lane] = mk<T>(hk * (fr - er), hk * (fi - ei));
+          cp = cm;
+        }
       }
       // charges in Morton order; with gperm, q is in caller order and the
       // sorted copy is written to qs_out for the near field
@@ -163,11 +143,21 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t* __restrict__ leaf_of
       const int jl = max(lo_l, c0) - c0, jh = min(hi_l, c0 + cnt) - c0;
       for (int j = jl + g; j < jh; j += G) {
         const cplx<T> b = sb[n * 64 + j];
+        if constexpr (DIP) {
+          const cplx<T> bn = sbn[n * 64 + j];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const cplx<T> qq = sq[r * 64 + j];
-          cmac(accP[r], qq, b);
-          cmacc(accN[r], qq, b);
+          for (int r = 0; r < NR; ++r) {
+            const cplx<T> qq = sq[r * 64 + j];
+            cmac(accP[r], qq, b);
+            cmac(accN[r], qq, bn);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const cplx<T> qq = sq[r * 64 + j];
+            cmac(accP[r], qq, b);
+            cmacc(accN[r], qq, b);
+          }
         }
       }
     }
@@ -663,7 +653,7 @@ __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
   }
 }
 
-#include "near.h"
+#include "farfield.h"
 
 // ------------------------------------------------------------------ misc
 template <class T>
@@ -748,9 +738,8 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   }
   pl->coef_total = coef;
   pl->flag_total = box0;
-  // HFMM_M2L=valu selects the VALU downward kernel at every level (ablation)
-  const char* m2l_env = std::getenv("HFMM_M2L");
-  pl->use_mfma = !(m2l_env && std::string(m2l_env) == "valu");
+  // the tree's option selects the VALU downward kernels at every level (reference, ablation)
+  pl->use_mfma = !t.m2l_valu;
 
   // near field: pair arguments k r are bounded by the 3 x 3 leaf block
   const double lside = t.leaf_side();
@@ -762,7 +751,8 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   // the first two candidates of each are polynomials in t itself (kPlainDeg)
   pl->near_fast = fit_near_poly(X * X * (1 + 1e-9), F32, F32 ? candF : candD, 5, 2, F32 ? 1e-6 : 2e-13, pl->poly);
   const double mean = double(t.n) / double(t.nleaves);
-  pl->G = mean >= 40 ? 1 : (mean >= 20 ? 2 : 4);
+  const int G0 = mean >= 40 ? 1 : (mean >= 20 ? 2 : 4);
+  for (int g = 0; g < 3; ++g) pl->G[g] = G0;
 
   if (L >= 2) {
     const LevelInfo& lf = pl->lv[L];
@@ -948,69 +938,11 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   return pl;
 }
 
-template <class T, int NR, int D, bool FAST>
-void launch_p2p4(int G, int grid, const P2PArgs<T>& a, hipStream_t st) {
-  switch (G) {
-    case 1: k_p2p4<T, NR, D, FAST, 1><<<grid, 256, 0, st>>>(a); break;
-    case 2: k_p2p4<T, NR, D, FAST, 2><<<grid, 256, 0, st>>>(a); break;
-    default: k_p2p4<T, NR, D, FAST, 4><<<grid, 256, 0, st>>>(a); break;
-  }
-}
-
-// Near field of one column group: the 4-sibling kernel for trees of depth >= 2,
-// the per-leaf kernel for a single leaf.
-template <class T, int NR>
-void launch_p2p(const Tree& t, const FmmPlan<T>& pl, const P2PArgs<T>& a, int G, hipStream_t st) {
-  const int deg = pl.poly.deg;
-  if (t.L < 2) {
-    const int grid = (int)t.nleaves;
-    if (!pl.near_fast) {
-      k_p2p<T, NR, 1, false><<<grid, 64, 0, st>>>(a);
-    } else if constexpr (std::is_same<T, float>::value) {
-      switch (deg) {
-        case 5: k_p2p<T, NR, 5, true><<<grid, 64, 0, st>>>(a); break;
-        case 7: k_p2p<T, NR, 7, true><<<grid, 64, 0, st>>>(a); break;
-        case 9: k_p2p<T, NR, 9, true><<<grid, 64, 0, st>>>(a); break;
-        case 12: k_p2p<T, NR, 12, true><<<grid, 64, 0, st>>>(a); break;
-        default: k_p2p<T, NR, 16, true><<<grid, 64, 0, st>>>(a); break;
-      }
-    } else {
-      switch (deg) {
-        case 8: k_p2p<T, NR, 8, true><<<grid, 64, 0, st>>>(a); break;
-        case 10: k_p2p<T, NR, 10, true><<<grid, 64, 0, st>>>(a); break;
-        case 12: k_p2p<T, NR, 12, true><<<grid, 64, 0, st>>>(a); break;
-        case 16: k_p2p<T, NR, 16, true><<<grid, 64, 0, st>>>(a); break;
-        default: k_p2p<T, NR, 24, true><<<grid, 64, 0, st>>>(a); break;
-      }
-    }
-    return;
-  }
-  const int grid = (int)(t.nleaves / 4);
-  if (!pl.near_fast) {
-    launch_p2p4<T, NR, 1, false>(G, grid, a, st);
-  } else if constexpr (std::is_same<T, float>::value) {
-    switch (deg) {
-      case 5: launch_p2p4<T, NR, 5, true>(G, grid, a, st); break;
-      case 7: launch_p2p4<T, NR, 7, true>(G, grid, a, st); break;
-      case 9: launch_p2p4<T, NR, 9, true>(G, grid, a, st); break;
-      case 12: launch_p2p4<T, NR, 12, true>(G, grid, a, st); break;
-      default: launch_p2p4<T, NR, 16, true>(G, grid, a, st); break;
-    }
-  } else {
-    switch (deg) {
-      case 8: launch_p2p4<T, NR, 8, true>(G, grid, a, st); break;
-      case 10: launch_p2p4<T, NR, 10, true>(G, grid, a, st); break;
-      case 12: launch_p2p4<T, NR, 12, true>(G, grid, a, st); break;
-      case 16: launch_p2p4<T, NR, 16, true>(G, grid, a, st); break;
-      default: launch_p2p4<T, NR, 24, true>(G, grid, a, st); break;
-    }
-  }
-}
 
 template <class T>
-P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
+P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0, int nr,
                     const uint8_t* flags, bool accumulate, const int* alive, const int32_t* operm = nullptr,
-                    bool far = false) {
+                    const cplx<T>* Lleaf = nullptr, const cplx<T>* dn = nullptr) {
   P2PArgs<T> a{};
   a.operm = operm;
   a.leaf_off = t.leaf_off.p;
@@ -1023,7 +955,7 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.nrhs = nrhs;
   a.r0 = r0;
   a.L = t.L;
-  a.G = pl.G;
+  a.G = pl.G[nr_group(nr)];
   a.accumulate = accumulate ? 1 : 0;
   a.k = T(pl.k);
   a.kls = T(pl.k * t.leaf_side());
@@ -1037,9 +969,10 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.c1 = T(P.c1);
   a.jinv = T(1.0 / P.c1);
   a.Lc = nullptr;
-  if (far && t.L >= 2) {  // the leaf level's local expansions, for the L2P kernel
+  a.dn = dn;
+  if (Lleaf && t.L >= 2) {  // the leaf level's local expansions, for the L2P kernel
     const LevelInfo& lf = pl.lv[t.L];
-    a.Lc = pl.Lc.p + lf.coef * nrhs;
+    a.Lc = Lleaf;
     a.pL = lf.p;
     a.K = pl.K;
     a.wscale = T(pl.k / (2 * lf.s));
@@ -1098,17 +1031,16 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
 }
 
 // Far-field chain of one column group: M2M levels L-1 .. 2, M2L of every
-// level, L2L levels 3 .. r (MFMA kernels, or the VALU ones for the
-// ablation), then k_down_tree: L2L of the last levels r+1 .. L and the L2P
-// into pl.far (Morton order), r = max(2, L - 2).  `fa` carries the points
-// and far-field scales.
+// level, L2L levels 3 .. r (MFMA kernels, or the VALU ones on request),
+// then k_down_tree: L2L of the last levels r+1 .. L and the L2P into w.far,
+// r = max(2, L - 2).  `fa` carries the points and far-field scales.
 template <class T, int NR>
-void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* flags, hipStream_t st,
-               const int* alive, const P2PArgs<T>& fa) {
+void far_chain(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, int nrhs, int r0, const uint8_t* flags,
+               hipStream_t st, const int* alive, const P2PArgs<T>& fa) {
   const int L = t.L;
   const int rl = std::max(2, L - 2);  // the down tree starts below this level
-  cplx<T>* M = pl.M.p;
-  cplx<T>* Lc = pl.Lc.p;
+  cplx<T>* M = w.M;
+  cplx<T>* Lc = w.Lc;
   if (pl.use_mfma) {
     for (int l = L - 1; l >= 2; --l) {
       const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
@@ -1187,7 +1119,7 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
     g.W2 = pl.l2l.p + pl.l2l_off[rl + 1];
     g.P2 = pl.lv[rl + 2].P;
   }
-  g.far = pl.far.p;
+  g.far = w.far;
   const size_t sh = (size_t)(4 * NR * g.P1 + 16 * NR * g.P2) * sizeof(cplx<T>);
   k_down_tree<T, NR><<<1 << (2 * rl), 256, sh, st>>>(g);
   HFMM_LAUNCH_CHECK();
@@ -1198,20 +1130,27 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, int nrhs, int r0, const uint8_t* f
 // of depth >= 2 (and 2^18 points or more) the far-field chain then runs on
 // the tree's side stream while the near field runs on `st` (smaller trees
 // run both on `st`, near field first).  The near field writes (or adds to)
-// phi, the chain ends with the L2P into the far-field scratch pl.far, both
+// phi, the chain ends with the L2P into the far-field array w.far, both
 // through `perm` when given, and a last streaming kernel adds the far
 // field to phi.  Stage timing: [1] P2M, [2] the far-field chain including
 // the L2P (side stream, beside [4]), [4] the near field, [3] the sum,
-// including the wait for [2].
+// including the wait for [2].  With dn the sources are dipoles (sorted I/O).
 template <class T, int NR>
-void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
+void run_cols(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
               const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm,
-              const int32_t* perm, cplx<T>* qs) {
+              const int32_t* perm, cplx<T>* qs, const cplx<T>* dn) {
   const int L = t.L;
   const int64_t N = t.n;
   const cplx<T>* rel = rel_of<T>(t);
   const double k = pl.k;
   const cplx<T>* qnear = perm ? qs : q;
+  const int G = pl.G[nr_group(NR)];
+  auto near = [&](const P2PArgs<T>& a) {
+    if (dn)
+      launch_p2p_dipole<T, NR>(L, t.nleaves, a, st);
+    else
+      launch_p2p<T, NR>(L, t.nleaves, pl.near_fast, pl.poly.deg, a, G, st);
+  };
   if (L >= 2) {
     HFMM_REQUIRE(t.side != nullptr, "fmm: internal: tree without a side stream");
     // small trees: the chain on `st` itself (two events would cost more
@@ -1219,24 +1158,31 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     const bool overlap = t.n >= (int64_t(1) << 18);
     hipStream_t cs = overlap ? t.side : st;
     const LevelInfo& lf = pl.lv[L];
-    // basis [(p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
-    const size_t sh = (size_t)std::max(lf.p + 1 + NR, 2 * NR) * 64 * sizeof(cplx<T>);
+    const int nb = dn ? 2 : 1;
+    // basis [nb (p+1)][64] and charges [NR][64], reused as the [NR][2][64] partial sums
+    const size_t sh = (size_t)std::max(nb * (lf.p + 1) + NR, 2 * NR) * 64 * sizeof(cplx<T>);
     const int lpb = 4 * sh <= 65536 ? 4 : (2 * sh <= 65536 ? 2 : 1);  // waves per block
     // leaves per wave: small leaves share a wave
     const double mean = double(N) / double(t.nleaves);
     const int lpw = (mean <= 20 && 4 * (lf.p + 1) <= 64) ? 4 : ((mean <= 40 && 2 * (lf.p + 1) <= 64) ? 2 : 1);
-    auto p2m = [&](auto lc) {
+    const T hk = T(k / 2), sl = T(lf.s);
+    auto p2m = [&](auto lc, auto dc) {
       constexpr int LPW = decltype(lc)::value;
-      k_p2m<T, NR, LPW><<<(int)(t.nleaves / (lpb * LPW)), 64 * lpb, lpb * sh, st>>>(
-          t.leaf_off.p, rel, q, N, nrhs, r0, pl.M.p + lf.coef * nrhs, lf.p, T(k / (2 * lf.s)), T(k * k / 4), pl.K,
-          flags ? flags + lf.box0 : nullptr, alive, perm, qs);
+      constexpr bool DIP = decltype(dc)::value;
+      k_p2m<T, NR, LPW, DIP><<<(int)(t.nleaves / (lpb * LPW)), 64 * lpb, lpb * sh, st>>>(
+          t.leaf_off.p, rel, q, N, nrhs, r0, w.M + lf.coef * nrhs, lf.p, T(k / (2 * lf.s)), T(k * k / 4), pl.K,
+          flags ? flags + lf.box0 : nullptr, alive, perm, qs, dn, hk, sl);
     };
-    if (lpw == 4)
-      p2m(std::integral_constant<int, 4>{});
-    else if (lpw == 2)
-      p2m(std::integral_constant<int, 2>{});
-    else
-      p2m(std::integral_constant<int, 1>{});
+    if (dn) {
+      HFMM_REQUIRE(perm == nullptr, "fmm: internal: dipole sources need sorted input");
+      p2m(std::integral_constant<int, 1>{}, std::true_type{});
+    } else if (lpw == 4) {
+      p2m(std::integral_constant<int, 4>{}, std::false_type{});
+    } else if (lpw == 2) {
+      p2m(std::integral_constant<int, 2>{}, std::false_type{});
+    } else {
+      p2m(std::integral_constant<int, 1>{}, std::false_type{});
+    }
     HFMM_LAUNCH_CHECK();
     const int e_p2m = tm ? tm->mark(1, st) : -1;
     if (overlap) {
@@ -1245,37 +1191,73 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int
     }
     // the near field is queued first: when the host is not ahead of the
     // device, the chain's many launches would otherwise delay its start
-    const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
-    launch_p2p<T, NR>(t, pl, a, pl.G, st);
-    HFMM_LAUNCH_CHECK();
+    const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, NR, flags, accumulate, alive, perm, nullptr, dn);
+    near(a);
     const int e_p2p = tm ? tm->mark(4, st, e_p2m) : -1;
-    const P2PArgs<T> b = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, false, alive, perm, true);
-    far_chain<T, NR>(t, pl, nrhs, r0, flags, cs, alive, b);
+    const P2PArgs<T> b =
+        p2p_args<T>(t, pl, qnear, phi, nrhs, r0, NR, flags, false, alive, perm, w.Lc + lf.coef * nrhs);
+    far_chain<T, NR>(t, pl, w, nrhs, r0, flags, cs, alive, b);
     if (tm) tm->mark(2, cs, overlap ? e_p2m : e_p2p);
     if (overlap) {
       HFMM_HIP(hipEventRecord(t.join, t.side));
       HFMM_HIP(hipStreamWaitEvent(st, t.join, 0));
     }
-    k_combine<T, NR><<<(int)((N + 255) / 256), 256, 0, st>>>(phi, pl.far.p, N, r0, alive);
+    k_combine<T, NR><<<(int)((N + 255) / 256), 256, 0, st>>>(phi, w.far, N, r0, alive);
     HFMM_LAUNCH_CHECK();
     if (tm) tm->mark(3, st, overlap ? e_p2p : -1);
     return;
   }
   // a single leaf: the near field is the whole sum
-  const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, flags, accumulate, alive, perm);
-  launch_p2p<T, NR>(t, pl, a, pl.G, st);
-  HFMM_LAUNCH_CHECK();
+  const P2PArgs<T> a = p2p_args<T>(t, pl, qnear, phi, nrhs, r0, NR, flags, accumulate, alive, perm, nullptr, dn);
+  near(a);
   if (tm) tm->mark(4, st);
 }
 
-// Launch-shape autotuner, run once per plan on the tree it serves (the
-// kernels' cost does not depend on the charges, so zeros are used): the P2P
-// lanes per target G in {1, 2, 4} and the M2L target tile (8 x 8 or 4 x 4).
-// HFMM_TUNE=0 keeps the defaults.
+// ------------------------------------------------------------------ tuning
+struct TuneVal {
+  int G = 1;
+  int m2l_small = 0;
+};
+
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::map<std::string, TuneVal>& tune_table() {
+  static std::map<std::string, TuneVal> t;
+  return t;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  HFMM_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HFMM_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string a(prop.gcnArchName);
+  for (char& c : a)
+    if (c == ' ') c = '_';
+  return a;
+}
+
+// Key of a plan's launch shapes: device architecture, precision, depth,
+// mean leaf occupancy, near-field polynomial and the level orders.
 template <class T>
-void autotune(const Tree& t, FmmPlan<T>& pl) {
-  const char* e = std::getenv("HFMM_TUNE");
-  if ((e && std::string(e) == "0") || t.L < 2) return;
+std::string plan_key(const Tree& t, const FmmPlan<T>& pl) {
+  std::ostringstream os;
+  os << device_arch() << ":" << (std::is_same<T, float>::value ? "fp32" : "fp64") << ":L" << t.L;
+  char mean[32];
+  std::snprintf(mean, sizeof mean, ":m%.1f", double(t.n) / double(t.nleaves));
+  os << mean << ":d" << (pl.near_fast ? pl.poly.deg : 0) << ":p";
+  for (int l = 0; l <= t.L; ++l) os << (l ? "," : "") << pl.lv[l].p;
+  return os.str();
+}
+
+// Launch-shape autotuner for one column-group width (the kernels' cost does
+// not depend on the charges, so zeros are used): the P2P lanes per target
+// G in {1, 2, 4} and, for one column, the M2L target tile (8 x 8 or 4 x 4).
+template <class T, int NR>
+void autotune_group(const Tree& t, FmmPlan<T>& pl) {
+  constexpr int g = NR >= 4 ? 2 : (NR >= 2 ? 1 : 0);
   hipStream_t st;
   HFMM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   hipEvent_t e0, e1;
@@ -1288,11 +1270,11 @@ void autotune(const Tree& t, FmmPlan<T>& pl) {
     (void)hipStreamDestroy(st);
   };
   try {
-    pl.ensure_work(1);
-    pl.qs.ensure(t.n);
-    pl.phis.ensure(t.n);
-    HFMM_HIP(hipMemsetAsync(pl.qs.p, 0, t.n * sizeof(cplx<T>), st));
-    HFMM_HIP(hipMemsetAsync(pl.M.p, 0, pl.coef_total * sizeof(cplx<T>), st));
+    pl.ensure_work(NR);
+    pl.qs.ensure((size_t)t.n * NR);
+    pl.phis.ensure((size_t)t.n * NR);
+    HFMM_HIP(hipMemsetAsync(pl.qs.p, 0, (size_t)t.n * NR * sizeof(cplx<T>), st));
+    HFMM_HIP(hipMemsetAsync(pl.M.p, 0, (size_t)pl.coef_total * NR * sizeof(cplx<T>), st));
     auto timed = [&](auto&& fn) {
       float best = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
@@ -1306,21 +1288,25 @@ void autotune(const Tree& t, FmmPlan<T>& pl) {
       }
       return best;
     };
-    const P2PArgs<T> a = p2p_args<T>(t, pl, pl.qs.p, pl.phis.p, 1, 0, nullptr, false, nullptr);
+    const P2PArgs<T> a = p2p_args<T>(t, pl, pl.qs.p, pl.phis.p, NR, 0, NR, nullptr, false, nullptr);
     // the fastest G; a larger G within 5 % of it wins (the choice stays
     // the same from one plan to the next when two are that close)
-    int bestG = pl.G;
-    float bestms = 1e30f;
+    float ms[3];
     const int Gs[3] = {1, 2, 4};
-    for (int i = 0; i < 3; ++i) pl.tune_ms[i] = timed([&] { launch_p2p<T, 1>(t, pl, a, Gs[i], st); });
-    for (int i = 0; i < 3; ++i) bestms = std::min(bestms, pl.tune_ms[i]);
+    float bestms = 1e30f;
+    for (int i = 0; i < 3; ++i) {
+      ms[i] = timed([&] { launch_p2p<T, NR>(t.L, t.nleaves, pl.near_fast, pl.poly.deg, a, Gs[i], st); });
+      bestms = std::min(bestms, ms[i]);
+    }
+    int bestG = pl.G[g];
     for (int i = 0; i < 3; ++i)
-      if (pl.tune_ms[i] <= 1.05f * bestms) bestG = Gs[i];
-    pl.G = bestG;
-    if (pl.use_mfma) {
+      if (ms[i] <= 1.05f * bestms) bestG = Gs[i];
+    pl.G[g] = bestG;
+    if (g == 0) {
+      for (int i = 0; i < 3; ++i) pl.tune_ms[i] = ms[i];
       bool any_choice = false;
       for (int l = 2; l <= t.L; ++l) any_choice = any_choice || (pl.mf[l].fit4 && pl.mf[l].tile == 8);
-      if (any_choice) {
+      if (pl.use_mfma && any_choice) {
         pl.m2l_small = false;
         const float big = timed([&] { launch_m2l<T, 1>(t, pl, pl.M.p, pl.Lc.p, 1, 0, nullptr, nullptr, st); });
         pl.m2l_small = true;
@@ -1340,6 +1326,95 @@ void autotune(const Tree& t, FmmPlan<T>& pl) {
 }  // namespace
 
 template <class T>
+void ensure_tuned(Tree& t, FmmPlan<T>& pl, int nrhs) {
+  if (t.L < 2) {  // nothing to choose on a single leaf
+    for (int g = 0; g < 3; ++g) pl.tuned[g] = true;
+    return;
+  }
+  bool need[3] = {false, false, false};
+  for (int r0 = 0; r0 < nrhs;) {
+    const int left = nrhs - r0, w = left >= 4 ? 4 : (left >= 2 ? 2 : 1);
+    need[nr_group(w)] = true;
+    r0 += w;
+  }
+  if (pl.tune_key.empty()) pl.tune_key = plan_key<T>(t, pl);
+  for (int g = 0; g < 3; ++g) {
+    if (!need[g] || pl.tuned[g]) continue;
+    const std::string key = pl.tune_key + ":c" + std::to_string(1 << g) + (pl.use_mfma ? "" : ":valu");
+    {
+      std::lock_guard<std::mutex> lk(tune_mutex());
+      auto it = tune_table().find(key);
+      if (it != tune_table().end()) {
+        pl.G[g] = it->second.G;
+        if (g == 0) pl.m2l_small = it->second.m2l_small != 0;
+        pl.tuned[g] = true;
+        pl.tune_source = 2;
+        continue;
+      }
+    }
+    if (t.autotune) {
+      if (g == 0)
+        autotune_group<T, 1>(t, pl);
+      else if (g == 1)
+        autotune_group<T, 2>(t, pl);
+      else
+        autotune_group<T, 4>(t, pl);
+      pl.tune_source = 1;
+      std::lock_guard<std::mutex> lk(tune_mutex());
+      TuneVal v;
+      v.G = pl.G[g];
+      v.m2l_small = pl.m2l_small ? 1 : 0;
+      tune_table()[key] = v;
+    }
+    pl.tuned[g] = true;
+  }
+}
+
+void tune_cache_save(const std::string& path) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  std::ofstream f(path);
+  HFMM_REQUIRE(f.good(), "tune_cache_save: cannot open " + path);
+  f << "# hfmm tuning cache: key G m2l_small\n";
+  for (const auto& kv : tune_table()) f << kv.first << " " << kv.second.G << " " << kv.second.m2l_small << "\n";
+  HFMM_REQUIRE(f.good(), "tune_cache_save: write failed on " + path);
+}
+
+int tune_cache_load(const std::string& path) {
+  std::ifstream f(path);
+  HFMM_REQUIRE(f.good(), "tune_cache_load: cannot open " + path);
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  std::string line;
+  int n = 0;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream is(line);
+    std::string key;
+    TuneVal v;
+    if (!(is >> key >> v.G >> v.m2l_small)) throw Error(HFMM_ERR_ARG, "tune_cache_load: bad line: " + line);
+    HFMM_REQUIRE(v.G == 1 || v.G == 2 || v.G == 4, "tune_cache_load: lanes per target must be 1, 2 or 4");
+    tune_table()[key] = v;
+    ++n;
+  }
+  return n;
+}
+
+int tune_cache_size() {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  return (int)tune_table().size();
+}
+
+void tune_cache_clear() {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  tune_table().clear();
+}
+
+template <class T>
+FmmPlan<T>* find_plan(Tree& t, double k, int p) {
+  auto it = t.plans.find(std::make_tuple(k, p, std::is_same<T, float>::value ? 1 : 0));
+  return it == t.plans.end() ? nullptr : static_cast<FmmPlan<T>*>(it->second.get());
+}
+
+template <class T>
 FmmPlan<T>& get_plan(Tree& t, double k, int p) {
   HFMM_REQUIRE(std::isfinite(k) && k > 0, "fmm: k must be finite and > 0");
   HFMM_REQUIRE(p >= 1 && p <= 40, "fmm: p must be in [1, 40]");
@@ -1347,7 +1422,7 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p) {
   auto it = t.plans.find(key);
   if (it == t.plans.end()) {
     auto pl = make_plan<T>(t, k, p);
-    autotune<T>(t, *pl);
+    ensure_tuned<T>(t, *pl, 1);
     it = t.plans.emplace(key, std::move(pl)).first;
   }
   return *static_cast<FmmPlan<T>*>(it->second.get());
@@ -1356,19 +1431,26 @@ FmmPlan<T>& get_plan(Tree& t, double k, int p) {
 template <class T>
 void fmm_sorted(const Tree& t, FmmPlan<T>& pl, const cplx<T>* q, cplx<T>* phi, int nrhs, const uint8_t* flags,
                 bool accumulate, hipStream_t st, const int* alive, StageTimer* tm, const int32_t* perm,
-                cplx<T>* qs) {
+                cplx<T>* qs, const FmmWork<T>* w, const cplx<T>* dn) {
   HFMM_REQUIRE(!perm || (t.L >= 2 && qs && !flags), "fmm: internal: permuted I/O needs a tree of depth >= 2");
-  pl.ensure_work(nrhs);
+  FmmWork<T> own;
+  if (!w) {
+    pl.ensure_work(nrhs);
+    own.M = pl.M.p;
+    own.Lc = pl.Lc.p;
+    own.far = pl.far.p;
+    w = &own;
+  }
   for (int r0 = 0; r0 < nrhs;) {
     const int left = nrhs - r0;
     if (left >= 4) {
-      run_cols<T, 4>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs);
+      run_cols<T, 4>(t, pl, *w, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs, dn);
       r0 += 4;
     } else if (left >= 2) {
-      run_cols<T, 2>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs);
+      run_cols<T, 2>(t, pl, *w, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs, dn);
       r0 += 2;
     } else {
-      run_cols<T, 1>(t, pl, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs);
+      run_cols<T, 1>(t, pl, *w, q, phi, nrhs, r0, flags, accumulate, st, alive, tm, perm, qs, dn);
       r0 += 1;
     }
   }
@@ -1391,12 +1473,31 @@ void source_flags(const Tree& t, int64_t lo, int64_t hi, uint8_t* d_flags, hipSt
   }
 }
 
+namespace {
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HFMM_HIP(hipStreamIsCapturing(st, &cs));
+  return cs != hipStreamCaptureStatusNone;
+}
+
+// Sorted unit normals (the point order of the tree) in the working precision.
+template <class T>
+__global__ void k_gather_normals(const double2* __restrict__ nrm, const int32_t* __restrict__ perm, int64_t N,
+                                 cplx<T>* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double2 v = nrm[perm[j]];
+  out[j] = mk<T>(T(v.x), T(v.y));
+}
+}  // namespace
+
 template <class T>
 void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, hipStream_t st,
                StageTimer* tm) {
   HFMM_REQUIRE(nrhs >= 1, "fmm_apply: nrhs must be >= 1");
   HFMM_REQUIRE(q != nullptr && phi != nullptr, "fmm_apply: NULL array");
   FmmPlan<T>& pl = get_plan<T>(t, k, p);
+  if (!capturing(st)) ensure_tuned<T>(t, pl, nrhs);
   const int64_t total = t.n * nrhs;
   pl.qs.ensure(total);
   pl.phis.ensure(total);
@@ -1417,14 +1518,86 @@ void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrh
   if (tm) tm->mark(5, st);
 }
 
+template <class T>
+void fmm_apply_dipole(Tree& t, double k, int p, const cplx<T>* q, const double* normals, cplx<T>* phi, int nrhs,
+                      hipStream_t st) {
+  HFMM_REQUIRE(nrhs >= 1, "fmm_apply_dipole: nrhs must be >= 1");
+  HFMM_REQUIRE(q != nullptr && phi != nullptr && normals != nullptr, "fmm_apply_dipole: NULL array");
+  FmmPlan<T>& pl = get_plan<T>(t, k, p);
+  const int64_t total = t.n * nrhs;
+  pl.qs.ensure(total);
+  pl.phis.ensure(total);
+  pl.dns.ensure(t.n);
+  k_gather<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(q, pl.qs.p, t.perm.p, t.n);
+  HFMM_LAUNCH_CHECK();
+  k_gather_normals<T><<<blocks_for(t.n), 256, 0, st>>>(reinterpret_cast<const double2*>(normals), t.perm.p, t.n,
+                                                      pl.dns.p);
+  HFMM_LAUNCH_CHECK();
+  fmm_sorted<T>(t, pl, pl.qs.p, pl.phis.p, nrhs, nullptr, false, st, nullptr, nullptr, nullptr, nullptr, nullptr,
+                pl.dns.p);
+  k_scatter<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(pl.phis.p, phi, t.perm.p, t.n);
+  HFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+size_t fmm_apply_scratch(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrhs, void* scratch,
+                         size_t bytes, hipStream_t st) {
+  HFMM_REQUIRE(nrhs >= 1, "fmm_apply: nrhs must be >= 1");
+  HFMM_REQUIRE(q != nullptr && phi != nullptr, "fmm_apply: NULL array");
+  FmmPlan<T>* pl = find_plan<T>(t, k, p);
+  if (!pl)
+    throw Error(HFMM_ERR_STATE,
+                "fmm_apply (no allocation): no plan for this (k, p, precision) on the tree; make it first "
+                "(hfmm_fmm_plan_info or one hfmm_fmm_apply)");
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t cb = sizeof(cplx<T>);
+  const size_t nq = (size_t)t.n * nrhs * cb;
+  const size_t nexp = t.L >= 2 ? (size_t)pl->coef_total * nrhs * cb : 0;
+  // regions: M, Lc, far, qs (depth >= 2); qs, phis (a single leaf)
+  const size_t need = t.L >= 2 ? 2 * up(nexp) + 2 * up(nq) : 2 * up(nq);
+  if (need > bytes) return need;
+  char* base = static_cast<char*>(scratch);
+  if (t.L >= 2) {
+    FmmWork<T> w;
+    w.M = reinterpret_cast<cplx<T>*>(base);
+    w.Lc = reinterpret_cast<cplx<T>*>(base + up(nexp));
+    w.far = reinterpret_cast<cplx<T>*>(base + 2 * up(nexp));
+    cplx<T>* qs = reinterpret_cast<cplx<T>*>(base + 2 * up(nexp) + up(nq));
+    fmm_sorted<T>(t, *pl, q, phi, nrhs, nullptr, false, st, nullptr, nullptr, t.perm.p, qs, &w);
+  } else {
+    cplx<T>* qs = reinterpret_cast<cplx<T>*>(base);
+    cplx<T>* phis = reinterpret_cast<cplx<T>*>(base + up(nq));
+    k_gather<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(q, qs, t.perm.p, t.n);
+    HFMM_LAUNCH_CHECK();
+    FmmWork<T> w;  // unused on a single leaf
+    fmm_sorted<T>(t, *pl, qs, phis, nrhs, nullptr, false, st, nullptr, nullptr, nullptr, nullptr, &w);
+    k_scatter<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(phis, phi, t.perm.p, t.n);
+    HFMM_LAUNCH_CHECK();
+  }
+  return 0;
+}
+
 template FmmPlan<float>& get_plan<float>(Tree&, double, int);
 template FmmPlan<double>& get_plan<double>(Tree&, double, int);
+template FmmPlan<float>* find_plan<float>(Tree&, double, int);
+template FmmPlan<double>* find_plan<double>(Tree&, double, int);
+template void ensure_tuned<float>(Tree&, FmmPlan<float>&, int);
+template void ensure_tuned<double>(Tree&, FmmPlan<double>&, int);
 template void fmm_sorted<float>(const Tree&, FmmPlan<float>&, const float2*, float2*, int, const uint8_t*, bool,
-                                hipStream_t, const int*, StageTimer*, const int32_t*, float2*);
+                                hipStream_t, const int*, StageTimer*, const int32_t*, float2*,
+                                const FmmWork<float>*, const float2*);
 template void fmm_sorted<double>(const Tree&, FmmPlan<double>&, const double2*, double2*, int, const uint8_t*, bool,
-                                 hipStream_t, const int*, StageTimer*, const int32_t*, double2*);
+                                 hipStream_t, const int*, StageTimer*, const int32_t*, double2*,
+                                 const FmmWork<double>*, const double2*);
 template void fmm_apply<float>(Tree&, double, int, const float2*, float2*, int, hipStream_t, StageTimer*);
 template void fmm_apply<double>(Tree&, double, int, const double2*, double2*, int, hipStream_t, StageTimer*);
+template void fmm_apply_dipole<float>(Tree&, double, int, const float2*, const double*, float2*, int, hipStream_t);
+template void fmm_apply_dipole<double>(Tree&, double, int, const double2*, const double*, double2*, int,
+                                       hipStream_t);
+template size_t fmm_apply_scratch<float>(Tree&, double, int, const float2*, float2*, int, void*, size_t,
+                                         hipStream_t);
+template size_t fmm_apply_scratch<double>(Tree&, double, int, const double2*, double2*, int, void*, size_t,
+                                          hipStream_t);
 
 StageTimer::~StageTimer() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);

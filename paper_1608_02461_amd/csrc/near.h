@@ -1,171 +1,20 @@
 // Near-field (P2P) kernels of the FMM: the direct sum of G(x - y) q(y) over
-// the sources in a target leaf's 3 x 3 leaf neighbourhood (Sec. 3, the near
-// part of the FMM sum), G = (i/4) H0^(1)(k r).  Included once, by fmm.hip,
-// inside its anonymous namespace, after the fmaT/log2T/cmac helpers; kept in
-// a file of its own so that its source identifies the measured kernel.
+// the sources in a target leaf's 3 x 3 leaf neighbourhood (the near part of
+// the FMM calculation flow, Sec. 5.1.2), G = (i/4) H0^(1)(k r) (Sec. 5.2, the
+// 2-D Green's function).  Included only by near.hip, inside an anonymous
+// namespace; kept in a file of its own so that its source identifies the
+// measured kernel.
 #pragma once
 
-template <class T>
-struct P2PArgs {
-  const int32_t* leaf_off;
-  const cplx<T>* rel;
-  const cplx<T>* q;
-  cplx<T>* phi;
-  const uint8_t* flags;  // leaf-level source flags or NULL
-  const int* alive;      // device flag: 0 skips the launch's work, or NULL
-  const int32_t* operm;  // NULL: phi in Morton order; else phi[operm[i]] (caller order)
-  int64_t N;
-  int nrhs, r0, L, G, accumulate;
-  T k, kls;  // k and k * leaf side
-  T cJ[32], cY[32];
-  T ua, ub;  // centred polynomial variable u = ua t + ub
-  T c1, jinv;  // J0 is carried as Jc = c1 J0; jinv = 1 / c1
-  // far field (L2P) of the target leaves, or Lc = NULL for none: local
-  // expansions [leaf][nrhs][2 pL + 1] of the leaf level, the Bessel series
-  // length and the scales (as in P2M)
-  const cplx<T>* Lc;
-  int pL, K;
-  T wscale, yscale;
-};
+#include "devutil.h"
+#include "p2p.h"
+#include "special.h"
 
-// L2P at one target, d = position relative to its leaf centre: the local
-// expansion sum_m L_m J_m(k rho) e^{i m theta} of the leaf (Sec. 5.1.2), for
-// every column.  With w = (k/2)(dx + i dy) (in the level's scaling) and
-// J_m e^{i m theta} = w^m / m! S_m, the positive orders are a Horner sum in
-// w and the negative ones, J_{-m} e^{-i m theta} = (-1)^m conj(w)^m / m! S_m,
-// one in conj(w); S_m runs downward alongside (sseries, sdown).
-template <class T, int NR>
-__device__ __forceinline__ void far_field(const P2PArgs<T>& a, const cplx<T>* Lleaf, cplx<T> d, cplx<T> (&F)[NR]) {
-  const int pL = a.pL, P = 2 * pL + 1;
-  const cplx<T>* Lf = Lleaf + pL;  // Lf[r P + m], m in [-pL, pL]
-  const T wr = a.wscale * d.x, wi = a.wscale * d.y;
-  const T y = a.yscale * (d.x * d.x + d.y * d.y);
-  T s1 = sseries(pL + 1, a.K, y), s0 = sseries(pL, a.K, y);
-  cplx<T> A[NR], B[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) A[r] = B[r] = mk<T>(0, 0);
-  cplx<T> lp[NR], lm[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    lp[r] = Lf[r * P + pL];
-    lm[r] = Lf[r * P - pL];
-  }
-  for (int n = pL; n >= 0; --n) {
-    // s0 = S_n, s1 = S_{n+1}; lp, lm = L_n, L_{-n}; the next pair loads ahead
-    cplx<T> lpn[NR], lmn[NR];
-    const int n1 = n > 0 ? n - 1 : 0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      lpn[r] = Lf[r * P + n1];
-      lmn[r] = Lf[r * P - n1];
-    }
-    const T inv = rcpT(T(n + 1));
-    const T sgs = (n & 1) ? -s0 : s0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      // A <- S_n L_n + (w / (n+1)) A;  B <- (-1)^n S_n L_{-n} + (conj(w) / (n+1)) B  (n >= 1)
-      const T ar = (A[r].x * wr - A[r].y * wi) * inv, ai = (A[r].x * wi + A[r].y * wr) * inv;
-      A[r] = mk<T>(fmaT(s0, lp[r].x, ar), fmaT(s0, lp[r].y, ai));
-      if (n > 0) {
-        const T br = (B[r].x * wr + B[r].y * wi) * inv, bi = (B[r].y * wr - B[r].x * wi) * inv;
-        B[r] = mk<T>(fmaT(sgs, lm[r].x, br), fmaT(sgs, lm[r].y, bi));
-      }
-      lp[r] = lpn[r];
-      lm[r] = lmn[r];
-    }
-    if (n > 0) {
-      const T sm = sdown(n, y, s0, s1);
-      s1 = s0;
-      s0 = sm;
-    }
-  }
-  // F = A_0 + conj(w) B_1
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-    F[r] = mk<T>(A[r].x + wr * B[r].x + wi * B[r].y, A[r].y + wr * B[r].y - wi * B[r].x);
-}
+// v_log_f32 without the denormal-input rescaling: every argument here is
+// (k r)^2 of two distinct FP32 positions, far above the denormal range.
+__device__ __forceinline__ float log2T(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double log2T(double x) { return log2(x); }
 
-// The last d = L - r levels of the downward pass below one box b of level r
-// and the L2P at every point of its 4^d leaves, one block of 256 threads per
-// box: L (level r+1) = its M2L part + L2L from L_b; L (level r+2, d = 2) the
-// same from level r+1; then far[i] = (i/4) sum_m L_m J_m(k rho) e^{i m theta}
-// for every point i of the leaves, stored at a.operm[i] when set (the
-// caller's order), else at i.  The intermediate levels stay in LDS.
-template <class T>
-struct DownTreeArgs {
-  P2PArgs<T> a;          // points, columns, far-field scales (far_field)
-  const cplx<T>* Lr;     // level r: final local expansions
-  const cplx<T>* L1;     // level r+1: M2L parts (d >= 1)
-  const cplx<T>* L2;     // level r+2: M2L parts (d = 2)
-  const cplx<T>* W1;     // L2L table level r -> r+1: [c][P0][P1]
-  const cplx<T>* W2;     // L2L table level r+1 -> r+2: [c][P1][P2]
-  cplx<T>* far;          // N x nrhs, written through a.operm when set
-  int d, P0, P1, P2;
-};
-
-template <class T, int NR>
-__global__ __launch_bounds__(256) void k_down_tree(DownTreeArgs<T> g) {
-  extern __shared__ unsigned char smem_raw[];
-  chain_priority();
-  const P2PArgs<T>& a = g.a;
-  if (a.alive && !a.alive[0]) return;
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const int P0 = g.P0, P1 = g.P1, P2 = g.P2, nrhs = a.nrhs, r0 = a.r0;
-  cplx<T>* s1 = reinterpret_cast<cplx<T>*>(smem_raw);  // [4][NR][P1]
-  cplx<T>* s2 = s1 + 4 * NR * P1;                        // [16][NR][P2]
-  if (g.d >= 1) {
-    for (int it = tid; it < 4 * NR * P1; it += 256) {
-      const int c = it / (NR * P1), rem = it - c * NR * P1, r = rem / P1, lo = rem - r * P1;
-      cplx<T> acc = g.L1[((size_t)(4 * b + c) * nrhs + r0 + r) * P1 + lo];
-      const cplx<T>* src = g.Lr + ((size_t)b * nrhs + r0 + r) * P0;
-      const cplx<T>* W = g.W1 + (size_t)c * P0 * P1 + lo;
-      for (int m = 0; m < P0; ++m) cmac(acc, W[(size_t)m * P1], src[m]);
-      s1[it] = acc;
-    }
-    __syncthreads();
-  }
-  if (g.d == 2) {
-    for (int it = tid; it < 16 * NR * P2; it += 256) {
-      const int c2 = it / (NR * P2), rem = it - c2 * NR * P2, r = rem / P2, lo = rem - r * P2;
-      cplx<T> acc = g.L2[((size_t)(16 * b + c2) * nrhs + r0 + r) * P2 + lo];
-      const cplx<T>* src = s1 + ((c2 >> 2) * NR + r) * P1;
-      const cplx<T>* W = g.W2 + (size_t)(c2 & 3) * P1 * P2 + lo;
-      for (int m = 0; m < P1; ++m) cmac(acc, W[(size_t)m * P2], src[m]);
-      s2[it] = acc;
-    }
-    __syncthreads();
-  }
-  // L2P: 256 / 4^d threads per leaf
-  const int nleaf = 1 << (2 * g.d), tpl = 256 >> (2 * g.d);
-  const int lf = tid / tpl, sub = tid - lf * tpl;
-  const int leaf = nleaf * b + lf;
-  const int PL = g.d == 2 ? P2 : (g.d == 1 ? P1 : P0);
-  const cplx<T>* Lleaf = g.d == 2 ? s2 + (size_t)lf * NR * PL
-                                  : (g.d == 1 ? s1 + (size_t)lf * NR * PL : g.Lr + ((size_t)b * nrhs + r0) * PL);
-  const int t0 = a.leaf_off[leaf], t1 = a.leaf_off[leaf + 1];
-  for (int i = t0 + sub; i < t1; i += tpl) {
-    cplx<T> F[NR];
-    far_field<T, NR>(a, Lleaf, a.rel[i], F);
-    const int64_t o = a.operm ? a.operm[i] : i;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) g.far[(size_t)(r0 + r) * a.N + o] = mk<T>(T(-0.25) * F[r].y, T(0.25) * F[r].x);
-  }
-}
-
-// phi += far over columns [r0, r0 + NR): both in the same point order.
-template <class T, int NR>
-__global__ __launch_bounds__(256) void k_combine(cplx<T>* __restrict__ phi, const cplx<T>* __restrict__ far,
-                                                 int64_t N, int r0, const int* alive) {
-  if (alive && !alive[0]) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const size_t j = (size_t)(r0 + r) * N + i;
-    const cplx<T> f = far[j], v = phi[j];
-    phi[j] = mk<T>(v.x + f.x, v.y + f.y);
-  }
-}
 // Running sums of q (J0 + i Y0) over one target's sources, J0 carried as
 // Jc = c1 J0:  Re = sum (qx J0 - qy Y0) = jinv aj - ay,
 //              Im = sum (qx Y0 + qy J0) = by + jinv bj.
@@ -365,17 +214,6 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   }
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2);
-// this maps hardware block b to a logical block so that every XCD walks one
-// contiguous range of the Morton order, and neighbouring blocks, which read
-// the same leaves, share an L2.  Identity when the grid is not a multiple of 8.
-__device__ __forceinline__ int xcd_swizzle(int b, int n) {
-  if (n & 7) return b;
-  return (b & 7) * (n >> 3) + (b >> 3);
-}
-
-// P2P, one block per parent box: its 4 waves are the 4 sibling target
-// leaves, and the union of their 3 x 3 neighbourhoods (a 4 x 4 block of
 // leaves) is staged in LDS once, positions relative to the parent centre and
 // scaled by k.  In row-major leaf order each wave's sources are 3 contiguous
 // runs (one per row) and the own leaf splits the middle run: 4 unmasked
@@ -557,6 +395,115 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
         p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2);
       }
       finish(ti, act, acc, G, g);
+    }
+  }
+}
+
+// Double-layer near field: phi_i += sum_j q_j dG/dn_j(x_i, y_j) over the
+// sources of the 3 x 3 leaf neighbourhood, with the normal derivative of the
+// 2-D Green's function taken at the source (Sec. 5.2):
+//   dG/dn_y = (i k / 4) H1(k r) (x - y).n_y / r = (k/4) (i J1 - Y1) c,
+//   c = (k (x - y)).n / (k r).
+// One wave per target leaf; the pair arithmetic runs in FP64 with the
+// full-range H1 routine (the boundary carries few sources, so this kernel
+// is small next to the volume near field).  Pairs at zero distance add
+// nothing (a flat element exerts no double-layer field on its own midpoint).
+template <class T, int NR>
+__global__ __launch_bounds__(64) void k_p2p_dipole(P2PArgs<T> a) {
+  constexpr int SCH = 256;
+  __shared__ double2 spos[SCH], snrm[SCH];
+  __shared__ cplx<T> sq[NR][SCH];
+  __shared__ int s_lo[9], s_pre[10], s_n;
+  __shared__ double s_ox[9], s_oy[9];
+  const int leaf = blockIdx.x;
+  if (a.alive && !a.alive[0]) return;
+  const int t0 = a.leaf_off[leaf], t1 = a.leaf_off[leaf + 1];
+  if (t0 == t1) return;
+  const int lane = threadIdx.x;
+  if (lane == 0) {
+    int bx, by;
+    demorton((uint32_t)leaf, bx, by);
+    const int nb = 1 << a.L;
+    int n = 0, pos = 0;
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int sx = bx + dx, sy = by + dy;
+        if (sx < 0 || sy < 0 || sx >= nb || sy >= nb) continue;
+        const uint32_t sl = morton((uint32_t)sx, (uint32_t)sy);
+        if (a.flags && !a.flags[sl]) continue;
+        const int lo = a.leaf_off[sl], hi = a.leaf_off[sl + 1];
+        if (lo == hi) continue;
+        s_lo[n] = lo;
+        s_pre[n] = pos;
+        s_ox[n] = double(dx) * (double)a.kls;
+        s_oy[n] = double(dy) * (double)a.kls;
+        pos += hi - lo;
+        ++n;
+      }
+    s_pre[n] = pos;
+    s_n = n;
+  }
+  __syncthreads();
+  const int nseg = s_n, total = s_pre[nseg];
+  if (total == 0 && a.accumulate) return;
+  const double k = (double)a.k;
+  for (int rb = t0; rb < t1; rb += 64) {
+    const int ti = rb + lane;
+    const bool act = ti < t1;
+    double xt = 0, yt = 0;
+    if (act) {
+      const cplx<T> d = a.rel[ti];
+      xt = k * (double)d.x;
+      yt = k * (double)d.y;
+    }
+    double accr[NR], acci[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) accr[r] = acci[r] = 0.0;
+    for (int c0 = 0; c0 < total; c0 += SCH) {
+      const int cnt = min(SCH, total - c0);
+      __syncthreads();
+      for (int idx = lane; idx < cnt; idx += 64) {
+        const int gi = c0 + idx;
+        int sg = 0;
+        while (sg + 1 < nseg && gi >= s_pre[sg + 1]) ++sg;
+        const int slot = s_lo[sg] + gi - s_pre[sg];
+        const cplx<T> d = a.rel[slot];
+        spos[idx] = make_double2(fma(k, (double)d.x, s_ox[sg]), fma(k, (double)d.y, s_oy[sg]));
+        const cplx<T> nv = a.dn[slot];
+        snrm[idx] = make_double2((double)nv.x, (double)nv.y);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sq[r][idx] = a.q[(size_t)(a.r0 + r) * a.N + slot];
+      }
+      __syncthreads();
+      if (act) {
+        for (int j = 0; j < cnt; ++j) {
+          const double dx = xt - spos[j].x, dy = yt - spos[j].y;
+          const double kr = sqrt(dx * dx + dy * dy);
+          if (!(kr > 0.0)) continue;
+          const double2 h = h1_general(kr);
+          const double c = 0.25 * k * (dx * snrm[j].x + dy * snrm[j].y) / kr;
+          const double vr = -c * h.y, vi = c * h.x;  // (k/4) c (i J1 - Y1)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double qr = (double)sq[r][j].x, qi = (double)sq[r][j].y;
+            accr[r] += qr * vr - qi * vi;
+            acci[r] += qr * vi + qi * vr;
+          }
+        }
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const size_t idx = (size_t)(a.r0 + r) * a.N + (a.operm ? a.operm[ti] : ti);
+        cplx<T> v = mk<T>(T(accr[r]), T(acci[r]));
+        if (a.accumulate) {
+          const cplx<T> o = a.phi[idx];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        a.phi[idx] = v;
+      }
     }
   }
 }

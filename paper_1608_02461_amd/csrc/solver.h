@@ -37,7 +37,17 @@ struct Solver {
   DevBuf<double2> V, Z, H, sn, g, y, hcur, part;
   DevBuf<double> cs, bnorm, est, rn, npart;
   DevBuf<int> active, jj, iters, state;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  double ms_setup = 0;             // wall time of solver_create (ms)
+  // outward unit normals of the boundary elements at their sorted slots
+  // (zero at interior nodes), for the double-layer pass
+  DevBuf<float2> nrm32;
+  DevBuf<double2> nrm64;
+  // BiCGSTAB workspace: r, r^, p, v, s, t, p^, s^ (n*n x nrhs each) and scalars
+  DevBuf<double2> bw;
+  DevBuf<double2> bsc;
+  DevBuf<double> bpart;
+  DevBuf<int> bact;
   ~Solver();
 };
 
@@ -50,5 +60,21 @@ void precond_apply(Solver& s, const double2* r, int64_t rs, double2* z, int64_t 
                    const int* alive, hipStream_t st);
 hfmm_status fgmres(Solver** s, int nprob, const double2* const* b, double2* const* x, int m, int maxit, double rtol,
                    bool use_graph, hfmm_solve_info* info, hipStream_t st);
+
+// u = the boundary-element solution with source f and Dirichlet data g at
+// the element midpoints (Sec. 5.2, boundary and interior equations with the
+// double-layer and 1/2 delta terms).  f, u: n*n x nrhs; g: 4(n+1) x nrhs.
+void dirichlet_apply(Solver& s, const double2* f, const double2* g, double2* u, hipStream_t st);
+
+// k^2 constant on nb x nb blocks of (n/nb)^2 nodes; kb row-major, block rows follow y.
+void solver_set_k2_blocks(Solver& s, const double* kb, int nb, hipStream_t st);
+
+// grad[b] = sum over the nodes x of block b of Re(conj(mu_x) u_x) (n/nb nodes a side).
+void k2_gradient(int n, const double2* u, const double2* mu, int nb, double* grad, hipStream_t st);
+
+// Right-preconditioned BiCGSTAB (van der Vorst 1992) with the same operator
+// and preconditioner; all FP64 on the device.
+hfmm_status bicgstab(Solver& s, const double2* b, double2* x, int maxit, double rtol, hfmm_solve_info* info,
+                     hipStream_t st);
 
 }  // namespace hfmm

@@ -547,6 +547,186 @@ __global__ void k_zero(cplx<T>* __restrict__ a, int64_t n) {
   if (i < n) a[i] = mk<T>(0, 0);
 }
 
+// ------------------------------------------------------------------ Dirichlet data
+// Dipole densities of the double-layer pass: -w g at the boundary slots
+// (q2 is zero at every other slot).
+template <class T>
+__global__ void k_dip_density(const double2* __restrict__ g, const int32_t* __restrict__ iperm, int64_t nn, int ng,
+                              int64_t N, double w, cplx<T>* __restrict__ q2, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ng * nrhs) return;
+  const int64_t c = i / ng, a = i - c * ng;
+  const double2 v = g[c * ng + a];
+  q2[c * N + iperm[nn + a]] = mk<T>(T(-w * v.x), T(-w * v.y));
+}
+
+// V_Gamma - D_Gamma - g/2 at the boundary nodes (phi holds V - D).
+template <class T>
+__global__ void k_vg_gather_half(const cplx<T>* __restrict__ phi, const int32_t* __restrict__ iperm, int64_t nn,
+                                 int ng, int64_t N, const double2* __restrict__ g, cplx<T>* __restrict__ vg, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ng * nrhs) return;
+  const int64_t c = i / ng, a = i - c * ng;
+  const cplx<T> p = phi[c * N + iperm[nn + a]];
+  const double2 v = g[c * ng + a];
+  vg[i] = mk<T>(T((double)p.x - 0.5 * v.x), T((double)p.y - 0.5 * v.y));
+}
+
+template <class T>
+__global__ void k_sorted_normals(const double2* __restrict__ nrm, const int32_t* __restrict__ perm, int64_t N,
+                                 cplx<T>* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double2 v = nrm[perm[j]];
+  out[j] = mk<T>(T(v.x), T(v.y));
+}
+
+// ------------------------------------------------------------------ k^2 blocks, adjoint gradient
+__global__ void k_k2_blocks(const double* __restrict__ kb, int nb, int n, double* __restrict__ k2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * n) return;
+  const int ix = (int)(i % n), iy = (int)(i / n), s = n / nb;
+  k2[i] = kb[(iy / s) * nb + ix / s];
+}
+
+// grad[b] = sum_{x in block b} Re(conj(mu_x) u_x), rows of the block in
+// order (deterministic).
+__global__ void k_k2_grad(const double2* __restrict__ u, const double2* __restrict__ mu, int n, int nb,
+                          double* __restrict__ grad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb * nb) return;
+  const int by = b / nb, bx = b - by * nb, s = n / nb;
+  double acc = 0;
+  for (int iy = by * s; iy < (by + 1) * s; ++iy)
+    for (int ix = bx * s; ix < (bx + 1) * s; ++ix) {
+      const int64_t i = (int64_t)iy * n + ix;
+      acc += mu[i].x * u[i].x + mu[i].y * u[i].y;
+    }
+  grad[b] = acc;
+}
+
+// ------------------------------------------------------------------ BiCGSTAB
+// Partial sums of conj(a) . b per column over chunks (fixed order).
+__global__ __launch_bounds__(kRed) void k_bdot(const double2* __restrict__ a, const double2* __restrict__ b, int64_t nn,
+                                               double2* __restrict__ part, int nblk) {
+  const int c = blockIdx.y;
+  const double2* ac = a + (int64_t)c * nn;
+  const double2* bc = b + (int64_t)c * nn;
+  const int64_t b0 = (int64_t)blockIdx.x * kChunk;
+  double sx = 0, sy = 0;
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = b0 + e * kRed + threadIdx.x;
+    if (x < nn) {
+      const double2 p = cmulc(ac[x], bc[x]);
+      sx += p.x;
+      sy += p.y;
+    }
+  }
+  __shared__ double2 red[kRed];
+  red[threadIdx.x] = make_double2(sx, sy);
+  __syncthreads();
+  for (int k = kRed / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      red[threadIdx.x].x += red[threadIdx.x + k].x;
+      red[threadIdx.x].y += red[threadIdx.x + k].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)c * nblk + blockIdx.x] = red[0];
+}
+
+// out[c * ostride] = sum of the column's partials
+__global__ __launch_bounds__(64) void k_bdot_fin(const double2* __restrict__ part, int nblk, double2* __restrict__ out,
+                                                 int ostride) {
+  const int c = blockIdx.x;
+  double sx = 0, sy = 0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    sx += part[(int64_t)c * nblk + b].x;
+    sy += part[(int64_t)c * nblk + b].y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off);
+    sy += __shfl_xor(sy, off);
+  }
+  if (threadIdx.x == 0) out[(int64_t)c * ostride] = make_double2(sx, sy);
+}
+
+// Per-column scalars, sc[c * 8 + .]: 0 rho (previous), 1 alpha, 2 omega,
+// 3 beta, 4..6 dot results.  stage 0: beta from rho_i (dot 4) (beta = 0 on
+// the first iteration); stage 1: alpha = rho_i / (r^, v) (dot 5); stage 2:
+// omega = (t, s) / (t, t) (dots 5, 6).  A zero denominator stops the column
+// (breakdown; the column keeps its iterate).
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = cabs2(b);
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__global__ void k_bscal(double2* __restrict__ sc, int* __restrict__ act, int nrhs, int stage, int first) {
+  const int c = threadIdx.x;
+  if (c >= nrhs || !act[c]) return;
+  double2* v = sc + c * 8;
+  if (stage == 0) {
+    const double2 rho = v[4];
+    if (first) {
+      v[3] = make_double2(0, 0);
+    } else if (cabs2(v[0]) == 0.0 || cabs2(v[2]) == 0.0) {
+      act[c] = 0;
+      return;
+    } else {
+      v[3] = cmul(cdiv(rho, v[0]), cdiv(v[1], v[2]));
+    }
+    v[0] = rho;
+  } else if (stage == 1) {
+    if (cabs2(v[5]) == 0.0) {
+      act[c] = 0;
+      return;
+    }
+    v[1] = cdiv(v[0], v[5]);
+  } else {
+    v[2] = cabs2(v[6]) > 0.0 ? cdiv(v[5], v[6]) : make_double2(0, 0);
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ void k_bupd_p(double2* __restrict__ p, const double2* __restrict__ r, const double2* __restrict__ v,
+                         const double2* __restrict__ sc, const int* __restrict__ act, int64_t nn) {
+  const int c = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn || !act[c]) return;
+  const double2 beta = sc[c * 8 + 3], om = sc[c * 8 + 2];
+  const int64_t j = (int64_t)c * nn + i;
+  const double2 ov = cmul(om, v[j]);
+  const double2 d = make_double2(p[j].x - ov.x, p[j].y - ov.y);
+  const double2 bd = cmul(beta, d);
+  p[j] = make_double2(r[j].x + bd.x, r[j].y + bd.y);
+}
+
+// s = r - alpha v
+__global__ void k_bupd_s(double2* __restrict__ s, const double2* __restrict__ r, const double2* __restrict__ v,
+                         const double2* __restrict__ sc, const int* __restrict__ act, int64_t nn) {
+  const int c = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn || !act[c]) return;
+  const double2 al = sc[c * 8 + 1];
+  const int64_t j = (int64_t)c * nn + i;
+  const double2 av = cmul(al, v[j]);
+  s[j] = make_double2(r[j].x - av.x, r[j].y - av.y);
+}
+
+// x += alpha p^ + omega s^;  r = s - omega t
+__global__ void k_bupd_xr(double2* __restrict__ x, double2* __restrict__ r, const double2* __restrict__ ph,
+                          const double2* __restrict__ sh, const double2* __restrict__ s, const double2* __restrict__ t,
+                          const double2* __restrict__ sc, const int* __restrict__ act, int64_t nn) {
+  const int c = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn || !act[c]) return;
+  const double2 al = sc[c * 8 + 1], om = sc[c * 8 + 2];
+  const int64_t j = (int64_t)c * nn + i;
+  const double2 a = cmul(al, ph[j]), b = cmul(om, sh[j]), w = cmul(om, t[j]);
+  x[j] = make_double2(x[j].x + a.x + b.x, x[j].y + a.y + b.y);
+  r[j] = make_double2(s[j].x - w.x, s[j].y - w.y);
+}
+
 // ------------------------------------------------------------------ helpers
 template <class T> DevBuf<cplx<T>>& q1_of(Solver& s);
 template <> DevBuf<float2>& q1_of<float>(Solver& s) { return s.q1f; }
@@ -591,8 +771,49 @@ void precond_impl(Solver& s, const double2* r, int64_t rs, double2* z, int64_t z
   HFMM_LAUNCH_CHECK();
 }
 
+// The boundary-element solution with Dirichlet data g (Sec. 5.2): pass 1
+// adds the double layer of the data, -sum_b w g_b dG/dn_b, to the volume
+// potential at every node; the boundary equation takes V_Gamma - D_Gamma -
+// g/2 (the 1/2 delta term) into q' = B (...) = w S^{-1}(g/2 + D - V); pass 2
+// adds the single layer of q' at the interior nodes (interior equation).
+template <class T> DevBuf<cplx<T>>& nrm_of(Solver& s);
+template <> DevBuf<float2>& nrm_of<float>(Solver& s) { return s.nrm32; }
+template <> DevBuf<double2>& nrm_of<double>(Solver& s) { return s.nrm64; }
+
 template <class T>
-void setup_precision(Solver& s, const double2* A, int64_t ld, hipStream_t st) {
+void dirichlet_impl(Solver& s, const double2* f, const double2* g, double2* u, hipStream_t st) {
+  Tree& t = *s.tree;
+  FmmPlan<T>& pl = get_plan<T>(t, s.k0, s.p);
+  const int64_t N = t.n;
+  const int nr = s.nrhs;
+  const int ng = (int)s.ng;
+  cplx<T>* q1 = q1_of<T>(s).p;
+  cplx<T>* q2 = q2_of<T>(s).p;
+  cplx<T>* phi = phi_of<T>(s).p;
+  cplx<T>* vg = vg_of<T>(s).p;
+  k_prec_gather<T><<<nblocks(N * nr), 256, 0, st>>>(f, s.nn, nullptr, s.nn, t.perm.p, N, s.h * s.h, q1, nr, nullptr);
+  HFMM_LAUNCH_CHECK();
+  fmm_sorted<T>(t, pl, q1, phi, nr, s.flags1.p, false, st);
+  k_dip_density<T><<<nblocks((int64_t)ng * nr), 256, 0, st>>>(g, t.iperm.p, s.nn, ng, N, s.h, q2, nr);
+  HFMM_LAUNCH_CHECK();
+  fmm_sorted<T>(t, pl, q2, phi, nr, s.flags2.p, true, st, nullptr, nullptr, nullptr, nullptr, nullptr,
+                nrm_of<T>(s).p);
+  k_vg_gather_half<T><<<nblocks((int64_t)ng * nr), 256, 0, st>>>(phi, t.iperm.p, s.nn, ng, N, g, vg, nr);
+  HFMM_LAUNCH_CHECK();
+  if (nr == 1)
+    k_bgemv<T, 1><<<(ng + 3) / 4, 256, 0, st>>>(B_of<T>(s).p, vg, ng, t.iperm.p, s.nn, N, q2, nr, nullptr);
+  else
+    k_bgemv<T, 4><<<(ng + 3) / 4, 256, 0, st>>>(B_of<T>(s).p, vg, ng, t.iperm.p, s.nn, N, q2, nr, nullptr);
+  HFMM_LAUNCH_CHECK();
+  fmm_sorted<T>(t, pl, q2, phi, nr, s.flags2.p, true, st);
+  const double2 sv = make_double2(s.svol.real(), s.svol.imag());
+  k_prec_scatter<T><<<nblocks(s.nn * nr), 256, 0, st>>>(phi, f, s.nn, u, s.nn, nullptr, t.iperm.p, s.nn, N, sv, nr,
+                                                       nullptr);
+  HFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+void setup_precision(Solver& s, const double2* A, int64_t ld, const double2* nrm_caller, hipStream_t st) {
   const int64_t N = s.tree->n;
   const int64_t ng = s.ng;
   B_of<T>(s).alloc(ng * ng);
@@ -605,7 +826,11 @@ void setup_precision(Solver& s, const double2* A, int64_t ld, hipStream_t st) {
   // q2 is zero away from the boundary slots, which are the only ones written
   k_zero<T><<<nblocks(N * s.nrhs), 256, 0, st>>>(q2_of<T>(s).p, N * s.nrhs);
   HFMM_LAUNCH_CHECK();
+  nrm_of<T>(s).alloc(N);
+  k_sorted_normals<T><<<nblocks(N), 256, 0, st>>>(nrm_caller, s.tree->perm.p, N, nrm_of<T>(s).p);
+  HFMM_LAUNCH_CHECK();
   FmmPlan<T>& pl = get_plan<T>(*s.tree, s.k0, s.p);
+  ensure_tuned<T>(*s.tree, pl, s.nrhs);
   pl.ensure_work(s.nrhs);
 }
 
@@ -614,6 +839,7 @@ void setup_precision(Solver& s, const double2* A, int64_t ld, hipStream_t st) {
 Solver::~Solver() {
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  if (ev2) (void)hipEventDestroy(ev2);
 }
 
 void fd_matvec(int n, double h, const double* d_k2, double k2c, const double2* x, double2* y, int nrhs,
@@ -639,6 +865,7 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
   HFMM_REQUIRE(leaf >= 1, "solver_create: leaf_size must be >= 1");
   HFMM_REQUIRE(nrhs >= 1 && nrhs <= 64, "solver_create: nrhs must be in [1, 64]");
   HFMM_REQUIRE(d_k2 != nullptr || std::isfinite(k2c), "solver_create: k2_const must be finite");
+  const auto t_setup = std::chrono::steady_clock::now();
   auto s = std::make_unique<Solver>();
   s->n = n;
   s->h = h;
@@ -673,6 +900,16 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
   }
   DevBuf<double> dxy;
   dxy.upload(xy);
+  // outward unit normals of the elements (bottom, right, top, left), zero at interior nodes
+  std::vector<double2> nrm(N, make_double2(0, 0));
+  for (int m = 0; m <= n; ++m) {
+    nrm[s->nn + m] = make_double2(0, -1);
+    nrm[s->nn + (n + 1) + m] = make_double2(1, 0);
+    nrm[s->nn + 2 * (n + 1) + m] = make_double2(0, 1);
+    nrm[s->nn + 3 * (n + 1) + m] = make_double2(-1, 0);
+  }
+  DevBuf<double2> dnrm;
+  dnrm.upload(nrm);
   s->tree = build_tree(dxy.p, N, 0.0, 0.0, 1.0, leaf, st);
   HFMM_REQUIRE(s->tree->L >= 2, "solver_create: tree depth below 2");
 
@@ -722,12 +959,14 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
   s->condS = normS * *std::max_element(hcol.begin(), hcol.end());
 
   if (fp32)
-    setup_precision<float>(*s, A.p, ld, st);
+    setup_precision<float>(*s, A.p, ld, dnrm.p, st);
   else
-    setup_precision<double>(*s, A.p, ld, st);
+    setup_precision<double>(*s, A.p, ld, dnrm.p, st);
   HFMM_HIP(hipEventCreate(&s->ev0));
   HFMM_HIP(hipEventCreate(&s->ev1));
+  HFMM_HIP(hipEventCreate(&s->ev2));
   HFMM_HIP(hipStreamSynchronize(st));
+  s->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
   return s;
 }
 
@@ -749,6 +988,32 @@ void precond_apply(Solver& s, const double2* r, int64_t rs, double2* z, int64_t 
     precond_impl<float>(s, r, rs, z, zs, jstate, alive, st);
   else
     precond_impl<double>(s, r, rs, z, zs, jstate, alive, st);
+}
+
+void dirichlet_apply(Solver& s, const double2* f, const double2* g, double2* u, hipStream_t st) {
+  HFMM_REQUIRE(f != nullptr && g != nullptr && u != nullptr, "dirichlet_apply: NULL array");
+  HFMM_REQUIRE(f != u, "dirichlet_apply: f and u must not alias");
+  if (s.fp32)
+    dirichlet_impl<float>(s, f, g, u, st);
+  else
+    dirichlet_impl<double>(s, f, g, u, st);
+}
+
+void solver_set_k2_blocks(Solver& s, const double* kb, int nb, hipStream_t st) {
+  HFMM_REQUIRE(kb != nullptr, "set_k2_blocks: NULL array");
+  HFMM_REQUIRE(nb >= 1 && nb <= s.n && s.n % nb == 0, "set_k2_blocks: nb must divide n");
+  s.k2.ensure(s.nn);
+  k_k2_blocks<<<nblocks(s.nn), 256, 0, st>>>(kb, nb, s.n, s.k2.p);
+  HFMM_LAUNCH_CHECK();
+  s.field = true;
+}
+
+void k2_gradient(int n, const double2* u, const double2* mu, int nb, double* grad, hipStream_t st) {
+  HFMM_REQUIRE(n >= 1, "k2_gradient: n must be >= 1");
+  HFMM_REQUIRE(nb >= 1 && nb <= n && n % nb == 0, "k2_gradient: nb must divide n");
+  HFMM_REQUIRE(u != nullptr && mu != nullptr && grad != nullptr, "k2_gradient: NULL array");
+  k_k2_grad<<<nblocks((int64_t)nb * nb), 256, 0, st>>>(u, mu, n, nb, grad);
+  HFMM_LAUNCH_CHECK();
 }
 
 namespace {
@@ -844,7 +1109,7 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
     HFMM_REQUIRE(b[q] != nullptr && x[q] != nullptr, "fgmres: NULL array");
     ensure_krylov(*S[q], m, st);
   }
-  double ms_prec = 0;
+  double ms_prec = 0, ms_kry = 0;
   // ||b||
   for (int q = 0; q < nprob; ++q) {
     Solver& s = *S[q];
@@ -960,13 +1225,16 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
           HFMM_HIP(hipGraphLaunch(gexec, st));
         } else {
           for (int q : live) arnoldi_step(*S[q], maxit, rtol, st, timed ? S[q]->ev1 : nullptr);
+          if (timed) HFMM_HIP(hipEventRecord(S[0]->ev2, st));
         }
         for (int q : live) HFMM_HIP(hipMemcpyAsync(&alive[q], S[q]->state.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
         HFMM_HIP(hipStreamSynchronize(st));
         if (timed) {
-          float ms = 0;
+          float ms = 0, mk = 0;
           HFMM_HIP(hipEventElapsedTime(&ms, S[0]->ev0, S[0]->ev1));
+          HFMM_HIP(hipEventElapsedTime(&mk, S[0]->ev1, S[0]->ev2));
           ms_prec += ms;
+          ms_kry += mk;
         }
       }
       // ---- end of cycle: x += Z R^{-1} g
@@ -1011,12 +1279,145 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
     }
     in.restarts = P.restarts;
     in.ms_precond = ms_prec;
+    in.ms_krylov = ms_kry;
     in.ms_total = ms_total;
+    in.ms_setup = S[q]->ms_setup;
     if (info) info[q] = in;
     if (P.numeric) worst = HFMM_ERR_NUMERIC;
     else if (!in.converged && worst == HFMM_OK) worst = HFMM_NOT_CONVERGED;
   }
   return worst;
+}
+
+hfmm_status bicgstab(Solver& s, const double2* b, double2* x, int maxit, double rtol, hfmm_solve_info* info,
+                     hipStream_t st) {
+  HFMM_REQUIRE(b != nullptr && x != nullptr, "bicgstab: NULL array");
+  HFMM_REQUIRE(maxit >= 1, "bicgstab: maxit must be >= 1");
+  HFMM_REQUIRE(std::isfinite(rtol) && rtol > 0, "bicgstab: rtol must be > 0");
+  const auto t_start = std::chrono::steady_clock::now();
+  const int nr = s.nrhs;
+  const int64_t nn = s.nn;
+  const int nblk = (int)((nn + kChunk - 1) / kChunk);
+  s.bw.ensure((size_t)8 * nn * nr);
+  s.bsc.ensure((size_t)8 * nr);
+  s.bpart.ensure((size_t)nblk * nr * 2);  // nblk * nr complex partial sums
+  s.npart.ensure((size_t)nblk * nr);
+  s.rn.ensure(nr);
+  s.bact.ensure(nr);
+  s.bnorm.ensure(nr);
+  double2* W = s.bw.p;
+  double2 *r = W, *rh = W + nn * nr, *pv = W + 2 * nn * nr, *v = W + 3 * nn * nr, *sv = W + 4 * nn * nr,
+          *tv = W + 5 * nn * nr, *ph = W + 6 * nn * nr, *sh = W + 7 * nn * nr;
+  double2* part = reinterpret_cast<double2*>(s.bpart.p);
+  double2* sc = s.bsc.p;
+  const double ih2 = 1.0 / (s.h * s.h);
+  const double* k2 = s.field ? s.k2.p : nullptr;
+  const dim3 gv(nblocks(nn), nr), gd(nblk, nr);
+  auto norms = [&](const double2* vec, std::vector<double>& out) {
+    k_nrm_part<<<gd, kRed, 0, st>>>(vec, nn, nn, nullptr, nullptr, s.npart.p, nblk);
+    k_nrm_fin<<<nr, 64, 0, st>>>(s.npart.p, nblk, nullptr, nullptr, s.rn.p, nullptr, 1);
+    HFMM_LAUNCH_CHECK();
+    out.resize(nr);
+    HFMM_HIP(hipMemcpyAsync(out.data(), s.rn.p, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HFMM_HIP(hipStreamSynchronize(st));
+  };
+  auto dot = [&](const double2* a, const double2* c, int slot) {  // into sc[col * 8 + slot]
+    k_bdot<<<gd, kRed, 0, st>>>(a, c, nn, part, nblk);
+    k_bdot_fin<<<nr, 64, 0, st>>>(part, nblk, sc + slot, 8);
+    HFMM_LAUNCH_CHECK();
+  };
+  std::vector<double> bn, rn;
+  norms(b, bn);
+  // r = b - A x, r^ = r, p = v = 0, scalars rho = alpha = omega = 1
+  k_fd<<<gv, 256, 0, st>>>(s.n, ih2, k2, s.k2c, x, nn, r, nn, b, nn, nr, nullptr, nullptr);
+  HFMM_LAUNCH_CHECK();
+  HFMM_HIP(hipMemcpyAsync(rh, r, (size_t)nn * nr * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  k_zero<double><<<nblocks(2 * nn * nr), 256, 0, st>>>(pv, 2 * nn * nr);  // p and v
+  HFMM_LAUNCH_CHECK();
+  std::vector<double2> hsc(8 * nr, make_double2(0, 0));
+  for (int c = 0; c < nr; ++c) hsc[c * 8 + 0] = hsc[c * 8 + 1] = hsc[c * 8 + 2] = make_double2(1, 0);
+  HFMM_HIP(hipMemcpyAsync(sc, hsc.data(), hsc.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  norms(r, rn);
+  std::vector<int> act(nr, 0), conv(nr, 0);
+  bool numeric = false;
+  for (int c = 0; c < nr; ++c) {
+    if (!(bn[c] > 0)) {
+      conv[c] = 1;  // b = 0: x = 0 is exact when x0 = 0; the residual check below decides
+      continue;
+    }
+    if (!std::isfinite(rn[c])) numeric = true;
+    conv[c] = rn[c] <= rtol * bn[c];
+    act[c] = !conv[c] && std::isfinite(rn[c]);
+  }
+  HFMM_HIP(hipMemcpyAsync(s.bact.p, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+  HFMM_HIP(hipStreamSynchronize(st));
+  int it = 0;
+  double ms_prec = 0;
+  for (; it < maxit; ++it) {
+    bool any = false;
+    for (int c = 0; c < nr; ++c) any = any || act[c];
+    if (!any) break;
+    dot(rh, r, 4);
+    k_bscal<<<1, 64, 0, st>>>(sc, s.bact.p, nr, 0, it == 0 ? 1 : 0);
+    k_bupd_p<<<gv, 256, 0, st>>>(pv, r, v, sc, s.bact.p, nn);
+    HFMM_LAUNCH_CHECK();
+    HFMM_HIP(hipEventRecord(s.ev0, st));
+    precond_apply(s, pv, nn, ph, nn, nullptr, nullptr, st);
+    HFMM_HIP(hipEventRecord(s.ev1, st));
+    k_fd<<<gv, 256, 0, st>>>(s.n, ih2, k2, s.k2c, ph, nn, v, nn, nullptr, 0, nr, nullptr, nullptr);
+    HFMM_LAUNCH_CHECK();
+    dot(rh, v, 5);
+    k_bscal<<<1, 64, 0, st>>>(sc, s.bact.p, nr, 1, 0);
+    k_bupd_s<<<gv, 256, 0, st>>>(sv, r, v, sc, s.bact.p, nn);
+    HFMM_LAUNCH_CHECK();
+    precond_apply(s, sv, nn, sh, nn, nullptr, nullptr, st);
+    k_fd<<<gv, 256, 0, st>>>(s.n, ih2, k2, s.k2c, sh, nn, tv, nn, nullptr, 0, nr, nullptr, nullptr);
+    HFMM_LAUNCH_CHECK();
+    dot(tv, sv, 5);
+    dot(tv, tv, 6);
+    k_bscal<<<1, 64, 0, st>>>(sc, s.bact.p, nr, 2, 0);
+    k_bupd_xr<<<gv, 256, 0, st>>>(x, r, ph, sh, sv, tv, sc, s.bact.p, nn);
+    HFMM_LAUNCH_CHECK();
+    norms(r, rn);  // synchronises
+    float mp = 0;
+    HFMM_HIP(hipEventElapsedTime(&mp, s.ev0, s.ev1));
+    ms_prec += mp;
+    std::vector<int> dact(nr);
+    HFMM_HIP(hipMemcpyAsync(dact.data(), s.bact.p, nr * sizeof(int), hipMemcpyDeviceToHost, st));
+    HFMM_HIP(hipStreamSynchronize(st));
+    bool change = false;
+    for (int c = 0; c < nr; ++c) {
+      if (!act[c]) continue;
+      if (!std::isfinite(rn[c])) numeric = true;
+      if (!dact[c] || !std::isfinite(rn[c]) || rn[c] <= rtol * bn[c]) {
+        act[c] = 0;
+        change = true;
+      }
+    }
+    if (change) HFMM_HIP(hipMemcpyAsync(s.bact.p, act.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  // true residual
+  k_fd<<<gv, 256, 0, st>>>(s.n, ih2, k2, s.k2c, x, nn, r, nn, b, nn, nr, nullptr, nullptr);
+  HFMM_LAUNCH_CHECK();
+  norms(r, rn);
+  hfmm_solve_info in{};
+  in.nrhs = nr;
+  in.iters = it;
+  in.restarts = 0;
+  in.converged = 1;
+  for (int c = 0; c < nr; ++c) {
+    const double rel = bn[c] > 0 ? rn[c] / bn[c] : (rn[c] > 0 ? INFINITY : 0.0);
+    if (!std::isfinite(rel)) numeric = numeric || !(bn[c] == 0);
+    in.rel_res_true = std::max(in.rel_res_true, rel);
+    in.converged = in.converged && (rel <= rtol);
+  }
+  in.rel_res_est = in.rel_res_true;
+  in.ms_precond = 2.0 * ms_prec;  // the first of the two applies of an iteration is timed
+  in.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  in.ms_setup = s.ms_setup;
+  if (info) *info = in;
+  if (numeric) return HFMM_ERR_NUMERIC;
+  return in.converged ? HFMM_OK : HFMM_NOT_CONVERGED;
 }
 
 }  // namespace hfmm

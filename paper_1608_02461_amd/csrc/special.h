@@ -85,6 +85,85 @@ __host__ __device__ inline double2 h0_general(double x) {
   return r;
 }
 
+// (J1(x), Y1(x)) for x > 0, by the same three ranges as h0_general:
+//   x < 4        power series (DLMF 10.2.2 and 10.8.1 with n = 1):
+//                J1 = (x/2) sum_k t_k,  t_k = (-x^2/4)^k / (k! (k+1)!),
+//                Y1 = -2/(pi x) + (2/pi)(ln(x/2) + gamma_E) J1
+//                     - (1/pi)(x/2) sum_k (H_k + H_{k+1}) t_k  (H_k harmonic numbers);
+//   4 <= x < 20  Miller's backward recurrence (normalised as in h0_general)
+//                for J0, J1 and the series obtained by differentiating the
+//                Neumann series of Y0 (Y1 = -Y0', J_2k' = (J_{2k-1} - J_{2k+1})/2):
+//                Y1 = (2/pi)[(ln(x/2) + gamma_E) J1 - J0/x
+//                            + sum_{k>=1} (-1)^k (J_{2k-1} - J_{2k+1}) / k];
+//   x >= 20      Hankel's expansion (DLMF 10.17.3) with nu = 1,
+//                a_k = a_{k-1} (4 - (2k-1)^2) / (8k).
+__host__ __device__ inline double2 h1_general(double x) {
+  double2 r;
+  if (x < 4.0) {
+    const double y = 0.25 * x * x;
+    double t = 1.0, S = 1.0, Hk = 0.0, Hk1 = 1.0, Yh = Hk + Hk1;
+    for (int k = 1; k <= 24; ++k) {
+      t *= -y / (double(k) * double(k + 1));
+      Hk += 1.0 / double(k);
+      Hk1 += 1.0 / double(k + 1);
+      S += t;
+      Yh += (Hk + Hk1) * t;
+    }
+    const double J1 = 0.5 * x * S;
+    r.x = J1;
+    r.y = -2.0 / (kPi * x) + (2.0 / kPi) * (log(0.5 * x) + kEulerGamma) * J1 - (0.5 * x / kPi) * Yh;
+  } else if (x < 20.0) {
+    int N = (int)x + 30;
+    N += N & 1;
+    const double inv = 1.0 / x;
+    double fp1 = 0.0, f = 1e-30, norm = 0.0, S = 0.0, f1 = 0.0;
+    // f holds f_n; walk n = N .. 1 producing f_{n-1}
+    for (int n = N; n >= 1; --n) {
+      if ((n & 1) == 0) {
+        norm += 2.0 * f;
+      } else {
+        // f_n with n = 2k - 1 enters with (-1)^k / k, with n = 2k + 1 (k >= 1) with -(-1)^k / k
+        const int ka = (n + 1) >> 1, kb = (n - 1) >> 1;
+        S += ((ka & 1) ? -f : f) / double(ka);
+        if (kb >= 1) S -= ((kb & 1) ? -f : f) / double(kb);
+      }
+      if (n == 1) f1 = f;
+      double fm = 2.0 * n * inv * f - fp1;
+      fp1 = f;
+      f = fm;
+    }
+    norm += f;
+    const double J0 = f / norm, J1 = f1 / norm;
+    r.x = J1;
+    r.y = (2.0 / kPi) * ((log(0.5 * x) + kEulerGamma) * J1 - J0 * inv + S / norm);
+  } else {
+    double a = 1.0, sr = 1.0, si = 0.0, last = 1.0;
+    const double inv = 1.0 / x;
+    double xp = 1.0;
+    for (int k = 1; k <= 40; ++k) {
+      double an = a * double(4 - (2 * k - 1) * (2 * k - 1)) / (8.0 * k);
+      xp *= inv;
+      double term = an * xp;
+      if (fabs(term) > last) break;
+      switch (k & 3) {
+        case 0: sr += term; break;
+        case 1: si += term; break;
+        case 2: sr -= term; break;
+        default: si -= term; break;
+      }
+      a = an;
+      last = fabs(term);
+      if (last < 1e-17) break;
+    }
+    double s, c;
+    sincos(x - 0.75 * kPi, &s, &c);
+    const double amp = sqrt(2.0 / (kPi * x));
+    r.x = amp * (c * sr - s * si);
+    r.y = amp * (s * sr + c * si);
+  }
+  return r;
+}
+
 // Host: J_n(x) for n = 0..nmax.
 void besselj_seq(int nmax, double x, std::vector<double>& J);
 // Host: H_n^(1)(x) = J_n + i Y_n for n = 0..nmax, x > 0.

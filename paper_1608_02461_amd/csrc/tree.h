@@ -35,6 +35,11 @@ struct Tree {
   // creates them
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // options of the plans made from now on (hfmm_tree_set_options): the VALU
+  // downward kernels instead of MFMA (reference and ablation), and whether
+  // the autotuner times launch shapes (else defaults; the cache still applies)
+  bool m2l_valu = false;
+  bool autotune = true;
 
   Tree() = default;
   Tree(const Tree&) = delete;

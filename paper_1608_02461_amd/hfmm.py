@@ -37,7 +37,8 @@ class HFMMError(RuntimeError):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("nrhs", ctypes.c_int32), ("rel_res_true", ctypes.c_double), ("rel_res_est", ctypes.c_double),
-                ("ms_precond", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_precond", ctypes.c_double), ("ms_krylov", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_setup", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -53,6 +54,17 @@ _SIGS = {
                         ctypes.POINTER(_i32)], _i32),
     "hfmm_tree_export": ([_vp, _vp, _vp, _vp], _i32),
     "hfmm_tree_destroy": ([_vp], _i32),
+    "hfmm_tree_set_options": ([_vp, _i32, _i32], _i32),
+    "hfmm_fmm_apply_dipole": ([_vp, _f64, _i32, _i32, _vp, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_tune_cache_save": ([ctypes.c_char_p], _i32),
+    "hfmm_tune_cache_load": ([ctypes.c_char_p, ctypes.POINTER(_i32)], _i32),
+    "hfmm_tune_cache_size": ([], _i32),
+    "hfmm_tune_cache_clear": ([], _i32),
+    "hfmm_solver_set_k2_blocks": ([_vp, _vp, _i32, _vp], _i32),
+    "hfmm_k2_gradient": ([_i32, _vp, _vp, _i32, _vp, _vp], _i32),
+    "hfmm_dirichlet_apply": ([_vp, _vp, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_solver_boundary_nodes": ([_vp, _vp, _vp], _i32),
+    "hfmm_bicgstab_solve": ([_vp, _vp, _vp, _i32, _f64, ctypes.POINTER(SolveInfo), _vp], _i32),
     "hfmm_fmm_apply": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
     "hfmm_fmm_apply_timed": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_float), _vp], _i32),
     "hfmm_fmm_plan_info": ([_vp, _f64, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -144,6 +156,10 @@ class Tree:
         _check(lib().hfmm_tree_info(self.handle, ctypes.byref(L), ctypes.byref(n), ctypes.byref(nl), ctypes.byref(mx)))
         return {"levels": L.value, "n_points": n.value, "n_leaves": nl.value, "max_leaf_count": mx.value}
 
+    def set_options(self, m2l_valu=False, autotune=True):
+        """Options of the plans made from now on (cached plans are dropped)."""
+        _check(lib().hfmm_tree_set_options(self.handle, int(m2l_valu), int(autotune)))
+
     def export(self, stream=None):
         inf = self.info()
         perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
@@ -174,6 +190,52 @@ def hfmm_fmm_apply(tree, k, p, q, prec=FP64, stream=None):
     _check(lib().hfmm_fmm_apply(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), qc.shape[0],
                                 _stream(stream)))
     return _from_colmajor(phi, squeeze)
+
+
+def hfmm_fmm_apply_dipole(tree, k, p, q, normals, prec=FP64, stream=None):
+    """phi_i = sum_{j: r_ij > 0} q_j dG/dn_j(x_i, x_j) (double layer); normals (n, 2) float64 unit vectors."""
+    dtype = torch.complex128 if prec == FP64 else torch.complex64
+    qc, squeeze = _colmajor(q, dtype, "q")
+    if qc.shape[1] != tree.n:
+        raise ValueError("q has the wrong number of points")
+    _require_cuda(normals, torch.float64, "normals")
+    if tuple(normals.shape) != (tree.n, 2):
+        raise ValueError("normals must be (n, 2)")
+    nrm = normals.contiguous()
+    phi = torch.empty_like(qc)
+    _check(lib().hfmm_fmm_apply_dipole(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(nrm), _ptr(phi),
+                                       qc.shape[0], _stream(stream)))
+    return _from_colmajor(phi, squeeze)
+
+
+def hfmm_tune_cache_save(path):
+    _check(lib().hfmm_tune_cache_save(os.fsencode(path)))
+
+
+def hfmm_tune_cache_load(path):
+    n = _i32()
+    _check(lib().hfmm_tune_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def hfmm_tune_cache_size():
+    return lib().hfmm_tune_cache_size()
+
+
+def hfmm_tune_cache_clear():
+    _check(lib().hfmm_tune_cache_clear())
+
+
+def hfmm_k2_gradient(n, u, mu, nb, stream=None):
+    """Block sums of Re(conj(mu) u) over nb x nb blocks (nb = n: per node); u, mu (n*n,) complex128."""
+    _require_cuda(u, torch.complex128, "u")
+    _require_cuda(mu, torch.complex128, "mu")
+    if u.numel() != n * n or mu.numel() != n * n:
+        raise ValueError("u and mu must have n*n entries")
+    uc, mc = u.contiguous(), mu.contiguous()
+    grad = torch.empty(nb * nb, dtype=torch.float64, device=u.device)
+    _check(lib().hfmm_k2_gradient(int(n), _ptr(uc), _ptr(mc), int(nb), _ptr(grad), _stream(stream)))
+    return grad.view(nb, nb)
 
 
 # stage names of hfmm_fmm_apply_timed; on a tree of depth >= 2 "upward" is
@@ -239,6 +301,37 @@ class Solver:
             _require_cuda(k2, torch.float64, "k2")
             k2 = k2.contiguous()
         _check(lib().hfmm_solver_set_k2(self.handle, _ptr(k2), float(k2_const), _stream(stream)))
+
+    def set_k2_blocks(self, kb, stream=None):
+        """k^2 constant on square blocks: kb (nb, nb) float64, block rows follow y."""
+        _require_cuda(kb, torch.float64, "kb")
+        kb = kb.contiguous()
+        _check(lib().hfmm_solver_set_k2_blocks(self.handle, _ptr(kb), int(kb.shape[0]), _stream(stream)))
+
+    def boundary_nodes(self, stream=None):
+        """(4(n+1), 2) element midpoints in the library's boundary order."""
+        xy = torch.empty((4 * (self.n + 1), 2), dtype=torch.float64, device=self.device)
+        _check(lib().hfmm_solver_boundary_nodes(self.handle, _ptr(xy), _stream(stream)))
+        return xy
+
+    def dirichlet_apply(self, f, g, stream=None):
+        """Boundary-element solution with source f (n*n) and Dirichlet data g (4(n+1)) at the midpoints."""
+        fc, squeeze = _colmajor(f, torch.complex128, "f")
+        gc, _ = _colmajor(g, torch.complex128, "g")
+        if fc.shape[1] != self.n * self.n or gc.shape[1] != 4 * (self.n + 1) or gc.shape[0] != fc.shape[0]:
+            raise ValueError("f must have n*n rows and g 4(n+1) rows, with the same columns")
+        u = torch.empty_like(fc)
+        _check(lib().hfmm_dirichlet_apply(self.handle, _ptr(fc), _ptr(gc), _ptr(u), fc.shape[0], _stream(stream)))
+        return _from_colmajor(u, squeeze)
+
+    def bicgstab(self, b, x0=None, maxit=5000, rtol=1e-6, stream=None, strict=False):
+        bc, squeeze = _colmajor(b, torch.complex128, "b")
+        x = torch.zeros_like(bc) if x0 is None else _colmajor(x0, torch.complex128, "x0")[0].clone()
+        info = SolveInfo()
+        st = lib().hfmm_bicgstab_solve(self.handle, _ptr(bc), _ptr(x), int(maxit), float(rtol), ctypes.byref(info),
+                                       _stream(stream))
+        _check(st, allow_not_converged=not strict)
+        return _from_colmajor(x, squeeze), info.as_dict()
 
     def precond_apply(self, r, stream=None):
         rc, squeeze = _colmajor(r, torch.complex128, "r")

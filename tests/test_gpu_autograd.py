@@ -7,7 +7,7 @@ import torch
 
 from oracle import adjoint
 from paper_1608_02461_amd import hfmm, workloads
-from paper_1608_02461_amd.autograd import expand_blocks, helmholtz_solve
+from paper_1608_02461_amd.autograd import helmholtz_solve
 from gpu_util import rel, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
@@ -28,7 +28,7 @@ def test_gradient_matches_oracle_adjoint(prec):
     n, nb, k0 = 64, 4, 20.0
     kb, f, P, d, s = setup(n, nb, k0, 81, 100, prec)
     kbt = to_dev(kb).requires_grad_(True)
-    u = helmholtz_solve(expand_blocks(kbt, n), to_dev(f), s, restart=40, rtol=1e-11)
+    u = helmholtz_solve(kbt, to_dev(f), s, restart=40, rtol=1e-11)
     Pt = to_dev(P)
     r = u[Pt] - to_dev(d)
     J = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
@@ -43,14 +43,14 @@ def test_gradient_matches_central_differences():
     n, nb, k0 = 48, 4, 16.0
     kb, f, P, d, s = setup(n, nb, k0, 82, 80, hfmm.FP64)
     kbt = to_dev(kb).requires_grad_(True)
-    u = helmholtz_solve(expand_blocks(kbt, n), to_dev(f), s, restart=40, rtol=1e-12)
+    u = helmholtz_solve(kbt, to_dev(f), s, restart=40, rtol=1e-12)
     r = u[to_dev(P)] - to_dev(d)
     (0.5 * (r.real ** 2 + r.imag ** 2).sum()).backward()
     g = to_np(kbt.grad)
 
     def J_of(kbv):
         with torch.no_grad():
-            uu = helmholtz_solve(expand_blocks(to_dev(kbv), n), to_dev(f), s, restart=40, rtol=1e-12)
+            uu = helmholtz_solve(to_dev(kbv), to_dev(f), s, restart=40, rtol=1e-12)
             rr = uu[to_dev(P)] - to_dev(d)
             return float(0.5 * (rr.real ** 2 + rr.imag ** 2).sum())
 
@@ -70,9 +70,36 @@ def test_gradient_wrt_source():
     w = workloads.complex_normal(rng, n * n)
     s = hfmm.Solver(n, k0, p=6, leaf_size=16)
     ft = to_dev(f).requires_grad_(True)
-    u = helmholtz_solve(to_dev(np.full(n * n, k0 * k0)), ft, s, restart=40, rtol=1e-12)
+    u = helmholtz_solve(to_dev(np.full((1, 1), k0 * k0)), ft, s, restart=40, rtol=1e-12)
     L = (to_dev(w) * u).real.sum()
     L.backward()
     # L = Re(w^T A^{-1} f): dL/dRe f + i dL/dIm f = conj(A^{-T} w) ... = conj(A^{-1} w) for real symmetric A
     ref = np.conj(adjoint.solve(n, k0 * k0, w))
     assert rel(to_np(ft.grad), ref) <= 1e-8
+
+
+@pytest.mark.parametrize("n,nb", [(12, 12), (12, 3), (256, 16), (5, 1)])
+def test_k2_gradient_product(n, nb):
+    """The library's gradient product equals the block sums of Re(conj(mu) u)."""
+    rng = np.random.default_rng(n + nb)
+    u = workloads.complex_normal(rng, n * n)
+    mu = workloads.complex_normal(rng, n * n)
+    g = to_np(hfmm.hfmm_k2_gradient(n, to_dev(u), to_dev(mu), nb))
+    s = n // nb
+    ref = np.real(np.conj(mu) * u).reshape(nb, s, nb, s).sum(axis=(1, 3))
+    assert g.shape == (nb, nb)
+    assert np.allclose(g, ref, rtol=1e-13, atol=1e-12)
+
+
+def test_set_k2_blocks_matches_field():
+    """The solver's operator with a block field equals the FD operator of the expanded field."""
+    from oracle import fd
+    n, nb, k0 = 24, 4, 10.0
+    rng = np.random.default_rng(9)
+    kb = rng.uniform(50, 150, (nb, nb))
+    s = hfmm.Solver(n, k0, p=4, leaf_size=16)
+    s.set_k2_blocks(to_dev(kb))
+    b = workloads.complex_normal(rng, n * n)
+    x, info = s.solve(to_dev(b), restart=40, rtol=1e-10)
+    A = fd.matrix(n, adjoint.expand_blocks(kb, n))
+    assert np.linalg.norm(b - A @ to_np(x)) / np.linalg.norm(b) <= 1e-10

@@ -151,7 +151,7 @@ def test_c2_full_size_sampled(p):
 
 @pytest.mark.parametrize("N,leaf,k,p", [(4356, 32, 16.0, 6), (20000, 8, 300.0, 6), (3000, 16, 100.0, 12),
                                         (70000, 16, 100.0, 8), (70000, 16, 400.0, 8)])
-def test_mfma_downward_matches_valu(N, leaf, k, p, monkeypatch):
+def test_mfma_downward_matches_valu(N, leaf, k, p):
     """The MFMA L2L+M2L kernel and the VALU one compute the same sums.  The
     k = 300 and k = 400 cases have coarse levels whose M2L source windows do
     not fit in LDS at once (FP64 at k = 300, both precisions at k = 400), so
@@ -161,9 +161,8 @@ def test_mfma_downward_matches_valu(N, leaf, k, p, monkeypatch):
     q = q[:, 0]
     out = {}
     for mode in ("mfma", "valu"):
-        if mode == "valu":
-            monkeypatch.setenv("HFMM_M2L", "valu")
         t = hfmm.Tree(to_dev(xy), leaf_size=leaf)
+        t.set_options(m2l_valu=(mode == "valu"))
         out[mode] = (to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q), prec=hfmm.FP64)),
                      to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q.astype(np.complex64)), prec=hfmm.FP32)))
     assert rel(out["mfma"][0], out["valu"][0]) <= 1e-12
