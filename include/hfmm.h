@@ -129,6 +129,25 @@ hfmm_status hfmm_tree_set_options(hfmm_tree t, int32_t m2l_valu, int32_t autotun
 hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
                            const void* d_q, void* d_phi, int32_t nrhs, hipStream_t stream);
 
+/* The same apply without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and errors as hfmm_fmm_apply; the
+ * work arrays (expansions of every level, far field, sorted charges) come
+ * from a fixed device array of hfmm_fmm_noalloc_capacity() bytes (64 MiB)
+ * that each GPU the library runs on holds until the process ends.
+ * - The plan of (k, p, prec) must already exist on the tree (made by
+ *   hfmm_fmm_plan_info or an earlier hfmm_fmm_apply); else HFMM_ERR_STATE.
+ * - An apply that needs more work memory than the array holds (about
+ *   2 coefficients-per-box x nrhs + 2 N nrhs complex values) is rejected
+ *   with HFMM_ERR_ARG before any launch.
+ * - Every call on a GPU shares that GPU's array: calls that overlap on one
+ *   GPU (other streams or threads) race.  Async on stream. */
+hfmm_status hfmm_fmm_apply_noalloc(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
+                                   const void* d_q, void* d_phi, int32_t nrhs, hipStream_t stream);
+
+/* Bytes of the fixed work array of hfmm_fmm_apply_noalloc. */
+int64_t hfmm_fmm_noalloc_capacity(void);
+
 /* The same apply with hipEvents around its stages (tracing): ms_stages
  * (host, 6 floats) receives device times in ms.  On a tree of depth >= 2:
  * [1] P2M (which also gathers the charges into Morton order), [2] the

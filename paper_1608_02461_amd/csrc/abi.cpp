@@ -5,6 +5,7 @@
 #include <string>
 #include <vector>
 
+#include "handles.h"
 #include "solver.h"
 
 namespace {
@@ -14,33 +15,6 @@ thread_local std::string g_last_error;
 namespace hfmm {
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace hfmm
-
-struct hfmm_tree_s {
-  std::unique_ptr<hfmm::Tree> t;
-};
-struct hfmm_solver_s {
-  std::unique_ptr<hfmm::Solver> s;
-};
-
-#define HFMM_GUARD_BEGIN try {
-#define HFMM_GUARD_END                                              \
-  }                                                                 \
-  catch (const hfmm::Error& e) {                                    \
-    hfmm::set_last_error(e.what());                                 \
-    return e.code;                                                  \
-  }                                                                 \
-  catch (const std::bad_alloc&) {                                   \
-    hfmm::set_last_error("host allocation failed");                 \
-    return HFMM_ERR_OOM;                                            \
-  }                                                                 \
-  catch (const std::exception& e) {                                 \
-    hfmm::set_last_error(std::string("internal: ") + e.what());     \
-    return HFMM_ERR_INTERNAL;                                       \
-  }                                                                 \
-  catch (...) {                                                     \
-    hfmm::set_last_error("internal: unknown exception");            \
-    return HFMM_ERR_INTERNAL;                                       \
-  }
 
 extern "C" {
 

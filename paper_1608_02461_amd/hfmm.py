@@ -66,6 +66,8 @@ _SIGS = {
     "hfmm_solver_boundary_nodes": ([_vp, _vp, _vp], _i32),
     "hfmm_bicgstab_solve": ([_vp, _vp, _vp, _i32, _f64, ctypes.POINTER(SolveInfo), _vp], _i32),
     "hfmm_fmm_apply": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_fmm_apply_noalloc": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, _vp], _i32),
+    "hfmm_fmm_noalloc_capacity": ([], _i64),
     "hfmm_fmm_apply_timed": ([_vp, _f64, _i32, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_float), _vp], _i32),
     "hfmm_fmm_plan_info": ([_vp, _f64, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                             ctypes.POINTER(_i64)], _i32),
@@ -236,6 +238,24 @@ def hfmm_k2_gradient(n, u, mu, nb, stream=None):
     grad = torch.empty(nb * nb, dtype=torch.float64, device=u.device)
     _check(lib().hfmm_k2_gradient(int(n), _ptr(uc), _ptr(mc), int(nb), _ptr(grad), _stream(stream)))
     return grad.view(nb, nb)
+
+
+def hfmm_fmm_apply_noalloc(tree, k, p, q, prec=FP64, phi=None, stream=None):
+    """hfmm_fmm_apply with no device allocation in the library (its fixed work
+    array); the plan of (k, p, prec) must exist.  phi (column-major layout as
+    returned by a previous call, or None) receives the result."""
+    dtype = torch.complex128 if prec == FP64 else torch.complex64
+    qc, squeeze = _colmajor(q, dtype, "q")
+    if qc.shape[1] != tree.n:
+        raise ValueError("q has the wrong number of points")
+    out = torch.empty_like(qc) if phi is None else phi
+    _check(lib().hfmm_fmm_apply_noalloc(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(out), qc.shape[0],
+                                        _stream(stream)))
+    return _from_colmajor(out, squeeze)
+
+
+def hfmm_fmm_noalloc_capacity():
+    return lib().hfmm_fmm_noalloc_capacity()
 
 
 # stage names of hfmm_fmm_apply_timed; on a tree of depth >= 2 "upward" is
