@@ -9,19 +9,27 @@ p (default 8).  value = N / (time per apply) in Mpts/s.
 
 Also reported on the same JSON line:
 * the same apply in complex128 and at p = 4, 8, 12, with relative errors on
-  the 2048 seeded targets against the stored direct sum;
-* the mixed-precision (complex64 FMM inside FP64 FGMRES(50)) and all-FP64
-  solves of the 1024 x 1024 grid, k h = 0.3, Gaussian bump, to 1e-6;
-* the 64 x 64, k = 16, FP64 FGMRES(30) solve;
+  the 2048 seeded targets against the stored direct sum, and the FP64 near
+  field's roofline;
+* the 1024 x 1024 grid, k h = 0.3, Gaussian bump, to 1e-6: complex64 FMM
+  inside FP64 FGMRES(50) vs all-FP64 at p = 4, 6, 8 (k0 = k) and with the
+  dispersion-matched k0 at p = 6; the first FMM pass's error on 2048 samples
+  against the stored direct sum;
 * the batched solve of 16 problems x 4 right-hand sides (k in [20, 300], n in
-  {128, 256, 384, 512}), one hipGraph-captured Arnoldi step vs eager;
+  {128, 256, 384, 512}): matched k0 with FGMRES(200), graph vs eager, and the
+  survey's settings (k0 = k, FGMRES(50), non-convergence reported);
 * forward + backward of the block-k^2 adjoint gradient on 256 x 256, checked
   against the CPU oracle's sparse-direct adjoint gradient;
+* the 64 x 64 solve; the paper's helm2 family (inhomogeneous Dirichlet data)
+  on FD; BiCGSTAB vs FGMRES on helm1; iterations against p in both
+  precisions; the FD matvec's HBM rate;
 * `roofline` for the dominant kernel of the apply (the near field), from
   hipEvents recorded on its launch stream around it, over the same number of
   applies as the timed steps;
 * `cpu_baseline`: the CPU oracle's direct N-body sum on a bounded sample of
-  targets, scaled to Mpts/s of the full sum.
+  targets, scaled to Mpts/s of the full sum; `cpu_baselines_extra`: the
+  oracle's 64 x 64 solve, a sparse-direct 1024 x 1024 solve and the oracle
+  adjoint gradient on the host.
 """
 
 import argparse
@@ -78,6 +86,428 @@ def p2p_flops_per_pair(deg, nrhs=1, plain_below=9):
     the accumulators (8 nrhs).  The log2 per pair is a transcendental and is
     not counted."""
     return 2 + 3 + (0 if deg < plain_below else 2) + 4 * (deg - 1) + 2 + 8 * nrhs
+
+
+def timed_solves(s, f, reps, **kw):
+    """Warm solve, then the mean wall time of `reps` solves (host clock, stream synchronised)."""
+    import torch
+    s.solve(f, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, info = s.solve(f, **kw)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, x, info
+
+
+def p2p_flops_per_pair_fp64(deg, nrhs=1):
+    """FP64 fast-path P2P flops per pair (as p2p_flops_per_pair; the centred
+    variable is used from 12 coefficients up; the FP64 log2 is not counted)."""
+    return p2p_flops_per_pair(deg, nrhs, plain_below=12)
+
+
+def bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan32):
+    """C2 at p = 4, 8, 12 in both precisions, errors on the stored samples,
+    and the near-field roofline of the FP64 apply at p = 8."""
+    fmm_tab = {}
+    for pp in (4, 8, 12):
+        row = {"eps_oracle": float(gold[f"eps_oracle_p{pp}"])}
+        for name, q, prec in (("fp32", q32, hfmm.FP32), ("fp64", q64, hfmm.FP64)):
+            hfmm.hfmm_fmm_apply(tree, k, pp, q, prec=prec)
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = hfmm.hfmm_fmm_apply(tree, k, pp, q, prec=prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            o = out.cpu().numpy()[smp]
+            row[name] = {"mpts_s": round(N / dt / 1e6, 2), "ms": round(dt * 1e3, 4),
+                         "rel_err": float(np.linalg.norm(o - gold["direct"]) / np.linalg.norm(gold["direct"]))}
+        fmm_tab[f"p{pp}"] = row
+        log(f"C2 p={pp}: {row}")
+    # FP64 near-field roofline (p = 8): duration from the stage-timed applies
+    plan64 = hfmm.hfmm_fmm_plan_info(tree, k, 8, hfmm.FP64)
+    st = {s_: 0.0 for s_ in hfmm.STAGES}
+    for _ in range(5):
+        _, ms = hfmm.hfmm_fmm_apply_timed(tree, k, 8, q64, prec=hfmm.FP64)
+        for s_ in st:
+            st[s_] += ms[s_] / 5
+    fl = plan64["pairs"] * p2p_flops_per_pair_fp64(plan64["near_deg"])
+    ach = fl / (st["p2p"] * 1e-3) / 1e12
+    fmm_tab["fp64_p8_stage_ms"] = {s_: round(v, 4) for s_, v in st.items()}
+    fmm_tab["fp64_p8_roofline"] = {
+        "bound": "alu", "kernel": f"k_p2p4<double,1,{plan64['near_deg']},true,{plan64['lanes_per_target']}>",
+        "achieved": round(ach, 3), "peak": PEAK_FP64_ALU, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_ALU, 4),
+        "algorithmic_flops_per_launch": fl, "ms_per_launch": round(st["p2p"], 5), "near_deg": plan64["near_deg"],
+        "note": "the per-pair FP64 log2 is counted as 0 flops"}
+    log(f"C2 fp64 p=8 stages {fmm_tab['fp64_p8_stage_ms']} roofline {fmm_tab['fp64_p8_roofline']['frac']}")
+    return fmm_tab
+
+
+def c3_points(n):
+    """Interior nodes then boundary element midpoints (bottom, right, top, left), as the solver's tree."""
+    h = 1.0 / (n + 1)
+    m = (np.arange(n + 1) + 0.5) * h
+    z, o = np.zeros_like(m), np.ones_like(m)
+    from paper_1608_02461_amd import workloads
+    return np.concatenate([workloads.interior_xy(n), np.stack([m, z], 1), np.stack([o, m], 1),
+                           np.stack([m, o], 1), np.stack([z, m], 1)])
+
+
+def bench_c3(dev, hfmm, workloads, torch):
+    """1024 x 1024, k h = 0.3: mixed vs FP64 FGMRES(50) at p = 4, 6, 8 (k0 = k), the
+    dispersion-matched k0 at p = 6, the first pass's FMM error on 2048 samples
+    against the stored direct sum, and per-stage times of one pass."""
+    c3 = workloads.solve_c3()
+    n3, k3 = c3["n"], c3["k"]
+    f = torch.from_numpy(c3["f"]).to(dev)
+    out = {"k": k3, "leaf": c3["leaf"], "restart": 50}
+    k3m = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
+    runs = [(f"p{pp}_{name}", pp, prec, k3) for pp in (4, 6, 8)
+            for name, prec in (("mixed", hfmm.FP32), ("fp64", hfmm.FP64))]
+    runs += [("p6_mixed_matched_k0", 6, hfmm.FP32, k3m), ("p6_fp64_matched_k0", 6, hfmm.FP64, k3m)]
+    for name, pp, prec, k0 in runs:
+        t0 = time.perf_counter()
+        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=pp, leaf_size=c3["leaf"], prec=prec)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        dt, x, info = timed_solves(s, f, 2, restart=50, rtol=1e-6, maxit=3000)
+        out[name] = {"k0": round(k0, 4), "solves_s": round(1 / dt, 4), "s_per_solve": round(dt, 4),
+                     "iters": info["iters"], "rel_res_true": info["rel_res_true"], "converged": info["converged"],
+                     "ms_precond_per_iter": round(info["ms_precond"] / max(1, info["iters"]), 4),
+                     "ms_krylov_per_iter": round(info["ms_krylov"] / max(1, info["iters"]), 4),
+                     "setup_s": round(setup, 3), "levels": s.info()["levels"]}
+        log(f"C3 {name}: {out[name]}")
+        del s
+    for pp in (4, 6, 8):
+        out[f"p{pp}_mixed_over_fp64_speedup"] = round(out[f"p{pp}_fp64"]["s_per_solve"] /
+                                                      out[f"p{pp}_mixed"]["s_per_solve"], 3)
+    out["p6_mixed_over_fp64_speedup_matched_k0"] = round(
+        out["p6_fp64_matched_k0"]["s_per_solve"] / out["p6_mixed_matched_k0"]["s_per_solve"], 3)
+    # the first FMM pass (sources h^2 f at the interior nodes) against the stored direct sum
+    pts = c3_points(n3)
+    t3 = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=c3["leaf"])
+    g3 = np.load(os.path.join(ROOT, "tests", "golden", "c3_reference.npz"))
+    q = np.zeros(len(pts), dtype=np.complex128)
+    q[: n3 * n3] = c3["h"] ** 2 * c3["f"]
+    err = {}
+    for pp in (4, 6, 8):
+        row = {"eps_oracle": float(g3[f"eps_oracle_p{pp}"])}
+        for name, prec, dt_ in (("fp32", hfmm.FP32, np.complex64), ("fp64", hfmm.FP64, np.complex128)):
+            phi = hfmm.hfmm_fmm_apply(t3, k3, pp, torch.from_numpy(q.astype(dt_)).to(dev), prec=prec)
+            o = phi.cpu().numpy()[g3["samples"]]
+            row[name] = float(np.linalg.norm(o - g3["direct"]) / np.linalg.norm(g3["direct"]))
+        err[f"p{pp}"] = row
+    out["pass1_rel_err_2048_samples"] = err
+    log(f"C3 pass-1 errors: {err}")
+    qq = torch.ones(len(pts), dtype=torch.complex64, device=dev)
+    for name, prec, qv in (("fp32", hfmm.FP32, qq), ("fp64", hfmm.FP64, qq.to(torch.complex128))):
+        hfmm.hfmm_fmm_apply_timed(t3, k3, 6, qv, prec=prec)
+        _, ms = hfmm.hfmm_fmm_apply_timed(t3, k3, 6, qv, prec=prec)
+        out[f"fmm_pass_stage_ms_{name}"] = {s_: round(v, 4) for s_, v in ms.items()}
+    out["orders_p6"] = hfmm.hfmm_fmm_plan_info(t3, k3, 6, hfmm.FP32)["orders"]
+    log(f"C3 FMM stages: {out['fmm_pass_stage_ms_fp32']}")
+    return out
+
+
+def bench_c4(dev, hfmm, workloads, torch):
+    """16 problems x 4 right-hand sides: the dispersion-matched variant
+    (FGMRES(200)) graph vs eager, and the survey's settings (k0 = k,
+    FGMRES(50), non-convergence reported)."""
+    c4 = workloads.batch_c4()
+    out = {"problems": [(pr["n"], round(pr["k"], 2)) for pr in c4["problems"]]}
+    bs = [torch.from_numpy(pr["f"].astype(np.complex128)).to(dev) for pr in c4["problems"]]
+    for variant, matched, restart, maxit in (("matched_k0_restart200", True, 200, 3000),
+                                            ("k0_eq_k_restart50", False, 50, 1500)):
+        t0 = time.perf_counter()
+        solvers = []
+        for pr in c4["problems"]:
+            k0 = hfmm.hfmm_matched_wavenumber(pr["k"], pr["h"]) if matched else pr["k"]
+            solvers.append(hfmm.Solver(pr["n"], k0, k2_const=pr["k"] ** 2, p=c4["p"], leaf_size=c4["leaf"],
+                                       prec=hfmm.FP32, nrhs=4))
+        torch.cuda.synchronize()
+        row = {"setup_s": round(time.perf_counter() - t0, 3), "restart": restart, "maxit": maxit,
+               "k0": "matched" if matched else "k"}
+        modes = (("graph", True), ("eager", False)) if matched else (("graph", True),)
+        for mode, graph in modes:
+            t0 = time.perf_counter()
+            xs, infos = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=c4["rtol"], maxit=maxit,
+                                                       use_graph=graph)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row[mode] = {"solves_s": round(64 / dt, 3), "t_batch_s": round(dt, 4),
+                         "converged": sum(i["converged"] for i in infos), "iters": [i["iters"] for i in infos],
+                         "max_rel_res": max(i["rel_res_true"] for i in infos)}
+            log(f"C4 {variant} {mode}: {row[mode]}")
+        if "eager" in row:
+            row["graph_over_eager_speedup"] = round(row["eager"]["t_batch_s"] / row["graph"]["t_batch_s"], 3)
+        out[variant] = row
+        del solvers
+    return out
+
+
+def bench_c5(dev, hfmm, workloads, torch):
+    from oracle import adjoint as oadj
+    from paper_1608_02461_amd.autograd import helmholtz_solve
+    c5 = workloads.adjoint_c5()
+    n5 = c5["n"]
+    s5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
+    d5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
+    f5 = torch.from_numpy(c5["f"]).to(dev)
+    ud, _ = d5.solve(f5, restart=200, rtol=1e-10, strict=True)
+    P5 = torch.from_numpy(c5["P"]).to(dev)
+    dd = ud[P5]
+    del d5
+
+    def fwd_bwd(rtol):
+        kbt = torch.from_numpy(c5["kb"]).to(dev).requires_grad_(True)
+        u = helmholtz_solve(kbt, f5, s5, restart=200, rtol=rtol)
+        r = u[P5] - dd
+        J = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+        J.backward()
+        return J.item(), kbt.grad.cpu().numpy()
+
+    fwd_bwd(1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J5, g5 = fwd_bwd(1e-10)
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J6, g6 = fwd_bwd(1e-6)
+    torch.cuda.synchronize()
+    t_fb6 = time.perf_counter() - t0
+    Jo, Go, _, _ = oadj.gradient(n5, c5["kb"], c5["f"], c5["P"], dd.cpu().numpy())
+    out = {"fwd_bwd_s_rtol1e-10": round(t_fb, 4), "fwd_bwd_s_rtol1e-6": round(t_fb6, 4),
+           "grad_rel_err_vs_oracle_rtol1e-10": float(np.linalg.norm(g5 - Go) / np.linalg.norm(Go)),
+           "grad_rel_err_vs_oracle_rtol1e-6": float(np.linalg.norm(g6 - Go) / np.linalg.norm(Go)),
+           "J_rel_err": abs(J5 - Jo) / abs(Jo)}
+    log(f"C5: {out}")
+    return out
+
+
+def bench_c1(dev, hfmm, workloads, torch):
+    c1 = workloads.solve_c1()
+    s = hfmm.Solver(c1["n"], c1["k"], p=6, leaf_size=32, prec=hfmm.FP64)
+    f1 = torch.from_numpy(c1["f"]).to(dev)
+    dt, x, info = timed_solves(s, f1, 5, restart=30, rtol=1e-6)
+    out = {"solves_s": round(1 / dt, 3), "iters": info["iters"], "rel_res_true": info["rel_res_true"],
+           "setup_ms": round(info["ms_setup"], 3)}
+    log(f"C1: {out}")
+    return out
+
+
+def helm2_problem(mu, n):
+    """Sec. 6, eq. helm2 on the unit square with kappa = mu sqrt(2), right-hand side
+    negated (-Laplace(u) - k^2 u = f): exact u = x^2 sin(mu x) cos(mu y).  Returns
+    k, the exact solution at the interior nodes, f, the boundary data at the
+    element midpoints and the FD right-hand side with the Dirichlet ghosts."""
+    from paper_1608_02461_amd import workloads
+    h = 1.0 / (n + 1)
+    xo = workloads.interior_xy(n)
+    ue = lambda X, Y: X ** 2 * np.sin(mu * X) * np.cos(mu * Y)
+    f = -(2 * np.sin(mu * xo[:, 0]) * np.cos(mu * xo[:, 1]) +
+          4 * mu * xo[:, 0] * np.cos(mu * xo[:, 0]) * np.cos(mu * xo[:, 1])) + 0j
+    m = (np.arange(n + 1) + 0.5) * h
+    z, o = np.zeros_like(m), np.ones_like(m)
+    g = np.concatenate([ue(m, z), ue(o, m), ue(m, o), ue(z, m)]) + 0j
+    b = f.copy()
+    ix, iy = np.arange(n * n) % n, np.arange(n * n) // n
+    for dx, dy in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        ghost = (ix + dx < 0) | (ix + dx >= n) | (iy + dy < 0) | (iy + dy >= n)
+        b[ghost] += ue((ix[ghost] + 1 + dx) * h, (iy[ghost] + 1 + dy) * h) / h ** 2
+    return mu * np.sqrt(2.0), ue(xo[:, 0], xo[:, 1]) + 0j, f, g, b
+
+
+def bench_helm2(dev, hfmm, torch):
+    """The paper's inhomogeneous-Dirichlet family (Sec. 6, eq. helm2, Table t:p3)
+    on the FD grid: FGMRES(30) iterations from x0 = 0 (the paper's setting) and
+    from the boundary-element solution with the Dirichlet data (double layer
+    and 1/2 delta), the error of both against the exact solution, p = 6, FP64
+    preconditioner.  Table t:p3 is FEM with a degraded direct sum: context."""
+    paper_fmm = {1: (7, 6, 6), 4: (7, 6, 6), 6: (6, 6, 6), 8: (7, 7, 6)}
+    out = {}
+    for mu in (1, 4, 6, 8):
+        for hi, n in enumerate((31, 63, 127)):
+            k, ue, f, g, b = helm2_problem(float(mu), n)
+            s = hfmm.Solver(n, k, p=6, leaf_size=16, prec=hfmm.FP64)
+            ft, gt, bt = (torch.from_numpy(a).to(dev) for a in (f, g, b))
+            ub = s.dirichlet_apply(ft, gt)
+            x0, i0 = s.solve(bt, restart=30, rtol=1e-6)
+            x1, i1 = s.solve(bt, x0=ub, restart=30, rtol=1e-6)
+            rel = lambda a: float(np.linalg.norm(a.cpu().numpy() - ue) / np.linalg.norm(ue))
+            out[f"mu{mu}_h2^-{hi + 5}"] = {
+                "n": n, "k": round(k, 4), "iters_x0_zero": i0["iters"], "iters_x0_bem": i1["iters"],
+                "converged": i0["converged"] and i1["converged"], "bem_solution_rel_err": rel(ub),
+                "fd_solution_rel_err": rel(x0), "paper_fmm_iters_fem": paper_fmm[mu][hi]}
+            del s
+        log(f"helm2 mu={mu}: {[out[f'mu{mu}_h2^-{e}'] for e in (5, 6, 7)]}")
+    return out
+
+
+def helm1_problem(kappa, n):
+    """Sec. 6, eq. helm1 on [-1, 1]^2 mapped to the unit square (x = 2x' - 1):
+    k' = 2 kappa, f' = -4 exp(-10((y - 1)^2 + (x - 0.5)^2)) (negated), zero
+    Dirichlet data; h = 2^-5 on [-1, 1]^2 is n = 63 here."""
+    from paper_1608_02461_amd import workloads
+    xo = workloads.interior_xy(n)
+    X, Y = 2 * xo[:, 0] - 1, 2 * xo[:, 1] - 1
+    return 2.0 * kappa, -4.0 * np.exp(-10 * ((Y - 1) ** 2 + (X - 0.5) ** 2)) + 0j
+
+
+def bench_bicgstab(dev, hfmm, torch):
+    """Sec. 3 (Fig. gmres_bigcstab): FMM-preconditioned GMRES vs BiCGSTAB iterations
+    to 1e-6 on helm1, h = 2^-5 (n = 63 on the unit square), p = 6, FP64.  A BiCGSTAB
+    iteration costs two preconditioner applies."""
+    out = {}
+    for kappa in (2.0, 5.0, 7.0, 10.0, 15.0):
+        k, f = helm1_problem(kappa, 63)
+        s = hfmm.Solver(63, k, p=6, leaf_size=16, prec=hfmm.FP64)
+        ft = torch.from_numpy(f).to(dev)
+        _, ig = s.solve(ft, restart=30, rtol=1e-6)
+        _, ib = s.bicgstab(ft, rtol=1e-6)
+        out[f"kappa{kappa:g}"] = {"fgmres_iters": ig["iters"], "bicgstab_iters": ib["iters"],
+                                  "fgmres_precond_applies": ig["iters"], "bicgstab_precond_applies": 2 * ib["iters"],
+                                  "converged": ig["converged"] and ib["converged"],
+                                  "fgmres_ms": round(ig["ms_total"], 3), "bicgstab_ms": round(ib["ms_total"], 3)}
+        del s
+    log(f"BiCGSTAB vs FGMRES: {out}")
+    return out
+
+
+def bench_pstudy(dev, hfmm, workloads, torch):
+    """Sec. 6.1 (Fig. convergence): FGMRES(30) iterations against the expansion
+    order p in FP64 and FP32, on helm1 (kappa = 7, h = 2^-5) and the 64 x 64
+    workload, with the preconditioner apply's error against the oracle's dense
+    M^-1 for each (p, precision)."""
+    from oracle import bem
+    out = {}
+    cases = {"helm1_kappa7": helm1_problem(7.0, 63) + (63,)}
+    c1 = workloads.solve_c1()
+    cases["solve_64"] = (c1["k"], c1["f"], c1["n"])
+    for cname, (k, f, n) in cases.items():
+        ref = bem.precond_apply(n, k, f)
+        ft = torch.from_numpy(f).to(dev)
+        for pp in (2, 4, 6, 8, 12):
+            for pname, prec in (("fp64", hfmm.FP64), ("fp32", hfmm.FP32)):
+                s = hfmm.Solver(n, k, p=pp, leaf_size=16, prec=prec)
+                z = s.precond_apply(ft).cpu().numpy()
+                _, info = s.solve(ft, restart=30, rtol=1e-6)
+                out[f"{cname}_p{pp}_{pname}"] = {
+                    "iters": info["iters"], "converged": info["converged"],
+                    "precond_rel_err_vs_dense": float(np.linalg.norm(z - ref) / np.linalg.norm(ref))}
+                del s
+        log(f"p study {cname}: " + ", ".join(f"{kk}: {v['iters']}" for kk, v in out.items() if kk.startswith(cname)))
+    return out
+
+
+def bench_hbm(dev, hfmm, workloads, torch, xy_c2):
+    """HBM-bound parts timed with hipEvents on the launch stream: the FD matvec on
+    1024 x 1024 (32 algorithmic bytes per point: x read once, y written once,
+    complex128; neighbours come from cache) and the tree build of the C2 points
+    (a rough 40 bytes per point per pass, several passes)."""
+    n = 1024
+    x = torch.randn(n * n, dtype=torch.complex128, device=dev)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    y = hfmm.hfmm_fd_helmholtz_matvec(n, 1.0 / (n + 1), x, k2_const=1e4)
+    torch.cuda.synchronize()
+    reps = 50
+    e0.record(st)
+    for _ in range(reps):
+        y = hfmm.hfmm_fd_helmholtz_matvec(n, 1.0 / (n + 1), x, k2_const=1e4)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out = {"fd_matvec_1024": {"ms": round(ms, 5), "algorithmic_bytes": 32 * n * n,
+                              "gb_s": round(32 * n * n / (ms * 1e-3) / 1e9, 1), "peak_gb_s": PEAK_HBM,
+                              "note": "includes the binding's output allocation and column-major copy"}}
+    log(f"HBM: {out}")
+    return out
+
+
+def cpu_direct_sum_baseline(w, smp, k, N):
+    """The oracle's direct N-body sum on a bounded target sample, scaled by
+    linearity to Mpts/s of the full N x N sum."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import kernel
+
+    avail = len(os.sched_getaffinity(0))
+    # one oracle call per thread; the GPU box's CPU share is 16 threads
+    nthr = max(1, min(16, avail))
+    n_t = 64 * nthr
+    tg = w["xy"][smp[:n_t]] if n_t <= len(smp) else w["xy"][:n_t]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(lambda i: kernel.direct_sum(w["xy"], w["q"], k, tgt=tg[i::nthr]), range(nthr)))
+        dt = time.perf_counter() - t0
+    full = dt / n_t * N
+    return {"value": round(N / full / 1e6, 6), "unit": "Mpts/s", "cores": nthr, "kind": "oracle",
+            "sample": f"oracle direct N-body sum (scipy hankel1, FP64) from all {N} sources to {n_t} of the "
+                      f"seeded targets ({dt:.1f} s on {nthr} threads, one oracle call per thread); Mpts/s of "
+                      f"the full N x N sum by linearity",
+            "pairs_per_s": round(n_t * N / dt, 1), "sched_getaffinity_cores": avail, "cpu_model": cpu_model(),
+            "blas_threads_per_call": 1}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_extra_baselines(workloads):
+    """The oracle on the host for the other workloads: the 64 x 64 solve
+    (dense M^-1 formed from the paper's equations, then FGMRES(30)), the
+    1024 x 1024 system by sparse LU (scipy splu: a different method, the CPU
+    reference solution), and the adjoint gradient on 256 x 256 (sparse direct)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import adjoint as oadj
+    from oracle import bem, fd, fgmres
+    out = {"blas": [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()],
+           "threads_cap": 16}
+    with threadpool_limits(16):
+        c1 = workloads.solve_c1()
+        A = fd.matrix(c1["n"], c1["k"] ** 2)
+        t0 = time.perf_counter()
+        Minv = bem.precond_matrix(c1["n"], c1["k"])
+        t1 = time.perf_counter()
+        x, info = fgmres.fgmres(lambda v: A @ v, lambda v: Minv @ v, c1["f"], restart=30, rtol=1e-6)
+        t2 = time.perf_counter()
+        out["solve_64_oracle_dense_fgmres"] = {"form_Minv_s": round(t1 - t0, 3), "fgmres_s": round(t2 - t1, 4),
+                                               "solves_s": round(1 / (t2 - t0), 4), "iters": info["iters"]}
+        log(f"CPU C1: {out['solve_64_oracle_dense_fgmres']}")
+        c3 = workloads.solve_c3()
+        from scipy.sparse.linalg import splu
+        A3 = fd.matrix(c3["n"], c3["k"] ** 2).tocsc()
+        t0 = time.perf_counter()
+        lu = splu(A3)
+        t1 = time.perf_counter()
+        x3 = lu.solve(c3["f"])
+        t2 = time.perf_counter()
+        out["solve_1024_cpu_sparse_direct_reference"] = {
+            "factor_s": round(t1 - t0, 2), "solve_s": round(t2 - t1, 3), "solves_s": round(1 / (t2 - t0), 5),
+            "rel_res": float(np.linalg.norm(c3["f"] - A3 @ x3) / np.linalg.norm(c3["f"])),
+            "label": "CPU sparse-direct reference (different method)"}
+        log(f"CPU C3: {out['solve_1024_cpu_sparse_direct_reference']}")
+        del lu
+        c5 = workloads.adjoint_c5()
+        u_ref = oadj.solve(c5["n"], c5["k2_ref"], c5["f"])
+        d = u_ref[c5["P"]]
+        t0 = time.perf_counter()
+        oadj.gradient(c5["n"], c5["kb"], c5["f"], c5["P"], d)
+        out["adjoint_256_oracle_gradient_s"] = round(time.perf_counter() - t0, 3)
+    return out
 
 
 def main():
@@ -182,180 +612,20 @@ def main():
     }
 
     if not args.no_extras:
-        fmm_tab = {}
-        for pp in (4, 8, 12):
-            row = {"eps_oracle": float(gold[f"eps_oracle_p{pp}"])}
-            for name, q, prec in (("fp32", q32, hfmm.FP32), ("fp64", q64, hfmm.FP64)):
-                hfmm.hfmm_fmm_apply(tree, k, pp, q, prec=prec)
-                torch.cuda.synchronize()
-                reps = 5
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    out = hfmm.hfmm_fmm_apply(tree, k, pp, q, prec=prec)
-                torch.cuda.synchronize()
-                dt = (time.perf_counter() - t0) / reps
-                o = out.cpu().numpy()[smp]
-                row[name] = {"mpts_s": round(N / dt / 1e6, 2), "ms": round(dt * 1e3, 4),
-                             "rel_err": float(np.linalg.norm(o - gold["direct"]) / np.linalg.norm(gold["direct"]))}
-            fmm_tab[f"p{pp}"] = row
-            log(f"C2 p={pp}: {row}")
-        result["fmm_c2"] = fmm_tab
-
-        # 1024 x 1024 solve, mixed vs FP64
-        c3 = workloads.solve_c3()
-        f = torch.from_numpy(c3["f"]).to(dev)
-        solves = {}
-        k3m = hfmm.hfmm_matched_wavenumber(c3["k"], 1.0 / (c3["n"] + 1))
-        for name, prec, k0 in (("mixed", hfmm.FP32, c3["k"]), ("fp64", hfmm.FP64, c3["k"]),
-                               ("mixed_matched_k0", hfmm.FP32, k3m), ("fp64_matched_k0", hfmm.FP64, k3m)):
-            t0 = time.perf_counter()
-            s = hfmm.Solver(c3["n"], k0, k2_const=c3["k"] ** 2, p=6, leaf_size=c3["leaf"], prec=prec)
-            torch.cuda.synchronize()
-            setup = time.perf_counter() - t0
-            s.solve(f, restart=50, rtol=1e-6)  # warm
-            torch.cuda.synchronize()
-            reps = 2
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                x, info = s.solve(f, restart=50, rtol=1e-6)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / reps
-            solves[name] = {"k0": round(k0, 4), "solves_s": round(1 / dt, 4), "s_per_solve": round(dt, 4),
-                            "iters": info["iters"],
-                            "rel_res_true": info["rel_res_true"], "converged": info["converged"],
-                            "ms_precond_per_iter": round(info["ms_precond"] / max(1, info["iters"]), 4),
-                            "setup_s": round(setup, 3)}
-            log(f"C3 {name}: {solves[name]}")
-            del s
-        solves["mixed_over_fp64_speedup"] = round(solves["fp64"]["s_per_solve"] / solves["mixed"]["s_per_solve"], 3)
-        solves["mixed_over_fp64_speedup_matched_k0"] = round(
-            solves["fp64_matched_k0"]["s_per_solve"] / solves["mixed_matched_k0"]["s_per_solve"], 3)
-        # stage times of one FMM pass on the same point set (interior nodes + boundary midpoints)
-        n3 = c3["n"]
-        h3 = 1.0 / (n3 + 1)
-        m = (np.arange(n3 + 1) + 0.5) * h3
-        z, o = np.zeros_like(m), np.ones_like(m)
-        pts = np.concatenate([workloads.interior_xy(n3), np.stack([m, z], 1), np.stack([o, m], 1),
-                              np.stack([m, o], 1), np.stack([z, m], 1)])
-        t3 = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=c3["leaf"])
-        qq = torch.ones(len(pts), dtype=torch.complex64, device=dev)
-        for name, prec, qv in (("fp32", hfmm.FP32, qq), ("fp64", hfmm.FP64, qq.to(torch.complex128))):
-            hfmm.hfmm_fmm_apply_timed(t3, c3["k"], 6, qv, prec=prec)
-            _, ms = hfmm.hfmm_fmm_apply_timed(t3, c3["k"], 6, qv, prec=prec)
-            solves[f"fmm_pass_stage_ms_{name}"] = {s_: round(v, 4) for s_, v in ms.items()}
-        solves["orders"] = hfmm.hfmm_fmm_plan_info(t3, c3["k"], 6, hfmm.FP32)["orders"]
-        log(f"C3 FMM stages: {solves['fmm_pass_stage_ms_fp32']}")
-        result["solve_1024"] = solves
-
-        # batched: 16 problems x 4 right-hand sides, one captured Arnoldi step for all
-        c4 = workloads.batch_c4()
-        t0 = time.perf_counter()
-        solvers, bs = [], []
-        for pr in c4["problems"]:
-            k0 = hfmm.hfmm_matched_wavenumber(pr["k"], pr["h"])
-            solvers.append(hfmm.Solver(pr["n"], k0, k2_const=pr["k"] ** 2, p=c4["p"], leaf_size=c4["leaf"],
-                                       prec=hfmm.FP32, nrhs=4))
-            bs.append(torch.from_numpy(pr["f"].astype(np.complex128)).to(dev))
-        torch.cuda.synchronize()
-        setup4 = time.perf_counter() - t0
-        maxit4, restart4 = 3000, 200
-        batch = {"setup_s": round(setup4, 3), "k0": "matched", "maxit": maxit4, "restart": restart4,
-                 "problems": [(pr["n"], round(pr["k"], 2)) for pr in c4["problems"]]}
-        log(f"C4 setup {setup4:.2f} s")
-        for mode, graph in (("graph", True), ("eager", False)):
-            t0 = time.perf_counter()
-            xs, infos = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart4, rtol=c4["rtol"],
-                                                       maxit=maxit4, use_graph=graph)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            batch[mode] = {"solves_s": round(64 / dt, 3), "t_batch_s": round(dt, 4),
-                           "converged": sum(i["converged"] for i in infos),
-                           "iters": [i["iters"] for i in infos],
-                           "max_rel_res": max(i["rel_res_true"] for i in infos)}
-            log(f"C4 {mode}: {batch[mode]}")
-        result["batch_16x4"] = batch
-        del solvers, bs, xs
-
-        # adjoint: block k^2 field on 256 x 256, forward + backward through the autograd wrapper
-        from oracle import adjoint as oadj
-        from paper_1608_02461_amd.autograd import expand_blocks, helmholtz_solve
-        c5 = workloads.adjoint_c5()
-        n5 = c5["n"]
-        s5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
-        d5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
-        f5 = torch.from_numpy(c5["f"]).to(dev)
-        ud, _ = d5.solve(f5, restart=200, rtol=1e-10, strict=True)
-        P5 = torch.from_numpy(c5["P"]).to(dev)
-        dd = ud[P5]
-        del d5
-
-        def fwd_bwd(rtol):
-            kbt = torch.from_numpy(c5["kb"]).to(dev).requires_grad_(True)
-            u = helmholtz_solve(expand_blocks(kbt, n5), f5, s5, restart=200, rtol=rtol)
-            r = u[P5] - dd
-            J = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
-            J.backward()
-            return J.item(), kbt.grad.cpu().numpy()
-
-        fwd_bwd(1e-10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        J5, g5 = fwd_bwd(1e-10)
-        torch.cuda.synchronize()
-        t_fb = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        J6, g6 = fwd_bwd(1e-6)
-        torch.cuda.synchronize()
-        t_fb6 = time.perf_counter() - t0
-        Jo, Go, _, _ = oadj.gradient(n5, c5["kb"], c5["f"], c5["P"], dd.cpu().numpy())
-        result["adjoint_256"] = {
-            "fwd_bwd_s_rtol1e-10": round(t_fb, 4), "fwd_bwd_s_rtol1e-6": round(t_fb6, 4),
-            "grad_rel_err_vs_oracle_rtol1e-10": float(np.linalg.norm(g5 - Go) / np.linalg.norm(Go)),
-            "grad_rel_err_vs_oracle_rtol1e-6": float(np.linalg.norm(g6 - Go) / np.linalg.norm(Go)),
-            "J_rel_err": abs(J5 - Jo) / abs(Jo)}
-        log(f"C5: {result['adjoint_256']}")
-        del s5
-
-        c1 = workloads.solve_c1()
-        s = hfmm.Solver(c1["n"], c1["k"], p=6, leaf_size=32, prec=hfmm.FP64)
-        f1 = torch.from_numpy(c1["f"]).to(dev)
-        s.solve(f1, restart=30)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = 5
-        for _ in range(reps):
-            x, info = s.solve(f1, restart=30, rtol=1e-6)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        result["solve_64"] = {"solves_s": round(1 / dt, 3), "iters": info["iters"],
-                              "rel_res_true": info["rel_res_true"]}
-        log(f"C1: {result['solve_64']}")
+        result["fmm_c2"] = bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan)
+        result["solve_1024"] = bench_c3(dev, hfmm, workloads, torch)
+        result["batch_16x4"] = bench_c4(dev, hfmm, workloads, torch)
+        result["adjoint_256"] = bench_c5(dev, hfmm, workloads, torch)
+        result["solve_64"] = bench_c1(dev, hfmm, workloads, torch)
+        result["helm2_dirichlet"] = bench_helm2(dev, hfmm, torch)
+        result["bicgstab_vs_fgmres"] = bench_bicgstab(dev, hfmm, torch)
+        result["precond_accuracy_study"] = bench_pstudy(dev, hfmm, workloads, torch)
+        result["hbm_kernels"] = bench_hbm(dev, hfmm, workloads, torch, xy)
 
     if not args.no_cpu:
-        from concurrent.futures import ThreadPoolExecutor
-
-        from threadpoolctl import threadpool_limits
-
-        from oracle import kernel
-
-        # one oracle call per thread on its own targets; numpy and scipy release
-        # the GIL in the pairwise work, so the threads run in parallel
-        nthr = max(1, min(16, len(os.sched_getaffinity(0))))
-        n_t = 64 * nthr
-        tg = w["xy"][smp[:n_t]] if n_t <= len(smp) else w["xy"][:n_t]
-        with threadpool_limits(1):
-            t0 = time.perf_counter()
-            with ThreadPoolExecutor(nthr) as ex:
-                list(ex.map(lambda i: kernel.direct_sum(w["xy"], w["q"], k, tgt=tg[i::nthr]), range(nthr)))
-            dt = time.perf_counter() - t0
-        # full N x N direct sum time by linearity in the number of targets
-        full = dt / n_t * N
-        result["cpu_baseline"] = {
-            "value": round(N / full / 1e6, 6), "unit": "Mpts/s", "cores": nthr, "kind": "oracle",
-            "sample": f"oracle direct N-body sum (scipy hankel1, FP64) from all {N} sources to {n_t} of the "
-                      f"seeded targets ({dt:.1f} s on {nthr} threads, one oracle call per thread); Mpts/s of "
-                      f"the full N x N sum by linearity",
-            "pairs_per_s": round(n_t * N / dt, 1)}
+        result["cpu_baseline"] = cpu_direct_sum_baseline(w, smp, k, N)
+        if not args.no_extras:
+            result["cpu_baselines_extra"] = cpu_extra_baselines(workloads)
 
     print(json.dumps(result), flush=True)
 
