@@ -217,7 +217,9 @@ hfmm_status hfmm_fd_helmholtz_matvec(int32_t n, double h, const double* d_k2, do
  *
  * d_k2/k2_const  the operator's k^2 field (copied), as in the matvec.
  * k0             preconditioner wavenumber (> 0).
- * p, leaf_size   FMM order and leaf occupancy (leaf_size >= 1).
+ * p, leaf_size   FMM order and leaf occupancy; leaf_size = 0 times one
+ *                preconditioner apply on the trees of leaf sizes 16, 32 and 64
+ *                and keeps the fastest (hfmm_solver_info reports the choice).
  * precond_prec   HFMM_FP32: the whole preconditioner runs in complex64 (the
  *                Krylov part stays FP64); HFMM_FP64: all FP64.
  * nrhs           columns solved together (independent Krylov spaces, one
@@ -274,9 +276,16 @@ hfmm_status hfmm_fgmres_solve(hfmm_solver s, const double* d_b, double* d_x, int
                               hipStream_t stream);
 
 /* The same solve for nprob solvers at once: d_b[i], d_x[i] belong to s[i].
- * use_graph = 1 captures one Arnoldi step of every problem into a hipGraph
- * that is replayed (kernels of finished problems exit at once); 0 runs the
- * same kernels eagerly.  info has nprob entries.  Synchronises `stream`. */
+ * Restart cycles run in lockstep.  With several problems each runs its
+ * Arnoldi steps on a stream of its own (forked from and joined to `stream`),
+ * so that their kernels overlap on the device.
+ * use_graph = 1 captures one Arnoldi step of each problem once per call into
+ * a hipGraph of its own (the step reads its index and flags from device
+ * memory) and replays it: 4 replays per problem between two reads of the
+ * flags, a finished column or problem making every later kernel of it
+ * return at once (device-side early exit).  use_graph = 0 launches the same
+ * kernels eagerly, one step at a time, with the flags read after every
+ * step.  info has nprob entries.  Synchronises `stream`. */
 hfmm_status hfmm_fgmres_solve_batched(hfmm_solver* s, int32_t nprob, const double* const* d_b,
                                       double* const* d_x, int32_t restart, int32_t maxit, double rtol,
                                       int32_t use_graph, hfmm_solve_info* info, hipStream_t stream);
@@ -313,9 +322,10 @@ hfmm_status hfmm_solver_boundary_nodes(hfmm_solver s, double* d_xy, hipStream_t 
 hfmm_status hfmm_bicgstab_solve(hfmm_solver s, const double* d_b, double* d_x, int32_t maxit, double rtol,
                                 hfmm_solve_info* info, hipStream_t stream);
 
-/* Boundary-matrix diagnostics of a solver: N_Gamma and the 1-norm condition
- * estimate ||S||_1 ||S^{-1}||_1 (host outputs, may be NULL). */
-hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels);
+/* Diagnostics of a solver: N_Gamma, the 1-norm condition estimate
+ * ||S||_1 ||S^{-1}||_1 of the boundary matrix, the tree depth and the leaf
+ * size in use (host outputs, each may be NULL). */
+hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels, int32_t* leaf_size);
 
 hfmm_status hfmm_solver_destroy(hfmm_solver s);
 

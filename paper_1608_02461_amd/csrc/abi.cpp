@@ -372,12 +372,13 @@ hfmm_status hfmm_fgmres_solve_batched(hfmm_solver* s, int32_t nprob, const doubl
   HFMM_GUARD_END
 }
 
-hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels) {
+hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels, int32_t* leaf_size) {
   HFMM_GUARD_BEGIN
   HFMM_REQUIRE(s != nullptr && s->s, "solver_info: NULL solver");
   if (n_gamma) *n_gamma = (int32_t)s->s->ng;
   if (cond_S) *cond_S = s->s->condS;
   if (levels) *levels = s->s->tree->L;
+  if (leaf_size) *leaf_size = s->s->leaf;
   return HFMM_OK;
   HFMM_GUARD_END
 }

@@ -39,6 +39,7 @@ struct Solver {
   DevBuf<int> active, jj, iters, state;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   double ms_setup = 0;             // wall time of solver_create (ms)
+  std::vector<std::pair<int, float>> leaf_ms;  // leaf-size candidates timed (leaf_size 0)
   // outward unit normals of the boundary elements at their sorted slots
   // (zero at interior nodes), for the double-layer pass
   DevBuf<float2> nrm32;

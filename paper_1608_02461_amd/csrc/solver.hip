@@ -8,9 +8,9 @@
 //   z        = phi_Omega + S_vol r.
 // FGMRES (Sec. 3-4, right preconditioning, flexible form): all FP64, CGS2,
 // complex Givens rotations.  The Arnoldi step reads its index j and the
-// per-column activity flags from device memory, so one step of any number
-// of problems can be captured in a hipGraph and replayed; kernels of
-// finished columns/problems return at once.
+// per-column activity flags from device memory, so one captured step of a
+// problem can be replayed from a hipGraph for every step and cycle; kernels
+// of finished columns/problems return at once.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -22,6 +22,7 @@ namespace hfmm {
 namespace {
 
 constexpr int kRed = 256;     // threads per reduction block
+constexpr int kGraphSteps = 4;  // graph replays per problem between two reads of the flags
 constexpr int kElems = 4;     // elements per thread in the dot kernels
 constexpr int kChunk = kRed * kElems;
 
@@ -855,6 +856,73 @@ void fd_matvec(int n, double h, const double* d_k2, double k2c, const double2* x
   HFMM_LAUNCH_CHECK();
 }
 
+namespace {
+
+// Leaf-size autotuning: the tree over the solver's points for each candidate
+// leaf size, timed on both passes of the preconditioner (source flags of the
+// interior and of the boundary, as in an apply) with zero charges; the
+// fastest tree is kept.  Candidates whose leaves are too large for k0 are
+// skipped.
+template <class T>
+std::unique_ptr<Tree> choose_leaf(Solver& s, const double* dxy, int64_t N, hipStream_t st) {
+  static const int cand[] = {16, 32, 64};
+  std::unique_ptr<Tree> best;
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  HFMM_HIP(hipEventCreate(&e0));
+  HFMM_HIP(hipEventCreate(&e1));
+  try {
+    for (int leaf : cand) {
+      auto t = build_tree(dxy, N, 0.0, 0.0, 1.0, leaf, st);
+      if (t->L < 2) continue;
+      int64_t ftot = 0;
+      for (int l = 0; l <= t->L; ++l) ftot += int64_t(1) << (2 * l);
+      DevBuf<uint8_t> f1(ftot), f2(ftot);
+      source_flags(*t, 0, s.nn, f1.p, st);
+      source_flags(*t, s.nn, N, f2.p, st);
+      FmmPlan<T>* pl = nullptr;
+      try {
+        pl = &get_plan<T>(*t, s.k0, s.p);
+      } catch (const Error& e) {
+        if (e.code == HFMM_ERR_ARG) continue;  // leaves too large for this wavenumber
+        throw;
+      }
+      ensure_tuned<T>(*t, *pl, s.nrhs);
+      pl->ensure_work(s.nrhs);
+      DevBuf<cplx<T>> q((size_t)N * s.nrhs), phi((size_t)N * s.nrhs);
+      k_zero<T><<<nblocks(N * s.nrhs), 256, 0, st>>>(q.p, N * s.nrhs);
+      HFMM_LAUNCH_CHECK();
+      float ms = 1e30f;
+      for (int rep = 0; rep < 4; ++rep) {  // the first is a warm-up
+        HFMM_HIP(hipEventRecord(e0, st));
+        fmm_sorted<T>(*t, *pl, q.p, phi.p, s.nrhs, f1.p, false, st);
+        fmm_sorted<T>(*t, *pl, q.p, phi.p, s.nrhs, f2.p, true, st);
+        HFMM_HIP(hipEventRecord(e1, st));
+        HFMM_HIP(hipEventSynchronize(e1));
+        float d = 0;
+        HFMM_HIP(hipEventElapsedTime(&d, e0, e1));
+        if (rep) ms = std::min(ms, d);
+      }
+      s.leaf_ms.push_back(std::make_pair(leaf, ms));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = std::move(t);
+        s.leaf = leaf;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HFMM_REQUIRE(best != nullptr, "solver_create: no leaf size in {16, 32, 64} suits this wavenumber and grid");
+  return best;
+}
+
+}  // namespace
+
 std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, double k2c, double k0, int p, int leaf,
                                       bool fp32, int nrhs, hipStream_t st) {
   HFMM_REQUIRE(n >= 2, "solver_create: n must be >= 2");
@@ -862,7 +930,7 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
                "solver_create: h must equal 1/(n+1) (unit square)");
   HFMM_REQUIRE(std::isfinite(k0) && k0 > 0, "solver_create: k0 must be > 0");
   HFMM_REQUIRE(p >= 1 && p <= 40, "solver_create: p must be in [1, 40]");
-  HFMM_REQUIRE(leaf >= 1, "solver_create: leaf_size must be >= 1");
+  HFMM_REQUIRE(leaf >= 0, "solver_create: leaf_size must be >= 0 (0: chosen by timing)");
   HFMM_REQUIRE(nrhs >= 1 && nrhs <= 64, "solver_create: nrhs must be in [1, 64]");
   HFMM_REQUIRE(d_k2 != nullptr || std::isfinite(k2c), "solver_create: k2_const must be finite");
   const auto t_setup = std::chrono::steady_clock::now();
@@ -910,7 +978,10 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
   }
   DevBuf<double2> dnrm;
   dnrm.upload(nrm);
-  s->tree = build_tree(dxy.p, N, 0.0, 0.0, 1.0, leaf, st);
+  if (leaf > 0)
+    s->tree = build_tree(dxy.p, N, 0.0, 0.0, 1.0, leaf, st);
+  else
+    s->tree = fp32 ? choose_leaf<float>(*s, dxy.p, N, st) : choose_leaf<double>(*s, dxy.p, N, st);
   HFMM_REQUIRE(s->tree->L >= 2, "solver_create: tree depth below 2");
 
   // per-level source flags of the two passes
@@ -1141,19 +1212,58 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
   }
   HFMM_HIP(hipStreamSynchronize(st));
 
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  std::vector<int> captured;  // problems whose Arnoldi step the current graph holds
-  auto drop_graph = [&]() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
-    captured.clear();
+  // Several problems: each runs its Arnoldi steps on a stream of its own,
+  // forked from and joined to `st`, so that their kernels overlap on the
+  // device.  With use_graph, one Arnoldi step of each problem is captured
+  // once per solve into a graph of its own (the capture's origin is the
+  // problem's stream, from which the FMM forks its far-field chain onto the
+  // tree's side stream) and replayed; the step reads j and its flags from
+  // device memory, so the same graph serves every step and every cycle.
+  const bool multi = nprob > 1;
+  std::vector<hipStream_t> pst(nprob, st);
+  std::vector<hipEvent_t> join_ev;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipGraph_t> graph(nprob, nullptr);
+  std::vector<hipGraphExec_t> gexec(nprob, nullptr);
+  auto drop_all = [&]() {
+    for (auto& g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (auto& g : graph)
+      if (g) (void)hipGraphDestroy(g);
+    if (multi) {
+      for (hipStream_t q : pst) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+      }
+    }
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
   };
   std::vector<int> alive(nprob, 0);
+  // graph replays per problem between two reads of the flags: steps past the
+  // end of a cycle are no-ops (every kernel of a finished column or problem
+  // returns at once), so the host need not look after every step
+  const int chunk = use_graph ? kGraphSteps : 1;
 
   try {
+    if (multi) {
+      join_ev.resize(nprob, nullptr);
+      for (int q = 0; q < nprob; ++q) {
+        HFMM_HIP(hipStreamCreateWithFlags(&pst[q], hipStreamNonBlocking));
+        HFMM_HIP(hipEventCreateWithFlags(&join_ev[q], hipEventDisableTiming));
+      }
+      HFMM_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+      // the problems' streams start after the caller's work on `st` (b, x)
+      HFMM_HIP(hipStreamSynchronize(st));
+    }
+    if (use_graph) {
+      for (int q = 0; q < nprob; ++q) {
+        HFMM_HIP(hipStreamBeginCapture(pst[q], hipStreamCaptureModeThreadLocal));
+        arnoldi_step(*S[q], maxit, rtol, pst[q]);
+        HFMM_HIP(hipStreamEndCapture(pst[q], &graph[q]));
+        HFMM_HIP(hipGraphInstantiate(&gexec[q], graph[q], nullptr, nullptr, 0));
+      }
+    }
     for (;;) {
       // ---- cycle start: r = b - A x into V_0, beta = ||r||
       bool any_active = false;
@@ -1202,33 +1312,37 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
       }
       if (!any_active) break;
 
-      // ---- Arnoldi steps
-      for (int step = 0; step < m; ++step) {
-        std::vector<int> live;
-        for (int q = 0; q < nprob; ++q)
-          if (!ps[q].done && alive[q]) live.push_back(q);
-        if (live.empty()) break;
+      // ---- Arnoldi steps: `chunk` steps of every live problem, then the
+      // host reads their flags
+      std::vector<int> live;
+      for (int q = 0; q < nprob; ++q)
+        if (!ps[q].done && alive[q]) live.push_back(q);
+      for (int step = 0; step < m && !live.empty(); step += chunk) {
         const bool timed = (nprob == 1 && !use_graph);
         if (timed) HFMM_HIP(hipEventRecord(S[0]->ev0, st));
-        if (use_graph) {
-          // one graph holds one step of every live problem; recapture when
-          // that set shrinks (plans and workspaces already exist, so the step
-          // allocates nothing)
-          if (live != captured) {
-            drop_graph();
-            HFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            for (int q : live) arnoldi_step(*S[q], maxit, rtol, st);
-            HFMM_HIP(hipStreamEndCapture(st, &graph));
-            HFMM_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-            captured = live;
+        if (multi) HFMM_HIP(hipEventRecord(fork_ev, st));
+        for (int q : live) {
+          if (multi) HFMM_HIP(hipStreamWaitEvent(pst[q], fork_ev, 0));
+          for (int u = 0; u < chunk; ++u) {
+            if (use_graph)
+              HFMM_HIP(hipGraphLaunch(gexec[q], pst[q]));
+            else
+              arnoldi_step(*S[q], maxit, rtol, pst[q], timed ? S[q]->ev1 : nullptr);
           }
-          HFMM_HIP(hipGraphLaunch(gexec, st));
-        } else {
-          for (int q : live) arnoldi_step(*S[q], maxit, rtol, st, timed ? S[q]->ev1 : nullptr);
-          if (timed) HFMM_HIP(hipEventRecord(S[0]->ev2, st));
+          if (multi) {
+            HFMM_HIP(hipEventRecord(join_ev[q], pst[q]));
+            HFMM_HIP(hipStreamWaitEvent(st, join_ev[q], 0));
+          }
         }
+        if (timed) HFMM_HIP(hipEventRecord(S[0]->ev2, st));
         for (int q : live) HFMM_HIP(hipMemcpyAsync(&alive[q], S[q]->state.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
         HFMM_HIP(hipStreamSynchronize(st));
+        {  // finished problems launch nothing more
+          std::vector<int> still;
+          for (int q : live)
+            if (alive[q]) still.push_back(q);
+          live.swap(still);
+        }
         if (timed) {
           float ms = 0, mk = 0;
           HFMM_HIP(hipEventElapsedTime(&ms, S[0]->ev0, S[0]->ev1));
@@ -1258,10 +1372,10 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
       }
     }
   } catch (...) {
-    drop_graph();
+    drop_all();
     throw;
   }
-  drop_graph();
+  drop_all();
 
   const double ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -79,7 +79,8 @@ _SIGS = {
     "hfmm_fgmres_solve": ([_vp, _vp, _vp, _i32, _i32, _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
     "hfmm_fgmres_solve_batched": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _i32,
                                    _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
-    "hfmm_solver_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32)], _i32),
+    "hfmm_solver_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+                         _i32),
     "hfmm_solver_destroy": ([_vp], _i32),
 }
 
@@ -369,9 +370,10 @@ class Solver:
         return _from_colmajor(x, squeeze), info.as_dict()
 
     def info(self):
-        ng, cond, L = _i32(), _f64(), _i32()
-        _check(lib().hfmm_solver_info(self.handle, ctypes.byref(ng), ctypes.byref(cond), ctypes.byref(L)))
-        return {"n_gamma": ng.value, "cond_S": cond.value, "levels": L.value}
+        ng, cond, L, leaf = _i32(), _f64(), _i32(), _i32()
+        _check(lib().hfmm_solver_info(self.handle, ctypes.byref(ng), ctypes.byref(cond), ctypes.byref(L),
+                                      ctypes.byref(leaf)))
+        return {"n_gamma": ng.value, "cond_S": cond.value, "levels": L.value, "leaf_size": leaf.value}
 
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:

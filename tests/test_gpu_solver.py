@@ -173,7 +173,7 @@ def test_batched_equals_individual(use_graph):
 
 
 def test_solver_invalid_arguments():
-    for kw in [dict(n=1, k0=5.0), dict(n=16, k0=0.0), dict(n=16, k0=5.0, p=0), dict(n=16, k0=5.0, leaf_size=0)]:
+    for kw in [dict(n=1, k0=5.0), dict(n=16, k0=0.0), dict(n=16, k0=5.0, p=0), dict(n=16, k0=5.0, leaf_size=-1)]:
         n = kw.pop("n")
         k0 = kw.pop("k0")
         with pytest.raises(hfmm.HFMMError):
@@ -214,3 +214,17 @@ def test_first_graph_solve_equals_eager():
     for a, b, p, q in zip(xg, xe, ig, ie):
         assert p["iters"] == q["iters"]
         assert np.array_equal(to_np(a), to_np(b))
+
+
+def test_leaf_size_autotune():
+    """leaf_size = 0 times the candidate trees and keeps one; the solve still meets rtol."""
+    w = workloads.solve_c1()
+    n, k = w["n"], w["k"]
+    s = hfmm.Solver(n, k, p=6, leaf_size=0, prec=hfmm.FP32)
+    inf = s.info()
+    say(f"  chosen leaf {inf['leaf_size']} (levels {inf['levels']})")
+    assert inf["leaf_size"] in (16, 32, 64)
+    x, info = s.solve(to_dev(w["f"]), restart=30, rtol=1e-6)
+    A = fd.matrix(n, k * k)
+    assert info["converged"] == 1
+    assert np.linalg.norm(w["f"] - A @ to_np(x)) <= 1e-6 * np.linalg.norm(w["f"])
