@@ -69,6 +69,7 @@ struct FmmPlan : PlanBase {
   DevBuf<cplx<T>> qs, phis;  // sorted scratch for the public apply
   DevBuf<cplx<T>> far;        // far field of a pass, in the output's point order
   DevBuf<cplx<T>> dns;        // sorted unit normals of a double-layer apply
+  DevBuf<double2> l2tab;      // FP64 near field: log2 table (1/c_i, log2 c_i), 128 entries
   double max_table = 0;
 
   int64_t npts = 0;  // points of the tree

@@ -750,6 +750,15 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   static const int candD[] = {8, 10, 12, 16, 24};  // (both lists match the launch_p2p switches)
   // the first two candidates of each are polynomials in t itself (kPlainDeg)
   pl->near_fast = fit_near_poly(X * X * (1 + 1e-9), F32, F32 ? candF : candD, 5, 2, F32 ? 1e-6 : 2e-13, pl->poly);
+  if (!F32) {
+    // the near field's FP64 log2 table: c_i = 1/2 + (i + 1/2)/256, i = 0..127
+    std::vector<double2> tab(128);
+    for (int i = 0; i < 128; ++i) {
+      const long double c = 0.5L + (i + 0.5L) / 256.0L;
+      tab[i] = make_double2((double)(1.0L / c), (double)log2l(c));
+    }
+    pl->l2tab.upload(tab);
+  }
   const double mean = double(t.n) / double(t.nleaves);
   const int G0 = mean >= 40 ? 1 : (mean >= 20 ? 2 : 4);
   for (int g = 0; g < 3; ++g) pl->G[g] = G0;
@@ -970,6 +979,7 @@ P2PArgs<T> p2p_args(const Tree& t, const FmmPlan<T>& pl, const cplx<T>* q, cplx<
   a.jinv = T(1.0 / P.c1);
   a.Lc = nullptr;
   a.dn = dn;
+  a.l2tab = pl.l2tab.p;
   if (Lleaf && t.L >= 2) {  // the leaf level's local expansions, for the L2P kernel
     const LevelInfo& lf = pl.lv[t.L];
     a.Lc = Lleaf;

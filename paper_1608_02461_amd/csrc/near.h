@@ -10,10 +10,33 @@
 #include "p2p.h"
 #include "special.h"
 
-// v_log_f32 without the denormal-input rescaling: every argument here is
-// (k r)^2 of two distinct FP32 positions, far above the denormal range.
-__device__ __forceinline__ float log2T(float x) { return __builtin_amdgcn_logf(x); }
-__device__ __forceinline__ double log2T(double x) { return log2(x); }
+// log2 of the pair argument t = (k r)^2 > 0.
+// FP32: v_log_f32 without the denormal-input rescaling: every argument here
+// is (k r)^2 of two distinct FP32 positions, far above the denormal range.
+// FP64: a table-driven reduction (the method of P. T. P. Tang, "Table-driven
+// implementation of the logarithm function in IEEE floating-point
+// arithmetic", ACM TOMS 16, 1990, with the table inverted instead of exact
+// products): t = m 2^e with m in [1/2, 1) (frexp); the top 7 fraction bits i
+// of m pick c_i = 1/2 + (i + 1/2)/256, and
+//     log2 t = e + log2 c_i + log2(1 + r),   r = m (1/c_i) - 1,  |r| <= 1/256,
+// with log2(1 + r) = r (1/ln 2)(1 - r/2 + r^2/3 - r^3/4 + r^4/5) + O(r^6).
+// The table (1/c_i, log2 c_i) is staged in LDS by the kernel.  Absolute
+// error below 1e-14 (the near-field fit tolerates 2e-13).
+constexpr double kInvLn2 = 1.4426950408889634074;
+__device__ __forceinline__ double log2_tab(double t, const double2* __restrict__ tab) {
+  const double m = __builtin_amdgcn_frexp_mant(t);
+  const int e = __builtin_amdgcn_frexp_exp(t);
+  const double2 c = tab[(__double2hiint(m) >> 13) & 127];
+  const double r = fma(m, c.x, -1.0);
+  double P = kInvLn2 / 5.0;
+  P = fma(P, r, -kInvLn2 / 4.0);
+  P = fma(P, r, kInvLn2 / 3.0);
+  P = fma(P, r, -kInvLn2 / 2.0);
+  P = fma(P, r, kInvLn2);
+  return fma(r, P, (double)e + c.y);
+}
+__device__ __forceinline__ float log2T(float x, const double2*) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double log2T(double x, const double2* tab) { return log2_tab(x, tab); }
 
 // Running sums of q (J0 + i Y0) over one target's sources, J0 carried as
 // Jc = c1 J0:  Re = sum (qx J0 - qy Y0) = jinv aj - ay,
@@ -76,8 +99,10 @@ __device__ __forceinline__ double pin_vgpr(double x) { return x; }
 // full-range FP64 routine.  MASK zeroes the pair at t = 0 (a point with
 // itself, or a coincident point).
 template <class T, int D, bool FAST, bool MASK>
-__device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y, T cj2, T cy2) {
-  // cj2, cy2: a.cJ[D - 2], a.cY[D - 2] (pinned in VGPRs by the caller)
+__device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y, T cj2, T cy2,
+                                        const double2* __restrict__ l2tab) {
+  // cj2, cy2: a.cJ[D - 2], a.cY[D - 2] (pinned in VGPRs by the caller);
+  // l2tab: the FP64 log2 table in LDS (unused in FP32)
   bool valid = true;
   if (MASK) {
     valid = t > T(0);
@@ -92,7 +117,7 @@ __device__ __forceinline__ void h0_pair(const P2PArgs<T>& a, T t, T& J, T& Y, T 
       j = fmaT(j, u, a.cJ[i]);
       yh = fmaT(yh, u, a.cY[i]);
     }
-    Y = fmaT(j, log2T(t), yh);
+    Y = fmaT(j, log2T(t, l2tab), yh);
     J = j;
   } else {
     const double2 h = h0_general(sqrt((double)t));
@@ -112,11 +137,16 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
   __shared__ cplx<T> sq[NR][SCH];
   __shared__ int s_lo[9], s_pre[10], s_n, s_total, s_nonown;
   __shared__ T s_ox[9], s_oy[9];
+  __shared__ double2 s_l2[sizeof(T) == 8 ? 128 : 1];
   const int leaf = blockIdx.x;
   if (a.alive && !a.alive[0]) return;
   const int t0 = a.leaf_off[leaf], t1 = a.leaf_off[leaf + 1];
   if (t0 == t1) return;
   const int lane = threadIdx.x;
+  if constexpr (sizeof(T) == 8 && FAST) {
+    s_l2[lane] = a.l2tab[lane];
+    s_l2[lane + 64] = a.l2tab[lane + 64];
+  }
   if (lane == 0) {
     int bx, by;
     demorton((uint32_t)leaf, bx, by);
@@ -183,7 +213,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         const T dx = xt - s.x, dy = yt - s.y;
         const T t = fmaT(dx, dx, dy * dy);
         T J, Y;
-        h0_pair<T, D, FAST, false>(a, t, J, Y, a.cJ[D >= 2 ? D - 2 : 0], a.cY[D >= 2 ? D - 2 : 0]);
+        h0_pair<T, D, FAST, false>(a, t, J, Y, a.cJ[D >= 2 ? D - 2 : 0], a.cY[D >= 2 ? D - 2 : 0], s_l2);
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
       }
@@ -192,7 +222,7 @@ __global__ __launch_bounds__(64) void k_p2p(P2PArgs<T> a) {
         const T dx = xt - s.x, dy = yt - s.y;
         const T t = fmaT(dx, dx, dy * dy);
         T J, Y;
-        h0_pair<T, D, FAST, true>(a, t, J, Y, a.cJ[D >= 2 ? D - 2 : 0], a.cY[D >= 2 ? D - 2 : 0]);
+        h0_pair<T, D, FAST, true>(a, t, J, Y, a.cJ[D >= 2 ? D - 2 : 0], a.cY[D >= 2 ? D - 2 : 0], s_l2);
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
       }
@@ -228,14 +258,14 @@ struct P2P4Cfg {
 template <class T, int D, bool FAST, bool MASK, int NR, int G>
 __device__ __forceinline__ void p2p_run(const P2PArgs<T>& a, const cplx<T>* __restrict__ spos,
                                         const cplx<T> (*sq)[P2P4Cfg<T, NR>::SCAP], int lo, int hi, int g, T xt,
-                                        T yt, PairSum<T, NR>& acc, T cj2, T cy2) {
+                                        T yt, PairSum<T, NR>& acc, T cj2, T cy2, const double2* __restrict__ l2) {
 #pragma unroll 4
   for (int j = lo + g; j < hi; j += G) {
     const cplx<T> s = spos[j];
     const T dx = xt - s.x, dy = yt - s.y;
     const T t = fmaT(dx, dx, dy * dy);
     T J, Y;
-    h0_pair<T, D, FAST, MASK>(a, t, J, Y, cj2, cy2);
+    h0_pair<T, D, FAST, MASK>(a, t, J, Y, cj2, cy2, l2);
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc.add(r, sq[r][j], J, Y);
   }
@@ -248,8 +278,12 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
   __shared__ cplx<T> sq[NR][SCAP];
   __shared__ int s_pre[17], s_lo[16], s_rounds[4];
   __shared__ T s_ox[16], s_oy[16];
+  __shared__ double2 s_l2[sizeof(T) == 8 ? 128 : 1];
   if (a.alive && !a.alive[0]) return;
   const int parent = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+  if constexpr (sizeof(T) == 8 && FAST) {
+    if (threadIdx.x < 128) s_l2[threadIdx.x] = a.l2tab[threadIdx.x];
+  }
   int px, py;
   demorton((uint32_t)parent, px, py);
   const int nb = 1 << a.L;
@@ -351,8 +385,8 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
       acc.zero();
 #pragma unroll
       for (int sgi = 0; sgi < 4; ++sgi)
-        p2p_run<T, D, FAST, false, NR, GG>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], gl, xt, yt, acc, cj2, cy2);
-      p2p_run<T, D, FAST, true, NR, GG>(a, spos, sq, own_lo, own_hi, gl, xt, yt, acc, cj2, cy2);
+        p2p_run<T, D, FAST, false, NR, GG>(a, spos, sq, sg_lo[sgi], sg_hi[sgi], gl, xt, yt, acc, cj2, cy2, s_l2);
+      p2p_run<T, D, FAST, true, NR, GG>(a, spos, sq, own_lo, own_hi, gl, xt, yt, acc, cj2, cy2, s_l2);
       finish(ti, act, acc, GG, gl);
       return 64 / GG;
     };
@@ -389,10 +423,10 @@ __global__ __launch_bounds__(256) void k_p2p4(P2PArgs<T> a) {
 #pragma unroll
         for (int sgi = 0; sgi < 4; ++sgi) {
           const int lo = max(sg_lo[sgi], c0) - c0, hi = min(sg_hi[sgi], c0 + cnt) - c0;
-          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2);
+          p2p_run<T, D, FAST, false, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2, s_l2);
         }
         const int lo = max(own_lo, c0) - c0, hi = min(own_hi, c0 + cnt) - c0;
-        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2);
+        p2p_run<T, D, FAST, true, NR, G>(a, spos, sq, lo, hi, g, xt, yt, acc, cj2, cy2, s_l2);
       }
       finish(ti, act, acc, G, g);
     }

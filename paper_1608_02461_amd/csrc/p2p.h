@@ -32,6 +32,8 @@ struct P2PArgs {
   // sources carries a density q and a unit normal dn[j] (sorted order), and
   // the pair kernel is dG/dn_y = (i k / 4) H1(k r) (x - y).n / r instead of G
   const cplx<T>* dn;
+  // FP64 log2 table: 128 entries (1/c_i, log2 c_i), c_i = 1/2 + (i + 1/2)/256
+  const double2* l2tab;
 };
 
 // Near field of one column group [r0, r0 + NR) on a tree of depth L with
