@@ -521,7 +521,242 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
   }
 }
 
-// FP32: at most 96 registers per lane (88 used), so that a block fits
+// M2L offset classes, o = (ox + 3) * 7 + (oy + 3), by target parity: a
+// target at even x has sources at ox in [-2, 3], at odd x in [-3, 2] (the
+// children of its parent's neighbours), and likewise in y, less the 3 x 3
+// near block: 27 classes per parity.  Grouped by the parities whose lists
+// hold them: 16 classes with |ox|, |oy| <= 2 are in every list; the 5 with
+// oy = +3 (|ox| <= 2) are in the lists of the two parities with even y, and
+// likewise oy = -3 (odd y), ox = +3 (even x), ox = -3 (odd x); each parity
+// adds one corner (ox, oy = +-3).  Wave w of a block takes 4 common classes,
+// the pair group w (patches kPairA[w], kPairB[w]) and the corner of patch w:
+// 27 MFMA k-step groups from 10 A fragments.
+__constant__ int kCommonO[16] = {8, 9, 10, 11, 12, 15, 19, 22, 26, 29, 33, 36, 37, 38, 39, 40};
+__constant__ int kPairO[4][5] = {{13, 20, 27, 34, 41}, {7, 14, 21, 28, 35}, {43, 44, 45, 46, 47}, {1, 2, 3, 4, 5}};
+__constant__ int kPairA[4] = {0, 2, 0, 1};
+__constant__ int kPairB[4] = {1, 3, 2, 3};
+__constant__ int kCornerO[4] = {48, 6, 42, 0};
+
+// The 8 x 8-target block with its four 4 x 4 patches grouped by target
+// parity (patch p holds the targets of parity (p & 1, p >> 1), every other
+// box of the tile), so each patch walks exactly its 27 interaction-list
+// classes: 27 MFMA k-step groups per wave instead of 40 over all classes.
+// The 8 x 8-target block with its four 4 x 4 patches grouped by target
+// parity (patch p holds the targets of parity (p & 1, p >> 1), every other
+// box of the tile), so each patch walks exactly its 27 interaction-list
+// classes: 27 MFMA k-step groups per wave instead of 40 over all classes.
+template <class T>
+__device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int lblock, T* Ms) {
+  constexpr int NP = 4;
+  typedef typename Acc4<T>::type V4;
+  T* red = Ms;  // the reduction reuses the window once the products are done
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nbt = a.nb / a.tile;
+  const int pb = lblock % a.gx, rt = lblock / a.gx;
+  const int bx0 = (pb % nbt) * a.tile, by0 = (pb / nbt) * a.tile;
+  const int wx0 = max(0, bx0 - 2), wy0 = max(0, by0 - 2);
+  const int WW = min(a.nb, bx0 + a.tile + 2) - wx0, WH = min(a.nb, by0 + a.tile + 2) - wy0;
+  const int zb = WW * WH;  // the zero box
+  const int P = a.P, KS = a.KS, KSL = a.KSL;
+  const int KPs = 4 * ((KSL + 3) & ~3) + 2;  // LDS stride of one box's slice (whole chunks)
+  const int j = lane & 15, kq = lane >> 4;
+  int tx[NP], ty[NP];
+  uint32_t tbox[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {  // patch p = target parity (p & 1, p >> 1)
+    tx[p] = bx0 + 2 * (j & 3) + (p & 1);
+    ty[p] = by0 + 2 * (j >> 2) + (p >> 1);
+    tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
+  }
+  const size_t cstride = (size_t)a.RT * a.KSA * 64;
+  const T* Abase = a.Af + (size_t)rt * a.KSA * 64 + lane;
+  // LDS position of the source box of class o for patch p (the zero box when
+  // it is outside the grid or not adjacent to the target's parent)
+  // (the class lists below are exactly the interaction lists of each
+  // parity, so only sources outside the grid read the zero box); p may be a
+  // wave-uniform runtime value
+  auto src_base = [&](int o, int p) {
+    const int ox = o / 7 - 3, oy = o % 7 - 3;
+    const int sx = bx0 + 2 * (j & 3) + (p & 1) + ox, sy = by0 + 2 * (j >> 2) + (p >> 1) + oy;
+    const bool v = sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb;
+    return (v ? (sx - wx0) + (sy - wy0) * WW : zb) * KPs + kq;
+  };
+  for (int r = 0; r < args.nr; ++r) {
+    V4 acc[NP], accA = V4{0, 0, 0, 0}, accB = accA, accC = accA;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = V4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < KS; k0 += KSL) {
+      __syncthreads();
+      // stage the slice [4 k0, 4 k0 + 4 KSL) of the real columns of the
+      // window.  Lanes in groups of P take one complex coefficient each of
+      // gpw boxes per wave step (lanes loop over coefficients when P > 64);
+      // the loads of 4 steps are issued before their LDS stores.  The
+      // columns past 2 P that the slice's whole MFMA chunks read are zeroed
+      // apart.
+      {
+        const int gpw = P <= 64 ? 64 / P : 1;  // boxes per wave step
+        const int g = P <= 64 ? lane / P : 0, m0 = P <= 64 ? lane - g * P : lane;
+        const int lo = 4 * k0, hi = 4 * (k0 + KSL);  // real columns of the slice
+        const uint32_t mW = 0xffffffffu / (uint32_t)WW + 1u;
+        const bool on = g < gpw;
+        const uint8_t* fl = a.fsrc;
+        const size_t bstride = (size_t)args.nrhs * P;  // between boxes
+        for (int m = m0; m < P; m += 64) {
+          const cplx<T>* Mm = a.M + (size_t)(args.r0 + r) * P + m;
+          for (int b0 = w * gpw; b0 < zb; b0 += 4 * 4 * gpw) {
+            cplx<T> v[4];
+            uint8_t f[4];
+            int lb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int box = b0 + u * 4 * gpw + g;
+              lb[u] = on && box < zb ? box : -1;
+              v[u] = mk<T>(0, 0);
+              f[u] = 1;
+              if (lb[u] >= 0) {
+                const int by = (int)__umulhi((uint32_t)box, mW), bx = box - by * WW;
+                const uint32_t gb = morton((uint32_t)(wx0 + bx), (uint32_t)(wy0 + by));
+                v[u] = Mm[gb * bstride];
+                if (fl) f[u] = fl[gb];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (lb[u] >= 0) {
+                T* row = Ms + (size_t)lb[u] * KPs - lo;
+                const T re = f[u] ? v[u].x : T(0), im = f[u] ? v[u].y : T(0);
+                if (m >= lo && m < hi) row[m] = re;
+                if (m + P >= lo && m + P < hi) row[m + P] = im;
+              }
+          }
+        }
+        // zero padding: columns [2 P, 4 (k0 + min(KSL, KS - k0))) of every box
+        const int z0 = max(2 * P, lo), z1 = 4 * (k0 + min(KSL, KS - k0));
+        if (z1 > z0) {
+          const int nz = z1 - z0;
+          const uint32_t mZ = 0xffffffffu / (uint32_t)nz + 1u;
+          for (int i = tid; i < zb * nz; i += kM2LThreads) {
+            const int box = (int)__umulhi((uint32_t)i, mZ);
+            Ms[(size_t)box * KPs + z0 - lo + (i - box * nz)] = T(0);
+          }
+        }
+      }
+      if (w == 0)
+        for (int n = lane; n < KPs; n += 64) Ms[zb * KPs + n] = T(0);
+      __syncthreads();
+      const T* Ab = Abase + (size_t)k0 * 64;  // this slice's k steps
+      // the wave's 10 classes (4 common, 5 of its pair group, its corner);
+      // the A fragments of the next chunk, also across classes, load one
+      // chunk ahead.  The last chunk of a slice may have fewer than 4 k steps
+      // (ns).
+      const int pa = kPairA[w], pb = kPairB[w];
+      auto cls = [&](int i) { return i < 4 ? kCommonO[w + 4 * i] : (i < 9 ? kPairO[w][i - 4] : kCornerO[w]); };
+      const int nst = min(KSL, KS - k0);
+      const int nch = (nst + 3) >> 2;
+      T an[4];
+      {
+        const T* A0 = Ab + (size_t)cls(0) * cstride;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
+      }
+#pragma unroll 1
+      for (int oi = 0; oi < 10; ++oi) {
+        const int o = cls(oi);
+        const int kind = oi < 4 ? 0 : (oi < 9 ? 1 : 2);  // common, pair, corner
+        int base[NP];
+        if (kind == 0) {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
+        } else {
+          base[0] = src_base(o, kind == 1 ? pa : w);
+          base[1] = kind == 1 ? src_base(o, pb) : base[0];
+          base[2] = base[3] = base[0];
+        }
+        const T* A = Ab + (size_t)o * cstride;
+        const T* An = oi + 1 < 10 ? Ab + (size_t)cls(oi + 1) * cstride : A;
+        for (int c = 0; c < nch; ++c) {
+          T av[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[u] = an[u];
+          if (c + 1 < nch) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
+          } else if (oi + 1 < 10) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
+          }
+          const int ns = min(4, nst - 4 * c);
+          if (kind == 0) {
+            T bv[NP][4];
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];  // in the box's stride
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (u < ns)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
+          } else if (kind == 1) {
+            T bv[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) bv[h][u] = Ms[base[h] + (c * 4 + u) * 4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (u < ns) {
+                accA = mfma16(av[u], bv[0][u], accA);
+                accB = mfma16(av[u], bv[1][u], accB);
+              }
+          } else {
+            T bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bv[u] = Ms[base[0] + (c * 4 + u) * 4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (u < ns) accC = mfma16(av[u], bv[u], accC);
+          }
+        }
+      }
+    }
+    {
+      const int pa = kPairA[w], pb = kPairB[w];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (p == pa) acc[p] += accA;
+        if (p == pb) acc[p] += accB;
+        if (p == w) acc[p] += accC;
+      }
+    }
+    // sum the 4 waves' partial products in LDS
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[((w * NP + p) * 4 + q) * 64 + lane] = acc[p][q];
+    __syncthreads();
+    if (w < NP) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T s = red[((0 * NP + w) * 4 + q) * 64 + lane] + red[((1 * NP + w) * 4 + q) * 64 + lane] +
+                    red[((2 * NP + w) * 4 + q) * 64 + lane] + red[((3 * NP + w) * 4 + q) * 64 + lane];
+        const int i = rt * 16 + out_row<T>(kq, q);
+        if (i < 2 * P) {
+          uint32_t tb = tbox[0];
+#pragma unroll
+          for (int p = 1; p < NP; ++p)
+            if (w == p) tb = tbox[p];
+          T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tb * args.nrhs + args.r0 + r) * P + (i < P ? i : i - P));
+          dst[i < P ? 0 : 1] = s;
+        }
+      }
+    }
+  }
+}
+
+// FP32: at most 96 registers per lane (91 used), so that a block fits
 // beside four near-field blocks on a CU
 template <class T> struct M2LWaves { static constexpr int value = sizeof(T) == 4 ? 5 : 1; };
 
@@ -540,7 +775,7 @@ void k_m2l_mfma(M2LAllArgs<T> args) {
     if (i < args.nlev && (int)blockIdx.x >= args.lv[i].block0) a = args.lv[i];
   const int lblock = (int)blockIdx.x - a.block0;
   if (a.tile == 8)
-    m2l_block<T, 4>(args, a, lblock, Ms);
+    m2l_block_par<T>(args, a, lblock, Ms);
   else
     m2l_block<T, 1>(args, a, lblock, Ms);
 }
@@ -569,7 +804,7 @@ constexpr int kTTChunk = 16;
 // LDS budget of one M2L block (the launch takes the largest over its
 // levels): small enough that a block fits beside the four near-field blocks
 // a CU holds, so that the far-field chain progresses while the near field runs
-constexpr size_t kM2LLds = 24 * 1024;
+constexpr size_t kM2LLds = 32 * 1024;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {
