@@ -50,17 +50,19 @@ PEAK_HBM = 8000.0       # GB/s
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "p2p_fmm_c2_n1m_k100_p8_fp32_pmc.md")
+M2L_SUMMARY = os.path.join(ROOT, "profiles", "m2l_mfma_fmm_c2_c3_counters.md")
+PEAK_FP32_MFMA = 157.3  # TFLOP/s, dense FP32 matrix cores
+PEAK_FP64_MFMA = 78.6
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading on
-    a plain device copy of known size), or None when the summary is absent,
-    is for another kernel, or the near-field source has changed since."""
+def profile_record(path, kernel):
+    """The JSON record of a committed counter summary, or None when the
+    summary is absent, is for another kernel, or its source file has changed
+    since the counters were taken (SHA-256 of `source`)."""
     import hashlib
     import re
     try:
-        txt = open(PMC_SUMMARY).read()
+        txt = open(path).read()
     except OSError:
         return None
     m = re.search(r"```json\n(.*?)\n```", txt, re.S)
@@ -70,7 +72,78 @@ def measured_traffic(kernel):
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     if rec["kernel"] != kernel or hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
-    return rec["bytes_per_launch"]
+    return rec
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading on
+    a plain device copy of known size), or None when the summary is absent,
+    is for another kernel, or the near-field source has changed since."""
+    rec = profile_record(PMC_SUMMARY, kernel)
+    return None if rec is None else rec["bytes_per_launch"]
+
+
+def _deinterleave(v):
+    v = v & 0x55555555
+    v = (v | (v >> 1)) & 0x33333333
+    v = (v | (v >> 2)) & 0x0F0F0F0F
+    v = (v | (v >> 4)) & 0x00FF00FF
+    return (v | (v >> 8)) & 0x0000FFFF
+
+
+def m2l_translations(tree):
+    """Interaction-list translations per level (Sec. 5.1.2): pairs of
+    non-empty boxes of one level whose parents are neighbours (or the same)
+    while they are not neighbours themselves, counted from the tree's leaf
+    occupancy (Morton order, parents occupied when a child is)."""
+    _, off = tree.export()
+    occ = np.diff(off.cpu().numpy()) > 0
+    L = tree.info()["levels"]
+    out = {}
+    for lev in range(L, 1, -1):
+        side = 1 << lev
+        idx = np.arange(side * side)
+        grid = np.zeros((side, side), bool)
+        grid[_deinterleave(idx), _deinterleave(idx >> 1)] = occ
+        X, Y = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+        c = 0
+        for dx in range(-3, 4):
+            for dy in range(-3, 4):
+                if max(abs(dx), abs(dy)) <= 1:
+                    continue
+                sx, sy = X + dx, Y + dy
+                ok = (sx >= 0) & (sx < side) & (sy >= 0) & (sy < side) & grid
+                ok &= (np.abs(sx // 2 - X // 2) <= 1) & (np.abs(sy // 2 - Y // 2) <= 1)
+                c += int(grid[sx[ok], sy[ok]].sum())
+        out[lev] = c
+        occ = occ.reshape(-1, 4).any(1)
+    return out
+
+
+def m2l_algorithmic_flops(tree, orders, nrhs=1):
+    """Real flops of the M2L as dense complex products: a translation at
+    level l maps 2 p_l + 1 coefficients to 2 p_l + 1, each complex
+    multiply-add 8 flops."""
+    return sum(c * 8 * (2 * orders[lev] + 1) ** 2 * nrhs for lev, c in m2l_translations(tree).items())
+
+
+def m2l_roofline(tree, orders, ms, prec_name, counters_key=None):
+    """M2L rate from the launch's hipEvent time on its own stream (`ms`)
+    against the MFMA peak of its precision; the executed-to-algorithmic
+    ratio comes from the committed MFMA counter summary when it matches the
+    current source."""
+    fl = m2l_algorithmic_flops(tree, orders)
+    peak = PEAK_FP32_MFMA if prec_name == "fp32" else PEAK_FP64_MFMA
+    ach = fl / (ms * 1e-3) / 1e12
+    out = {"bound": "mfma", "kernel": f"k_m2l_mfma<{'float' if prec_name == 'fp32' else 'double'}>",
+           "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+           "algorithmic_flops_per_launch": fl, "ms_per_launch": round(ms, 5),
+           "translations_per_level": m2l_translations(tree)}
+    rec = profile_record(M2L_SUMMARY, "k_m2l_mfma") if counters_key else None
+    if rec is not None and counters_key in rec["executed_flops"]:
+        out["executed_over_algorithmic"] = round(rec["executed_flops"][counters_key] / fl, 3)
+    return out
 
 
 def log(*a):
@@ -141,7 +214,9 @@ def bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan32):
         "achieved": round(ach, 3), "peak": PEAK_FP64_ALU, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_ALU, 4),
         "algorithmic_flops_per_launch": fl, "ms_per_launch": round(st["p2p"], 5), "near_deg": plan64["near_deg"],
         "note": "the per-pair FP64 log2 is counted as 0 flops"}
-    log(f"C2 fp64 p=8 stages {fmm_tab['fp64_p8_stage_ms']} roofline {fmm_tab['fp64_p8_roofline']['frac']}")
+    fmm_tab["fp64_p8_m2l_roofline"] = m2l_roofline(tree, plan64["orders"], st["m2l"], "fp64", "c2_p8_fp64")
+    log(f"C2 fp64 p=8 stages {fmm_tab['fp64_p8_stage_ms']} roofline {fmm_tab['fp64_p8_roofline']['frac']} "
+        f"M2L {fmm_tab['fp64_p8_m2l_roofline']['frac']}")
     return fmm_tab
 
 
@@ -206,6 +281,8 @@ def bench_c3(dev, hfmm, workloads, torch):
         hfmm.hfmm_fmm_apply_timed(t3, k3, 6, qv, prec=prec)
         _, ms = hfmm.hfmm_fmm_apply_timed(t3, k3, 6, qv, prec=prec)
         out[f"fmm_pass_stage_ms_{name}"] = {s_: round(v, 4) for s_, v in ms.items()}
+        orders = hfmm.hfmm_fmm_plan_info(t3, k3, 6, prec)["orders"]
+        out[f"fmm_pass_m2l_roofline_{name}"] = m2l_roofline(t3, orders, ms["m2l"], name, f"c3_p6_{name}")
     out["orders_p6"] = hfmm.hfmm_fmm_plan_info(t3, k3, 6, hfmm.FP32)["orders"]
     log(f"C3 FMM stages: {out['fmm_pass_stage_ms_fp32']}")
     return out
@@ -510,6 +587,69 @@ def cpu_extra_baselines(workloads):
     return out
 
 
+PROFILE_CASES = ("c2-fp64", "c3-pass-fp32", "c3-pass-fp64", "c3-solve")
+
+
+def copy_probe(torch, dev):
+    """One device-to-device copy of 64 Mi doubles (512 MiB read, 512 MiB
+    written): the calibration of the HBM byte counters."""
+    src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def profile_case(name, steps, warmup, probe):
+    """One workload alone, for a profiler (no JSON line):
+    c2-fp64        the headline apply in complex128 (N = 2^20, k = 100, leaf 64, p = 8);
+    c3-pass-fp32   the first FMM pass of the 1024 x 1024 preconditioner (sources
+    c3-pass-fp64   h^2 f at the interior nodes, k h = 0.3, leaf 32, p = 6);
+    c3-solve       solver set-up (tree, boundary inverse, plans) then `steps`
+                   complex64-preconditioned FGMRES(50) solves of that system with
+                   the dispersion-matched k0, p = 6."""
+    import torch
+    from paper_1608_02461_amd import hfmm, workloads
+    dev = torch.device("cuda:0")
+    if name == "c2-fp64":
+        w = workloads.fmm_c2()
+        tree = hfmm.Tree(torch.from_numpy(w["xy"]).to(dev), leaf_size=w["leaf"])
+        q = torch.from_numpy(w["q"]).to(dev)
+        run = lambda: hfmm.hfmm_fmm_apply(tree, w["k"], 8, q, prec=hfmm.FP64)
+    elif name.startswith("c3-pass"):
+        c3 = workloads.solve_c3()
+        n3 = c3["n"]
+        pts = c3_points(n3)
+        tree = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=c3["leaf"])
+        q = np.zeros(len(pts), dtype=np.complex128)
+        q[: n3 * n3] = c3["h"] ** 2 * c3["f"]
+        prec, dt = (hfmm.FP32, np.complex64) if name.endswith("fp32") else (hfmm.FP64, np.complex128)
+        qd = torch.from_numpy(q.astype(dt)).to(dev)
+        run = lambda: hfmm.hfmm_fmm_apply(tree, c3["k"], 6, qd, prec=prec)
+    elif name == "c3-solve":
+        c3 = workloads.solve_c3()
+        n3, k3 = c3["n"], c3["k"]
+        k0 = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
+        f = torch.from_numpy(c3["f"]).to(dev)
+        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=c3["leaf"], prec=hfmm.FP32)
+        warmup = 0
+        run = lambda: s.solve(f, restart=50, rtol=1e-6, maxit=3000)
+    else:
+        raise SystemExit(f"unknown profile case {name}; one of {PROFILE_CASES}")
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    log(f"profile {name}: {steps} runs")
+    for _ in range(steps):
+        out = run()
+    torch.cuda.synchronize()
+    if name == "c3-solve":
+        log(f"profile {name}: {out[1]}")
+    if probe:
+        copy_probe(torch, dev)
+    print(f"profile {name} done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,7 +660,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed applies, copy 512 MiB device to device once (counter calibration)")
+    ap.add_argument("--profile", choices=PROFILE_CASES,
+                    help="run one workload alone for a profiler (steps after warmup) and print no JSON line")
     args = ap.parse_args()
+    if args.profile:
+        profile_case(args.profile, args.steps, args.warmup, args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
               "described in DESIGN.md and not built", file=sys.stderr)
@@ -563,12 +708,7 @@ def main():
     value = N / (elapsed / args.steps) / 1e6
 
     if args.copy_probe:
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe(torch, dev)
 
     # ---------------- per-stage device times (hipEvents on the launch stream), same applies
     stages = {s: 0.0 for s in hfmm.STAGES}
@@ -609,6 +749,8 @@ def main():
         "tree_build_ms": round(t_tree * 1e3, 4), "tree_build_first_ms": round(t_tree_first * 1e3, 3),
         "rel_err_2048_samples": err32,
         "roofline": roofline,
+        # the M2L launch on the far-field chain's stream (beside the near field)
+        "m2l_roofline": m2l_roofline(tree, plan["orders"], stages["m2l"], "fp32", f"c2_p{p}_fp32"),
     }
 
     if not args.no_extras:

@@ -149,14 +149,16 @@ hfmm_status hfmm_fmm_apply_noalloc(hfmm_tree t, double k, int32_t p, hfmm_precis
 int64_t hfmm_fmm_noalloc_capacity(void);
 
 /* The same apply with hipEvents around its stages (tracing): ms_stages
- * (host, 6 floats) receives device times in ms.  On a tree of depth >= 2:
+ * (host, 9 floats) receives device times in ms.  On a tree of depth >= 2:
  * [1] P2M (which also gathers the charges into Morton order), [2] the
  * far-field chain M2M + M2L + L2L + L2P, which runs on the tree's second
  * stream beside [4] the near field (P2P) on trees of 2^18 points or more
  * (after it on smaller ones), and [3] the sum of both written in caller
- * order, including the wait for [2]; [0] and [5] are 0.  On a single leaf:
- * [0] the gather, [4] the direct sum, [5] the scatter.  Synchronises
- * `stream`. */
+ * order, including the wait for [2]; [0] and [5] are 0.  The chain's parts,
+ * timed on the stream they run on: [6] the M2M levels, [7] the M2L launch,
+ * [8] the L2L levels and the L2P (with the option m2l_valu the whole chain
+ * counts under [8] and [6], [7] are 0).  On a single leaf: [0] the gather,
+ * [4] the direct sum, [5] the scatter, the rest 0.  Synchronises `stream`. */
 hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
                                  const void* d_q, void* d_phi, int32_t nrhs, float* ms_stages,
                                  hipStream_t stream);

@@ -156,7 +156,7 @@ hfmm_status hfmm_fmm_apply_timed(hfmm_tree t, double k, int32_t p, hfmm_precisio
   else
     hfmm::fmm_apply<float>(*t->t, k, p, static_cast<const float2*>(d_q), static_cast<float2*>(d_phi), nrhs, stream,
                            &tm);
-  tm.collect(ms_stages, 6);
+  tm.collect(ms_stages, 9);
   return HFMM_OK;
   HFMM_GUARD_END
 }

@@ -1279,13 +1279,17 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
 // level, L2L levels 3 .. r (MFMA kernels, or the VALU ones on request),
 // then k_down_tree: L2L of the last levels r+1 .. L and the L2P into w.far,
 // r = max(2, L - 2).  `fa` carries the points and far-field scales.
+// Stage timing (tm set): [6] the M2M levels, [7] the M2L, [8] the L2L
+// levels with the down tree, all on `st`.
 template <class T, int NR>
 void far_chain(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, int nrhs, int r0, const uint8_t* flags,
-               hipStream_t st, const int* alive, const P2PArgs<T>& fa) {
+               hipStream_t st, const int* alive, const P2PArgs<T>& fa, StageTimer* tm) {
   const int L = t.L;
   const int rl = std::max(2, L - 2);  // the down tree starts below this level
   cplx<T>* M = w.M;
   cplx<T>* Lc = w.Lc;
+  const int e0 = tm ? tm->mark(-1, st) : -1;
+  int e_up = -1, e_m2l = -1;
   if (pl.use_mfma) {
     for (int l = L - 1; l >= 2; --l) {
       const LevelInfo &lp = pl.lv[l], &lc = pl.lv[l + 1];
@@ -1309,7 +1313,9 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, int nrhs, int
       k_tt_mfma<T><<<dim3((ta.nparents + 15) / 16, mf.RT), 256, 0, st>>>(ta);
       HFMM_LAUNCH_CHECK();
     }
+    if (tm) e_up = tm->mark(6, st, e0);
     launch_m2l<T, NR>(t, pl, M, Lc, nrhs, r0, flags, alive, st);
+    if (tm) e_m2l = tm->mark(7, st, e_up);
     for (int l = 3; l <= rl; ++l) {
       const LevelInfo &li = pl.lv[l], &lp = pl.lv[l - 1];
       const MfmaLevel& mf = pl.mf[l];
@@ -1368,6 +1374,8 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, int nrhs, int
   const size_t sh = (size_t)(4 * NR * g.P1 + 16 * NR * g.P2) * sizeof(cplx<T>);
   k_down_tree<T, NR><<<1 << (2 * rl), 256, sh, st>>>(g);
   HFMM_LAUNCH_CHECK();
+  // the VALU path's M2L and L2L share launches: both count under [8]
+  if (tm) tm->mark(8, st, e_m2l >= 0 ? e_m2l : e0);
 }
 
 // One column group (NR columns from r0).  P2M (which also gathers the
@@ -1378,8 +1386,8 @@ void far_chain(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, int nrhs, int
 // phi, the chain ends with the L2P into the far-field array w.far, both
 // through `perm` when given, and a last streaming kernel adds the far
 // field to phi.  Stage timing: [1] P2M, [2] the far-field chain including
-// the L2P (side stream, beside [4]), [4] the near field, [3] the sum,
-// including the wait for [2].  With dn the sources are dipoles (sorted I/O).
+// the L2P (side stream, beside [4]; its parts in [6], [7], [8]), [4] the
+// near field, [3] the sum, including the wait for [2].  With dn the sources are dipoles (sorted I/O).
 template <class T, int NR>
 void run_cols(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, const cplx<T>* q, cplx<T>* phi, int nrhs, int r0,
               const uint8_t* flags, bool accumulate, hipStream_t st, const int* alive, StageTimer* tm,
@@ -1441,7 +1449,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, const cplx<T>*
     const int e_p2p = tm ? tm->mark(4, st, e_p2m) : -1;
     const P2PArgs<T> b =
         p2p_args<T>(t, pl, qnear, phi, nrhs, r0, NR, flags, false, alive, perm, w.Lc + lf.coef * nrhs);
-    far_chain<T, NR>(t, pl, w, nrhs, r0, flags, cs, alive, b);
+    far_chain<T, NR>(t, pl, w, nrhs, r0, flags, cs, alive, b, tm);
     if (tm) tm->mark(2, cs, overlap ? e_p2m : e_p2p);
     if (overlap) {
       HFMM_HIP(hipEventRecord(t.join, t.side));
@@ -1750,7 +1758,6 @@ void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrh
   if (t.L >= 2) {
     // the P2M kernel gathers the charges into Morton order and the near-field
     // kernel writes the potentials back in caller order
-    if (tm) tm->mark(0, st);
     fmm_sorted<T>(t, pl, q, phi, nrhs, nullptr, false, st, nullptr, tm, t.perm.p, pl.qs.p);
   } else {
     k_gather<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(q, pl.qs.p, t.perm.p, t.n);
@@ -1759,8 +1766,8 @@ void fmm_apply(Tree& t, double k, int p, const cplx<T>* q, cplx<T>* phi, int nrh
     fmm_sorted<T>(t, pl, pl.qs.p, pl.phis.p, nrhs, nullptr, false, st, nullptr, tm);
     k_scatter<T><<<dim3(blocks_for(t.n), nrhs), 256, 0, st>>>(pl.phis.p, phi, t.perm.p, t.n);
     HFMM_LAUNCH_CHECK();
+    if (tm) tm->mark(5, st);
   }
-  if (tm) tm->mark(5, st);
 }
 
 template <class T>

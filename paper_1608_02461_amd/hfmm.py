@@ -259,10 +259,11 @@ def hfmm_fmm_noalloc_capacity():
     return lib().hfmm_fmm_noalloc_capacity()
 
 
-# stage names of hfmm_fmm_apply_timed; on a tree of depth >= 2 "upward" is
-# P2M, "downward" the far-field chain (M2M + M2L + L2L + L2P) on the tree's
-# second stream beside "p2p", and "l2p" the output (see include/hfmm.h)
-STAGES = ("gather", "upward", "downward", "l2p", "p2p", "scatter")
+# stage names of hfmm_fmm_apply_timed (the order of its ms_stages); on a tree
+# of depth >= 2 "far_chain" (M2M + M2L + L2L + L2P) runs on the tree's second
+# stream beside "p2p", "combine" adds the two (and waits for the chain), and
+# "m2m", "m2l", "l2l_l2p" are the chain's parts
+STAGES = ("gather", "p2m", "far_chain", "combine", "p2p", "scatter", "m2m", "m2l", "l2l_l2p")
 
 
 def hfmm_fmm_apply_timed(tree, k, p, q, prec=FP64, stream=None):
@@ -270,7 +271,7 @@ def hfmm_fmm_apply_timed(tree, k, p, q, prec=FP64, stream=None):
     dtype = torch.complex128 if prec == FP64 else torch.complex64
     qc, squeeze = _colmajor(q, dtype, "q")
     phi = torch.empty_like(qc)
-    ms = (ctypes.c_float * 6)()
+    ms = (ctypes.c_float * len(STAGES))()
     _check(lib().hfmm_fmm_apply_timed(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), qc.shape[0], ms,
                                       _stream(stream)))
     return _from_colmajor(phi, squeeze), dict(zip(STAGES, list(ms)))
