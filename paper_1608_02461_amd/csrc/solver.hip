@@ -88,21 +88,39 @@ __global__ void k_assemble_S(const double2* __restrict__ yg, int ng, double k0, 
   A[idx] = v;
 }
 
-__global__ __launch_bounds__(1024) void k_gj_pivot(const double2* __restrict__ A, int64_t ld, int ng, int c,
-                                                   int* __restrict__ piv, double2* __restrict__ pv,
-                                                   int* __restrict__ sing) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  double best = -1.0;
-  int bi = c;
-  for (int i = c + threadIdx.x; i < ng; i += 1024) {
-    const double v = cabs2(A[(int64_t)i * ld + c]);
-    if (v > best) { best = v; bi = i; }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
+// ---------------------------------------------------------------- S inverse
+// Gauss-Jordan inverse of the boundary matrix with partial pivoting, in
+// panels of kPanel columns, on the row-major augmented matrix [S | I]
+// (ng rows, ld = 2 ng).  For a panel of columns P = [c0, c0 + nb):
+//  1. an LU with partial pivoting of the panel's rows c0.. (a column-major
+//     copy, one launch per column) chooses the pivot rows; these are the
+//     rows unblocked Gauss-Jordan would choose, since eliminating rows above
+//     c0 does not change the rows below;
+//  2. the row exchanges are applied to the whole matrix, after which the
+//     pivot rows R = [c0, c0 + nb) hold the block A_RP;
+//  3. the panel's eliminations together are the row operation
+//     M = I + W E_R^T with W_R = A_RP^-1 - I and W_O = -A_OP A_RP^-1 on the
+//     other rows O, so the columns right of the panel take the rank-nb
+//     update A += W A_R (A_R copied first), a complex FP64 GEMM.
+// After the last panel the right half holds S^-1.
+constexpr int kPanel = 32;
+
+// Column-major copy of the panel's rows c0..ng-1: Wk[c * m + r].
+__global__ void k_pl_copy(const double2* __restrict__ A, int64_t ld, int c0, int m, int nb,
+                          double2* __restrict__ Wk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * nb) return;
+  const int c = (int)(t / m), r = (int)(t - (int64_t)c * m);
+  Wk[t] = A[(int64_t)(c0 + r) * ld + c0 + c];
+}
+
+// Largest |.|^2 of column c of the workspace over rows [c, m), as (value,
+// row) with the lowest row on ties; one block of kRed threads.
+__device__ void pl_argmax_block(double v, int r, double* sv, int* si) {
+  sv[threadIdx.x] = v;
+  si[threadIdx.x] = r;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = kRed / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       const double o = sv[threadIdx.x + s];
       const int oi = si[threadIdx.x + s];
@@ -113,57 +131,258 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(const double2* __restrict__ A
     }
     __syncthreads();
   }
+}
+
+// Exchange workspace rows c and pr (all nb columns), record the pivot row
+// and flag an exact zero pivot.  Called by one block.
+__device__ void pl_take_pivot(double2* Wk, int m, int nb, int c, int pr, double pv, int* piv, int* sing) {
+  if (threadIdx.x < nb && pr != c) {
+    const double2 a = Wk[(int64_t)threadIdx.x * m + c];
+    Wk[(int64_t)threadIdx.x * m + c] = Wk[(int64_t)threadIdx.x * m + pr];
+    Wk[(int64_t)threadIdx.x * m + pr] = a;
+  }
   if (threadIdx.x == 0) {
-    piv[0] = si[0];
-    pv[0] = A[(int64_t)si[0] * ld + c];
-    if (!(sv[0] > 0.0)) sing[0] = 1;
+    piv[c] = pr;
+    if (!(pv > 0.0)) sing[0] = 1;
   }
 }
 
-__global__ void k_gj_swap_scale(double2* __restrict__ A, int64_t ld, int c, const int* __restrict__ piv,
-                                const double2* __restrict__ pv) {
-  const int64_t j = c + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ld) return;
-  const int pr = piv[0];
-  const double2 p = pv[0];
-  const double d = cabs2(p);
-  const double2 inv = d > 0 ? make_double2(p.x / d, -p.y / d) : make_double2(0, 0);
-  const double2 a = A[(int64_t)c * ld + j];
-  double2 b = a;
-  if (pr != c) {
-    b = A[(int64_t)pr * ld + j];
-    A[(int64_t)pr * ld + j] = a;
+// Pivot of the panel's first column (one block).
+__global__ __launch_bounds__(kRed) void k_pl_pivot0(double2* __restrict__ Wk, int m, int nb, int* __restrict__ piv,
+                                                    int* __restrict__ sing) {
+  __shared__ double sv[kRed];
+  __shared__ int si[kRed];
+  double best = -1.0;
+  int bi = 0;
+  for (int r = threadIdx.x; r < m; r += kRed) {
+    const double v = cabs2(Wk[r]);
+    if (v > best) { best = v; bi = r; }
   }
-  A[(int64_t)c * ld + j] = cmul(b, inv);
+  pl_argmax_block(best, bi, sv, si);
+  const int pr = si[0];
+  const double pv = sv[0];
+  __syncthreads();
+  pl_take_pivot(Wk, m, nb, 0, pr, pv, piv, sing);
 }
 
-__global__ void k_gj_col(const double2* __restrict__ A, int64_t ld, int ng, int c, double2* __restrict__ f) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ng) f[i] = A[(int64_t)i * ld + c];
+// LU step c of the panel: rows r > c take l = W[r, c] / W[c, c] and
+// W[r, c+1..] -= l W[c, c+1..].  Each block then offers the largest entry of
+// column c + 1 over its rows; the last block to finish (device counter)
+// picks the pivot of column c + 1, exchanges the rows and resets the
+// counter for the next launch.
+__global__ __launch_bounds__(kRed) void k_pl_step(double2* __restrict__ Wk, int m, int nb, int c,
+                                                  int* __restrict__ piv, int* __restrict__ sing,
+                                                  double* __restrict__ pval, int* __restrict__ prow,
+                                                  unsigned* __restrict__ counter) {
+  __shared__ double sv[kRed];
+  __shared__ int si[kRed];
+  __shared__ bool last;
+  const int r = blockIdx.x * kRed + threadIdx.x;
+  const bool next = c + 1 < nb;
+  double best = -1.0;
+  if (r > c && r < m) {
+    const double2 p = Wk[(int64_t)c * m + c];
+    const double d = cabs2(p);
+    const double2 inv = d > 0 ? make_double2(p.x / d, -p.y / d) : make_double2(0, 0);
+    const double2 l = cmul(Wk[(int64_t)c * m + r], inv);
+    Wk[(int64_t)c * m + r] = l;
+    for (int cc = c + 1; cc < nb; ++cc) {
+      const double2 u = Wk[(int64_t)cc * m + c];
+      double2 v = Wk[(int64_t)cc * m + r];
+      v.x -= l.x * u.x - l.y * u.y;
+      v.y -= l.x * u.y + l.y * u.x;
+      Wk[(int64_t)cc * m + r] = v;
+      if (cc == c + 1) best = cabs2(v);
+    }
+  }
+  if (!next) return;  // uniform over the grid
+  __threadfence();     // this block's rows are visible before it reports
+  pl_argmax_block(best, r, sv, si);
+  if (threadIdx.x == 0) {
+    pval[blockIdx.x] = sv[0];
+    prow[blockIdx.x] = si[0];
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double b = -1.0;
+  int bi = c + 1;
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += kRed) {
+    const double v = pval[q];
+    const int vi = prow[q];
+    if (v > b || (v == b && vi < bi)) { b = v; bi = vi; }
+  }
+  pl_argmax_block(b, bi, sv, si);
+  const int pr = si[0] > c ? si[0] : c + 1;
+  const double pv = sv[0];
+  __syncthreads();
+  pl_take_pivot(Wk, m, nb, c + 1, pr, pv, piv, sing);
+  if (threadIdx.x == 0) counter[0] = 0;
 }
 
-__global__ void k_gj_elim(double2* __restrict__ A, int64_t ld, int c, const double2* __restrict__ f) {
-  const int i = blockIdx.y;
-  if (i == c) return;
-  const int64_t j = c + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The panel's row exchanges, in order, on columns [c0, ld) of A: one thread
+// per column.
+__global__ void k_pl_swap_rows(double2* __restrict__ A, int64_t ld, int c0, int nb, const int* __restrict__ piv) {
+  const int64_t j = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ld) return;
-  const double2 fi = f[i];
-  if (fi.x == 0.0 && fi.y == 0.0) return;
-  const double2 r = A[(int64_t)c * ld + j];
-  double2 v = A[(int64_t)i * ld + j];
-  v.x -= fi.x * r.x - fi.y * r.y;
-  v.y -= fi.x * r.y + fi.y * r.x;
-  A[(int64_t)i * ld + j] = v;
+  for (int c = 0; c < nb; ++c) {
+    const int pr = piv[c];
+    if (pr == c) continue;
+    const int64_t a = (int64_t)(c0 + c) * ld + j, b = (int64_t)(c0 + pr) * ld + j;
+    const double2 t = A[a];
+    A[a] = A[b];
+    A[b] = t;
+  }
 }
 
-__global__ void k_colsum(const double2* __restrict__ A, int64_t ld, int ng, int col0, double* __restrict__ out) {
+// X = A_RP^-1 (nb x nb, row-major) by in-place Gauss-Jordan without
+// exchanges: the pivots are those the panel's LU chose.  One block.
+__global__ __launch_bounds__(1024) void k_pl_inv(const double2* __restrict__ A, int64_t ld, int c0, int nb,
+                                                 double2* __restrict__ X) {
+  __shared__ double2 a[kPanel][kPanel + 1];
+  __shared__ double2 colk[kPanel];
+  const int i = threadIdx.x / kPanel, j = threadIdx.x % kPanel;
+  const bool in = i < nb && j < nb;
+  if (in) a[i][j] = A[(int64_t)(c0 + i) * ld + c0 + j];
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const double2 p = a[k][k];
+    const double d = cabs2(p);
+    const double2 pinv = d > 0 ? make_double2(p.x / d, -p.y / d) : make_double2(0, 0);
+    if (in && j == k) colk[i] = a[i][k];
+    __syncthreads();
+    if (in && i == k) a[k][j] = j == k ? pinv : cmul(a[k][j], pinv);
+    __syncthreads();
+    if (in && i != k) {
+      const double2 f = colk[i];
+      if (j == k) {
+        a[i][k] = make_double2(-(f.x * pinv.x - f.y * pinv.y), -(f.x * pinv.y + f.y * pinv.x));
+      } else {
+        const double2 u = a[k][j];
+        a[i][j].x -= f.x * u.x - f.y * u.y;
+        a[i][j].y -= f.x * u.y + f.y * u.x;
+      }
+    }
+    __syncthreads();
+  }
+  if (in) X[i * kPanel + j] = a[i][j];
+}
+
+// W (ng x kPanel, row-major): rows in R get X - I, the other rows
+// -A[row, P] X.
+__global__ void k_pl_W(const double2* __restrict__ A, int64_t ld, int ng, int c0, int nb,
+                       const double2* __restrict__ X, double2* __restrict__ W) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ng * kPanel) return;
+  const int i = (int)(t / kPanel), kk = (int)(t % kPanel);
+  double2 w = make_double2(0, 0);
+  if (kk < nb) {
+    if (i >= c0 && i < c0 + nb) {
+      w = X[(i - c0) * kPanel + kk];
+      if (i - c0 == kk) w.x -= 1.0;
+    } else {
+      const double2* ar = A + (int64_t)i * ld + c0;
+      double sx = 0, sy = 0;
+      for (int q = 0; q < nb; ++q) {
+        const double2 av = ar[q], xv = X[q * kPanel + kk];
+        sx += av.x * xv.x - av.y * xv.y;
+        sy += av.x * xv.y + av.y * xv.x;
+      }
+      w = make_double2(-sx, -sy);
+    }
+  }
+  W[t] = w;
+}
+
+// T = A[R, j0:ld) (kPanel rows, row-major, stride tn = ld - j0); rows past
+// nb are zero.
+__global__ void k_pl_T(const double2* __restrict__ A, int64_t ld, int c0, int nb, int64_t j0,
+                       double2* __restrict__ T) {
+  const int64_t tn = ld - j0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tn * kPanel) return;
+  const int kk = (int)(t / tn);
+  const int64_t j = t - kk * tn;
+  T[t] = kk < nb ? A[(int64_t)(c0 + kk) * ld + j0 + j] : make_double2(0, 0);
+}
+
+// A[0:ng, j0:ld) += W T: 64 x 64 output tiles, each of 256 threads holding
+// 4 x 4 complex accumulators (rows ty + 16 p, columns tx + 16 q), W and T
+// tiles staged in LDS.  K = kPanel (rows of T past the panel are zero).
+constexpr int kGT = 64;
+__global__ __launch_bounds__(256) void k_pl_gemm(double2* __restrict__ A, int64_t ld, int ng, int64_t j0,
+                                                 const double2* __restrict__ W, const double2* __restrict__ T) {
+  __shared__ double2 sW[kGT][kPanel];
+  __shared__ double2 sT[kPanel][kGT];
+  const int64_t tn = ld - j0;
+  const int row0 = blockIdx.y * kGT;
+  const int64_t col0 = (int64_t)blockIdx.x * kGT;
+  for (int e = threadIdx.x; e < kGT * kPanel; e += 256) {
+    const int r = e / kPanel, kk = e % kPanel;
+    sW[r][kk] = row0 + r < ng ? W[(int64_t)(row0 + r) * kPanel + kk] : make_double2(0, 0);
+    const int kt = e / kGT, cc = e % kGT;
+    sT[kt][cc] = col0 + cc < tn ? T[(int64_t)kt * tn + col0 + cc] : make_double2(0, 0);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double accx[4][4], accy[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) accx[p][q] = accy[p][q] = 0.0;
+#pragma unroll 4
+  for (int kk = 0; kk < kPanel; ++kk) {
+    double2 w[4], u[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) w[p] = sW[ty + 16 * p][kk];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = sT[kk][tx + 16 * q];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        accx[p][q] = fma(w[p].x, u[q].x, fma(-w[p].y, u[q].y, accx[p][q]));
+        accy[p][q] = fma(w[p].x, u[q].y, fma(w[p].y, u[q].x, accy[p][q]));
+      }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int i = row0 + ty + 16 * p;
+    if (i >= ng) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = col0 + tx + 16 * q;
+      if (j >= tn) continue;
+      double2* a = A + (int64_t)i * ld + j0 + j;
+      double2 v = *a;
+      v.x += accx[p][q];
+      v.y += accy[p][q];
+      *a = v;
+    }
+  }
+}
+
+// Column sums of |A| over rows, columns [col0, col0 + ng): partial sums of
+// row slabs (blockIdx.y), then a pass over the slabs.
+constexpr int kSumSlabs = 32;
+__global__ void k_colsum_part(const double2* __restrict__ A, int64_t ld, int ng, int col0,
+                              double* __restrict__ part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ng) return;
+  const int rs = (ng + kSumSlabs - 1) / kSumSlabs;
+  const int r0 = blockIdx.y * rs, r1 = min(ng, r0 + rs);
+  double s = 0;
+  for (int i = r0; i < r1; ++i) s += sqrt(cabs2(A[(int64_t)i * ld + col0 + j]));
+  part[(int64_t)blockIdx.y * ng + j] = s;
+}
+
+__global__ void k_colsum_fin(const double* __restrict__ part, int ng, double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ng) return;
   double s = 0;
-  for (int i = 0; i < ng; ++i) {
-    const double2 v = A[(int64_t)i * ld + col0 + j];
-    s += sqrt(cabs2(v));
-  }
+  for (int b = 0; b < kSumSlabs; ++b) s += part[(int64_t)b * ng + j];
   out[j] = s;
 }
 
@@ -1003,31 +1222,46 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
   k_assemble_S<<<nblocks((int64_t)ng * ld), 256, 0, st>>>(dyg.p, ng, k0, h, make_double2(dg.real(), dg.imag()),
                                                            A.p);
   HFMM_LAUNCH_CHECK();
-  DevBuf<double> colsum(ng);
+  DevBuf<double> colsum(ng), cpart((size_t)kSumSlabs * ng);
   std::vector<double> hcol(ng);
-  k_colsum<<<nblocks(ng), 256, 0, st>>>(A.p, ld, ng, 0, colsum.p);
-  HFMM_LAUNCH_CHECK();
-  HFMM_HIP(hipMemcpyAsync(hcol.data(), colsum.p, ng * sizeof(double), hipMemcpyDeviceToHost, st));
-  HFMM_HIP(hipStreamSynchronize(st));
-  const double normS = *std::max_element(hcol.begin(), hcol.end());
-  DevBuf<int> piv(1), sing(1);
-  DevBuf<double2> pv(1), f(ng);
+  auto column_sums = [&](int col0) {
+    k_colsum_part<<<dim3(nblocks(ng), kSumSlabs), 256, 0, st>>>(A.p, ld, ng, col0, cpart.p);
+    k_colsum_fin<<<nblocks(ng), 256, 0, st>>>(cpart.p, ng, colsum.p);
+    HFMM_LAUNCH_CHECK();
+    HFMM_HIP(hipMemcpyAsync(hcol.data(), colsum.p, ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HFMM_HIP(hipStreamSynchronize(st));
+    return *std::max_element(hcol.begin(), hcol.end());
+  };
+  const double normS = column_sums(0);
+  // blocked Gauss-Jordan (see k_pl_gemm and the kernels before it)
+  const int nred = nblocks(ng, kRed);
+  DevBuf<double2> Wk((size_t)ng * kPanel), W((size_t)ng * kPanel), X((size_t)kPanel * kPanel),
+      T((size_t)kPanel * ld);
+  DevBuf<int> piv(kPanel), sing(1), prow(nred);
+  DevBuf<double> pval(nred);
+  DevBuf<unsigned> counter(1);
   HFMM_HIP(hipMemsetAsync(sing.p, 0, sizeof(int), st));
-  for (int c = 0; c < ng; ++c) {
-    k_gj_pivot<<<1, 1024, 0, st>>>(A.p, ld, ng, c, piv.p, pv.p, sing.p);
-    k_gj_swap_scale<<<nblocks(ld - c), 256, 0, st>>>(A.p, ld, c, piv.p, pv.p);
-    k_gj_col<<<nblocks(ng), 256, 0, st>>>(A.p, ld, ng, c, f.p);
-    k_gj_elim<<<dim3(nblocks(ld - c), ng), 256, 0, st>>>(A.p, ld, c, f.p);
+  HFMM_HIP(hipMemsetAsync(counter.p, 0, sizeof(unsigned), st));
+  for (int c0 = 0; c0 < ng; c0 += kPanel) {
+    const int nb = std::min(kPanel, ng - c0), m = ng - c0;
+    k_pl_copy<<<nblocks((int64_t)m * nb), 256, 0, st>>>(A.p, ld, c0, m, nb, Wk.p);
+    k_pl_pivot0<<<1, kRed, 0, st>>>(Wk.p, m, nb, piv.p, sing.p);
+    for (int c = 0; c + 1 < nb; ++c)
+      k_pl_step<<<nblocks(m, kRed), kRed, 0, st>>>(Wk.p, m, nb, c, piv.p, sing.p, pval.p, prow.p, counter.p);
+    k_pl_swap_rows<<<nblocks(ld - c0), 256, 0, st>>>(A.p, ld, c0, nb, piv.p);
+    k_pl_inv<<<1, 1024, 0, st>>>(A.p, ld, c0, nb, X.p);
+    k_pl_W<<<nblocks((int64_t)ng * kPanel), 256, 0, st>>>(A.p, ld, ng, c0, nb, X.p, W.p);
+    const int64_t j0 = c0 + nb, tn = ld - j0;
+    k_pl_T<<<nblocks(tn * kPanel), 256, 0, st>>>(A.p, ld, c0, nb, j0, T.p);
+    k_pl_gemm<<<dim3((unsigned)((tn + kGT - 1) / kGT), (unsigned)((ng + kGT - 1) / kGT)), 256, 0, st>>>(
+        A.p, ld, ng, j0, W.p, T.p);
   }
   HFMM_LAUNCH_CHECK();
   int hs = 0;
   HFMM_HIP(hipMemcpyAsync(&hs, sing.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  k_colsum<<<nblocks(ng), 256, 0, st>>>(A.p, ld, ng, ng, colsum.p);
-  HFMM_LAUNCH_CHECK();
-  HFMM_HIP(hipMemcpyAsync(hcol.data(), colsum.p, ng * sizeof(double), hipMemcpyDeviceToHost, st));
-  HFMM_HIP(hipStreamSynchronize(st));
+  const double normSi = column_sums(ng);
   if (hs) throw Error(HFMM_ERR_NUMERIC, "solver_create: boundary matrix is singular");
-  s->condS = normS * *std::max_element(hcol.begin(), hcol.end());
+  s->condS = normS * normSi;
 
   if (fp32)
     setup_precision<float>(*s, A.p, ld, dnrm.p, st);
