@@ -1036,16 +1036,29 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
         const double cx = (c & 1) - 0.5, cy = (c >> 1) - 0.5;
         const std::complex<double> d(cx * sch, cy * sch);  // child centre - parent centre
         const double r = std::abs(d);
-        besselj_seq(lp.p + lc.p, k * r, J);
+        const int D = lp.p + lc.p;
+        besselj_seq(D, k * r, J);
         const double th_pc = std::arg(-d), th_cp = std::arg(d);
+        // entries depend on the index difference and on |index| through the
+        // scales: tabulate both once per child
+        std::vector<std::complex<double>> cpc(2 * D + 1), ccp(2 * D + 1);
+        for (int nu = -D; nu <= D; ++nu) {
+          cpc[nu + D] = cyl_in(nu, J, th_pc);
+          ccp[nu + D] = cyl_in(nu, J, th_cp);
+        }
+        std::vector<double> sc(D + 1), sp(D + 1);
+        for (int a = 0; a <= D; ++a) {
+          sc[a] = std::pow(lc.s, a);
+          sp[a] = std::pow(lp.s, a);
+        }
         for (int n = -lc.p; n <= lc.p; ++n)
           for (int lo = -lp.p; lo <= lp.p; ++lo) {
-            std::complex<double> v = cyl_in(n - lo, J, th_pc) * std::pow(lc.s, std::abs(n)) / std::pow(lp.s, std::abs(lo));
+            std::complex<double> v = cpc[n - lo + D] * sc[std::abs(n)] / sp[std::abs(lo)];
             put(hm2m, pl->m2m_off[l] + ((size_t)c * lc.P + (n + lc.p)) * lp.P + (lo + lp.p), v);
           }
         for (int m = -lp.p; m <= lp.p; ++m)
           for (int lo = -lc.p; lo <= lc.p; ++lo) {
-            std::complex<double> v = cyl_in(m - lo, J, th_cp) * std::pow(lc.s, std::abs(lo)) / std::pow(lp.s, std::abs(m));
+            std::complex<double> v = ccp[m - lo + D] * sc[std::abs(lo)] / sp[std::abs(m)];
             put(hl2l, pl->l2l_off[l] + ((size_t)c * lp.P + (m + lp.p)) * lc.P + (lo + lc.p), v);
           }
       }
@@ -1069,9 +1082,13 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
           hankel_seq(2 * pp, k * std::abs(z), H);
           const double th = std::arg(z);
           const size_t o = (size_t)((ox + 3) * 7 + (oy + 3));
+          std::vector<std::complex<double>> cv(4 * pp + 1);
+          std::vector<double> sv(2 * pp + 1);
+          for (int nu = -2 * pp; nu <= 2 * pp; ++nu) cv[nu + 2 * pp] = cyl_out(nu, H, th);
+          for (int a = 0; a <= 2 * pp; ++a) sv[a] = std::pow(li.s, a);
           for (int n = -pp; n <= pp; ++n)
             for (int m = -pp; m <= pp; ++m) {
-              std::complex<double> v = cyl_out(n - m, H, th) * std::pow(li.s, std::abs(m) + std::abs(n));
+              std::complex<double> v = cv[n - m + 2 * pp] * sv[std::abs(m) + std::abs(n)];
               put(hm2l, pl->m2l_off[l] + (o * P + (n + pp)) * P + (m + pp), v);
             }
         }

@@ -176,23 +176,36 @@ __global__ __launch_bounds__(kRed) void k_pl_step(double2* __restrict__ Wk, int 
                                                   unsigned* __restrict__ counter) {
   __shared__ double sv[kRed];
   __shared__ int si[kRed];
+  __shared__ double2 su[kPanel];
   __shared__ bool last;
   const int r = blockIdx.x * kRed + threadIdx.x;
   const bool next = c + 1 < nb;
+  // the pivot row, staged once per block
+  if (threadIdx.x < nb) su[threadIdx.x] = Wk[(int64_t)threadIdx.x * m + c];
+  __syncthreads();
   double best = -1.0;
   if (r > c && r < m) {
-    const double2 p = Wk[(int64_t)c * m + c];
+    const double2 p = su[c];
     const double d = cabs2(p);
     const double2 inv = d > 0 ? make_double2(p.x / d, -p.y / d) : make_double2(0, 0);
-    const double2 l = cmul(Wk[(int64_t)c * m + r], inv);
+    // every load of the row is issued before any store
+    double2 v[kPanel];
+    const double2 x = Wk[(int64_t)c * m + r];
+#pragma unroll
+    for (int cc = 0; cc < kPanel; ++cc)
+      if (cc > c && cc < nb) v[cc] = Wk[(int64_t)cc * m + r];
+    const double2 l = cmul(x, inv);
     Wk[(int64_t)c * m + r] = l;
-    for (int cc = c + 1; cc < nb; ++cc) {
-      const double2 u = Wk[(int64_t)cc * m + c];
-      double2 v = Wk[(int64_t)cc * m + r];
-      v.x -= l.x * u.x - l.y * u.y;
-      v.y -= l.x * u.y + l.y * u.x;
-      Wk[(int64_t)cc * m + r] = v;
-      if (cc == c + 1) best = cabs2(v);
+#pragma unroll
+    for (int cc = 0; cc < kPanel; ++cc) {
+      if (cc > c && cc < nb) {
+        const double2 u = su[cc];
+        double2 w = v[cc];
+        w.x -= l.x * u.x - l.y * u.y;
+        w.y -= l.x * u.y + l.y * u.x;
+        Wk[(int64_t)cc * m + r] = w;
+        if (cc == c + 1) best = cabs2(w);
+      }
     }
   }
   if (!next) return;  // uniform over the grid
@@ -327,11 +340,20 @@ __global__ __launch_bounds__(256) void k_pl_gemm(double2* __restrict__ A, int64_
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  // the output tile is read first, so its loads overlap the products
   double accx[4][4], accy[4][4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < 4; ++p) {
+    const int i = row0 + ty + 16 * p;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) accx[p][q] = accy[p][q] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = col0 + tx + 16 * q;
+      double2 v = make_double2(0, 0);
+      if (i < ng && j < tn) v = A[(int64_t)i * ld + j0 + j];
+      accx[p][q] = v.x;
+      accy[p][q] = v.y;
+    }
+  }
 #pragma unroll 4
   for (int kk = 0; kk < kPanel; ++kk) {
     double2 w[4], u[4];
@@ -355,11 +377,7 @@ __global__ __launch_bounds__(256) void k_pl_gemm(double2* __restrict__ A, int64_
     for (int q = 0; q < 4; ++q) {
       const int64_t j = col0 + tx + 16 * q;
       if (j >= tn) continue;
-      double2* a = A + (int64_t)i * ld + j0 + j;
-      double2 v = *a;
-      v.x += accx[p][q];
-      v.y += accy[p][q];
-      *a = v;
+      A[(int64_t)i * ld + j0 + j] = make_double2(accx[p][q], accy[p][q]);
     }
   }
 }
