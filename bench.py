@@ -667,8 +667,8 @@ def main():
         profile_case(args.profile, args.steps, args.warmup, args.copy_probe)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
+              "is a design only and is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,4 +1,4 @@
-"""O-6: adjoint gradient of J(u) = 0.5 ||P u - d||^2 with respect to k^2 (test infrastructure).
+"""Adjoint gradient of J(u) = 0.5 ||P u - d||^2 with respect to k^2 (test infrastructure).
 
 u solves A(k^2) u = f with A = -Laplace_h - diag(k^2) (the FD module).  Since
 dA/dk^2_x = -e_x e_x^T, the derivative of J is

@@ -1,4 +1,4 @@
-"""O-3: the BEM-coupled preconditioner, dense closed form (test infrastructure).
+"""The BEM-coupled preconditioner, dense closed form (test infrastructure).
 
 Follows Sec. 5.2 (Green's representation with the Cauchy factor, the
 Dirichlet boundary equation for du/dn, then the interior equation) and
@@ -6,7 +6,7 @@ Sec. 5.3 (piecewise constant elements without nodes at the square's corners,
 the block matrix systems, and the analytic singular diagonal of the boundary
 matrix).
 
-Readings (paper silent or ambiguous; each listed in the design doc):
+Readings (where the paper is silent or ambiguous):
 * Sign: the representation formula with +int f G and G = (i/4) H0 holds for
   -Laplace(u) - k^2 u = f; that is the equation solved here, and the FD
   operator is -Laplace_h - k^2.

@@ -1,4 +1,4 @@
-"""O-7: right-preconditioned BiCGSTAB (test infrastructure).
+"""Right-preconditioned BiCGSTAB (test infrastructure).
 
 Follows Sec. 3, which names the Bi-Conjugate Gradient Stabilized method (van
 der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992) as the short-recurrence

@@ -1,4 +1,4 @@
-"""O-4: the 5-point finite-difference Helmholtz matrix (test infrastructure).
+"""The 5-point finite-difference Helmholtz matrix (test infrastructure).
 
 The paper's Sec. 2 states that discretising the Helmholtz problem gives a
 large sparse complex symmetric system A x = b; the discretisation used here

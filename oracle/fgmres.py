@@ -1,4 +1,4 @@
-"""O-5: right-preconditioned restarted flexible GMRES (test infrastructure).
+"""Right-preconditioned restarted flexible GMRES (test infrastructure).
 
 Follows Sec. 3 (Krylov subspaces; GMRES and its restarted form GMRES(m)) and
 Sec. 4 (right preconditioning A M^{-1} x^ = b, whose residual is the true

@@ -1,4 +1,4 @@
-"""O-2: reference 2-D Helmholtz FMM in plain numpy FP64 (test infrastructure).
+"""Reference 2-D Helmholtz FMM in plain numpy FP64 (test infrastructure).
 
 Follows Sec. 5.1.1 (hierarchical quad-tree subdivision down to the leaf
 level) and Sec. 5.1.2 (the calculation flow P2M -> M2M -> M2L -> L2L -> L2P,
@@ -19,7 +19,7 @@ all a, b,   in_n(a + b) = sum_m in_{n-m}(a) in_m(b).  From these:
     L2L  (c' -> c'') L''_l = sum_m L_m in_{m-l}(c'' - c')
     L2P  phi(x) = (i/4) sum_m L_m in_m(x - c')
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 * Tree: uniform depth L = max(2, ceil(log4(N / leaf))) over a square root box
   (smallest L with leaf * 4**L >= N); leaf <= 0 means one leaf (all pairs).
 * Order per level: p_l = p + floor(k d_l / 2), d_l the box diagonal; the index

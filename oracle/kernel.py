@@ -1,4 +1,4 @@
-"""O-1: the 2-D Helmholtz kernel and the direct N-body sum (test infrastructure).
+"""The 2-D Helmholtz kernel and the direct N-body sum (test infrastructure).
 
 Follows:
 * Sec. 5.2, 2-D free-space Green's function: G(P,Q) = (i/4) H0^(1)(k r),

@@ -1,6 +1,6 @@
-"""Writes c2_reference.npz: the direct N-body sum (oracle O-1) at sampled
+"""Writes c2_reference.npz: the direct N-body sum (oracle.kernel) at sampled
 targets of the N = 2^20, k = 100 workload, and the reference FMM's own
-relative error there for p = 4, 8, 12 (oracle O-2, leaf 64).
+relative error there for p = 4, 8, 12 (oracle.fmm, leaf 64).
 
 Calls only oracle/ and the seeded input recipe.  Run from the repository
 root:  python tests/golden/make_c2_reference.py

@@ -1,7 +1,7 @@
 """Writes c3_reference.npz: the first FMM pass of the preconditioner on the
 1024 x 1024 grid (k h = 0.3, Gaussian-bump source), as the direct N-body sum
-(oracle O-1) at 2048 seeded targets, and the reference FMM's own relative
-error there for p = 4, 6, 8 (oracle O-2, leaf 32).
+(oracle.kernel) at 2048 seeded targets, and the reference FMM's own relative
+error there for p = 4, 6, 8 (oracle.fmm, leaf 32).
 
 The pass sums the sources h^2 f at the interior nodes over the tree of
 interior nodes and boundary element midpoints (Sec. 5.3: the volume term is

@@ -1,4 +1,4 @@
-"""Pin of the adjoint gradient (O-6) against central finite differences of
+"""Pin of the adjoint gradient (oracle.adjoint) against central finite differences of
 J on the block values of k^2."""
 import numpy as np
 

@@ -1,4 +1,4 @@
-"""Pins of the dense BEM preconditioner (O-3): the self terms against
+"""Pins of the dense BEM preconditioner (oracle.bem): the self terms against
 independent quadrature, the boundary geometry, the paper's helm_fixed exact
 solution reproduced by z = M^{-1} f as h -> 0, complex symmetry of M^{-1},
 and the FMM form of the same preconditioner converging to the dense one."""

@@ -1,4 +1,4 @@
-"""Pins of the CPU BiCGSTAB (O-7): the sparse-direct solution, one iteration
+"""Pins of the CPU BiCGSTAB (oracle.bicgstab): the sparse-direct solution, one iteration
 with the exact inverse as preconditioner, a manufactured plane wave with the
 BEM preconditioner, and the zero right-hand side."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the FD matrix (O-4): discrete sine modes are exact eigenvectors
+"""Pins of the FD matrix (oracle.fd): discrete sine modes are exact eigenvectors
 with eigenvalue (4/h^2)(sin^2(m pi h/2) + sin^2(l pi h/2)) - k^2."""
 import numpy as np
 import pytest

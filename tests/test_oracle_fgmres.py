@@ -1,4 +1,4 @@
-"""Pins of the CPU FGMRES (O-5): the defining property (true relative
+"""Pins of the CPU FGMRES (oracle.fgmres): the defining property (true relative
 residual <= tol), sparse-direct solutions, a manufactured plane wave that
 solves the discrete problem exactly, a sine mode with a closed-form
 solution, flexibility, and the zero right-hand side."""

@@ -1,4 +1,4 @@
-"""Pins of the reference FMM (O-2): brute force on small N, error falling
+"""Pins of the reference FMM (oracle.fmm): brute force on small N, error falling
 with the order p down to round-off (Graf's addition theorem is exact in the
 limit), the stage identities on a two-particle chain, the tree depth rule
 and reciprocity within the FMM error."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's kernel and direct sum (O-1) against values the
+"""Pins of the oracle's kernel and direct sum (oracle.kernel) against values the
 mathematics fixes: an independent arbitrary-precision Hankel function
 (mpmath), the small-argument series (DLMF 10.8.2), the Wronskian
 (DLMF 10.5.2), reciprocity G(x, y) = G(y, x), and brute force."""
