@@ -53,7 +53,14 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
-    if (count) HFMM_HIP(hipMalloc(&p, count * sizeof(T)));
+    if (count) {
+      const hipError_t e = hipMalloc(&p, count * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        throw Error(e == hipErrorOutOfMemory ? HFMM_ERR_OOM : HFMM_ERR_HIP,
+                    "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes: " + hipGetErrorString(e));
+      }
+    }
     n = count;
   }
   void ensure(size_t count) { if (count > n) alloc(count); }
