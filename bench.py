@@ -18,6 +18,8 @@ Also reported on the same JSON line:
 * the batched solve of 16 problems x 4 right-hand sides (k in [20, 300], n in
   {128, 256, 384, 512}): matched k0 with FGMRES(200), graph vs eager, and the
   survey's settings (k0 = k, FGMRES(50), non-convergence reported);
+* the M2L with its operands rounded to FP16 / BF16 (accuracy experiment):
+  the N = 2^20 apply's error and the 1024 x 1024 solve's iterations;
 * forward + backward of the block-k^2 adjoint gradient on 256 x 256, checked
   against the CPU oracle's sparse-direct adjoint gradient;
 * the 64 x 64 solve; the paper's helm2 family (inhomogeneous Dirichlet data)
@@ -474,8 +476,50 @@ def bench_pstudy(dev, hfmm, workloads, torch):
                 out[f"{cname}_p{pp}_{pname}"] = {
                     "iters": info["iters"], "converged": info["converged"],
                     "precond_rel_err_vs_dense": float(np.linalg.norm(z - ref) / np.linalg.norm(ref))}
+                if pname == "fp32" and pp in (4, 6, 8):
+                    # M2L operands rounded to 16-bit formats (FP32 products)
+                    for rname in ("fp16", "bf16"):
+                        s.set_m2l_input_rounding(rname)
+                        z = s.precond_apply(ft).cpu().numpy()
+                        _, info = s.solve(ft, restart=30, rtol=1e-6, maxit=1000)
+                        out[f"{cname}_p{pp}_fp32_m2l_{rname}"] = {
+                            "iters": info["iters"], "converged": info["converged"],
+                            "precond_rel_err_vs_dense": float(np.linalg.norm(z - ref) / np.linalg.norm(ref))}
                 del s
         log(f"p study {cname}: " + ", ".join(f"{kk}: {v['iters']}" for kk, v in out.items() if kk.startswith(cname)))
+    return out
+
+
+def bench_m2l_rounding(dev, hfmm, workloads, torch, tree, gold, smp):
+    """The 16-bit M2L experiment at scale: the N = 2^20 apply's error on the
+    stored samples with the M2L operands rounded to FP16 / BF16 (p = 4, 8,
+    12), and the 1024 x 1024 solve (matched k0, p = 6) with each."""
+    w = workloads.fmm_c2()
+    q32 = torch.from_numpy(w["q"].astype(np.complex64)).to(dev)
+    out = {}
+    for rname in ("none", "fp16", "bf16"):
+        tree.set_m2l_input_rounding(rname)
+        for pp in (4, 8, 12):
+            phi = hfmm.hfmm_fmm_apply(tree, w["k"], pp, q32, prec=hfmm.FP32).cpu().numpy()[smp]
+            out[f"c2_p{pp}_{rname}_rel_err"] = float(np.linalg.norm(phi - gold["direct"]) /
+                                                    np.linalg.norm(gold["direct"]))
+    tree.set_m2l_input_rounding("none")
+    c3 = workloads.solve_c3()
+    n3, k3 = c3["n"], c3["k"]
+    k0 = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
+    f = torch.from_numpy(c3["f"]).to(dev)
+    s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=c3["leaf"], prec=hfmm.FP32)
+    for rname in ("none", "fp16", "bf16"):
+        s.set_m2l_input_rounding(rname)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = s.solve(f, restart=50, rtol=1e-6, maxit=600)
+        torch.cuda.synchronize()
+        out[f"solve_1024_matched_p6_{rname}"] = {"iters": info["iters"], "converged": info["converged"],
+                                                 "rel_res_true": info["rel_res_true"],
+                                                 "s": round(time.perf_counter() - t0, 4), "maxit": 600}
+    del s
+    log(f"M2L rounding: {out}")
     return out
 
 
@@ -762,6 +806,7 @@ def main():
         result["helm2_dirichlet"] = bench_helm2(dev, hfmm, torch)
         result["bicgstab_vs_fgmres"] = bench_bicgstab(dev, hfmm, torch)
         result["precond_accuracy_study"] = bench_pstudy(dev, hfmm, workloads, torch)
+        result["m2l_16bit_inputs"] = bench_m2l_rounding(dev, hfmm, workloads, torch, tree, gold, smp)
         result["hbm_kernels"] = bench_hbm(dev, hfmm, workloads, torch, xy)
 
     if not args.no_cpu:

@@ -109,6 +109,19 @@ hfmm_status hfmm_tree_destroy(hfmm_tree t);
  * Errors: values other than 0 and 1. */
 hfmm_status hfmm_tree_set_options(hfmm_tree t, int32_t m2l_valu, int32_t autotune);
 
+/* Accuracy experiment for the preconditioner-accuracy study (Sec. 6.1: a
+ * preconditioner need not be accurate): the operands of the matrix-core M2L
+ * (the translation matrices and the multipole coefficients) are rounded to
+ * FP16 (mode 1) or BF16 (mode 2), round to nearest even, before FP32
+ * products accumulated in FP32, which is what a 16-bit-input matrix-core
+ * product computes.  FP32 plans only (FP64 plans ignore it); levels whose
+ * window runs on the VALU kernel are not rounded.  For FP16 each level's
+ * table is scaled by a power of two into the format's range and the
+ * products are scaled back (exact); the multipole coefficients must fit
+ * FP16 as they are.  Mode 0 turns it off.  Cached plans are dropped.
+ * Errors: mode outside 0..2. */
+hfmm_status hfmm_tree_set_m2l_input_rounding(hfmm_tree t, int32_t mode);
+
 /* ------------------------------------------------------------------------
  * N-body sum (Sec. 5.1, the N-body sum) with the 2-D Helmholtz kernel
  * G = (i/4) H0^(1)(k r) (Sec. 5.2), evaluated by the FMM of Sec. 5.1.2:
@@ -328,6 +341,11 @@ hfmm_status hfmm_bicgstab_solve(hfmm_solver s, const double* d_b, double* d_x, i
  * ||S||_1 ||S^{-1}||_1 of the boundary matrix, the tree depth and the leaf
  * size in use (host outputs, each may be NULL). */
 hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, int32_t* levels, int32_t* leaf_size);
+
+/* hfmm_tree_set_m2l_input_rounding for the solver's FMM passes; the plan is
+ * rebuilt before returning (so a later captured solve allocates nothing).
+ * Synchronises the device.  Errors: NULL solver, mode outside 0..2. */
+hfmm_status hfmm_solver_set_m2l_input_rounding(hfmm_solver s, int32_t mode);
 
 hfmm_status hfmm_solver_destroy(hfmm_solver s);
 

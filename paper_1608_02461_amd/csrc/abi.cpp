@@ -97,6 +97,19 @@ hfmm_status hfmm_tree_set_options(hfmm_tree t, int32_t m2l_valu, int32_t autotun
   HFMM_GUARD_END
 }
 
+hfmm_status hfmm_tree_set_m2l_input_rounding(hfmm_tree t, int32_t mode) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "tree_set_m2l_input_rounding: NULL tree");
+  HFMM_REQUIRE(mode >= 0 && mode <= 2, "tree_set_m2l_input_rounding: mode must be 0, 1 or 2");
+  hfmm::Tree& tr = *t->t;
+  if (tr.side) HFMM_HIP(hipStreamSynchronize(tr.side));
+  HFMM_HIP(hipDeviceSynchronize());
+  tr.m2l_round = mode;
+  tr.plans.clear();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
 hfmm_status hfmm_fmm_apply_dipole(hfmm_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
                                   const double* d_normals, void* d_phi, int32_t nrhs, hipStream_t stream) {
   HFMM_GUARD_BEGIN
@@ -379,6 +392,24 @@ hfmm_status hfmm_solver_info(hfmm_solver s, int32_t* n_gamma, double* cond_S, in
   if (cond_S) *cond_S = s->s->condS;
   if (levels) *levels = s->s->tree->L;
   if (leaf_size) *leaf_size = s->s->leaf;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm_solver_set_m2l_input_rounding(hfmm_solver s, int32_t mode) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "solver_set_m2l_input_rounding: NULL solver");
+  HFMM_REQUIRE(mode >= 0 && mode <= 2, "solver_set_m2l_input_rounding: mode must be 0, 1 or 2");
+  hfmm::Solver& sv = *s->s;
+  hfmm::Tree& tr = *sv.tree;
+  if (tr.side) HFMM_HIP(hipStreamSynchronize(tr.side));
+  HFMM_HIP(hipDeviceSynchronize());
+  tr.m2l_round = mode;
+  tr.plans.clear();
+  if (sv.fp32)
+    (void)hfmm::get_plan<float>(tr, sv.k0, sv.p);
+  else
+    (void)hfmm::get_plan<double>(tr, sv.k0, sv.p);
   return HFMM_OK;
   HFMM_GUARD_END
 }

@@ -15,6 +15,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -319,6 +320,21 @@ __global__ void k_flags_up(const uint8_t* __restrict__ fc, uint8_t* __restrict__
 inline int blocks_for(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
 
 // ------------------------------------------------------------------ plan
+// A table entry rounded to FP16 (1) or BF16 (2), round to nearest even, and
+// back (the host side of the M2L rounding experiment).
+inline float round_host(float v, int mode) {
+  if (mode == 1) return (float)(_Float16)v;
+  if (mode == 2) {
+    uint32_t b;
+    std::memcpy(&b, &v, 4);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    b &= 0xffff0000u;
+    std::memcpy(&v, &b, 4);
+  }
+  return v;
+}
+inline double round_host(double v, int) { return v; }
+
 std::complex<double> cyl_in(int nu, const std::vector<double>& J, double th) {
   const int a = nu < 0 ? -nu : nu;
   double v = J[a];
@@ -361,6 +377,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   pl->flag_total = box0;
   // the tree's option selects the VALU downward kernels at every level (reference, ablation)
   pl->use_mfma = !t.m2l_valu;
+  pl->m2l_round = F32 ? t.m2l_round : 0;
 
   // near field: pair arguments k r are bounded by the 3 x 3 leaf block
   const double lside = t.leaf_side();
@@ -575,6 +592,24 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
         });
       }
     }
+    pl->m2l_oscale.assign(L + 1, 1.0);
+    if (pl->m2l_round) {  // accuracy experiment: 16-bit M2L matrices
+      for (int l = 2; l <= L; ++l) {
+        const MfmaLevel& m = pl->mf[l];
+        if (!(m.on || m.fit4)) continue;
+        T* A = haf.data() + m.af;
+        const size_t cnt = (size_t)49 * m.RT * m.KSA * 64;
+        double amax = 0;
+        for (size_t i = 0; i < cnt; ++i) amax = std::max(amax, std::fabs((double)A[i]));
+        // FP16: scale the level's table by a power of two into range (the
+        // kernel scales its output back); BF16 has FP32's exponent range
+        double sc = 1.0;
+        if (pl->m2l_round == 1)
+          while (amax / sc > 16384.0) sc *= 2.0;
+        for (size_t i = 0; i < cnt; ++i) A[i] = round_host(T(A[i] / sc), pl->m2l_round);
+        pl->m2l_oscale[l] = sc;
+      }
+    }
     if (haf.empty()) haf.resize(1);
     if (hwf.empty()) hwf.resize(1);
     if (hmf.empty()) hmf.resize(1);
@@ -637,6 +672,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
   const int L = t.L;
   M2LAllArgs<T> ma{};
   ma.alive = alive;
+  ma.round = pl.m2l_round;
   ma.nrhs = nrhs;
   ma.r0 = r0;
   ma.nr = NR;
@@ -669,6 +705,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
     v.tile = tile;
     v.gx = ((1 << l) / tile) * ((1 << l) / tile);
     v.block0 = blocks;
+    v.oscale = T(pl.m2l_oscale.empty() ? 1.0 : pl.m2l_oscale[l]);
     blocks += v.gx * mf.RT;
     lds = std::max(lds, small ? mf.lds4 : mf.lds);
   }

@@ -52,6 +52,7 @@ struct M2LLevel {
   // stride, zero beyond KS); KSL: k steps per LDS slice (all KS, or a
   // multiple of 4)
   int nb, P, RT, KS, KSA, KSL, tile, gx, block0;
+  T oscale;  // output scale (a power of two: the FP16 rounding experiment scales the level's table down)
 };
 
 template <class T>
@@ -60,7 +61,22 @@ struct M2LAllArgs {
   int nlev;
   const int* alive;
   int nrhs, r0, nr;
+  int round;  // multipole operands rounded to FP16 (1) or BF16 (2) when staged; 0: none
 };
+
+// An M2L operand rounded to FP16 or BF16 (round to nearest even) and back:
+// the products then see the inputs a matrix-core product with 16-bit
+// operands would see, accumulated in FP32.
+__device__ __forceinline__ float round_in(float v, int mode) {
+  if (mode == 1) return (float)(_Float16)v;
+  if (mode == 2) {
+    uint32_t b = __float_as_uint(v);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return __uint_as_float(b & 0xffff0000u);
+  }
+  return v;
+}
+__device__ __forceinline__ double round_in(double v, int) { return v; }
 
 // M2L of every level in one launch (the levels are independent; L2L runs
 // afterwards, top down).  One block = a tile x tile patch of target boxes
@@ -158,7 +174,8 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
             for (int u = 0; u < 4; ++u)
               if (lb[u] >= 0) {
                 T* row = Ms + (size_t)lb[u] * KPs - lo;
-                const T re = f[u] ? v[u].x : T(0), im = f[u] ? v[u].y : T(0);
+                const T re = f[u] ? round_in(v[u].x, args.round) : T(0);
+                const T im = f[u] ? round_in(v[u].y, args.round) : T(0);
                 if (m >= lo && m < hi) row[m] = re;
                 if (m + P >= lo && m + P < hi) row[m + P] = im;
               }
@@ -244,7 +261,7 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
           for (int p = 1; p < NP; ++p)
             if (w == p) tb = tbox[p];
           T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tb * args.nrhs + args.r0 + r) * P + (i < P ? i : i - P));
-          dst[i < P ? 0 : 1] = s;
+          dst[i < P ? 0 : 1] = s * a.oscale;
         }
       }
     }
@@ -355,7 +372,8 @@ __device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M
             for (int u = 0; u < 4; ++u)
               if (lb[u] >= 0) {
                 T* row = Ms + (size_t)lb[u] * KPs - lo;
-                const T re = f[u] ? v[u].x : T(0), im = f[u] ? v[u].y : T(0);
+                const T re = f[u] ? round_in(v[u].x, args.round) : T(0);
+                const T im = f[u] ? round_in(v[u].y, args.round) : T(0);
                 if (m >= lo && m < hi) row[m] = re;
                 if (m + P >= lo && m + P < hi) row[m + P] = im;
               }
@@ -479,7 +497,7 @@ __device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M
           for (int p = 1; p < NP; ++p)
             if (w == p) tb = tbox[p];
           T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tb * args.nrhs + args.r0 + r) * P + (i < P ? i : i - P));
-          dst[i < P ? 0 : 1] = s;
+          dst[i < P ? 0 : 1] = s * a.oscale;
         }
       }
     }

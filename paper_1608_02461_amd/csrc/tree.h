@@ -40,6 +40,9 @@ struct Tree {
   // the autotuner times launch shapes (else defaults; the cache still applies)
   bool m2l_valu = false;
   bool autotune = true;
+  // accuracy experiment: the M2L's operands rounded to FP16 (1) or BF16 (2)
+  // before the FP32 matrix-core products (FP32 plans only; 0: none)
+  int m2l_round = 0;
 
   Tree() = default;
   Tree(const Tree&) = delete;

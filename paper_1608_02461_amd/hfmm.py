@@ -79,6 +79,8 @@ _SIGS = {
     "hfmm_fgmres_solve": ([_vp, _vp, _vp, _i32, _i32, _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
     "hfmm_fgmres_solve_batched": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _i32,
                                    _f64, _i32, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "hfmm_tree_set_m2l_input_rounding": ([_vp, _i32], _i32),
+    "hfmm_solver_set_m2l_input_rounding": ([_vp, _i32], _i32),
     "hfmm_solver_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
                          _i32),
     "hfmm_solver_destroy": ([_vp], _i32),
@@ -162,6 +164,10 @@ class Tree:
     def set_options(self, m2l_valu=False, autotune=True):
         """Options of the plans made from now on (cached plans are dropped)."""
         _check(lib().hfmm_tree_set_options(self.handle, int(m2l_valu), int(autotune)))
+
+    def set_m2l_input_rounding(self, mode="none"):
+        """Accuracy experiment: M2L operands rounded to "fp16" or "bf16" ("none": off)."""
+        _check(lib().hfmm_tree_set_m2l_input_rounding(self.handle, ROUNDING[mode]))
 
     def export(self, stream=None):
         inf = self.info()
@@ -258,6 +264,9 @@ def hfmm_fmm_apply_noalloc(tree, k, p, q, prec=FP64, phi=None, stream=None):
 def hfmm_fmm_noalloc_capacity():
     return lib().hfmm_fmm_noalloc_capacity()
 
+
+# modes of the M2L input-rounding experiment
+ROUNDING = {"none": 0, "fp16": 1, "bf16": 2}
 
 # stage names of hfmm_fmm_apply_timed (the order of its ms_stages); on a tree
 # of depth >= 2 "far_chain" (M2M + M2L + L2L + L2P) runs on the tree's second
@@ -375,6 +384,10 @@ class Solver:
         _check(lib().hfmm_solver_info(self.handle, ctypes.byref(ng), ctypes.byref(cond), ctypes.byref(L),
                                       ctypes.byref(leaf)))
         return {"n_gamma": ng.value, "cond_S": cond.value, "levels": L.value, "leaf_size": leaf.value}
+
+    def set_m2l_input_rounding(self, mode="none"):
+        """Accuracy experiment: M2L operands rounded to "fp16" or "bf16" ("none": off)."""
+        _check(lib().hfmm_solver_set_m2l_input_rounding(self.handle, ROUNDING[mode]))
 
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:

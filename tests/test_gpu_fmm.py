@@ -167,3 +167,33 @@ def test_mfma_downward_matches_valu(N, leaf, k, p):
                      to_np(hfmm.hfmm_fmm_apply(t, k, p, to_dev(q.astype(np.complex64)), prec=hfmm.FP32)))
     assert rel(out["mfma"][0], out["valu"][0]) <= 1e-12
     assert rel(out["mfma"][1], out["valu"][1]) <= 3e-6
+
+
+@pytest.mark.parametrize("mode,bound", [("fp16", 2e-3), ("bf16", 2e-2)])
+def test_m2l_input_rounding(mode, bound):
+    """Accuracy experiment: the M2L operands rounded to FP16 / BF16.  The
+    error against the oracle FMM grows above the FP32 path's but stays
+    within a few units of the format's rounding (2^-11, 2^-8) relative to
+    the whole field; FP64 plans ignore the option, and turning it off
+    restores the FP32 result bit for bit."""
+    say(f"m2l rounding {mode}")
+    N, leaf, k, p = 4356, 32, 16.0, 6
+    xy, q = workloads.random_cloud(N, seed=91)
+    q = q[:, 0]
+    ref_fmm = ofmm.fmm(xy, q, k, p, leaf)
+    t = hfmm.Tree(to_dev(xy), leaf_size=leaf)
+    q32, q64 = to_dev(q.astype(np.complex64)), to_dev(q)
+    base32 = to_np(hfmm.hfmm_fmm_apply(t, k, p, q32, prec=hfmm.FP32))
+    base64 = to_np(hfmm.hfmm_fmm_apply(t, k, p, q64, prec=hfmm.FP64))
+    t.set_m2l_input_rounding(mode)
+    r32 = to_np(hfmm.hfmm_fmm_apply(t, k, p, q32, prec=hfmm.FP32))
+    r64 = to_np(hfmm.hfmm_fmm_apply(t, k, p, q64, prec=hfmm.FP64))
+    e0, e1 = rel(base32, ref_fmm), rel(r32, ref_fmm)
+    say(f"  fp32 {e0:.3e}  rounded {e1:.3e}")
+    assert e1 > 2 * e0
+    assert e1 <= bound
+    assert np.array_equal(r64, base64)
+    t.set_m2l_input_rounding("none")
+    assert np.array_equal(to_np(hfmm.hfmm_fmm_apply(t, k, p, q32, prec=hfmm.FP32)), base32)
+    with pytest.raises(hfmm.HFMMError):
+        hfmm._check(hfmm.lib().hfmm_tree_set_m2l_input_rounding(t.handle, 3))

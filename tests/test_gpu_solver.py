@@ -228,3 +228,17 @@ def test_leaf_size_autotune():
     A = fd.matrix(n, k * k)
     assert info["converged"] == 1
     assert np.linalg.norm(w["f"] - A @ to_np(x)) <= 1e-6 * np.linalg.norm(w["f"])
+
+
+def test_solve_with_bf16_m2l_converges():
+    """The preconditioner with its M2L operands rounded to BF16 still takes
+    the 64 x 64 solve to the true residual 1e-6 (Sec. 6.1: the
+    preconditioner need not be accurate)."""
+    w = workloads.solve_c1()
+    s = hfmm.Solver(w["n"], w["k"], p=w["p"], leaf_size=w["leaf"], prec=hfmm.FP32)
+    _, base = s.solve(to_dev(w["f"]), restart=w["restart"], rtol=w["rtol"])
+    s.set_m2l_input_rounding("bf16")
+    _, info = s.solve(to_dev(w["f"]), restart=w["restart"], rtol=w["rtol"])
+    say(f"  iterations fp32 {base['iters']} bf16 {info['iters']}")
+    assert info["converged"] == 1 and info["rel_res_true"] <= 1e-6
+    assert info["iters"] <= base["iters"] + 5
