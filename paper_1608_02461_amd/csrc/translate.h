@@ -97,6 +97,42 @@ __device__ __forceinline__ double round_in(double v, int) { return v; }
 // near-field blocks leave free on a CU and the chain runs beside them
 constexpr int kM2LThreads = 256;
 
+// With source flags (a pass whose sources sit in few boxes, such as the
+// boundary pass of the preconditioner): true, uniformly over the block, when
+// no box of the block's source window holds a source.
+template <class T>
+__device__ __forceinline__ bool m2l_window_empty(const M2LLevel<T>& a, int wx0, int wy0, int WW, int zb) {
+  bool any = false;
+  for (int b = threadIdx.x; b < zb && !any; b += kM2LThreads) {
+    const int by = b / WW, bx = b - by * WW;
+    any = a.fsrc[morton((uint32_t)(wx0 + bx), (uint32_t)(wy0 + by))] != 0;
+  }
+  return !__syncthreads_or(any);
+}
+
+// The block's local expansions when its window holds no source: zeros, in
+// the rows and boxes the products would have written.
+template <class T, int NP>
+__device__ __forceinline__ void m2l_write_zero(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int rt, int w,
+                                               int lane, const uint32_t (&tbox)[NP]) {
+  if (w >= NP) return;
+  const int kq = lane >> 4, P = a.P;
+  uint32_t tb = tbox[0];
+#pragma unroll
+  for (int p = 1; p < NP; ++p)
+    if (w == p) tb = tbox[p];
+  for (int r = 0; r < args.nr; ++r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = rt * 16 + out_row<T>(kq, q);
+      if (i < 2 * P) {
+        T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tb * args.nrhs + args.r0 + r) * P + (i < P ? i : i - P));
+        dst[i < P ? 0 : 1] = T(0);
+      }
+    }
+  }
+}
+
 template <class T, int NP>
 __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int lblock, T* Ms) {
   typedef typename Acc4<T>::type V4;
@@ -119,6 +155,10 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
     tx[p] = bx0 + (p & 1) * 4 + (j & 3);
     ty[p] = by0 + (p >> 1) * 4 + (j >> 2);
     tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
+  }
+  if (a.fsrc && m2l_window_empty<T>(a, wx0, wy0, WW, zb)) {
+    m2l_write_zero<T, NP>(args, a, rt, w, lane, tbox);
+    return;
   }
   const size_t cstride = (size_t)a.RT * a.KSA * 64;
   const T* Abase = a.Af + (size_t)rt * a.KSA * 64 + lane;
@@ -315,6 +355,10 @@ __device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M
     tx[p] = bx0 + 2 * (j & 3) + (p & 1);
     ty[p] = by0 + 2 * (j >> 2) + (p >> 1);
     tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
+  }
+  if (a.fsrc && m2l_window_empty<T>(a, wx0, wy0, WW, zb)) {
+    m2l_write_zero<T, NP>(args, a, rt, w, lane, tbox);
+    return;
   }
   const size_t cstride = (size_t)a.RT * a.KSA * 64;
   const T* Abase = a.Af + (size_t)rt * a.KSA * 64 + lane;
