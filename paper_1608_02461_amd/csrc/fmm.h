@@ -50,6 +50,10 @@ struct FmmPlan : PlanBase {
   std::vector<int64_t> m2m_off, l2l_off, m2l_off;
   std::vector<MfmaLevel> mf;   // per level
   DevBuf<T> afrag, wfrag, mfrag;  // per-lane MFMA fragments of the M2L / L2L / M2M matrices
+  // M2L levels split into class groups: partial sums (for 4 columns) and the
+  // per-tile counters of their last-block reduction (zero between launches)
+  DevBuf<T> m2l_part;
+  DevBuf<unsigned> m2l_cnt;
   int K = 0;
   // near field
   bool near_fast = false;

@@ -349,6 +349,46 @@ std::complex<double> cyl_out(int nu, const std::vector<std::complex<double>>& H,
   return v * std::exp(std::complex<double>(0, nu * th));
 }
 
+// Launch shape of the MFMA M2L at level l: the 8 x 8 target tile, or the
+// 4 x 4 one (on request, or where the 8 x 8 window does not fit in LDS).
+// A level of few blocks whose waves each walk a long chain of dependent
+// table loads (10 offset classes of ceil(KS / 4) MFMA chunks) splits its 40
+// classes over S = 2, 5 or 10 blocks per target tile and row tile, so that
+// more waves share the level and each walks 10 / S classes; the partial sums
+// meet in a last-block reduction.
+struct M2LShape {
+  bool use = false;
+  int tile = 0, KSL = 0, gx = 0, NP = 1, S = 1;
+  size_t lds = 0;
+};
+M2LShape m2l_shape(const MfmaLevel& mf, int l, bool small_pref) {
+  M2LShape s;
+  const bool small = (small_pref && mf.fit4) || !mf.on;
+  s.use = small ? mf.fit4 : mf.on;
+  if (!s.use) return s;
+  const int nb = 1 << l;
+  s.tile = small ? std::min(4, nb) : mf.tile;
+  s.KSL = small ? mf.KSL4 : mf.KSL;
+  s.lds = small ? mf.lds4 : mf.lds;
+  s.gx = (nb / s.tile) * (nb / s.tile);
+  s.NP = s.tile == 8 ? 4 : 1;
+  int nch = 0;  // MFMA chunks of one class
+  for (int k0 = 0; k0 < mf.KS; k0 += s.KSL) nch += (std::min(s.KSL, mf.KS - k0) + 3) / 4;
+  if (s.gx * mf.RT < kM2LSplitBlocks && 10 * nch > kM2LChain) {
+    s.S = 10;
+    for (int S : {2, 5})
+      if (10 * nch / S <= kM2LChain) {
+        s.S = S;
+        break;
+      }
+  }
+  return s;
+}
+// partial-sum elements of one launch with NR columns
+inline size_t m2l_part_elems(const M2LShape& s, const MfmaLevel& mf, int nr) {
+  return s.S > 1 ? (size_t)nr * s.gx * mf.RT * s.S * s.NP * 256 : 0;
+}
+
 template <class T>
 std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
   constexpr bool F32 = std::is_same<T, float>::value;
@@ -616,6 +656,21 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
     pl->afrag.upload(haf);
     pl->wfrag.upload(hwf);
     pl->mfrag.upload(hmf);
+    // class-group storage for either tile choice, up to 4 columns
+    size_t part = 1, cnt = 1;
+    for (int sm = 0; sm < 2; ++sm) {
+      size_t pp = 0, cc = 0;
+      for (int l = 2; l <= L; ++l) {
+        const M2LShape s = m2l_shape(pl->mf[l], l, sm == 1);
+        if (!s.use || s.S == 1) continue;
+        pp += m2l_part_elems(s, pl->mf[l], 4);
+        cc += (size_t)s.gx * pl->mf[l].RT;
+      }
+      part = std::max(part, pp);
+      cnt = std::max(cnt, cc);
+    }
+    pl->m2l_part.alloc(part);
+    pl->m2l_cnt.upload(std::vector<unsigned>(cnt, 0u));
   }
   return pl;
 }
@@ -677,20 +732,18 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
   ma.r0 = r0;
   ma.nr = NR;
   int blocks = 0;
-  size_t lds = 0;
+  size_t lds = 0, part = 0, cnt = 0;
   for (int l = 2; l <= L; ++l) {
     const LevelInfo& li = pl.lv[l];
     const MfmaLevel& mf = pl.mf[l];
-    const bool small = (pl.m2l_small && mf.fit4) || !mf.on;
-    const bool use = small ? mf.fit4 : mf.on;
-    if (!use) {
+    const M2LShape s = m2l_shape(mf, l, pl.m2l_small);
+    if (!s.use) {
       k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs, nullptr,
                                                  pl.m2l.p + pl.m2l_off[l], nullptr, li.P, 1, l, nrhs, r0,
                                                  flags ? flags + li.box0 : nullptr, alive);
       HFMM_LAUNCH_CHECK();
       continue;
     }
-    const int tile = small ? std::min(4, 1 << l) : mf.tile;
     M2LLevel<T>& v = ma.lv[ma.nlev++];
     v.M = M + li.coef * nrhs;
     v.Lc = Lc + li.coef * nrhs;
@@ -700,15 +753,25 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
     v.P = li.P;
     v.RT = mf.RT;
     v.KS = mf.KS;
-    v.KSL = small ? mf.KSL4 : mf.KSL;
+    v.KSL = s.KSL;
     v.KSA = mf.KSA;
-    v.tile = tile;
-    v.gx = ((1 << l) / tile) * ((1 << l) / tile);
+    v.tile = s.tile;
+    v.gx = s.gx;
     v.block0 = blocks;
     v.oscale = T(pl.m2l_oscale.empty() ? 1.0 : pl.m2l_oscale[l]);
-    blocks += v.gx * mf.RT;
-    lds = std::max(lds, small ? mf.lds4 : mf.lds);
+    v.S = s.S;
+    v.part = nullptr;
+    v.cnt = nullptr;
+    if (s.S > 1) {
+      v.part = pl.m2l_part.p + part;
+      v.cnt = pl.m2l_cnt.p + cnt;
+      part += m2l_part_elems(s, mf, NR);
+      cnt += (size_t)s.gx * mf.RT;
+    }
+    blocks += v.gx * mf.RT * s.S;
+    lds = std::max(lds, s.lds);
   }
+  HFMM_REQUIRE(part <= pl.m2l_part.n && cnt <= pl.m2l_cnt.n, "fmm: internal: M2L class-group storage too small");
   if (ma.nlev) {
     k_m2l_mfma<T><<<blocks, kM2LThreads, lds, st>>>(ma);
     HFMM_LAUNCH_CHECK();

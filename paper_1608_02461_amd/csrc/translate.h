@@ -53,6 +53,13 @@ struct M2LLevel {
   // multiple of 4)
   int nb, P, RT, KS, KSA, KSL, tile, gx, block0;
   T oscale;  // output scale (a power of two: the FP16 rounding experiment scales the level's table down)
+  // class groups: S > 1 splits the 40 offset classes over S blocks per
+  // target tile and row tile; their partial sums go to `part`
+  // ([nr][gx RT][S][NP][4][64]) and the last of the S blocks (counter
+  // `cnt`, one per target tile and row tile, left at zero) adds them up
+  int S;
+  T* part;
+  unsigned* cnt;
 };
 
 template <class T>
@@ -133,6 +140,55 @@ __device__ __forceinline__ void m2l_write_zero(const M2LAllArgs<T>& args, const 
   }
 }
 
+// Class groups: the block has stored its partial sums (agent-scope stores,
+// written through to the device-coherent level); once they are complete the
+// block counts itself in, and the last of the S blocks of its target tile
+// and row tile adds the S partial sums in group order (agent-scope loads),
+// writes the local expansions and resets the counter for the next launch.
+// No device-scope fence: on this GPU one writes back and invalidates the
+// whole L2 of the XCD, which costs the other blocks their cached tables.
+template <class T>
+__device__ __forceinline__ void part_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T part_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T, int NP>
+__device__ __forceinline__ void m2l_groups_sum(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int grp, int ngrp,
+                                               int rt, int w, int lane, const uint32_t (&tbox)[NP], T* Ms) {
+  int* last = reinterpret_cast<int*>(Ms);
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's partial-sum stores are complete
+  __syncthreads();                // (and every wave is done with the LDS)
+  if (threadIdx.x == 0)
+    last[0] = __hip_atomic_fetch_add(a.cnt + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+              (unsigned)(a.S - 1);
+  __syncthreads();
+  if (!last[0]) return;
+  if (w < NP) {
+    const int kq = lane >> 4, P = a.P;
+    uint32_t tb = tbox[0];
+#pragma unroll
+    for (int p = 1; p < NP; ++p)
+      if (w == p) tb = tbox[p];
+    for (int r = 0; r < args.nr; ++r) {
+      const T* src = a.part + ((size_t)r * ngrp + grp) * a.S * (NP * 256) + w * 256 + lane;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T s = T(0);
+        for (int g = 0; g < a.S; ++g) s += part_load(src + (size_t)g * (NP * 256) + q * 64);
+        const int i = rt * 16 + out_row<T>(kq, q);
+        if (i < 2 * P) {
+          T* dst = reinterpret_cast<T*>(a.Lc + ((size_t)tb * args.nrhs + args.r0 + r) * P + (i < P ? i : i - P));
+          dst[i < P ? 0 : 1] = s * a.oscale;
+        }
+      }
+    }
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(a.cnt + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class T, int NP>
 __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLevel<T>& a, int lblock, T* Ms) {
   typedef typename Acc4<T>::type V4;
@@ -140,7 +196,8 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nbt = a.nb / a.tile;
-  const int pb = lblock % a.gx, rt = lblock / a.gx;
+  const int ngrp = a.gx * a.RT, grp = lblock % ngrp, sg = lblock / ngrp;  // tile group, class group
+  const int pb = grp % a.gx, rt = grp / a.gx;
   const int bx0 = (pb % nbt) * a.tile, by0 = (pb / nbt) * a.tile;
   const int wx0 = max(0, bx0 - 2), wy0 = max(0, by0 - 2);
   const int WW = min(a.nb, bx0 + a.tile + 2) - wx0, WH = min(a.nb, by0 + a.tile + 2) - wy0;
@@ -156,8 +213,8 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
     ty[p] = by0 + (p >> 1) * 4 + (j >> 2);
     tbox[p] = morton((uint32_t)tx[p], (uint32_t)ty[p]);
   }
-  if (a.fsrc && m2l_window_empty<T>(a, wx0, wy0, WW, zb)) {
-    m2l_write_zero<T, NP>(args, a, rt, w, lane, tbox);
+  if (a.fsrc && m2l_window_empty<T>(a, wx0, wy0, WW, zb)) {  // the same for every class group
+    if (sg == 0) m2l_write_zero<T, NP>(args, a, rt, w, lane, tbox);
     return;
   }
   const size_t cstride = (size_t)a.RT * a.KSA * 64;
@@ -236,11 +293,14 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
         for (int n = lane; n < KPs; n += 64) Ms[zb * KPs + n] = T(0);
       __syncthreads();
       const T* Ab = Abase + (size_t)k0 * 64;  // this slice's k steps
-      // the wave's 10 offset classes (class index = wave mod 4) one after
-      // another; the A fragments of the next chunk, also across classes,
-      // load one chunk ahead.  The last chunk of a slice may have fewer than
-      // 4 k steps (ns).
-      auto cls = [&](int i) { return kClassO[8 * (i % 5) + w + 4 * (i / 5)]; };
+      // the wave's 10 / S offset classes (class index = wave mod 4, within
+      // the block's class group) one after another; the A fragments of the
+      // next chunk, also across classes, load one chunk ahead.  The last
+      // chunk of a slice may have fewer than 4 k steps (ns).
+      const int ncw = 10 / a.S;
+      auto cls = [&](int i) {
+        return a.S == 1 ? kClassO[8 * (i % 5) + w + 4 * (i / 5)] : kClassO[sg * 4 * ncw + w + 4 * i];
+      };
       const int nst = min(KSL, KS - k0);
       const int nch = (nst + 3) >> 2;
       T an[4];
@@ -250,13 +310,13 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
         for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
       }
 #pragma unroll 1
-      for (int oi = 0; oi < 10; ++oi) {
+      for (int oi = 0; oi < ncw; ++oi) {
         const int o = cls(oi);
         int base[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
         const T* A = Ab + (size_t)o * cstride;
-        const T* An = oi + 1 < 10 ? Ab + (size_t)cls(oi + 1) * cstride : A;
+        const T* An = oi + 1 < ncw ? Ab + (size_t)cls(oi + 1) * cstride : A;
         for (int c = 0; c < nch; ++c) {
           T av[4];
 #pragma unroll
@@ -264,7 +324,7 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
           if (c + 1 < nch) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
-          } else if (oi + 1 < 10) {
+          } else if (oi + 1 < ncw) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
           }
@@ -294,6 +354,10 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
       for (int q = 0; q < 4; ++q) {
         const T s = red[((0 * NP + w) * 4 + q) * 64 + lane] + red[((1 * NP + w) * 4 + q) * 64 + lane] +
                     red[((2 * NP + w) * 4 + q) * 64 + lane] + red[((3 * NP + w) * 4 + q) * 64 + lane];
+        if (a.S > 1) {
+          part_store(a.part + (((size_t)r * ngrp + grp) * a.S + sg) * (NP * 256) + (w * 4 + q) * 64 + lane, s);
+          continue;
+        }
         const int i = rt * 16 + out_row<T>(kq, q);
         if (i < 2 * P) {
           uint32_t tb = tbox[0];
@@ -306,6 +370,7 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
       }
     }
   }
+  if (a.S > 1) m2l_groups_sum<T, NP>(args, a, grp, ngrp, rt, w, lane, tbox, Ms);
 }
 
 // M2L offset classes, o = (ox + 3) * 7 + (oy + 3), by target parity: a
@@ -566,8 +631,10 @@ void k_m2l_mfma(M2LAllArgs<T> args) {
   for (int i = 1; i < kMaxLev; ++i)
     if (i < args.nlev && (int)blockIdx.x >= args.lv[i].block0) a = args.lv[i];
   const int lblock = (int)blockIdx.x - a.block0;
-  if (a.tile == 8)
+  if (a.tile == 8 && a.S == 1)
     m2l_block_par<T>(args, a, lblock, Ms);
+  else if (a.tile == 8)
+    m2l_block<T, 4>(args, a, lblock, Ms);
   else
     m2l_block<T, 1>(args, a, lblock, Ms);
 }
@@ -597,6 +664,10 @@ constexpr int kTTChunk = 16;
 // levels): small enough that a block fits beside the four near-field blocks
 // a CU holds, so that the far-field chain progresses while the near field runs
 constexpr size_t kM2LLds = 32 * 1024;
+// Class groups: a level of fewer than kM2LSplitBlocks blocks whose waves
+// would each walk more than kM2LChain dependent MFMA chunks is split
+constexpr int kM2LSplitBlocks = 128;
+constexpr int kM2LChain = 20;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_tt_mfma(TTArgs<T> a) {

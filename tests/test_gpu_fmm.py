@@ -116,6 +116,20 @@ def test_deterministic_repeat():
     assert np.array_equal(a, b)
 
 
+def test_timed_apply_matches_apply():
+    """The traced apply gives the plain apply's result bit for bit (on a tree
+    of 2^18 points or more, where the far-field chain runs on a second stream)."""
+    xy, q = workloads.random_cloud(300000, seed=3)
+    t = hfmm.Tree(to_dev(xy), leaf_size=32)
+    assert t.info()["levels"] >= 3
+    qd = to_dev(q[:, 0].astype(np.complex64))
+    a = to_np(hfmm.hfmm_fmm_apply(t, 60.0, 6, qd, prec=hfmm.FP32))
+    b, ms = hfmm.hfmm_fmm_apply_timed(t, 60.0, 6, qd, prec=hfmm.FP32)
+    assert np.array_equal(a, to_np(b))
+    assert set(ms) == set(hfmm.STAGES)
+    assert ms["m2l"] > 0 and ms["m2m"] > 0 and ms["p2p"] > 0
+
+
 def test_invalid_arguments():
     xy, q = workloads.random_cloud(100, seed=1)
     with pytest.raises(hfmm.HFMMError) as e:
