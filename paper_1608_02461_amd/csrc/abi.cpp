@@ -404,6 +404,7 @@ hfmm_status hfmm_solver_set_m2l_input_rounding(hfmm_solver s, int32_t mode) {
   hfmm::Tree& tr = *sv.tree;
   if (tr.side) HFMM_HIP(hipStreamSynchronize(tr.side));
   HFMM_HIP(hipDeviceSynchronize());
+  sv.drop_step_graph();
   tr.m2l_round = mode;
   tr.plans.clear();
   if (sv.fp32)

@@ -38,6 +38,14 @@ struct Solver {
   DevBuf<double> cs, bnorm, est, rn, npart;
   DevBuf<int> active, jj, iters, state;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  // one Arnoldi step captured into a graph (batched solve with graphs), kept
+  // from one solve to the next while restart, maxit and rtol are the same;
+  // every change to the solver drops it
+  hipGraph_t step_graph = nullptr;
+  hipGraphExec_t step_exec = nullptr;
+  int step_m = 0, step_maxit = 0;
+  double step_rtol = 0;
+  void drop_step_graph();
   double ms_setup = 0;             // wall time of solver_create (ms)
   std::vector<std::pair<int, float>> leaf_ms;  // leaf-size candidates timed (leaf_size 0)
   // outward unit normals of the boundary elements at their sorted slots

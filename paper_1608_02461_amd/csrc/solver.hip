@@ -1074,7 +1074,15 @@ void setup_precision(Solver& s, const double2* A, int64_t ld, const double2* nrm
 
 }  // namespace
 
+void Solver::drop_step_graph() {
+  if (step_exec) (void)hipGraphExecDestroy(step_exec);
+  if (step_graph) (void)hipGraphDestroy(step_graph);
+  step_exec = nullptr;
+  step_graph = nullptr;
+}
+
 Solver::~Solver() {
+  drop_step_graph();
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (ev2) (void)hipEventDestroy(ev2);
@@ -1294,6 +1302,7 @@ std::unique_ptr<Solver> solver_create(int n, double h, const double* d_k2, doubl
 }
 
 void solver_set_k2(Solver& s, const double* d_k2, double k2c, hipStream_t st) {
+  s.drop_step_graph();
   if (d_k2) {
     s.k2.ensure(s.nn);
     HFMM_HIP(hipMemcpyAsync(s.k2.p, d_k2, s.nn * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1325,6 +1334,7 @@ void dirichlet_apply(Solver& s, const double2* f, const double2* g, double2* u, 
 void solver_set_k2_blocks(Solver& s, const double* kb, int nb, hipStream_t st) {
   HFMM_REQUIRE(kb != nullptr, "set_k2_blocks: NULL array");
   HFMM_REQUIRE(nb >= 1 && nb <= s.n && s.n % nb == 0, "set_k2_blocks: nb must divide n");
+  s.drop_step_graph();
   s.k2.ensure(s.nn);
   k_k2_blocks<<<nblocks(s.nn), 256, 0, st>>>(kb, nb, s.n, s.k2.p);
   HFMM_LAUNCH_CHECK();
@@ -1347,6 +1357,7 @@ void ensure_krylov(Solver& s, int m, hipStream_t st) {
   const int nr = s.nrhs;
   const int64_t nn = s.nn;
   if (m != s.m) {
+    s.drop_step_graph();
     s.m = m;
     s.V.alloc((size_t)nr * (m + 1) * nn);
     s.Z.alloc((size_t)nr * m * nn);
@@ -1467,21 +1478,17 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
   // Several problems: each runs its Arnoldi steps on a stream of its own,
   // forked from and joined to `st`, so that their kernels overlap on the
   // device.  With use_graph, one Arnoldi step of each problem is captured
-  // once per solve into a graph of its own (the capture's origin is the
-  // problem's stream, from which the FMM forks its far-field chain onto the
-  // tree's side stream) and replayed; the step reads j and its flags from
-  // device memory, so the same graph serves every step and every cycle.
+  // into a graph of its own (the capture's origin is the problem's stream,
+  // from which the FMM forks its far-field chain onto the tree's side
+  // stream) and replayed; the step reads j and its flags from device
+  // memory, so the same graph serves every step and every cycle, and the
+  // solver keeps it for the next solve with the same restart, maxit and
+  // rtol.
   const bool multi = nprob > 1;
   std::vector<hipStream_t> pst(nprob, st);
   std::vector<hipEvent_t> join_ev;
   hipEvent_t fork_ev = nullptr;
-  std::vector<hipGraph_t> graph(nprob, nullptr);
-  std::vector<hipGraphExec_t> gexec(nprob, nullptr);
   auto drop_all = [&]() {
-    for (auto& g : gexec)
-      if (g) (void)hipGraphExecDestroy(g);
-    for (auto& g : graph)
-      if (g) (void)hipGraphDestroy(g);
     if (multi) {
       for (hipStream_t q : pst) {
         (void)hipStreamSynchronize(q);
@@ -1510,10 +1517,23 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
     }
     if (use_graph) {
       for (int q = 0; q < nprob; ++q) {
+        Solver& s = *S[q];
+        if (s.step_exec && s.step_m == m && s.step_maxit == maxit && s.step_rtol == rtol) continue;
+        s.drop_step_graph();
         HFMM_HIP(hipStreamBeginCapture(pst[q], hipStreamCaptureModeThreadLocal));
-        arnoldi_step(*S[q], maxit, rtol, pst[q]);
-        HFMM_HIP(hipStreamEndCapture(pst[q], &graph[q]));
-        HFMM_HIP(hipGraphInstantiate(&gexec[q], graph[q], nullptr, nullptr, 0));
+        try {
+          arnoldi_step(s, maxit, rtol, pst[q]);
+        } catch (...) {  // close the capture before the error leaves
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(pst[q], &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HFMM_HIP(hipStreamEndCapture(pst[q], &s.step_graph));
+        HFMM_HIP(hipGraphInstantiate(&s.step_exec, s.step_graph, nullptr, nullptr, 0));
+        s.step_m = m;
+        s.step_maxit = maxit;
+        s.step_rtol = rtol;
       }
     }
     for (;;) {
@@ -1577,7 +1597,7 @@ hfmm_status fgmres(Solver** S, int nprob, const double2* const* b, double2* cons
           if (multi) HFMM_HIP(hipStreamWaitEvent(pst[q], fork_ev, 0));
           for (int u = 0; u < chunk; ++u) {
             if (use_graph)
-              HFMM_HIP(hipGraphLaunch(gexec[q], pst[q]));
+              HFMM_HIP(hipGraphLaunch(S[q]->step_exec, pst[q]));
             else
               arnoldi_step(*S[q], maxit, rtol, pst[q], timed ? S[q]->ev1 : nullptr);
           }

@@ -216,6 +216,34 @@ def test_first_graph_solve_equals_eager():
         assert np.array_equal(to_np(a), to_np(b))
 
 
+def test_graph_kept_across_solves_and_dropped_on_change():
+    """The captured Arnoldi step is kept from one batched solve to the next
+    (same restart, maxit, rtol) and captured again after a new restart or a
+    change of k^2: every graph solve equals the eager one bit for bit."""
+    probs = [(96, 40.0), (64, 30.0)]
+    solvers = [hfmm.Solver(n, hfmm.hfmm_matched_wavenumber(k, 1 / (n + 1)), k2_const=k * k, p=6, leaf_size=32,
+                           prec=hfmm.FP32, nrhs=2) for n, k in probs]
+    rng = np.random.default_rng(120)
+
+    def rhs():
+        return [to_dev(workloads.complex_normal(rng, (n * n, 2))) for n, _ in probs]
+
+    def check(bs, restart):
+        xg, ig = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=1e-6, use_graph=True)
+        xe, ie = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=1e-6, use_graph=False)
+        for a, b, p, q in zip(xg, xe, ig, ie):
+            assert p["converged"] == 1 and p["iters"] == q["iters"]
+            assert np.array_equal(to_np(a), to_np(b))
+
+    check(rhs(), 60)
+    bs = rhs()
+    check(bs, 60)  # the kept graphs
+    check(bs, 40)  # captured again: new restart
+    for s, (n, k) in zip(solvers, probs):
+        s.set_k2(k2_const=(1.05 * k) ** 2)
+    check(bs, 40)  # captured again: new k^2
+
+
 def test_leaf_size_autotune():
     """leaf_size = 0 times the candidate trees and keeps one; the solve still meets rtol."""
     w = workloads.solve_c1()
