@@ -66,7 +66,9 @@ struct FmmPlan : PlanBase {
   int m2l_round = 0;        // M2L operands rounded to FP16 (1) or BF16 (2) (FP32 plans)
   std::vector<double> m2l_oscale;  // per level: power-of-two output scale of the M2L table (1 unless FP16)
   bool m2l_small = false;   // M2L on 4 x 4 target tiles (autotuned)
-  float tune_ms[5] = {0, 0, 0, 0, 0};  // P2P with G = 1, 2, 4 (one column); M2L 8x8, 4x4 tiles
+  bool m2l_split = true;    // coarse M2L levels split into class groups (autotuned)
+  // P2P with G = 1, 2, 4 (one column); M2L 8x8, 4x4 tiles; M2L without, with class groups
+  float tune_ms[7] = {0, 0, 0, 0, 0, 0, 0};
   int tune_source = 0;      // 0 defaults, 1 timed on this device, 2 from the tuning cache
   std::string tune_key;     // the cache key of this plan (without the column-group width)
   // work storage

@@ -361,7 +361,7 @@ struct M2LShape {
   int tile = 0, KSL = 0, gx = 0, NP = 1, S = 1;
   size_t lds = 0;
 };
-M2LShape m2l_shape(const MfmaLevel& mf, int l, bool small_pref) {
+M2LShape m2l_shape(const MfmaLevel& mf, int l, bool small_pref, bool split) {
   M2LShape s;
   const bool small = (small_pref && mf.fit4) || !mf.on;
   s.use = small ? mf.fit4 : mf.on;
@@ -374,7 +374,7 @@ M2LShape m2l_shape(const MfmaLevel& mf, int l, bool small_pref) {
   s.NP = s.tile == 8 ? 4 : 1;
   int nch = 0;  // MFMA chunks of one class
   for (int k0 = 0; k0 < mf.KS; k0 += s.KSL) nch += (std::min(s.KSL, mf.KS - k0) + 3) / 4;
-  if (s.gx * mf.RT < kM2LSplitBlocks && 10 * nch > kM2LChain) {
+  if (split && s.gx * mf.RT < kM2LSplitBlocks && 10 * nch > kM2LChain) {
     s.S = 10;
     for (int S : {2, 5})
       if (10 * nch / S <= kM2LChain) {
@@ -661,7 +661,7 @@ std::unique_ptr<FmmPlan<T>> make_plan(const Tree& t, double k, int p) {
     for (int sm = 0; sm < 2; ++sm) {
       size_t pp = 0, cc = 0;
       for (int l = 2; l <= L; ++l) {
-        const M2LShape s = m2l_shape(pl->mf[l], l, sm == 1);
+        const M2LShape s = m2l_shape(pl->mf[l], l, sm == 1, true);
         if (!s.use || s.S == 1) continue;
         pp += m2l_part_elems(s, pl->mf[l], 4);
         cc += (size_t)s.gx * pl->mf[l].RT;
@@ -736,7 +736,7 @@ void launch_m2l(const Tree& t, const FmmPlan<T>& pl, cplx<T>* M, cplx<T>* Lc, in
   for (int l = 2; l <= L; ++l) {
     const LevelInfo& li = pl.lv[l];
     const MfmaLevel& mf = pl.mf[l];
-    const M2LShape s = m2l_shape(mf, l, pl.m2l_small);
+    const M2LShape s = m2l_shape(mf, l, pl.m2l_small, pl.m2l_split);
     if (!s.use) {
       k_down<T, NR><<<1 << (2 * l), 64, 0, st>>>(M + li.coef * nrhs, Lc + li.coef * nrhs, nullptr,
                                                  pl.m2l.p + pl.m2l_off[l], nullptr, li.P, 1, l, nrhs, r0,
@@ -973,6 +973,7 @@ void run_cols(const Tree& t, FmmPlan<T>& pl, const FmmWork<T>& w, const cplx<T>*
 struct TuneVal {
   int G = 1;
   int m2l_small = 0;
+  int m2l_split = 1;
 };
 
 std::mutex& tune_mutex() {
@@ -1010,7 +1011,9 @@ std::string plan_key(const Tree& t, const FmmPlan<T>& pl) {
 
 // Launch-shape autotuner for one column-group width (the kernels' cost does
 // not depend on the charges, so zeros are used): the P2P lanes per target
-// G in {1, 2, 4} and, for one column, the M2L target tile (8 x 8 or 4 x 4).
+// G in {1, 2, 4} and, for one column, the M2L target tile (8 x 8 or 4 x 4)
+// and then, with that tile, whether the coarse levels split into class
+// groups (only when 3 % faster than without).
 template <class T, int NR>
 void autotune_group(const Tree& t, FmmPlan<T>& pl) {
   constexpr int g = NR >= 4 ? 2 : (NR >= 2 ? 1 : 0);
@@ -1071,6 +1074,17 @@ void autotune_group(const Tree& t, FmmPlan<T>& pl) {
         pl.tune_ms[4] = small;
         pl.m2l_small = small < big;
       }
+      bool any_split = false;
+      for (int l = 2; l <= t.L; ++l) any_split = any_split || m2l_shape(pl.mf[l], l, pl.m2l_small, true).S > 1;
+      if (pl.use_mfma && any_split) {
+        pl.m2l_split = false;
+        const float whole = timed([&] { launch_m2l<T, 1>(t, pl, pl.M.p, pl.Lc.p, 1, 0, nullptr, nullptr, st); });
+        pl.m2l_split = true;
+        const float parts = timed([&] { launch_m2l<T, 1>(t, pl, pl.M.p, pl.Lc.p, 1, 0, nullptr, nullptr, st); });
+        pl.tune_ms[5] = whole;
+        pl.tune_ms[6] = parts;
+        pl.m2l_split = parts < 0.97f * whole;
+      }
     }
   } catch (...) {
     cleanup();
@@ -1102,7 +1116,10 @@ void ensure_tuned(Tree& t, FmmPlan<T>& pl, int nrhs) {
       auto it = tune_table().find(key);
       if (it != tune_table().end()) {
         pl.G[g] = it->second.G;
-        if (g == 0) pl.m2l_small = it->second.m2l_small != 0;
+        if (g == 0) {
+          pl.m2l_small = it->second.m2l_small != 0;
+          pl.m2l_split = it->second.m2l_split != 0;
+        }
         pl.tuned[g] = true;
         pl.tune_source = 2;
         continue;
@@ -1120,6 +1137,7 @@ void ensure_tuned(Tree& t, FmmPlan<T>& pl, int nrhs) {
       TuneVal v;
       v.G = pl.G[g];
       v.m2l_small = pl.m2l_small ? 1 : 0;
+      v.m2l_split = pl.m2l_split ? 1 : 0;
       tune_table()[key] = v;
     }
     pl.tuned[g] = true;
@@ -1130,8 +1148,9 @@ void tune_cache_save(const std::string& path) {
   std::lock_guard<std::mutex> lk(tune_mutex());
   std::ofstream f(path);
   HFMM_REQUIRE(f.good(), "tune_cache_save: cannot open " + path);
-  f << "# hfmm tuning cache: key G m2l_small\n";
-  for (const auto& kv : tune_table()) f << kv.first << " " << kv.second.G << " " << kv.second.m2l_small << "\n";
+  f << "# hfmm tuning cache: key G m2l_small m2l_split\n";
+  for (const auto& kv : tune_table())
+    f << kv.first << " " << kv.second.G << " " << kv.second.m2l_small << " " << kv.second.m2l_split << "\n";
   HFMM_REQUIRE(f.good(), "tune_cache_save: write failed on " + path);
 }
 
@@ -1147,6 +1166,7 @@ int tune_cache_load(const std::string& path) {
     std::string key;
     TuneVal v;
     if (!(is >> key >> v.G >> v.m2l_small)) throw Error(HFMM_ERR_ARG, "tune_cache_load: bad line: " + line);
+    if (!(is >> v.m2l_split)) v.m2l_split = 1;  // files written before the class-group choice
     HFMM_REQUIRE(v.G == 1 || v.G == 2 || v.G == 4, "tune_cache_load: lanes per target must be 1, 2 or 4");
     tune_table()[key] = v;
     ++n;

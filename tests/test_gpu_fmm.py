@@ -130,6 +130,41 @@ def test_timed_apply_matches_apply():
     assert ms["m2l"] > 0 and ms["m2m"] > 0 and ms["p2p"] > 0
 
 
+def test_m2l_class_groups_on_and_off(tmp_path):
+    """The coarse M2L levels with and without class groups (each forced
+    through the tuning cache) give the same sums up to rounding order, and
+    both agree with the VALU downward kernels."""
+    xy, q = workloads.random_cloud(20000, seed=17)
+    q = q[:, 0]
+    k, p = 120.0, 8
+    hfmm.hfmm_tune_cache_clear()
+    t = hfmm.Tree(to_dev(xy), leaf_size=16)
+    for prec, dt in ((hfmm.FP64, np.complex128), (hfmm.FP32, np.complex64)):
+        hfmm.hfmm_fmm_apply(t, k, p, to_dev(q.astype(dt)), prec=prec)  # tunes, fills the cache
+    path = tmp_path / "tune.txt"
+    hfmm.hfmm_tune_cache_save(str(path))
+    lines = path.read_text().splitlines()
+    out = {}
+    for split in (0, 1):
+        body = [ln if ln.startswith("#") else " ".join(ln.split()[:3] + [str(split)]) for ln in lines]
+        f = tmp_path / f"tune{split}.txt"
+        f.write_text("\n".join(body) + "\n")
+        hfmm.hfmm_tune_cache_clear()
+        assert hfmm.hfmm_tune_cache_load(str(f)) >= 2
+        t2 = hfmm.Tree(to_dev(xy), leaf_size=16)
+        out[split] = [to_np(hfmm.hfmm_fmm_apply(t2, k, p, to_dev(q.astype(dt)), prec=prec))
+                      for prec, dt in ((hfmm.FP64, np.complex128), (hfmm.FP32, np.complex64))]
+    hfmm.hfmm_tune_cache_clear()
+    tv = hfmm.Tree(to_dev(xy), leaf_size=16)
+    tv.set_options(m2l_valu=True)
+    ref = to_np(hfmm.hfmm_fmm_apply(tv, k, p, to_dev(q), prec=hfmm.FP64))
+    assert rel(out[0][0], out[1][0]) <= 1e-13
+    assert rel(out[0][1], out[1][1]) <= 1e-6
+    for split in (0, 1):
+        assert rel(out[split][0], ref) <= 1e-12
+        assert rel(out[split][1], ref) <= 3e-6
+
+
 def test_invalid_arguments():
     xy, q = workloads.random_cloud(100, seed=1)
     with pytest.raises(hfmm.HFMMError) as e:
