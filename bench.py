@@ -59,8 +59,9 @@ PEAK_FP64_MFMA = 78.6
 
 def profile_record(path, kernel):
     """The JSON record of a committed counter summary, or None when the
-    summary is absent, is for another kernel, or its source file has changed
-    since the counters were taken (SHA-256 of `source`)."""
+    summary is absent, is for another kernel, or a source file it names has
+    changed since the counters were taken (SHA-256 of `source`, or of each
+    file in `sources` against `sources_sha256`)."""
     import hashlib
     import re
     try:
@@ -71,9 +72,13 @@ def profile_record(path, kernel):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if rec["kernel"] != kernel or hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if rec["kernel"] != kernel:
         return None
+    pairs = (zip(rec["sources"], rec["sources_sha256"]) if "sources" in rec
+             else [(rec["source"], rec["source_sha256"])])
+    for src, sha in pairs:
+        if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != sha:
+            return None
     return rec
 
 

@@ -1013,7 +1013,8 @@ std::string plan_key(const Tree& t, const FmmPlan<T>& pl) {
 // not depend on the charges, so zeros are used): the P2P lanes per target
 // G in {1, 2, 4} and, for one column, the M2L target tile (8 x 8 or 4 x 4)
 // and then, with that tile, whether the coarse levels split into class
-// groups (only when 3 % faster than without).
+// groups (only when 5 % faster than without, so that timing noise does not
+// flip the choice from one process to the next where the two are close).
 template <class T, int NR>
 void autotune_group(const Tree& t, FmmPlan<T>& pl) {
   constexpr int g = NR >= 4 ? 2 : (NR >= 2 ? 1 : 0);
@@ -1083,7 +1084,7 @@ void autotune_group(const Tree& t, FmmPlan<T>& pl) {
         const float parts = timed([&] { launch_m2l<T, 1>(t, pl, pl.M.p, pl.Lc.p, 1, 0, nullptr, nullptr, st); });
         pl.tune_ms[5] = whole;
         pl.tune_ms[6] = parts;
-        pl.m2l_split = parts < 0.97f * whole;
+        pl.m2l_split = parts < 0.95f * whole;
       }
     }
   } catch (...) {
