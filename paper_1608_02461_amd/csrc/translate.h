@@ -221,12 +221,14 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
   const T* Abase = a.Af + (size_t)rt * a.KSA * 64 + lane;
   // LDS position of the source box of class o for patch p (the zero box when
   // it is outside the grid or not adjacent to the target's parent)
+  // (computed without branches: both positions, then a select)
   auto src_base = [&](int o, int p) {
     const int ox = o / 7 - 3, oy = o % 7 - 3;
     const int sx = tx[p] + ox, sy = ty[p] + oy;
-    const bool v = sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb && abs((sx >> 1) - (tx[p] >> 1)) <= 1 &&
-                   abs((sy >> 1) - (ty[p] >> 1)) <= 1;
-    return (v ? (sx - wx0) + (sy - wy0) * WW : zb) * KPs + kq;
+    const bool v = ((unsigned)sx < (unsigned)a.nb) & ((unsigned)sy < (unsigned)a.nb) &
+                   ((unsigned)((sx >> 1) - (tx[p] >> 1) + 1) <= 2u) & ((unsigned)((sy >> 1) - (ty[p] >> 1) + 1) <= 2u);
+    const int in = __mul24(sy - wy0, WW) + (sx - wx0);
+    return __mul24(v ? in : zb, KPs) + kq;
   };
   for (int r = 0; r < args.nr; ++r) {
     V4 acc[NP];
@@ -321,19 +323,17 @@ __device__ __forceinline__ void m2l_block(const M2LAllArgs<T>& args, const M2LLe
           T av[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) av[u] = an[u];
-          if (c + 1 < nch) {
+          // the next chunk's fragments: of this class, else of the next one
+          // (after the last class, a harmless reload of this one)
+          const T* nx = c + 1 < nch ? A + (c * 4 + 4) * 64 : An;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
-          } else if (oi + 1 < ncw) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
-          }
-          const int ns = min(4, nst - 4 * c);
+          for (int u = 0; u < 4; ++u) an[u] = nx[u * 64];
           T bv[NP][4];
 #pragma unroll
           for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];  // in the box's stride
+          const int ns = min(4, nst - 4 * c);
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             if (u < ns)
@@ -435,8 +435,9 @@ __device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M
   auto src_base = [&](int o, int p) {
     const int ox = o / 7 - 3, oy = o % 7 - 3;
     const int sx = bx0 + 2 * (j & 3) + (p & 1) + ox, sy = by0 + 2 * (j >> 2) + (p >> 1) + oy;
-    const bool v = sx >= 0 && sy >= 0 && sx < a.nb && sy < a.nb;
-    return (v ? (sx - wx0) + (sy - wy0) * WW : zb) * KPs + kq;
+    const bool v = ((unsigned)sx < (unsigned)a.nb) & ((unsigned)sy < (unsigned)a.nb);
+    const int in = __mul24(sy - wy0, WW) + (sx - wx0);
+    return __mul24(v ? in : zb, KPs) + kq;
   };
   for (int r = 0; r < args.nr; ++r) {
     V4 acc[NP], accA = V4{0, 0, 0, 0}, accB = accA, accC = accA;
@@ -517,18 +518,22 @@ __device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M
 #pragma unroll
         for (int u = 0; u < 4; ++u) an[u] = A0[u * 64];
       }
-#pragma unroll 1
-      for (int oi = 0; oi < 10; ++oi) {
+      // one class: K = 0 common (the four patches), 1 pair (patches pa,
+      // pb), 2 corner (patch w); the kind is a template constant so that the
+      // chunk loop of each kind is straight-line code
+      auto walk = [&](auto kc, int oi) {
+        constexpr int K = decltype(kc)::value;
+        constexpr int NB = K == 0 ? 4 : (K == 1 ? 2 : 1);
         const int o = cls(oi);
-        const int kind = oi < 4 ? 0 : (oi < 9 ? 1 : 2);  // common, pair, corner
-        int base[NP];
-        if (kind == 0) {
+        int base[NB];
+        if constexpr (K == 0) {
 #pragma unroll
-          for (int p = 0; p < NP; ++p) base[p] = src_base(o, p);
+          for (int p = 0; p < 4; ++p) base[p] = src_base(o, p);
+        } else if constexpr (K == 1) {
+          base[0] = src_base(o, pa);
+          base[1] = src_base(o, pb);
         } else {
-          base[0] = src_base(o, kind == 1 ? pa : w);
-          base[1] = kind == 1 ? src_base(o, pb) : base[0];
-          base[2] = base[3] = base[0];
+          base[0] = src_base(o, w);
         }
         const T* A = Ab + (size_t)o * cstride;
         const T* An = oi + 1 < 10 ? Ab + (size_t)cls(oi + 1) * cstride : A;
@@ -536,47 +541,36 @@ __device__ __forceinline__ void m2l_block_par(const M2LAllArgs<T>& args, const M
           T av[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) av[u] = an[u];
-          if (c + 1 < nch) {
+          const T* nx = c + 1 < nch ? A + (c * 4 + 4) * 64 : An;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) an[u] = A[(c * 4 + 4 + u) * 64];
-          } else if (oi + 1 < 10) {
+          for (int u = 0; u < 4; ++u) an[u] = nx[u * 64];
+          T bv[NB][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) an[u] = An[u * 64];
-          }
+          for (int h = 0; h < NB; ++h)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bv[h][u] = Ms[base[h] + (c * 4 + u) * 4];
           const int ns = min(4, nst - 4 * c);
-          if (kind == 0) {
-            T bv[NP][4];
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
+          for (int u = 0; u < 4; ++u) {
+            if (u < ns) {
+              if constexpr (K == 0) {
 #pragma unroll
-              for (int u = 0; u < 4; ++u) bv[p][u] = Ms[base[p] + (c * 4 + u) * 4];  // in the box's stride
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              if (u < ns)
-#pragma unroll
-                for (int p = 0; p < NP; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
-          } else if (kind == 1) {
-            T bv[2][4];
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-              for (int u = 0; u < 4; ++u) bv[h][u] = Ms[base[h] + (c * 4 + u) * 4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              if (u < ns) {
+                for (int p = 0; p < 4; ++p) acc[p] = mfma16(av[u], bv[p][u], acc[p]);
+              } else if constexpr (K == 1) {
                 accA = mfma16(av[u], bv[0][u], accA);
                 accB = mfma16(av[u], bv[1][u], accB);
+              } else {
+                accC = mfma16(av[u], bv[0][u], accC);
               }
-          } else {
-            T bv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) bv[u] = Ms[base[0] + (c * 4 + u) * 4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              if (u < ns) accC = mfma16(av[u], bv[u], accC);
+            }
           }
         }
-      }
+      };
+#pragma unroll 1
+      for (int oi = 0; oi < 4; ++oi) walk(std::integral_constant<int, 0>{}, oi);
+#pragma unroll 1
+      for (int oi = 4; oi < 9; ++oi) walk(std::integral_constant<int, 1>{}, oi);
+      walk(std::integral_constant<int, 2>{}, 9);
     }
     {
       const int pa = kPairA[w], pb = kPairB[w];
