@@ -587,23 +587,132 @@ __global__ __launch_bounds__(64) void k_cgs_fin(const double2* __restrict__ part
   }
 }
 
-// w -= sum_{i<=j} V_i h_i
-__global__ void k_cgs_axpy(double2* __restrict__ V, int64_t vs, int64_t nn, const int* __restrict__ st,
-                           const int* __restrict__ active, const double2* __restrict__ hcur, int m1) {
+// Round 0's update w -= sum_{i<=j} V_i h_i (per point, i ascending) fused
+// with round 1's partial dots V_i^H w of the updated w, which stays in
+// registers: the same partial sums as k_cgs_dot over the block's kChunk
+// points, with one read and one write of w.
+__global__ __launch_bounds__(kRed) void k_cgs_axpy_dot(double2* __restrict__ V, int64_t vs, int64_t nn,
+                                                       const int* __restrict__ st, const int* __restrict__ active,
+                                                       const double2* __restrict__ hcur, double2* __restrict__ part,
+                                                       int m1, int nblk) {
   const int c = blockIdx.y;
   if (!active[c]) return;
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nn) return;
   const int j = st[0];
   double2* Vc = V + c * vs;
+  double2* w = Vc + (int64_t)(j + 1) * nn;
   const double2* h = hcur + (int64_t)c * m1;
-  double2 w = Vc[(int64_t)(j + 1) * nn + x];
-  for (int i = 0; i <= j; ++i) {
-    const double2 p = cmul(Vc[(int64_t)i * nn + x], h[i]);
-    w.x -= p.x;
-    w.y -= p.y;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double2 wv[kElems];
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = base + e * kRed + threadIdx.x;
+    wv[e] = x < nn ? w[x] : make_double2(0, 0);
   }
-  Vc[(int64_t)(j + 1) * nn + x] = w;
+  for (int i = 0; i <= j; ++i) {
+    const double2 hi = h[i];
+    const double2* Vi = Vc + (int64_t)i * nn;
+#pragma unroll
+    for (int e = 0; e < kElems; ++e) {
+      const int64_t x = base + e * kRed + threadIdx.x;
+      if (x < nn) {
+        const double2 p = cmul(Vi[x], hi);
+        wv[e].x -= p.x;
+        wv[e].y -= p.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = base + e * kRed + threadIdx.x;
+    if (x < nn) w[x] = wv[e];
+  }
+  __shared__ double2 red[4][kRed];
+  for (int i0 = 0; i0 <= j; i0 += 4) {
+    double2 acc[4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      acc[ii] = make_double2(0, 0);
+      if (i0 + ii <= j) {
+        const double2* Vi = Vc + (int64_t)(i0 + ii) * nn;
+#pragma unroll
+        for (int e = 0; e < kElems; ++e) {
+          const int64_t x = base + e * kRed + threadIdx.x;
+          if (x < nn) {
+            const double2 p = cmulc(Vi[x], wv[e]);
+            acc[ii].x += p.x;
+            acc[ii].y += p.y;
+          }
+        }
+      }
+      red[ii][threadIdx.x] = acc[ii];
+    }
+    __syncthreads();
+    for (int s = kRed / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          red[ii][threadIdx.x].x += red[ii][threadIdx.x + s].x;
+          red[ii][threadIdx.x].y += red[ii][threadIdx.x + s].y;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < 4 && i0 + (int)threadIdx.x <= j)
+      part[((int64_t)c * m1 + i0 + threadIdx.x) * nblk + blockIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+// Round 1's update (per point, i ascending) fused with the partial sums of
+// ||w||^2 of the result: the same partials as k_nrm_part over the block's
+// kChunk points.
+__global__ __launch_bounds__(kRed) void k_cgs_axpy_nrm(double2* __restrict__ V, int64_t vs, int64_t nn,
+                                                       const int* __restrict__ st, const int* __restrict__ active,
+                                                       const double2* __restrict__ hcur, int m1,
+                                                       double* __restrict__ part, int nblk) {
+  const int c = blockIdx.y;
+  if (!active[c]) return;
+  const int j = st[0];
+  double2* Vc = V + c * vs;
+  double2* w = Vc + (int64_t)(j + 1) * nn;
+  const double2* h = hcur + (int64_t)c * m1;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  double2 wv[kElems];
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = base + e * kRed + threadIdx.x;
+    wv[e] = x < nn ? w[x] : make_double2(0, 0);
+  }
+  for (int i = 0; i <= j; ++i) {
+    const double2 hi = h[i];
+    const double2* Vi = Vc + (int64_t)i * nn;
+#pragma unroll
+    for (int e = 0; e < kElems; ++e) {
+      const int64_t x = base + e * kRed + threadIdx.x;
+      if (x < nn) {
+        const double2 p = cmul(Vi[x], hi);
+        wv[e].x -= p.x;
+        wv[e].y -= p.y;
+      }
+    }
+  }
+  double s = 0;
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t x = base + e * kRed + threadIdx.x;
+    if (x < nn) {
+      w[x] = wv[e];
+      s += cabs2(wv[e]);
+    }
+  }
+  __shared__ double red[kRed];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = kRed / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)c * nblk + blockIdx.x] = red[0];
 }
 
 // ||v||^2 partials; v = base + c*cs (+ (j+1)*nn when st is given)
@@ -1395,13 +1504,14 @@ void arnoldi_step(Solver& s, int maxit, double rtol, hipStream_t st, hipEvent_t 
   k_fd<<<gv, 256, 0, st>>>(s.n, 1.0 / (s.h * s.h), s.field ? s.k2.p : nullptr, s.k2c, s.Z.p, zs, s.V.p, vs, nullptr,
                            0, nr, js, s.active.p);
   HFMM_LAUNCH_CHECK();
+  // classical Gram-Schmidt twice: dots, then round 0's update fused with
+  // round 1's dots, then round 1's update fused with the norm's partials
   const dim3 gd(s.nblk, nr), gf(m + 1, nr);
-  for (int round = 0; round < 2; ++round) {
-    k_cgs_dot<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.part.p, m + 1, s.nblk);
-    k_cgs_fin<<<gf, 64, 0, st>>>(s.part.p, s.nblk, js, s.active.p, s.hcur.p, s.H.p, m, round);
-    k_cgs_axpy<<<gv, 256, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.hcur.p, m + 1);
-  }
-  k_nrm_part<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.npart.p, s.nblk);
+  k_cgs_dot<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.part.p, m + 1, s.nblk);
+  k_cgs_fin<<<gf, 64, 0, st>>>(s.part.p, s.nblk, js, s.active.p, s.hcur.p, s.H.p, m, 0);
+  k_cgs_axpy_dot<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.hcur.p, s.part.p, m + 1, s.nblk);
+  k_cgs_fin<<<gf, 64, 0, st>>>(s.part.p, s.nblk, js, s.active.p, s.hcur.p, s.H.p, m, 1);
+  k_cgs_axpy_nrm<<<gd, kRed, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.hcur.p, m + 1, s.npart.p, s.nblk);
   k_nrm_fin<<<nr, 64, 0, st>>>(s.npart.p, s.nblk, js, s.active.p, s.rn.p, s.H.p, m);
   k_scale<<<gv, 256, 0, st>>>(s.V.p, vs, nn, js, s.active.p, s.rn.p);
   k_givens<<<1, 64, 0, st>>>(s.H.p, s.cs.p, s.sn.p, s.g.p, js, s.active.p, s.jj.p, s.iters.p, s.est.p, s.bnorm.p,
