@@ -44,3 +44,27 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(root, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(hfmm.LIB_PATH), reason="library not built")
+def test_tune_cache_file_round_trip(tmp_path):
+    """The tuning cache (host only) reads lines with and without the M2L
+    class-group column (files written before that choice existed load with
+    class groups allowed) and writes all four columns; an invalid lane count
+    or a short line is an argument error."""
+    hfmm.hfmm_tune_cache_clear()
+    f = tmp_path / "t.txt"
+    f.write_text("# hfmm tuning cache\nkeyA:c1 2 0\nkeyB:c1 4 1 0\n")
+    assert hfmm.hfmm_tune_cache_load(str(f)) == 2
+    assert hfmm.hfmm_tune_cache_size() == 2
+    out = tmp_path / "o.txt"
+    hfmm.hfmm_tune_cache_save(str(out))
+    rows = sorted(ln.split() for ln in out.read_text().splitlines() if not ln.startswith("#"))
+    assert rows == [["keyA:c1", "2", "0", "1"], ["keyB:c1", "4", "1", "0"]]
+    for bad in ("keyC:c1 3 0 1\n", "keyD:c1\n"):
+        g = tmp_path / "bad.txt"
+        g.write_text(bad)
+        with pytest.raises(hfmm.HFMMError):
+            hfmm.hfmm_tune_cache_load(str(g))
+    hfmm.hfmm_tune_cache_clear()
+    assert hfmm.hfmm_tune_cache_size() == 0
