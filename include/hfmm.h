@@ -135,6 +135,9 @@ hfmm_status hfmm_tree_set_m2l_input_rounding(hfmm_tree t, int32_t mode);
  * d_q   n x nrhs complex, device.   d_phi  n x nrhs complex, overwritten.
  * The first call for a (k, p, prec) builds and caches its translation plan
  * (host tables, uploaded synchronously).  Async on stream afterwards.
+ * The plan holds the work arrays of the apply (expansions, the M2L's
+ * class-group partial sums and counters): applies on one tree must not
+ * overlap in time (different streams without ordering, or threads).
  * Errors: k <= 0, p out of range, nrhs < 1, leaves too large for k
  * (k * leaf_side / sqrt(2) above 6), FP32 tables that
  * would overflow.
@@ -154,7 +157,9 @@ hfmm_status hfmm_fmm_apply(hfmm_tree t, double k, int32_t p, hfmm_precision prec
  *   2 coefficients-per-box x nrhs + 2 N nrhs complex values) is rejected
  *   with HFMM_ERR_ARG before any launch.
  * - Every call on a GPU shares that GPU's array: calls that overlap on one
- *   GPU (other streams or threads) race.  Async on stream. */
+ *   GPU (other streams or threads) race.  The M2L's class-group partial
+ *   sums and counters belong to the plan (allocated with it), so a call must
+ *   not overlap another apply on the same tree either.  Async on stream. */
 hfmm_status hfmm_fmm_apply_noalloc(hfmm_tree t, double k, int32_t p, hfmm_precision prec,
                                    const void* d_q, void* d_phi, int32_t nrhs, hipStream_t stream);
 
