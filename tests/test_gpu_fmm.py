@@ -132,15 +132,17 @@ def test_timed_apply_matches_apply():
 
 def test_m2l_class_groups_on_and_off(tmp_path):
     """The coarse M2L levels with and without class groups (each forced
-    through the tuning cache) give the same sums up to rounding order, and
-    both agree with the VALU downward kernels."""
-    xy, q = workloads.random_cloud(20000, seed=17)
-    q = q[:, 0]
+    through the tuning cache) give the same sums up to rounding order, for
+    one column and for 7 (column groups of 4, 2 and 1), and both agree with
+    the VALU downward kernels."""
+    xy, q7 = workloads.random_cloud(20000, seed=17, nrhs=7)
+    q = np.ascontiguousarray(q7[:, 0])
     k, p = 120.0, 8
     hfmm.hfmm_tune_cache_clear()
     t = hfmm.Tree(to_dev(xy), leaf_size=16)
     for prec, dt in ((hfmm.FP64, np.complex128), (hfmm.FP32, np.complex64)):
         hfmm.hfmm_fmm_apply(t, k, p, to_dev(q.astype(dt)), prec=prec)  # tunes, fills the cache
+        hfmm.hfmm_fmm_apply(t, k, p, to_dev(q7.astype(dt)), prec=prec)  # column groups of 4, 2, 1
     path = tmp_path / "tune.txt"
     hfmm.hfmm_tune_cache_save(str(path))
     lines = path.read_text().splitlines()
@@ -154,6 +156,8 @@ def test_m2l_class_groups_on_and_off(tmp_path):
         t2 = hfmm.Tree(to_dev(xy), leaf_size=16)
         out[split] = [to_np(hfmm.hfmm_fmm_apply(t2, k, p, to_dev(q.astype(dt)), prec=prec))
                       for prec, dt in ((hfmm.FP64, np.complex128), (hfmm.FP32, np.complex64))]
+        out[split] += [to_np(hfmm.hfmm_fmm_apply(t2, k, p, to_dev(q7.astype(dt)), prec=prec))
+                       for prec, dt in ((hfmm.FP64, np.complex128), (hfmm.FP32, np.complex64))]
     hfmm.hfmm_tune_cache_clear()
     tv = hfmm.Tree(to_dev(xy), leaf_size=16)
     tv.set_options(m2l_valu=True)
@@ -163,6 +167,14 @@ def test_m2l_class_groups_on_and_off(tmp_path):
     for split in (0, 1):
         assert rel(out[split][0], ref) <= 1e-12
         assert rel(out[split][1], ref) <= 3e-6
+        # several columns (M2L launches of 4, 2 and 1 columns): column 0
+        # equals the single-column apply, and every column agrees across
+        # the two shapes
+        assert rel(out[split][2][:, 0], out[split][0]) <= 1e-13
+        assert rel(out[split][3][:, 0], out[split][1]) <= 1e-6
+    for c in range(7):
+        assert rel(out[0][2][:, c], out[1][2][:, c]) <= 1e-13
+        assert rel(out[0][3][:, c], out[1][3][:, c]) <= 1e-6
 
 
 def test_invalid_arguments():
