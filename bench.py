@@ -51,8 +51,8 @@ PEAK_FP64_ALU = 78.6
 PEAK_HBM = 8000.0       # GB/s
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "p2p_fmm_c2_n1m_k100_p8_fp32_pmc.md")
-M2L_SUMMARY = os.path.join(ROOT, "profiles", "m2l_mfma_fmm_c2_c3_counters.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "p2p_fmm_n1m_k100_p8_fp32_pmc.md")
+M2L_SUMMARY = os.path.join(ROOT, "profiles", "m2l_mfma_fmm_n1m_and_n1024_counters.md")
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, dense FP32 matrix cores
 PEAK_FP64_MFMA = 78.6
 
@@ -187,7 +187,7 @@ def p2p_flops_per_pair_fp64(deg, nrhs=1):
 
 
 def bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan32):
-    """C2 at p = 4, 8, 12 in both precisions, errors on the stored samples,
+    """The 2^20-point apply at p = 4, 8, 12 in both precisions, errors on the stored samples,
     and the near-field roofline of the FP64 apply at p = 8."""
     fmm_tab = {}
     for pp in (4, 8, 12):
@@ -205,7 +205,7 @@ def bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan32):
             row[name] = {"mpts_s": round(N / dt / 1e6, 2), "ms": round(dt * 1e3, 4),
                          "rel_err": float(np.linalg.norm(o - gold["direct"]) / np.linalg.norm(gold["direct"]))}
         fmm_tab[f"p{pp}"] = row
-        log(f"C2 p={pp}: {row}")
+        log(f"2^20 apply p={pp}: {row}")
     # FP64 near-field roofline (p = 8): duration from the stage-timed applies
     plan64 = hfmm.hfmm_fmm_plan_info(tree, k, 8, hfmm.FP64)
     st = {s_: 0.0 for s_ in hfmm.STAGES}
@@ -221,13 +221,13 @@ def bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan32):
         "achieved": round(ach, 3), "peak": PEAK_FP64_ALU, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_ALU, 4),
         "algorithmic_flops_per_launch": fl, "ms_per_launch": round(st["p2p"], 5), "near_deg": plan64["near_deg"],
         "note": "the per-pair FP64 log2 is counted as 0 flops"}
-    fmm_tab["fp64_p8_m2l_roofline"] = m2l_roofline(tree, plan64["orders"], st["m2l"], "fp64", "c2_p8_fp64")
-    log(f"C2 fp64 p=8 stages {fmm_tab['fp64_p8_stage_ms']} roofline {fmm_tab['fp64_p8_roofline']['frac']} "
+    fmm_tab["fp64_p8_m2l_roofline"] = m2l_roofline(tree, plan64["orders"], st["m2l"], "fp64", "apply_2p20_p8_fp64")
+    log(f"2^20 apply fp64 p=8 stages {fmm_tab['fp64_p8_stage_ms']} roofline {fmm_tab['fp64_p8_roofline']['frac']} "
         f"M2L {fmm_tab['fp64_p8_m2l_roofline']['frac']}")
     return fmm_tab
 
 
-def c3_points(n):
+def solver_tree_points(n):
     """Interior nodes then boundary element midpoints (bottom, right, top, left), as the solver's tree."""
     h = 1.0 / (n + 1)
     m = (np.arange(n + 1) + 0.5) * h
@@ -237,21 +237,21 @@ def c3_points(n):
                            np.stack([m, o], 1), np.stack([z, m], 1)])
 
 
-def bench_c3(dev, hfmm, workloads, torch):
+def bench_solve_1024(dev, hfmm, workloads, torch):
     """1024 x 1024, k h = 0.3: mixed vs FP64 FGMRES(50) at p = 4, 6, 8 (k0 = k), the
     dispersion-matched k0 at p = 6, the first pass's FMM error on 2048 samples
     against the stored direct sum, and per-stage times of one pass."""
-    c3 = workloads.solve_c3()
-    n3, k3 = c3["n"], c3["k"]
-    f = torch.from_numpy(c3["f"]).to(dev)
-    out = {"k": k3, "leaf": c3["leaf"], "restart": 50}
+    w1024 = workloads.solve_1024()
+    n3, k3 = w1024["n"], w1024["k"]
+    f = torch.from_numpy(w1024["f"]).to(dev)
+    out = {"k": k3, "leaf": w1024["leaf"], "restart": 50}
     k3m = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
     runs = [(f"p{pp}_{name}", pp, prec, k3) for pp in (4, 6, 8)
             for name, prec in (("mixed", hfmm.FP32), ("fp64", hfmm.FP64))]
     runs += [("p6_mixed_matched_k0", 6, hfmm.FP32, k3m), ("p6_fp64_matched_k0", 6, hfmm.FP64, k3m)]
     for name, pp, prec, k0 in runs:
         t0 = time.perf_counter()
-        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=pp, leaf_size=c3["leaf"], prec=prec)
+        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=pp, leaf_size=w1024["leaf"], prec=prec)
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         dt, x, info = timed_solves(s, f, 2, restart=50, rtol=1e-6, maxit=3000)
@@ -260,7 +260,7 @@ def bench_c3(dev, hfmm, workloads, torch):
                      "ms_precond_per_iter": round(info["ms_precond"] / max(1, info["iters"]), 4),
                      "ms_krylov_per_iter": round(info["ms_krylov"] / max(1, info["iters"]), 4),
                      "setup_s": round(setup, 3), "levels": s.info()["levels"]}
-        log(f"C3 {name}: {out[name]}")
+        log(f"1024^2 solve {name}: {out[name]}")
         del s
     for pp in (4, 6, 8):
         out[f"p{pp}_mixed_over_fp64_speedup"] = round(out[f"p{pp}_fp64"]["s_per_solve"] /
@@ -268,11 +268,11 @@ def bench_c3(dev, hfmm, workloads, torch):
     out["p6_mixed_over_fp64_speedup_matched_k0"] = round(
         out["p6_fp64_matched_k0"]["s_per_solve"] / out["p6_mixed_matched_k0"]["s_per_solve"], 3)
     # the first FMM pass (sources h^2 f at the interior nodes) against the stored direct sum
-    pts = c3_points(n3)
-    t3 = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=c3["leaf"])
-    g3 = np.load(os.path.join(ROOT, "tests", "golden", "c3_reference.npz"))
+    pts = solver_tree_points(n3)
+    t3 = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=w1024["leaf"])
+    g3 = np.load(os.path.join(ROOT, "tests", "golden", "pass_1024_reference.npz"))
     q = np.zeros(len(pts), dtype=np.complex128)
-    q[: n3 * n3] = c3["h"] ** 2 * c3["f"]
+    q[: n3 * n3] = w1024["h"] ** 2 * w1024["f"]
     err = {}
     for pp in (4, 6, 8):
         row = {"eps_oracle": float(g3[f"eps_oracle_p{pp}"])}
@@ -282,33 +282,33 @@ def bench_c3(dev, hfmm, workloads, torch):
             row[name] = float(np.linalg.norm(o - g3["direct"]) / np.linalg.norm(g3["direct"]))
         err[f"p{pp}"] = row
     out["pass1_rel_err_2048_samples"] = err
-    log(f"C3 pass-1 errors: {err}")
+    log(f"1024^2 pass-1 errors: {err}")
     qq = torch.ones(len(pts), dtype=torch.complex64, device=dev)
     for name, prec, qv in (("fp32", hfmm.FP32, qq), ("fp64", hfmm.FP64, qq.to(torch.complex128))):
         hfmm.hfmm_fmm_apply_timed(t3, k3, 6, qv, prec=prec)
         _, ms = hfmm.hfmm_fmm_apply_timed(t3, k3, 6, qv, prec=prec)
         out[f"fmm_pass_stage_ms_{name}"] = {s_: round(v, 4) for s_, v in ms.items()}
         orders = hfmm.hfmm_fmm_plan_info(t3, k3, 6, prec)["orders"]
-        out[f"fmm_pass_m2l_roofline_{name}"] = m2l_roofline(t3, orders, ms["m2l"], name, f"c3_p6_{name}")
+        out[f"fmm_pass_m2l_roofline_{name}"] = m2l_roofline(t3, orders, ms["m2l"], name, f"pass_1024_p6_{name}")
     out["orders_p6"] = hfmm.hfmm_fmm_plan_info(t3, k3, 6, hfmm.FP32)["orders"]
-    log(f"C3 FMM stages: {out['fmm_pass_stage_ms_fp32']}")
+    log(f"1024^2 pass stages: {out['fmm_pass_stage_ms_fp32']}")
     return out
 
 
-def bench_c4(dev, hfmm, workloads, torch):
+def bench_batch_16x4(dev, hfmm, workloads, torch):
     """16 problems x 4 right-hand sides: the dispersion-matched variant
     (FGMRES(200)) graph vs eager, and the survey's settings (k0 = k,
     FGMRES(50), non-convergence reported)."""
-    c4 = workloads.batch_c4()
-    out = {"problems": [(pr["n"], round(pr["k"], 2)) for pr in c4["problems"]]}
-    bs = [torch.from_numpy(pr["f"].astype(np.complex128)).to(dev) for pr in c4["problems"]]
+    wb = workloads.batch_16x4()
+    out = {"problems": [(pr["n"], round(pr["k"], 2)) for pr in wb["problems"]]}
+    bs = [torch.from_numpy(pr["f"].astype(np.complex128)).to(dev) for pr in wb["problems"]]
     for variant, matched, restart, maxit in (("matched_k0_restart200", True, 200, 3000),
                                             ("k0_eq_k_restart50", False, 50, 1500)):
         t0 = time.perf_counter()
         solvers = []
-        for pr in c4["problems"]:
+        for pr in wb["problems"]:
             k0 = hfmm.hfmm_matched_wavenumber(pr["k"], pr["h"]) if matched else pr["k"]
-            solvers.append(hfmm.Solver(pr["n"], k0, k2_const=pr["k"] ** 2, p=c4["p"], leaf_size=c4["leaf"],
+            solvers.append(hfmm.Solver(pr["n"], k0, k2_const=pr["k"] ** 2, p=wb["p"], leaf_size=wb["leaf"],
                                        prec=hfmm.FP32, nrhs=4))
         torch.cuda.synchronize()
         row = {"setup_s": round(time.perf_counter() - t0, 3), "restart": restart, "maxit": maxit,
@@ -316,19 +316,19 @@ def bench_c4(dev, hfmm, workloads, torch):
         modes = (("graph", True), ("eager", False)) if matched else (("graph", True),)
         if matched:  # one untimed batch per mode: first-use costs (the graph capture, workspace) stay out
             for _, graph in modes:
-                hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=c4["rtol"], maxit=maxit,
+                hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=wb["rtol"], maxit=maxit,
                                                use_graph=graph)
             torch.cuda.synchronize()
         for mode, graph in modes:
             t0 = time.perf_counter()
-            xs, infos = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=c4["rtol"], maxit=maxit,
+            xs, infos = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=restart, rtol=wb["rtol"], maxit=maxit,
                                                        use_graph=graph)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             row[mode] = {"solves_s": round(64 / dt, 3), "t_batch_s": round(dt, 4),
                          "converged": sum(i["converged"] for i in infos), "iters": [i["iters"] for i in infos],
                          "max_rel_res": max(i["rel_res_true"] for i in infos)}
-            log(f"C4 {variant} {mode}: {row[mode]}")
+            log(f"16x4 batch {variant} {mode}: {row[mode]}")
         if "eager" in row:
             row["graph_over_eager_speedup"] = round(row["eager"]["t_batch_s"] / row["graph"]["t_batch_s"], 3)
         out[variant] = row
@@ -336,21 +336,21 @@ def bench_c4(dev, hfmm, workloads, torch):
     return out
 
 
-def bench_c5(dev, hfmm, workloads, torch):
+def bench_adjoint_256(dev, hfmm, workloads, torch):
     from oracle import adjoint as oadj
     from paper_1608_02461_amd.autograd import helmholtz_solve
-    c5 = workloads.adjoint_c5()
-    n5 = c5["n"]
-    s5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
-    d5 = hfmm.Solver(n5, c5["k0"], p=c5["p"], leaf_size=c5["leaf"], prec=hfmm.FP32)
-    f5 = torch.from_numpy(c5["f"]).to(dev)
+    wa = workloads.adjoint_256()
+    n5 = wa["n"]
+    s5 = hfmm.Solver(n5, wa["k0"], p=wa["p"], leaf_size=wa["leaf"], prec=hfmm.FP32)
+    d5 = hfmm.Solver(n5, wa["k0"], p=wa["p"], leaf_size=wa["leaf"], prec=hfmm.FP32)
+    f5 = torch.from_numpy(wa["f"]).to(dev)
     ud, _ = d5.solve(f5, restart=200, rtol=1e-10, strict=True)
-    P5 = torch.from_numpy(c5["P"]).to(dev)
+    P5 = torch.from_numpy(wa["P"]).to(dev)
     dd = ud[P5]
     del d5
 
     def fwd_bwd(rtol):
-        kbt = torch.from_numpy(c5["kb"]).to(dev).requires_grad_(True)
+        kbt = torch.from_numpy(wa["kb"]).to(dev).requires_grad_(True)
         u = helmholtz_solve(kbt, f5, s5, restart=200, rtol=rtol)
         r = u[P5] - dd
         J = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
@@ -367,23 +367,23 @@ def bench_c5(dev, hfmm, workloads, torch):
     J6, g6 = fwd_bwd(1e-6)
     torch.cuda.synchronize()
     t_fb6 = time.perf_counter() - t0
-    Jo, Go, _, _ = oadj.gradient(n5, c5["kb"], c5["f"], c5["P"], dd.cpu().numpy())
+    Jo, Go, _, _ = oadj.gradient(n5, wa["kb"], wa["f"], wa["P"], dd.cpu().numpy())
     out = {"fwd_bwd_s_rtol1e-10": round(t_fb, 4), "fwd_bwd_s_rtol1e-6": round(t_fb6, 4),
            "grad_rel_err_vs_oracle_rtol1e-10": float(np.linalg.norm(g5 - Go) / np.linalg.norm(Go)),
            "grad_rel_err_vs_oracle_rtol1e-6": float(np.linalg.norm(g6 - Go) / np.linalg.norm(Go)),
            "J_rel_err": abs(J5 - Jo) / abs(Jo)}
-    log(f"C5: {out}")
+    log(f"256^2 adjoint: {out}")
     return out
 
 
-def bench_c1(dev, hfmm, workloads, torch):
-    c1 = workloads.solve_c1()
-    s = hfmm.Solver(c1["n"], c1["k"], p=6, leaf_size=32, prec=hfmm.FP64)
-    f1 = torch.from_numpy(c1["f"]).to(dev)
+def bench_solve_64(dev, hfmm, workloads, torch):
+    w64 = workloads.solve_64()
+    s = hfmm.Solver(w64["n"], w64["k"], p=6, leaf_size=32, prec=hfmm.FP64)
+    f1 = torch.from_numpy(w64["f"]).to(dev)
     dt, x, info = timed_solves(s, f1, 5, restart=30, rtol=1e-6)
     out = {"solves_s": round(1 / dt, 3), "iters": info["iters"], "rel_res_true": info["rel_res_true"],
            "setup_ms": round(info["ms_setup"], 3)}
-    log(f"C1: {out}")
+    log(f"64^2 solve: {out}")
     return out
 
 
@@ -473,8 +473,8 @@ def bench_pstudy(dev, hfmm, workloads, torch):
     from oracle import bem
     out = {}
     cases = {"helm1_kappa7": helm1_problem(7.0, 63) + (63,)}
-    c1 = workloads.solve_c1()
-    cases["solve_64"] = (c1["k"], c1["f"], c1["n"])
+    w64 = workloads.solve_64()
+    cases["solve_64"] = (w64["k"], w64["f"], w64["n"])
     for cname, (k, f, n) in cases.items():
         ref = bem.precond_apply(n, k, f)
         ft = torch.from_numpy(f).to(dev)
@@ -504,21 +504,21 @@ def bench_m2l_rounding(dev, hfmm, workloads, torch, tree, gold, smp):
     """The 16-bit M2L experiment at scale: the N = 2^20 apply's error on the
     stored samples with the M2L operands rounded to FP16 / BF16 (p = 4, 8,
     12), and the 1024 x 1024 solve (matched k0, p = 6) with each."""
-    w = workloads.fmm_c2()
+    w = workloads.fmm_2p20()
     q32 = torch.from_numpy(w["q"].astype(np.complex64)).to(dev)
     out = {}
     for rname in ("none", "fp16", "bf16"):
         tree.set_m2l_input_rounding(rname)
         for pp in (4, 8, 12):
             phi = hfmm.hfmm_fmm_apply(tree, w["k"], pp, q32, prec=hfmm.FP32).cpu().numpy()[smp]
-            out[f"c2_p{pp}_{rname}_rel_err"] = float(np.linalg.norm(phi - gold["direct"]) /
+            out[f"apply_2p20_p{pp}_{rname}_rel_err"] = float(np.linalg.norm(phi - gold["direct"]) /
                                                     np.linalg.norm(gold["direct"]))
     tree.set_m2l_input_rounding("none")
-    c3 = workloads.solve_c3()
-    n3, k3 = c3["n"], c3["k"]
+    w1024 = workloads.solve_1024()
+    n3, k3 = w1024["n"], w1024["k"]
     k0 = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
-    f = torch.from_numpy(c3["f"]).to(dev)
-    s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=c3["leaf"], prec=hfmm.FP32)
+    f = torch.from_numpy(w1024["f"]).to(dev)
+    s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=w1024["leaf"], prec=hfmm.FP32)
     for rname in ("none", "fp16", "bf16"):
         s.set_m2l_input_rounding(rname)
         torch.cuda.synchronize()
@@ -533,10 +533,10 @@ def bench_m2l_rounding(dev, hfmm, workloads, torch, tree, gold, smp):
     return out
 
 
-def bench_hbm(dev, hfmm, workloads, torch, xy_c2):
+def bench_hbm(dev, hfmm, workloads, torch, xy_2p20):
     """HBM-bound parts timed with hipEvents on the launch stream: the FD matvec on
     1024 x 1024 (32 algorithmic bytes per point: x read once, y written once,
-    complex128; neighbours come from cache) and the tree build of the C2 points
+    complex128; neighbours come from cache) and the tree build of the 2^20 apply points
     (a rough 40 bytes per point per pass, several passes)."""
     n = 1024
     x = torch.randn(n * n, dtype=torch.complex128, device=dev)
@@ -608,40 +608,40 @@ def cpu_extra_baselines(workloads):
     out = {"blas": [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()],
            "threads_cap": 16}
     with threadpool_limits(16):
-        c1 = workloads.solve_c1()
-        A = fd.matrix(c1["n"], c1["k"] ** 2)
+        w64 = workloads.solve_64()
+        A = fd.matrix(w64["n"], w64["k"] ** 2)
         t0 = time.perf_counter()
-        Minv = bem.precond_matrix(c1["n"], c1["k"])
+        Minv = bem.precond_matrix(w64["n"], w64["k"])
         t1 = time.perf_counter()
-        x, info = fgmres.fgmres(lambda v: A @ v, lambda v: Minv @ v, c1["f"], restart=30, rtol=1e-6)
+        x, info = fgmres.fgmres(lambda v: A @ v, lambda v: Minv @ v, w64["f"], restart=30, rtol=1e-6)
         t2 = time.perf_counter()
         out["solve_64_oracle_dense_fgmres"] = {"form_Minv_s": round(t1 - t0, 3), "fgmres_s": round(t2 - t1, 4),
                                                "solves_s": round(1 / (t2 - t0), 4), "iters": info["iters"]}
-        log(f"CPU C1: {out['solve_64_oracle_dense_fgmres']}")
-        c3 = workloads.solve_c3()
+        log(f"CPU 64^2 solve: {out['solve_64_oracle_dense_fgmres']}")
+        w1024 = workloads.solve_1024()
         from scipy.sparse.linalg import splu
-        A3 = fd.matrix(c3["n"], c3["k"] ** 2).tocsc()
+        A3 = fd.matrix(w1024["n"], w1024["k"] ** 2).tocsc()
         t0 = time.perf_counter()
         lu = splu(A3)
         t1 = time.perf_counter()
-        x3 = lu.solve(c3["f"])
+        x3 = lu.solve(w1024["f"])
         t2 = time.perf_counter()
         out["solve_1024_cpu_sparse_direct_reference"] = {
             "factor_s": round(t1 - t0, 2), "solve_s": round(t2 - t1, 3), "solves_s": round(1 / (t2 - t0), 5),
-            "rel_res": float(np.linalg.norm(c3["f"] - A3 @ x3) / np.linalg.norm(c3["f"])),
+            "rel_res": float(np.linalg.norm(w1024["f"] - A3 @ x3) / np.linalg.norm(w1024["f"])),
             "label": "CPU sparse-direct reference (different method)"}
-        log(f"CPU C3: {out['solve_1024_cpu_sparse_direct_reference']}")
+        log(f"CPU 1024^2 solve: {out['solve_1024_cpu_sparse_direct_reference']}")
         del lu
-        c5 = workloads.adjoint_c5()
-        u_ref = oadj.solve(c5["n"], c5["k2_ref"], c5["f"])
-        d = u_ref[c5["P"]]
+        wa = workloads.adjoint_256()
+        u_ref = oadj.solve(wa["n"], wa["k2_ref"], wa["f"])
+        d = u_ref[wa["P"]]
         t0 = time.perf_counter()
-        oadj.gradient(c5["n"], c5["kb"], c5["f"], c5["P"], d)
+        oadj.gradient(wa["n"], wa["kb"], wa["f"], wa["P"], d)
         out["adjoint_256_oracle_gradient_s"] = round(time.perf_counter() - t0, 3)
     return out
 
 
-PROFILE_CASES = ("c2-fp64", "c3-pass-fp32", "c3-pass-fp64", "c3-solve")
+PROFILE_CASES = ("apply-2p20-fp64", "pass-1024-fp32", "pass-1024-fp64", "solve-1024")
 
 
 def copy_probe(torch, dev):
@@ -656,36 +656,36 @@ def copy_probe(torch, dev):
 
 def profile_case(name, steps, warmup, probe):
     """One workload alone, for a profiler (no JSON line):
-    c2-fp64        the headline apply in complex128 (N = 2^20, k = 100, leaf 64, p = 8);
-    c3-pass-fp32   the first FMM pass of the 1024 x 1024 preconditioner (sources
-    c3-pass-fp64   h^2 f at the interior nodes, k h = 0.3, leaf 32, p = 6);
-    c3-solve       solver set-up (tree, boundary inverse, plans) then `steps`
+    apply-2p20-fp64        the headline apply in complex128 (N = 2^20, k = 100, leaf 64, p = 8);
+    pass-1024-fp32   the first FMM pass of the 1024 x 1024 preconditioner (sources
+    pass-1024-fp64   h^2 f at the interior nodes, k h = 0.3, leaf 32, p = 6);
+    solve-1024       solver set-up (tree, boundary inverse, plans) then `steps`
                    complex64-preconditioned FGMRES(50) solves of that system with
                    the dispersion-matched k0, p = 6."""
     import torch
     from paper_1608_02461_amd import hfmm, workloads
     dev = torch.device("cuda:0")
-    if name == "c2-fp64":
-        w = workloads.fmm_c2()
+    if name == "apply-2p20-fp64":
+        w = workloads.fmm_2p20()
         tree = hfmm.Tree(torch.from_numpy(w["xy"]).to(dev), leaf_size=w["leaf"])
         q = torch.from_numpy(w["q"]).to(dev)
         run = lambda: hfmm.hfmm_fmm_apply(tree, w["k"], 8, q, prec=hfmm.FP64)
-    elif name.startswith("c3-pass"):
-        c3 = workloads.solve_c3()
-        n3 = c3["n"]
-        pts = c3_points(n3)
-        tree = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=c3["leaf"])
+    elif name.startswith("pass-1024"):
+        w1024 = workloads.solve_1024()
+        n3 = w1024["n"]
+        pts = solver_tree_points(n3)
+        tree = hfmm.Tree(torch.from_numpy(pts).to(dev), leaf_size=w1024["leaf"])
         q = np.zeros(len(pts), dtype=np.complex128)
-        q[: n3 * n3] = c3["h"] ** 2 * c3["f"]
+        q[: n3 * n3] = w1024["h"] ** 2 * w1024["f"]
         prec, dt = (hfmm.FP32, np.complex64) if name.endswith("fp32") else (hfmm.FP64, np.complex128)
         qd = torch.from_numpy(q.astype(dt)).to(dev)
-        run = lambda: hfmm.hfmm_fmm_apply(tree, c3["k"], 6, qd, prec=prec)
-    elif name == "c3-solve":
-        c3 = workloads.solve_c3()
-        n3, k3 = c3["n"], c3["k"]
+        run = lambda: hfmm.hfmm_fmm_apply(tree, w1024["k"], 6, qd, prec=prec)
+    elif name == "solve-1024":
+        w1024 = workloads.solve_1024()
+        n3, k3 = w1024["n"], w1024["k"]
         k0 = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
-        f = torch.from_numpy(c3["f"]).to(dev)
-        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=c3["leaf"], prec=hfmm.FP32)
+        f = torch.from_numpy(w1024["f"]).to(dev)
+        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=w1024["leaf"], prec=hfmm.FP32)
         warmup = 0
         run = lambda: s.solve(f, restart=50, rtol=1e-6, maxit=3000)
     else:
@@ -697,7 +697,7 @@ def profile_case(name, steps, warmup, probe):
     for _ in range(steps):
         out = run()
     torch.cuda.synchronize()
-    if name == "c3-solve":
+    if name == "solve-1024":
         log(f"profile {name}: {out[1]}")
     if probe:
         copy_probe(torch, dev)
@@ -729,7 +729,7 @@ def main():
     from paper_1608_02461_amd import hfmm, workloads
 
     dev = torch.device("cuda:0")
-    w = workloads.fmm_c2()
+    w = workloads.fmm_2p20()
     N, k, leaf, p = len(w["xy"]), w["k"], w["leaf"], args.p
     xy = torch.from_numpy(w["xy"]).to(dev)
     q32 = torch.from_numpy(w["q"].astype(np.complex64)).to(dev)
@@ -787,7 +787,7 @@ def main():
                 "algorithmic_bytes_per_launch": (8 + 8 + 4 + 8) * N,
                 "pairs_per_s": round(plan["pairs"] / (ms_p2p * 1e-3), 1)}
 
-    gold = np.load(os.path.join(ROOT, "tests", "golden", "c2_reference.npz"))
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "apply_2p20_reference.npz"))
     smp = gold["samples"]
     phi_np = phi.cpu().numpy()[smp]
     err32 = float(np.linalg.norm(phi_np - gold["direct"]) / np.linalg.norm(gold["direct"]))
@@ -804,15 +804,15 @@ def main():
         "rel_err_2048_samples": err32,
         "roofline": roofline,
         # the M2L launch on the far-field chain's stream (beside the near field)
-        "m2l_roofline": m2l_roofline(tree, plan["orders"], stages["m2l"], "fp32", f"c2_p{p}_fp32"),
+        "m2l_roofline": m2l_roofline(tree, plan["orders"], stages["m2l"], "fp32", f"apply_2p20_p{p}_fp32"),
     }
 
     if not args.no_extras:
-        result["fmm_c2"] = bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan)
-        result["solve_1024"] = bench_c3(dev, hfmm, workloads, torch)
-        result["batch_16x4"] = bench_c4(dev, hfmm, workloads, torch)
-        result["adjoint_256"] = bench_c5(dev, hfmm, workloads, torch)
-        result["solve_64"] = bench_c1(dev, hfmm, workloads, torch)
+        result["fmm_2p20"] = bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan)
+        result["solve_1024"] = bench_solve_1024(dev, hfmm, workloads, torch)
+        result["batch_16x4"] = bench_batch_16x4(dev, hfmm, workloads, torch)
+        result["adjoint_256"] = bench_adjoint_256(dev, hfmm, workloads, torch)
+        result["solve_64"] = bench_solve_64(dev, hfmm, workloads, torch)
         result["helm2_dirichlet"] = bench_helm2(dev, hfmm, torch)
         result["bicgstab_vs_fgmres"] = bench_bicgstab(dev, hfmm, torch)
         result["precond_accuracy_study"] = bench_pstudy(dev, hfmm, workloads, torch)

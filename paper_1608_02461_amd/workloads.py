@@ -7,14 +7,14 @@ All generators are numpy PCG64 (``numpy.random.default_rng(seed)``).
 Workloads (the paper runs its own synthetic PDE model problems, Sec. 6; no
 dataset is involved):
 
-* ``solve_c1``   64 x 64 interior grid, h = 1/65, k = 16, f complex N(0,1).
-* ``fmm_c2``     N = 2^20 uniform points in the unit square, complex N(0,1)
+* ``solve_64``   64 x 64 interior grid, h = 1/65, k = 16, f complex N(0,1).
+* ``fmm_2p20``     N = 2^20 uniform points in the unit square, complex N(0,1)
                  charges, k = 100, 2048 sampled targets.
-* ``solve_c3``   1024 x 1024 grid, k = 0.3/h, Gaussian bump
+* ``solve_1024``   1024 x 1024 grid, k = 0.3/h, Gaussian bump
                  f = exp(-|x - x0|^2 / 0.01) with x0 uniform in [0.25, 0.75]^2.
-* ``batch_c4``   16 problems, k uniform in [20, 300], n from {128,256,384,512}
+* ``batch_16x4``   16 problems, k uniform in [20, 300], n from {128,256,384,512}
                  with k h <= 0.6, 4 right-hand sides each, complex64 N(0,1).
-* ``adjoint_c5`` 256 x 256 grid, k^2 constant on 16 x 16 blocks with values in
+* ``adjoint_256`` 256 x 256 grid, k^2 constant on 16 x 16 blocks with values in
                  [0.8, 1.2] * 100^2, 512 sampled nodes, f complex N(0,1).
 """
 
@@ -37,13 +37,13 @@ def complex_normal(rng, shape, dtype=np.complex128):
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
 
 
-def solve_c1(n=64, k=16.0, seed=1):
+def solve_64(n=64, k=16.0, seed=1):
     rng = np.random.default_rng(seed)
     f = complex_normal(rng, n * n)
     return {"n": n, "h": grid_h(n), "k": k, "f": f, "p": 6, "leaf": 32, "restart": 30, "rtol": 1e-6}
 
 
-def fmm_c2(N=1 << 20, k=100.0, seed=2, n_samples=2048, nrhs=1):
+def fmm_2p20(N=1 << 20, k=100.0, seed=2, n_samples=2048, nrhs=1):
     rng = np.random.default_rng(seed)
     xy = rng.random((N, 2))
     q = complex_normal(rng, (N, nrhs) if nrhs > 1 else N)
@@ -51,7 +51,7 @@ def fmm_c2(N=1 << 20, k=100.0, seed=2, n_samples=2048, nrhs=1):
     return {"xy": xy, "q": q, "k": k, "samples": np.sort(samples), "leaf": 64}
 
 
-def solve_c3(n=1024, kh=0.3, seed=3):
+def solve_1024(n=1024, kh=0.3, seed=3):
     rng = np.random.default_rng(seed)
     h = grid_h(n)
     x0 = rng.uniform(0.25, 0.75, 2)
@@ -61,7 +61,7 @@ def solve_c3(n=1024, kh=0.3, seed=3):
     return {"n": n, "h": h, "k": kh / h, "f": f, "x0": x0, "leaf": 32, "restart": 50, "rtol": 1e-6}
 
 
-def batch_c4(seed=4, n_problems=16, nrhs=4, sizes=(128, 256, 384, 512), kh_max=0.6):
+def batch_16x4(seed=4, n_problems=16, nrhs=4, sizes=(128, 256, 384, 512), kh_max=0.6):
     rng = np.random.default_rng(seed)
     probs = []
     for _ in range(n_problems):
@@ -73,7 +73,7 @@ def batch_c4(seed=4, n_problems=16, nrhs=4, sizes=(128, 256, 384, 512), kh_max=0
     return {"problems": probs, "p": 6, "leaf": 32, "restart": 200, "rtol": 1e-6}
 
 
-def adjoint_c5(n=256, nb=16, k0=100.0, n_obs=512, seed=5):
+def adjoint_256(n=256, nb=16, k0=100.0, n_obs=512, seed=5):
     rng = np.random.default_rng(seed)
     kb = rng.uniform(0.8, 1.2, (nb, nb)) * k0 * k0
     P = np.sort(rng.choice(n * n, n_obs, replace=False))

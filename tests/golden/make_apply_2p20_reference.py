@@ -1,9 +1,9 @@
-"""Writes c2_reference.npz: the direct N-body sum (oracle.kernel) at sampled
+"""Writes apply_2p20_reference.npz: the direct N-body sum (oracle.kernel) at sampled
 targets of the N = 2^20, k = 100 workload, and the reference FMM's own
 relative error there for p = 4, 8, 12 (oracle.fmm, leaf 64).
 
 Calls only oracle/ and the seeded input recipe.  Run from the repository
-root:  python tests/golden/make_c2_reference.py
+root:  python tests/golden/make_apply_2p20_reference.py
 """
 import os
 import sys
@@ -21,7 +21,7 @@ N_SAMPLES = 2048
 
 
 def main():
-    w = workloads.fmm_c2()
+    w = workloads.fmm_2p20()
     xy, q, k = w["xy"], w["q"], w["k"]
     samples = w["samples"][:N_SAMPLES]
     t = time.time()
@@ -34,7 +34,7 @@ def main():
         err = np.linalg.norm(f - direct) / np.linalg.norm(direct)
         out[f"eps_oracle_p{p}"] = err
         print(f"oracle FMM p={p}: rel err {err:.3e} ({time.time() - t:.1f} s)", flush=True)
-    np.savez(os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_reference.npz"), **out)
+    np.savez(os.path.join(os.path.dirname(os.path.abspath(__file__)), "apply_2p20_reference.npz"), **out)
 
 
 if __name__ == "__main__":

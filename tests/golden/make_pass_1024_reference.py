@@ -1,4 +1,4 @@
-"""Writes c3_reference.npz: the first FMM pass of the preconditioner on the
+"""Writes pass_1024_reference.npz: the first FMM pass of the preconditioner on the
 1024 x 1024 grid (k h = 0.3, Gaussian-bump source), as the direct N-body sum
 (oracle.kernel) at 2048 seeded targets, and the reference FMM's own relative
 error there for p = 4, 6, 8 (oracle.fmm, leaf 32).
@@ -7,7 +7,7 @@ The pass sums the sources h^2 f at the interior nodes over the tree of
 interior nodes and boundary element midpoints (Sec. 5.3: the volume term is
 the dominant N_Omega x N_Omega product), so the targets are drawn from all
 nodes of that tree.  Calls only oracle/ and the seeded input recipe.  Run from
-the repository root:  python tests/golden/make_c3_reference.py
+the repository root:  python tests/golden/make_pass_1024_reference.py
 """
 import os
 import sys
@@ -26,7 +26,7 @@ SEED = 33
 
 
 def main():
-    w = workloads.solve_c3()
+    w = workloads.solve_1024()
     n, k, h = w["n"], w["k"], w["h"]
     pts = np.concatenate([bem.interior_nodes(n), bem.boundary_nodes(n)])
     q = np.zeros(pts.shape[0], dtype=np.complex128)
@@ -42,7 +42,7 @@ def main():
         err = np.linalg.norm(f - direct) / np.linalg.norm(direct)
         out[f"eps_oracle_p{p}"] = err
         print(f"oracle FMM p={p}: rel err {err:.3e} ({time.time() - t:.1f} s)", flush=True)
-    np.savez(os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_reference.npz"), **out)
+    np.savez(os.path.join(os.path.dirname(os.path.abspath(__file__)), "pass_1024_reference.npz"), **out)
 
 
 if __name__ == "__main__":

@@ -13,7 +13,7 @@ from gpu_util import rel, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "c2_reference.npz")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "apply_2p20_reference.npz")
 
 
 def morton_np(ix, iy):
@@ -190,13 +190,13 @@ def test_invalid_arguments():
         hfmm.hfmm_fmm_apply(t, 5000.0, 6, to_dev(q[:, 0]))
 
 
-@pytest.mark.skipif(not os.path.exists(GOLD), reason="stored C2 reference missing")
+@pytest.mark.skipif(not os.path.exists(GOLD), reason="stored 2^20 apply reference missing")
 @pytest.mark.parametrize("p", [4, 8, 12])
-def test_c2_full_size_sampled(p):
+def test_apply_2p20_full_size_sampled(p):
     """N = 2^20, k = 100, leaf 64: sampled targets against the stored direct sum."""
-    say(f"C2 full size p={p}")
+    say(f"2^20 apply full size p={p}")
     g = np.load(GOLD)
-    w = workloads.fmm_c2()
+    w = workloads.fmm_2p20()
     samples = g["samples"]
     assert np.array_equal(samples, w["samples"][: samples.size])
     t = hfmm.Tree(to_dev(w["xy"]), leaf_size=w["leaf"])

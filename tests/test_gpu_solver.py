@@ -59,17 +59,17 @@ def test_precond_fp32(n, k, p, leaf):
     assert rel(z, ref_fmm) <= 1e-4
 
 
-def test_c1_solve_fp64():
+def test_solve_64_fp64():
     """64 x 64, k = 16, FGMRES(30), p = 6, leaf 32: true residual <= 1e-6 and
     the error bound ||x - x*|| <= ||A^-1|| ||b - A x|| against sparse direct."""
-    w = workloads.solve_c1()
+    w = workloads.solve_64()
     n, k = w["n"], w["k"]
     s = hfmm.Solver(n, k, p=w["p"], leaf_size=w["leaf"], prec=hfmm.FP64)
     x, info = s.solve(to_dev(w["f"]), restart=w["restart"], rtol=w["rtol"])
     x = to_np(x)
     A = fd.matrix(n, k * k)
     res = np.linalg.norm(w["f"] - A @ x) / np.linalg.norm(w["f"])
-    say(f"  C1 fp64: iters={info['iters']} restarts={info['restarts']} rel_res={res:.3e} (reported {info['rel_res_true']:.3e})")
+    say(f"  64^2 fp64: iters={info['iters']} restarts={info['restarts']} rel_res={res:.3e} (reported {info['rel_res_true']:.3e})")
     assert info["converged"] == 1
     assert res <= 1e-6
     assert abs(res - info["rel_res_true"]) <= 1e-9
@@ -84,14 +84,14 @@ def test_c1_solve_fp64():
     assert abs(info["iters"] - io["iters"]) <= 5
 
 
-def test_c1_solve_fp32_preconditioner():
-    w = workloads.solve_c1()
+def test_solve_64_fp32_preconditioner():
+    w = workloads.solve_64()
     n, k = w["n"], w["k"]
     s = hfmm.Solver(n, k, p=w["p"], leaf_size=w["leaf"], prec=hfmm.FP32)
     x, info = s.solve(to_dev(w["f"]), restart=w["restart"], rtol=w["rtol"])
     A = fd.matrix(n, k * k)
     res = np.linalg.norm(w["f"] - A @ to_np(x)) / np.linalg.norm(w["f"])
-    say(f"  C1 fp32-precond: iters={info['iters']} rel_res={res:.3e}")
+    say(f"  64^2 fp32-precond: iters={info['iters']} rel_res={res:.3e}")
     assert info["converged"] == 1 and res <= 1e-6
 
 
@@ -246,7 +246,7 @@ def test_graph_kept_across_solves_and_dropped_on_change():
 
 def test_leaf_size_autotune():
     """leaf_size = 0 times the candidate trees and keeps one; the solve still meets rtol."""
-    w = workloads.solve_c1()
+    w = workloads.solve_64()
     n, k = w["n"], w["k"]
     s = hfmm.Solver(n, k, p=6, leaf_size=0, prec=hfmm.FP32)
     inf = s.info()
@@ -262,7 +262,7 @@ def test_solve_with_bf16_m2l_converges():
     """The preconditioner with its M2L operands rounded to BF16 still takes
     the 64 x 64 solve to the true residual 1e-6 (Sec. 6.1: the
     preconditioner need not be accurate)."""
-    w = workloads.solve_c1()
+    w = workloads.solve_64()
     s = hfmm.Solver(w["n"], w["k"], p=w["p"], leaf_size=w["leaf"], prec=hfmm.FP32)
     _, base = s.solve(to_dev(w["f"]), restart=w["restart"], rtol=w["rtol"])
     s.set_m2l_input_rounding("bf16")

@@ -129,7 +129,7 @@ def test_bicgstab_solve(prec):
     """BiCGSTAB with the FMM preconditioner reaches the true residual and the
     error bound against sparse direct; its count is beside the oracle's with
     the dense preconditioner (parity unpinned: both are reported)."""
-    w = workloads.solve_c1()
+    w = workloads.solve_64()
     n, k = w["n"], w["k"]
     s = hfmm.Solver(n, k, p=w["p"], leaf_size=w["leaf"], prec=prec)
     x, info = s.bicgstab(to_dev(w["f"]), rtol=1e-6)
@@ -167,7 +167,7 @@ def test_bicgstab_multi_rhs_zero_column_and_maxit():
 
 
 def test_solve_info_timings():
-    w = workloads.solve_c1()
+    w = workloads.solve_64()
     s = hfmm.Solver(w["n"], w["k"], p=6, leaf_size=32)
     _, info = s.solve(to_dev(w["f"]), restart=30)
     say(f"  setup {info['ms_setup']:.2f} ms, precond {info['ms_precond']:.2f} ms, krylov {info['ms_krylov']:.2f} ms, "

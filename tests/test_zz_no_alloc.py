@@ -17,7 +17,7 @@ def test_noalloc_matches_apply(prec, dt, tol):
     cap = hfmm.hfmm_fmm_noalloc_capacity()
     assert cap == 64 << 20
     cases = []
-    w = workloads.fmm_c2()
+    w = workloads.fmm_2p20()
     cases.append(("N=2^20 leaf 64", w["xy"], w["q"][:, None], 64, w["k"], 8))
     xy, q = workloads.random_cloud(3000, seed=91, nrhs=2)
     cases.append(("N=3000 leaf 16, 2 columns", xy, q, 16, 40.0, 10))
@@ -38,7 +38,7 @@ def test_noalloc_matches_apply(prec, dt, tol):
 
 
 def test_noalloc_limits():
-    w = workloads.fmm_c2()
+    w = workloads.fmm_2p20()
     t = hfmm.Tree(to_dev(w["xy"]), leaf_size=64)
     q2 = to_dev(np.repeat(w["q"][:, None], 2, axis=1))
     hfmm.hfmm_fmm_plan_info(t, w["k"], 8, hfmm.FP64)
