@@ -17,6 +17,10 @@ the definitions state:
                   the quad-tree of Sec. 5.1.1) written with Graf's addition
                   theorem, so that "the oracle's own FMM error at order p" has
                   a meaning.
+* ``fmm3``     -- the same flow on the oct-tree with the 3-D kernel
+                  exp(i k r) / (4 pi r) (Sec. 5.1.1, Sec. 5.2), with
+                  spherical-harmonic expansions and Gaunt-coefficient
+                  translations.
 * ``bem``      -- the dense BEM preconditioner of Sec. 5.2-5.3 (Dirichlet
                   boundary equation, interior equation, constant elements and
                   the analytic singular diagonal), and the solution with
@@ -31,4 +35,4 @@ Every function names the passage it follows.  Readings of passages where the
 paper is silent or ambiguous are stated at the function.
 """
 
-from . import kernel, fmm, bem, fd, fgmres, bicgstab, adjoint  # noqa: F401
+from . import kernel, fmm, fmm3, bem, fd, fgmres, bicgstab, adjoint  # noqa: F401
