@@ -354,6 +354,56 @@ hfmm_status hfmm_solver_set_m2l_input_rounding(hfmm_solver s, int32_t mode);
 
 hfmm_status hfmm_solver_destroy(hfmm_solver s);
 
+/* ------------------------------------------------------------------------
+ * 3-D FMM on an oct-tree (the 3-D decomposition of Sec. 5.1.1, the 3-D
+ * Green's function G = exp(i k r) / (4 pi r) of Sec. 5.2, the calculation
+ * flow of Sec. 5.1.2).
+ *
+ * hfmm3_build_tree: uniform oct-tree over the cube [x0, x0+side] x
+ * [y0, y0+side] x [z0, z0+side].
+ *   d_xyz      n x 3 FP64 (x, y, z) per point, device, caller-owned, read
+ *              during the call only.
+ *   leaf_size  >= 1; depth L = max(2, smallest L with leaf_size 8^L >= n),
+ *              at most 7.
+ * Errors: n < 1 or >= 2^30, side <= 0, a point outside the cube or
+ * non-finite (checked on the device, HFMM_ERR_ARG, nothing created), depth
+ * above 7.  Synchronises `stream`. */
+typedef struct hfmm3_tree_s* hfmm3_tree;
+hfmm_status hfmm3_build_tree(const double* d_xyz, int64_t n, double x0, double y0, double z0, double side,
+                             int32_t leaf_size, hipStream_t stream, hfmm3_tree* out);
+/* levels, points, leaves (8^L) and the largest leaf; each output may be NULL. */
+hfmm_status hfmm3_tree_info(hfmm3_tree t, int32_t* levels, int64_t* n_points, int64_t* n_leaves,
+                            int32_t* max_leaf_count);
+hfmm_status hfmm3_tree_destroy(hfmm3_tree t);
+
+/* phi[i] = sum_{j : |x_i - x_j| > 0} G(|x_i - x_j|) q[j], caller order.
+ * k     wavenumber > 0.   p  leaf expansion order, 1..20; level l uses
+ *       p_l = p + floor(k d_l / 2) (d_l the box diameter sqrt(3) side / 2^l),
+ *       (p_l + 1)^2 coefficients, each at most 20.
+ * prec  HFMM_FP64: q, phi complex128.  HFMM_FP32: complex64, FP32 arithmetic.
+ * d_q   n complex, device.   d_phi  n complex, device, overwritten.
+ * The first call for a (k, p, prec) builds and caches the plan: the
+ * translation tables (M2L for the 316 offsets of each level, M2M and L2L for
+ * the 8 child positions), built on the host and uploaded synchronously, and
+ * the expansion arrays.  Async on stream afterwards; applies on one tree
+ * must not overlap in time.
+ * Errors: k <= 0, p out of range, an order above 20, leaves too large for k
+ * (k times the leaf half-diagonal above 6), FP32 tables that would overflow,
+ * a tree of depth < 2. */
+hfmm_status hfmm3_fmm_apply(hfmm3_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                            void* d_phi, hipStream_t stream);
+
+/* The same apply with hipEvents between its stages: ms_stages (host, 6
+ * floats) receives [0] the upward pass (charge gather, P2M, M2M), [1] the
+ * M2L of every level, [2] the L2L levels, [3] the P2P, [4] the L2P (which
+ * adds the near field and writes caller order) and [5] the total, in ms.
+ * Synchronises `stream`. */
+hfmm_status hfmm3_fmm_apply_timed(hfmm3_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                                  void* d_phi, float* ms_stages, hipStream_t stream);
+
+/* Expansion order of each level (host, levels + 1 ints). */
+hfmm_status hfmm3_fmm_orders(hfmm3_tree t, double k, int32_t p, int32_t* orders);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,7 @@
 // extern "C" entry points of libhfmm.so (declared in include/hfmm.h).
 // Every call converts C++ exceptions into an hfmm_status and a thread-local
 // message; nothing throws across the interface.
+#include <cmath>
 #include <new>
 #include <string>
 #include <vector>
@@ -418,6 +419,86 @@ hfmm_status hfmm_solver_set_m2l_input_rounding(hfmm_solver s, int32_t mode) {
 hfmm_status hfmm_solver_destroy(hfmm_solver s) {
   HFMM_GUARD_BEGIN
   delete s;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+// ------------------------------------------------------------------ 3-D oct-tree FMM
+hfmm_status hfmm3_build_tree(const double* d_xyz, int64_t n, double x0, double y0, double z0, double side,
+                             int32_t leaf_size, hipStream_t stream, hfmm3_tree* out) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(out != nullptr, "build_tree3: out is NULL");
+  *out = nullptr;
+  auto h = std::make_unique<hfmm3_tree_s>();
+  h->t = hfmm::build_tree3(d_xyz, n, x0, y0, z0, side, leaf_size, stream);
+  *out = h.release();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_tree_info(hfmm3_tree t, int32_t* levels, int64_t* n_points, int64_t* n_leaves,
+                            int32_t* max_leaf_count) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "tree3_info: NULL tree");
+  if (levels) *levels = t->t->L;
+  if (n_points) *n_points = t->t->n;
+  if (n_leaves) *n_leaves = t->t->nleaves;
+  if (max_leaf_count) *max_leaf_count = t->t->max_leaf;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_tree_destroy(hfmm3_tree t) {
+  HFMM_GUARD_BEGIN
+  delete t;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+static void fmm3_check(hfmm3_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q, const void* d_phi,
+                       const char* who) {
+  HFMM_REQUIRE(t != nullptr && t->t, std::string(who) + ": NULL tree");
+  HFMM_REQUIRE(prec == HFMM_FP64 || prec == HFMM_FP32, std::string(who) + ": unknown precision");
+  HFMM_REQUIRE(std::isfinite(k) && k > 0, std::string(who) + ": k must be finite and > 0");
+  HFMM_REQUIRE(p >= 1 && p <= 20, std::string(who) + ": p must be in [1, 20]");
+  HFMM_REQUIRE(d_q != nullptr && d_phi != nullptr, std::string(who) + ": NULL array");
+}
+
+hfmm_status hfmm3_fmm_apply(hfmm3_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                            void* d_phi, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  fmm3_check(t, k, p, prec, d_q, d_phi, "fmm3_apply");
+  if (prec == HFMM_FP64)
+    hfmm::fmm3_apply<double>(*t->t, k, p, static_cast<const double2*>(d_q), static_cast<double2*>(d_phi), stream,
+                             nullptr);
+  else
+    hfmm::fmm3_apply<float>(*t->t, k, p, static_cast<const float2*>(d_q), static_cast<float2*>(d_phi), stream,
+                            nullptr);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_fmm_apply_timed(hfmm3_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
+                                  void* d_phi, float* ms_stages, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  fmm3_check(t, k, p, prec, d_q, d_phi, "fmm3_apply_timed");
+  HFMM_REQUIRE(ms_stages != nullptr, "fmm3_apply_timed: ms_stages is NULL");
+  if (prec == HFMM_FP64)
+    hfmm::fmm3_apply<double>(*t->t, k, p, static_cast<const double2*>(d_q), static_cast<double2*>(d_phi), stream,
+                             ms_stages);
+  else
+    hfmm::fmm3_apply<float>(*t->t, k, p, static_cast<const float2*>(d_q), static_cast<float2*>(d_phi), stream,
+                            ms_stages);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_fmm_orders(hfmm3_tree t, double k, int32_t p, int32_t* orders) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(t != nullptr && t->t, "fmm3_orders: NULL tree");
+  HFMM_REQUIRE(orders != nullptr, "fmm3_orders: orders is NULL");
+  const std::vector<int> o = hfmm::fmm3_orders(*t->t, k, p);
+  for (size_t l = 0; l < o.size(); ++l) orders[l] = o[l];
   return HFMM_OK;
   HFMM_GUARD_END
 }

@@ -1,0 +1,869 @@
+// 3-D Helmholtz FMM on the oct-tree (Sec. 5.1.1 in 3-D, the kernel
+// exp(i k r) / (4 pi r) of Sec. 5.2, the flow of Sec. 5.1.2).
+//
+// Expansions (the paper defers its 3-D expansions to a library; these follow
+// from the addition theorem of the spherical Hankel function):
+//   R_n^m(x) = j_n(k|x|) Y_n^m(x/|x|),  S_n^m(x) = h_n(k|x|) Y_n^m(x/|x|),
+//   Y_n^m orthonormal with the Condon-Shortley phase, n <= p_l, all m;
+//   P2M  M_nm = i k sum_j q_j conj(R_n^m(y_j - c)),  far field sum M_nm S_n^m(x - c)
+//   L2P  phi(x) = sum L_nm R_n^m(x - c)
+//   translations  T_{n'm',nm}(t) = 4 pi sum_l i^(n'+l-n) f_l(k|t|) conj(Y_l^(m'-m)(t/|t|))
+//                                  * integral(conj(Y_n'^m') Y_l^(m'-m) Y_n^m),
+//   f_l = j_l (M2M with t = parent - child centre, L2L with t = child -
+//   parent centre) or h_l (M2L with t = target - source centre).
+//
+// Data layout in HBM: the expansions of a level are [box (Morton)][Kp] reals,
+// Re of coefficient n^2+n+m at n^2+n+m, Im at P2 + n^2+n+m (P2 = (p_l+1)^2),
+// zero up to Kp = 2 P2 rounded up to 16.  Every translation is then a real
+// matrix product on the matrix cores, A = [[Re T, -Im T], [Im T, Re T]]:
+//   M2M  parent = [A_0 .. A_7] x (its 8 children's vectors, contiguous in
+//        Morton order): one product with K = 8 Kp_child;
+//   L2L  (the 8 children's vectors, contiguous) += [A_0; ..; A_7] x parent;
+//   M2L  for the 8 parity classes of target boxes, the 189 offsets of the
+//        class's interaction list, each a product over all targets of the
+//        class (sources outside the domain read zero).
+// The leaf kernels build R_n^m from solid harmonics: with u = k (x - c),
+// s = |u|, j_n(s) = s^n jh_n(s) and s^n Y_n^m = Rh_n^m(u_z, s^2) (u_x + i u_y)^m,
+// where jh_n (a power series in s^2, then the downward three-term
+// recurrence) and Rh_n^m (the normalised Legendre recurrence times powers of
+// s) are polynomials: no division, no special case at the box centre.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "devutil.h"
+#include "fmm3.h"
+#include "special.h"
+#include "tree.h"
+
+namespace hfmm {
+
+namespace {
+
+constexpr double kPi3 = 3.14159265358979323846;
+constexpr int kMaxP3 = 20;  // largest order of any level
+
+typedef float f32x4_3 __attribute__((ext_vector_type(4)));
+typedef double f64x4_3 __attribute__((ext_vector_type(4)));
+template <class T> struct Acc3;
+template <> struct Acc3<float> { typedef f32x4_3 type; };
+template <> struct Acc3<double> { typedef f64x4_3 type; };
+__device__ __forceinline__ f32x4_3 mfma3(float a, float b, f32x4_3 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4_3 mfma3(double a, double b, f64x4_3 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// row of the 16x16 accumulator in register q of lane group kq = lane/16
+template <class T> __device__ __forceinline__ int acc_row(int kq, int q);
+template <> __device__ __forceinline__ int acc_row<float>(int kq, int q) { return 4 * kq + q; }
+template <> __device__ __forceinline__ int acc_row<double>(int kq, int q) { return 4 * q + kq; }
+
+template <class T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
+__device__ __forceinline__ void sincosT(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincosT(double x, double* s, double* c) { sincos(x, s, c); }
+
+// ------------------------------------------------------------------ tree
+__global__ void k3_morton(const double* __restrict__ xyz, int n, double x0, double y0, double z0, double side,
+                          int L, uint32_t* __restrict__ keys, int32_t* __restrict__ vals, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+  const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && x >= x0 && x <= x0 + side && y >= y0 &&
+                  y <= y0 + side && z >= z0 && z <= z0 + side;
+  if (!ok) bad[0] = 1;
+  const int nb = 1 << L;
+  int ix = 0, iy = 0, iz = 0;
+  if (ok) {
+    ix = min(max((int)floor((x - x0) / side * nb), 0), nb - 1);
+    iy = min(max((int)floor((y - y0) / side * nb), 0), nb - 1);
+    iz = min(max((int)floor((z - z0) / side * nb), 0), nb - 1);
+  }
+  keys[i] = morton3((uint32_t)ix, (uint32_t)iy, (uint32_t)iz);
+  vals[i] = i;
+}
+
+__global__ void k3_finalize(const double* __restrict__ xyz, const uint32_t* __restrict__ skeys,
+                            const int32_t* __restrict__ perm, int n, double x0, double y0, double z0, double lside,
+                            double4* __restrict__ rel64, float4* __restrict__ rel32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  const uint32_t key = skeys[i];
+  const double cx = x0 + (compact3(key) + 0.5) * lside;
+  const double cy = y0 + (compact3(key >> 1) + 0.5) * lside;
+  const double cz = z0 + (compact3(key >> 2) + 0.5) * lside;
+  const double rx = xyz[3 * o] - cx, ry = xyz[3 * o + 1] - cy, rz = xyz[3 * o + 2] - cz;
+  rel64[i] = make_double4(rx, ry, rz, 0.0);
+  rel32[i] = make_float4((float)rx, (float)ry, (float)rz, 0.f);
+}
+
+// ------------------------------------------------------------------ leaf kernels
+template <class T>
+struct Leaf3Args {
+  const typename Vec4<T>::type* rel;  // sorted points minus leaf centre
+  const cplx<T>* qs;                  // sorted charges (P2M, P2P)
+  const cplx<T>* near;                // near field, sorted (L2P)
+  cplx<T>* near_out;                  // (P2P)
+  const int32_t* perm;                // (L2P)
+  const int32_t* off;                 // leaf offsets
+  T* E;                               // leaf-level M (P2M) or L (L2P)
+  cplx<T>* out;                       // caller order (L2P)
+  const T* rec;                       // (a, b) of the Legendre recurrence, then Q_m^m
+  int p, P2, Kp, nser, L;
+  T k, h;                             // wavenumber, leaf side (P2P)
+};
+
+// jh_n(s) = j_n(s) / s^n for n = 0..p into col[n * 64]: the power series
+// jh_n = 1/(2n+1)!! sum_t (-s^2/2)^t / (t! (2n+3)(2n+5)...(2n+2t+1)) at n = p
+// and p - 1 (K terms, by Horner), then jh_{n-1} = (2n+1) jh_n - s^2 jh_{n+1}.
+template <class T>
+__device__ __forceinline__ T jh_series(int n, int K, T s2) {
+  const T y = T(0.5) * s2;
+  T S = T(1);
+  for (int t = K; t >= 1; --t) S = fmaT(-y / (T(t) * T(2 * n + 2 * t + 1)), S, T(1));
+  T df = T(1);
+  for (int i = 3; i <= 2 * n + 1; i += 2) df *= T(i);
+  return S / df;
+}
+template <class T>
+__device__ __forceinline__ void jh_all(int p, int K, T s2, T* col) {
+  col[p * 64] = jh_series<T>(p, K, s2);
+  if (p >= 1) col[(p - 1) * 64] = jh_series<T>(p - 1, K, s2);
+  for (int n = p - 1; n >= 1; --n) col[(n - 1) * 64] = T(2 * n + 1) * col[n * 64] - s2 * col[(n + 1) * 64];
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// P2M: one wave per leaf; each lane takes one point of a 64-point chunk and
+// walks its R_n^m; the wave sums every coefficient over its lanes.
+template <class T>
+__global__ __launch_bounds__(64) void k3_p2m(Leaf3Args<T> a) {
+  __shared__ T jh[(kMaxP3 + 1) * 64];
+  __shared__ T acc[2 * (kMaxP3 + 1) * (kMaxP3 + 1)];
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int b0 = a.off[leaf], b1 = a.off[leaf + 1];
+  for (int c = lane; c < 2 * a.P2; c += 64) acc[c] = T(0);
+  __syncthreads();
+  const T* qmm = a.rec + (a.p + 1) * (a.p + 2);
+  for (int base = b0; base < b1; base += 64) {
+    const int i = base + lane;
+    const bool v = i < b1;
+    typename Vec4<T>::type r = a.rel[v ? i : b0];
+    cplx<T> q = a.qs[v ? i : b0];
+    if (!v) q = mk<T>(0, 0);
+    const T ux = a.k * r.x, uy = a.k * r.y, uz = a.k * r.z;
+    const T s2 = ux * ux + uy * uy + uz * uz;
+    jh_all<T>(a.p, a.nser, s2, jh + lane);
+    cplx<T> wm = mk<T>(1, 0);
+    for (int m = 0; m <= a.p; ++m) {
+      if (m > 0) wm = mk<T>(wm.x * ux - wm.y * uy, wm.x * uy + wm.y * ux);
+      T r2 = 0, r1 = qmm[m];
+      const T sg = (m & 1) ? T(-1) : T(1);
+      for (int n = m; n <= a.p; ++n) {
+        if (n > m) {
+          const T* ab = a.rec + 2 * (n * (n + 1) / 2 + m);
+          const T rn = ab[0] * (uz * r1 - ab[1] * s2 * r2);
+          r2 = r1;
+          r1 = rn;
+        }
+        const T jr = jh[n * 64 + lane] * r1;
+        const T bx = jr * wm.x, by = jr * wm.y;  // R_n^m (m >= 0)
+        // q conj(R_n^m)
+        const T pr = wave_sum(q.x * bx + q.y * by), pi = wave_sum(q.y * bx - q.x * by);
+        const int c = n * n + n + m;
+        if (lane == 0) {
+          acc[c] += pr;
+          acc[a.P2 + c] += pi;
+        }
+        if (m > 0) {
+          // conj(R_n^-m) = (-1)^m R_n^m
+          const T nr = wave_sum(sg * (q.x * bx - q.y * by)), ni = wave_sum(sg * (q.x * by + q.y * bx));
+          if (lane == 0) {
+            acc[c - 2 * m] += nr;
+            acc[a.P2 + c - 2 * m] += ni;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  T* out = a.E + (size_t)leaf * a.Kp;
+  for (int c = lane; c < a.Kp; c += 64) {
+    // times i k
+    T v = T(0);
+    if (c < a.P2) v = -a.k * acc[a.P2 + c];
+    else if (c < 2 * a.P2) v = a.k * acc[c - a.P2];
+    out[c] = v;
+  }
+}
+
+// L2P: one wave per leaf, one lane per point; the leaf's local expansion in
+// LDS; adds the near field and writes caller order.
+template <class T>
+__global__ __launch_bounds__(64) void k3_l2p(Leaf3Args<T> a) {
+  __shared__ T jh[(kMaxP3 + 1) * 64];
+  __shared__ T Ls[2 * (kMaxP3 + 1) * (kMaxP3 + 1)];
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int b0 = a.off[leaf], b1 = a.off[leaf + 1];
+  if (b0 == b1) return;
+  const T* src = a.E + (size_t)leaf * a.Kp;
+  for (int c = lane; c < 2 * a.P2; c += 64) Ls[c] = src[c];
+  __syncthreads();
+  const T* qmm = a.rec + (a.p + 1) * (a.p + 2);
+  for (int base = b0; base < b1; base += 64) {
+    const int i = base + lane;
+    const bool v = i < b1;
+    typename Vec4<T>::type r = a.rel[v ? i : b0];
+    const T ux = a.k * r.x, uy = a.k * r.y, uz = a.k * r.z;
+    const T s2 = ux * ux + uy * uy + uz * uz;
+    jh_all<T>(a.p, a.nser, s2, jh + lane);
+    T ar = 0, ai = 0;
+    cplx<T> wm = mk<T>(1, 0);
+    for (int m = 0; m <= a.p; ++m) {
+      if (m > 0) wm = mk<T>(wm.x * ux - wm.y * uy, wm.x * uy + wm.y * ux);
+      T r2 = 0, r1 = qmm[m];
+      const T sg = (m & 1) ? T(-1) : T(1);
+      for (int n = m; n <= a.p; ++n) {
+        if (n > m) {
+          const T* ab = a.rec + 2 * (n * (n + 1) / 2 + m);
+          const T rn = ab[0] * (uz * r1 - ab[1] * s2 * r2);
+          r2 = r1;
+          r1 = rn;
+        }
+        const T jr = jh[n * 64 + lane] * r1;
+        const T bx = jr * wm.x, by = jr * wm.y;
+        const int c = n * n + n + m;
+        const T lr = Ls[c], li = Ls[a.P2 + c];
+        ar += lr * bx - li * by;
+        ai += lr * by + li * bx;
+        if (m > 0) {
+          // R_n^-m = (-1)^m conj(R_n^m)
+          const T mr = Ls[c - 2 * m], mi = Ls[a.P2 + c - 2 * m];
+          ar += sg * (mr * bx + mi * by);
+          ai += sg * (mi * bx - mr * by);
+        }
+      }
+    }
+    if (v) {
+      const cplx<T> nf = a.near[i];
+      a.out[a.perm[i]] = mk<T>(nf.x + ar, nf.y + ai);
+    }
+  }
+}
+
+// P2P: one wave per target leaf, one lane per target point; the 27
+// neighbouring leaves' points staged through LDS 64 at a time.  Offsets
+// between leaf centres are whole multiples of the leaf side, so the
+// difference of two points is formed from leaf-relative coordinates.
+template <class T>
+__global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
+  typedef typename Vec4<T>::type V;
+  __shared__ V sp[64];
+  __shared__ cplx<T> sq[64];
+  const int leaf = xcd_swizzle(blockIdx.x, gridDim.x), lane = threadIdx.x;
+  const int t0 = a.off[leaf], t1 = a.off[leaf + 1];
+  if (t0 == t1) return;
+  const int bx = (int)compact3((uint32_t)leaf), by = (int)compact3((uint32_t)leaf >> 1),
+            bz = (int)compact3((uint32_t)leaf >> 2);
+  const int nb = 1 << a.L;
+  const T inv4pi = T(1.0 / (4.0 * kPi3));
+  for (int tb = t0; tb < t1; tb += 64) {
+    const int i = tb + lane;
+    const bool v = i < t1;
+    const V rt = a.rel[v ? i : t0];
+    T ar = 0, ai = 0;
+    for (int nbi = 0; nbi < 27; ++nbi) {
+      const int dx = nbi % 3 - 1, dy = (nbi / 3) % 3 - 1, dz = nbi / 9 - 1;
+      const int sx = bx + dx, sy = by + dy, sz = bz + dz;
+      if (sx < 0 || sy < 0 || sz < 0 || sx >= nb || sy >= nb || sz >= nb) continue;
+      const int s = (int)morton3((uint32_t)sx, (uint32_t)sy, (uint32_t)sz);
+      const int s0 = a.off[s], s1 = a.off[s + 1];
+      // target centre minus source centre
+      const T ox = T(-dx) * a.h, oy = T(-dy) * a.h, oz = T(-dz) * a.h;
+      for (int sb = s0; sb < s1; sb += 64) {
+        __syncthreads();
+        const int j = sb + lane;
+        if (j < s1) {
+          sp[lane] = a.rel[j];
+          sq[lane] = a.qs[j];
+        }
+        __syncthreads();
+        const int cnt = min(64, s1 - sb);
+        for (int jj = 0; jj < cnt; ++jj) {
+          const V ps = sp[jj];
+          const T ddx = (rt.x - ps.x) + ox, ddy = (rt.y - ps.y) + oy, ddz = (rt.z - ps.z) + oz;
+          const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          const T r = sqrt(r2);
+          const T inv = r2 > T(0) ? T(1) / r : T(0);
+          T sn, cs;
+          sincosT(a.k * r, &sn, &cs);
+          const cplx<T> qq = sq[jj];
+          const T gr = cs * inv, gi = sn * inv;
+          ar += qq.x * gr - qq.y * gi;
+          ai += qq.x * gi + qq.y * gr;
+        }
+      }
+    }
+    if (v) a.near_out[i] = mk<T>(ar * inv4pi, ai * inv4pi);
+  }
+}
+
+template <class T>
+__global__ void k3_gather(const cplx<T>* __restrict__ q, const int32_t* __restrict__ perm, int n,
+                          cplx<T>* __restrict__ qs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) qs[i] = q[perm[i]];
+}
+
+// ------------------------------------------------------------------ translations on MFMA
+// C[:, col] (+)= A x B[:, col] over 16-row tiles of A (RT of them) and 4-k
+// steps (KS), A laid out per lane: A_frag[rt][ks][lane] = A[16 rt + lane%16][4 ks + lane/16].
+// A block has 4 waves, each with kNC3 column tiles of 16 and up to kRG3 row
+// tiles (grid.y walks the row groups).  M2L mode: grid.z is the parity class
+// of the target boxes, a column is a class member, and the 189 offsets of the
+// class's interaction list are summed (table slot (dx+3)*49 + (dy+3)*7 + dz+3).
+constexpr int kNC3 = 2, kRG3 = 4, kColsPerBlock3 = 4 * kNC3 * 16;
+
+template <class T>
+struct Tr3Args {
+  const T* A;
+  const T* B;
+  T* C;
+  int RT, KS, ncols, crows, accumulate;
+  int64_t ldb, ldc, aslot;  // column strides; M2L: table stride per offset slot
+  int m2l, nb, h;           // M2L: boxes per axis, nb / 2
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
+  typedef typename Acc3<T>::type V4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, kq = lane >> 4;
+  const int rg0 = blockIdx.y * kRG3;
+  const int nrt = min(kRG3, a.RT - rg0);
+  const int px = blockIdx.z & 1, py = (blockIdx.z >> 1) & 1, pz = (blockIdx.z >> 2) & 1;
+  int tx[kNC3], ty[kNC3], tz[kNC3], obox[kNC3];
+  bool colv[kNC3];
+#pragma unroll
+  for (int c = 0; c < kNC3; ++c) {
+    const int col = (blockIdx.x * 4 + wave) * (kNC3 * 16) + c * 16 + j;
+    colv[c] = col < a.ncols;
+    const int cc = colv[c] ? col : 0;
+    if (a.m2l) {
+      tx[c] = 2 * (cc % a.h) + px;
+      ty[c] = 2 * ((cc / a.h) % a.h) + py;
+      tz[c] = 2 * (cc / (a.h * a.h)) + pz;
+      obox[c] = (int)morton3((uint32_t)tx[c], (uint32_t)ty[c], (uint32_t)tz[c]);
+    } else {
+      tx[c] = ty[c] = tz[c] = 0;
+      obox[c] = cc;
+    }
+  }
+  V4 acc[kRG3][kNC3];
+#pragma unroll
+  for (int r = 0; r < kRG3; ++r)
+#pragma unroll
+    for (int c = 0; c < kNC3; ++c) acc[r][c] = V4{0, 0, 0, 0};
+  const int noff = a.m2l ? 216 : 1;
+  for (int o = 0; o < noff; ++o) {
+    const T* Ao = a.A;
+    const T* bcol[kNC3];
+    bool bv[kNC3];
+    if (a.m2l) {
+      const int dx = o % 6 + px - 3, dy = (o / 6) % 6 + py - 3, dz = o / 36 + pz - 3;
+      if (max(max(abs(dx), abs(dy)), abs(dz)) <= 1) continue;
+      Ao = a.A + (size_t)((dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)) * a.aslot;
+#pragma unroll
+      for (int c = 0; c < kNC3; ++c) {
+        const int sx = tx[c] - dx, sy = ty[c] - dy, sz = tz[c] - dz;
+        bv[c] = colv[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < a.nb && sy < a.nb && sz < a.nb;
+        const int sb = bv[c] ? (int)morton3((uint32_t)sx, (uint32_t)sy, (uint32_t)sz) : 0;
+        bcol[c] = a.B + (size_t)sb * a.ldb;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < kNC3; ++c) {
+        bv[c] = colv[c];
+        bcol[c] = a.B + (size_t)obox[c] * a.ldb;
+      }
+    }
+    for (int ks0 = 0; ks0 < a.KS; ks0 += 4) {
+      T av[4][kRG3], bw[4][kNC3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int r = 0; r < kRG3; ++r)
+          av[u][r] = r < nrt ? Ao[((size_t)(rg0 + r) * a.KS + ks0 + u) * 64 + lane] : T(0);
+#pragma unroll
+        for (int c = 0; c < kNC3; ++c) bw[u][c] = bv[c] ? bcol[c][(ks0 + u) * 4 + kq] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < kRG3; ++r)
+          if (r < nrt) {
+#pragma unroll
+            for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(av[u][r], bw[u][c], acc[r][c]);
+          }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRG3; ++r) {
+    if (r >= nrt) continue;
+#pragma unroll
+    for (int c = 0; c < kNC3; ++c) {
+      if (!colv[c]) continue;
+      T* dst = a.C + (size_t)obox[c] * a.ldc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * (rg0 + r) + acc_row<T>(kq, q);
+        if (row < a.crows) dst[row] = a.accumulate ? dst[row] + acc[r][c][q] : acc[r][c][q];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host tables
+inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+inline int kpad(int P2) { return (2 * P2 + 15) / 16 * 16; }
+
+// Theta_n^m(x), m >= 0, of Y_n^m = Theta_n^m(cos th) e^{i m ph} (orthonormal,
+// Condon-Shortley phase) for n <= nmax: Q_m^m = (-1)^m sqrt((2m+1)!!/(4 pi (2m)!!)),
+// Q_n^m = a_n^m (x Q_{n-1}^m - b_n^m Q_{n-2}^m), Theta = Q (1 - x^2)^(m/2).
+void theta_table(int nmax, double x, std::vector<double>& out) {
+  out.assign((size_t)tri(nmax, nmax) + 1, 0.0);
+  const double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+  double qmm = 1.0 / std::sqrt(4.0 * kPi3), smm = 1.0;
+  for (int m = 0; m <= nmax; ++m) {
+    if (m > 0) {
+      qmm *= -std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+      smm *= s;
+    }
+    double q2 = 0.0, q1 = qmm;
+    out[tri(m, m)] = qmm * smm;
+    for (int n = m + 1; n <= nmax; ++n) {
+      const double an = std::sqrt((4.0 * n * n - 1.0) / (double(n) * n - double(m) * m));
+      const double bn = std::sqrt(std::max(0.0, ((n - 1.0) * (n - 1.0) - double(m) * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0)));
+      const double qn = an * (x * q1 - bn * q2);
+      out[tri(n, m)] = qn * smm;
+      q2 = q1;
+      q1 = qn;
+    }
+  }
+}
+
+inline double theta_signed(const std::vector<double>& th, int n, int m) {
+  // Theta_n^-m = (-1)^m Theta_n^m
+  return m >= 0 ? th[tri(n, m)] : ((-m) & 1 ? -th[tri(n, -m)] : th[tri(n, -m)]);
+}
+
+// Integrals of conj(Y_n'^m') Y_l^(m'-m) Y_n^m over the sphere by Gauss-Legendre
+// in cos(theta) (exact: the integrand is a polynomial of degree <= 2 (po + pi))
+// after the azimuthal integral (2 pi).
+struct GauntTab {
+  int po = 0, pi = 0, lmax = 0;
+  std::vector<double> g;  // [(a * P2i + b) * (lmax + 1) + l]
+};
+
+GauntTab gaunt_table(int po, int pi) {
+  GauntTab G;
+  G.po = po;
+  G.pi = pi;
+  G.lmax = po + pi;
+  const int P2o = (po + 1) * (po + 1), P2i = (pi + 1) * (pi + 1), nl = G.lmax + 1;
+  G.g.assign((size_t)P2o * P2i * nl, 0.0);
+  const int nq = G.lmax + 2;
+  std::vector<double> xs, ws;
+  gauss_legendre(nq, xs, ws);
+  std::vector<std::vector<double>> th(nq);
+  for (int q = 0; q < nq; ++q) theta_table(G.lmax, xs[q], th[q]);
+  for (int n1 = 0; n1 <= po; ++n1)
+    for (int m1 = -n1; m1 <= n1; ++m1)
+      for (int n = 0; n <= pi; ++n)
+        for (int m = -n; m <= n; ++m) {
+          const int mu = m1 - m;
+          for (int l = std::abs(n1 - n); l <= n1 + n; ++l) {
+            if (((n1 + n + l) & 1) || std::abs(mu) > l) continue;
+            double s = 0.0;
+            for (int q = 0; q < nq; ++q)
+              s += ws[q] * theta_signed(th[q], n1, m1) * theta_signed(th[q], l, mu) * theta_signed(th[q], n, m);
+            G.g[((size_t)(n1 * n1 + n1 + m1) * P2i + (n * n + n + m)) * nl + l] = 2.0 * kPi3 * s;
+          }
+        }
+  return G;
+}
+
+// T (P2o x P2i, row-major) for the shift t: f_l = j_l (regular) or h_l (singular).
+void translation3(const GauntTab& G, double k, const double t[3], bool singular,
+                  std::vector<std::complex<double>>& T) {
+  const int P2o = (G.po + 1) * (G.po + 1), P2i = (G.pi + 1) * (G.pi + 1), nl = G.lmax + 1;
+  const double r = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const double kr = k * r, ph = std::atan2(t[1], t[0]);
+  std::vector<double> th;
+  theta_table(G.lmax, t[2] / r, th);
+  std::vector<std::complex<double>> f(nl);
+  for (int l = 0; l < nl; ++l)
+    f[l] = std::complex<double>(std::sph_bessel(l, kr), singular ? std::sph_neumann(l, kr) : 0.0);
+  // conj(Y_l^mu(t)) for all l, mu
+  auto ycj = [&](int l, int mu) {
+    const std::complex<double> e = std::polar(1.0, -mu * ph);
+    return theta_signed(th, l, mu) * e;
+  };
+  const std::complex<double> ipow[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+  T.assign((size_t)P2o * P2i, 0.0);
+  for (int n1 = 0; n1 <= G.po; ++n1)
+    for (int m1 = -n1; m1 <= n1; ++m1)
+      for (int n = 0; n <= G.pi; ++n)
+        for (int m = -n; m <= n; ++m) {
+          const int a = n1 * n1 + n1 + m1, b = n * n + n + m, mu = m1 - m;
+          const double* g = &G.g[((size_t)a * P2i + b) * nl];
+          std::complex<double> s = 0.0;
+          for (int l = std::abs(n1 - n); l <= n1 + n; ++l) {
+            if (g[l] == 0.0) continue;
+            s += ipow[((n1 + l - n) % 4 + 4) % 4] * f[l] * ycj(l, mu) * g[l];
+          }
+          T[(size_t)a * P2i + b] = 4.0 * kPi3 * s;
+        }
+}
+
+// Real form of T into the per-lane fragment layout, at (row0, col0) of a
+// matrix with KS k-steps.
+template <class T>
+void put_frag(const std::vector<std::complex<double>>& Tm, int P2o, int P2i, int row0, int col0, int KS, T* dst,
+              double& amax) {
+  auto set = [&](int r, int c, double v) {
+    dst[((size_t)(r >> 4) * KS + (c >> 2)) * 64 + (r & 15) + 16 * (c & 3)] = T(v);
+    amax = std::max(amax, std::fabs(v));
+  };
+  for (int i = 0; i < P2o; ++i)
+    for (int jj = 0; jj < P2i; ++jj) {
+      const std::complex<double> z = Tm[(size_t)i * P2i + jj];
+      set(row0 + i, col0 + jj, z.real());
+      set(row0 + i, col0 + P2i + jj, -z.imag());
+      set(row0 + P2o + i, col0 + jj, z.imag());
+      set(row0 + P2o + i, col0 + P2i + jj, z.real());
+    }
+}
+
+template <class T>
+struct Plan3 : Plan3Base {
+  int L = 0, pl = 0, nser = 0;
+  std::vector<int> ord, P2, Kp;
+  std::vector<size_t> eoff, m2l_off, m2m_off, l2l_off;
+  DevBuf<T> M, Lc, A, rec;
+  DevBuf<cplx<T>> qs, near;
+  hipEvent_t ev[6] = {};
+  ~Plan3() override {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+template <class T>
+Plan3<T>& get_plan3(Tree3& t, double k, int p) {
+  const auto key = std::make_tuple(k, p, sizeof(T) == 4 ? 1 : 0);
+  auto it = t.plans.find(key);
+  if (it != t.plans.end()) return static_cast<Plan3<T>&>(*it->second);
+  auto pl = std::make_unique<Plan3<T>>();
+  Plan3<T>& P = *pl;
+  const int L = t.L;
+  P.L = L;
+  P.ord = fmm3_orders(t, k, p);
+  P.P2.assign(L + 1, 0);
+  P.Kp.assign(L + 1, 0);
+  for (int l = 2; l <= L; ++l) {
+    HFMM_REQUIRE(P.ord[l] <= kMaxP3, "fmm3_apply: an expansion order above 20 (lower p or k)");
+    P.P2[l] = (P.ord[l] + 1) * (P.ord[l] + 1);
+    P.Kp[l] = kpad(P.P2[l]);
+  }
+  P.pl = P.ord[L];
+  // the leaf series: |k (y - c)| <= k sqrt(3)/2 h
+  const double smax = k * std::sqrt(3.0) / 2.0 * t.leaf_side();
+  HFMM_REQUIRE(smax <= 6.0, "fmm3_apply: k times the leaf half-diagonal must be <= 6");
+  {
+    const double y = 0.5 * smax * smax;
+    double term = 1.0;
+    int K = 0;
+    while (K < 60) {
+      ++K;
+      term *= y / (K * (2.0 * K + 1.0));
+      if (term < 1e-18) break;
+    }
+    P.nser = K + 1;
+  }
+  // expansions
+  P.eoff.assign(L + 2, 0);
+  size_t tot = 0;
+  for (int l = 2; l <= L; ++l) {
+    P.eoff[l] = tot;
+    tot += ((size_t)1 << (3 * l)) * P.Kp[l];
+  }
+  P.M.alloc(tot);
+  P.Lc.alloc(tot);
+  // tables
+  P.m2l_off.assign(L + 1, 0);
+  P.m2m_off.assign(L + 1, 0);
+  P.l2l_off.assign(L + 1, 0);
+  size_t at = 0;
+  for (int l = 2; l <= L; ++l) {
+    P.m2l_off[l] = at;
+    at += (size_t)343 * P.Kp[l] * P.Kp[l];
+  }
+  for (int l = 2; l < L; ++l) {
+    P.m2m_off[l] = at;
+    at += (size_t)P.Kp[l] * 8 * P.Kp[l + 1];
+  }
+  for (int l = 3; l <= L; ++l) {
+    P.l2l_off[l] = at;
+    at += (size_t)8 * P.Kp[l] * P.Kp[l - 1];
+  }
+  std::vector<T> hA(at, T(0));
+  double amax = 0.0;
+  std::vector<std::complex<double>> Tm;
+  for (int l = 2; l <= L; ++l) {
+    const double s = t.side_len / double(1 << l);
+    const GauntTab G = gaunt_table(P.ord[l], P.ord[l]);
+    const int KS = P.Kp[l] / 4;
+    for (int dz = -3; dz <= 3; ++dz)
+      for (int dy = -3; dy <= 3; ++dy)
+        for (int dx = -3; dx <= 3; ++dx) {
+          if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) <= 1) continue;
+          const double tv[3] = {dx * s, dy * s, dz * s};
+          translation3(G, k, tv, true, Tm);
+          put_frag<T>(Tm, P.P2[l], P.P2[l], 0, 0, KS,
+                      hA.data() + P.m2l_off[l] + (size_t)((dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)) * P.Kp[l] * P.Kp[l],
+                      amax);
+        }
+  }
+  for (int l = 2; l < L; ++l) {
+    const double sc = t.side_len / double(1 << (l + 1));
+    const GauntTab G = gaunt_table(P.ord[l], P.ord[l + 1]);
+    const int KS = 8 * P.Kp[l + 1] / 4;
+    for (int oc = 0; oc < 8; ++oc) {
+      // parent centre minus child centre
+      const double tv[3] = {-((oc & 1) - 0.5) * sc, -(((oc >> 1) & 1) - 0.5) * sc, -(((oc >> 2) & 1) - 0.5) * sc};
+      translation3(G, k, tv, false, Tm);
+      put_frag<T>(Tm, P.P2[l], P.P2[l + 1], 0, oc * P.Kp[l + 1], KS, hA.data() + P.m2m_off[l], amax);
+    }
+  }
+  for (int l = 3; l <= L; ++l) {
+    const double sc = t.side_len / double(1 << l);
+    const GauntTab G = gaunt_table(P.ord[l], P.ord[l - 1]);
+    const int KS = P.Kp[l - 1] / 4;
+    for (int oc = 0; oc < 8; ++oc) {
+      // child centre minus parent centre
+      const double tv[3] = {((oc & 1) - 0.5) * sc, (((oc >> 1) & 1) - 0.5) * sc, (((oc >> 2) & 1) - 0.5) * sc};
+      translation3(G, k, tv, false, Tm);
+      put_frag<T>(Tm, P.P2[l], P.P2[l - 1], oc * P.Kp[l], 0, KS, hA.data() + P.l2l_off[l], amax);
+    }
+  }
+  HFMM_REQUIRE(std::isfinite(amax) && (sizeof(T) == 8 || amax < 1e30),
+               "fmm3_apply: translation entries out of range for this precision (lower p or raise k h)");
+  P.A.upload(hA);
+  // leaf recurrences: (a_n^m, b_n^m) for m <= n <= pl, then Q_m^m
+  {
+    const int pl_ = P.pl;
+    std::vector<T> rec((size_t)(pl_ + 1) * (pl_ + 2) + pl_ + 1, T(0));
+    for (int n = 0; n <= pl_; ++n)
+      for (int m = 0; m <= n; ++m) {
+        if (n > m) {
+          rec[2 * tri(n, m)] = T(std::sqrt((4.0 * n * n - 1.0) / (double(n) * n - double(m) * m)));
+          rec[2 * tri(n, m) + 1] =
+              T(std::sqrt(std::max(0.0, ((n - 1.0) * (n - 1.0) - double(m) * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0))));
+        }
+      }
+    double qmm = 1.0 / std::sqrt(4.0 * kPi3);
+    for (int m = 0; m <= pl_; ++m) {
+      if (m > 0) qmm *= -std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+      rec[(size_t)(pl_ + 1) * (pl_ + 2) + m] = T(qmm);
+    }
+    P.rec.upload(rec);
+  }
+  P.qs.alloc(t.n);
+  P.near.alloc(t.n);
+  for (auto& e : P.ev) HFMM_HIP(hipEventCreate(&e));
+  Plan3<T>& ref = P;
+  t.plans.emplace(key, std::move(pl));
+  return ref;
+}
+
+}  // namespace
+
+int tree3_depth(int64_t n, int leaf_size) {
+  if (leaf_size <= 0) return 0;
+  int L = 0;
+  while ((double)leaf_size * std::pow(8.0, L) < (double)n) ++L;
+  return std::max(2, L);
+}
+
+std::vector<int> fmm3_orders(const Tree3& t, double k, int p) {
+  std::vector<int> o(t.L + 1);
+  for (int l = 0; l <= t.L; ++l)
+    o[l] = p + (int)std::floor(k * std::sqrt(3.0) * t.side_len / std::ldexp(1.0, l) / 2.0);
+  return o;
+}
+
+std::unique_ptr<Tree3> build_tree3(const double* d_xyz, int64_t n, double x0, double y0, double z0, double side,
+                                   int leaf_size, hipStream_t stream) {
+  HFMM_REQUIRE(n >= 1, "build_tree3: n must be >= 1");
+  HFMM_REQUIRE(n < (int64_t(1) << 30), "build_tree3: n must be below 2^30");
+  HFMM_REQUIRE(std::isfinite(side) && side > 0, "build_tree3: side must be finite and > 0");
+  HFMM_REQUIRE(std::isfinite(x0) && std::isfinite(y0) && std::isfinite(z0), "build_tree3: root corner must be finite");
+  HFMM_REQUIRE(leaf_size >= 1, "build_tree3: leaf_size must be >= 1");
+  HFMM_REQUIRE(d_xyz != nullptr, "build_tree3: d_xyz is NULL");
+  auto t = std::make_unique<Tree3>();
+  t->n = n;
+  t->L = tree3_depth(n, leaf_size);
+  HFMM_REQUIRE(t->L <= 7, "build_tree3: depth above 7 (raise leaf_size)");
+  t->x0 = x0;
+  t->y0 = y0;
+  t->z0 = z0;
+  t->side_len = side;
+  t->leaf_size = leaf_size;
+  t->nleaves = int64_t(1) << (3 * t->L);
+  const int N = (int)n, blocks = (N + 255) / 256;
+  DevBuf<uint32_t> keys(N);
+  DevBuf<int32_t> vals(N);
+  DevBuf<int> bad(1);
+  HFMM_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), stream));
+  k3_morton<<<blocks, 256, 0, stream>>>(d_xyz, N, x0, y0, z0, side, t->L, keys.p, vals.p, bad.p);
+  HFMM_LAUNCH_CHECK();
+  int hbad = 0;
+  HFMM_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HFMM_HIP(hipStreamSynchronize(stream));
+  HFMM_REQUIRE(hbad == 0, "build_tree3: a coordinate is non-finite or outside the root cube");
+  radix_sort_pairs(keys, vals, N, 3 * t->L, stream);
+  t->perm = std::move(vals);
+  t->rel64.alloc(N);
+  t->rel32.alloc(N);
+  k3_finalize<<<blocks, 256, 0, stream>>>(d_xyz, keys.p, t->perm.p, N, x0, y0, z0, t->leaf_side(), t->rel64.p,
+                                          t->rel32.p);
+  HFMM_LAUNCH_CHECK();
+  t->leaf_off.alloc(t->nleaves + 1);
+  leaf_bounds(keys.p, N, t->nleaves, t->leaf_off.p, stream);
+  std::vector<int32_t> off(t->nleaves + 1);
+  HFMM_HIP(hipMemcpyAsync(off.data(), t->leaf_off.p, (t->nleaves + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          stream));
+  HFMM_HIP(hipStreamSynchronize(stream));
+  int mx = 0;
+  for (int64_t b = 0; b < t->nleaves; ++b) mx = std::max(mx, off[b + 1] - off[b]);
+  t->max_leaf = mx;
+  if (off[t->nleaves] != N) throw Error(HFMM_ERR_INTERNAL, "build_tree3: leaf offsets do not sum to n");
+  return t;
+}
+
+template <class T>
+void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, hipStream_t stream,
+                float* stage_ms) {
+  HFMM_REQUIRE(t.L >= 2, "fmm3_apply: the tree needs depth >= 2");
+  Plan3<T>& P = get_plan3<T>(t, k, p);
+  const int L = t.L, N = (int)t.n;
+  const int nleaves = (int)t.nleaves;
+  Leaf3Args<T> la{};
+  if constexpr (sizeof(T) == 8) la.rel = t.rel64.p;
+  else la.rel = t.rel32.p;
+  la.qs = P.qs.p;
+  la.near = P.near.p;
+  la.near_out = P.near.p;
+  la.perm = t.perm.p;
+  la.off = t.leaf_off.p;
+  la.out = d_phi;
+  la.rec = P.rec.p;
+  la.p = P.pl;
+  la.P2 = P.P2[L];
+  la.Kp = P.Kp[L];
+  la.nser = P.nser;
+  la.L = L;
+  la.k = T(k);
+  la.h = T(t.leaf_side());
+  if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[0], stream));
+  // upward pass
+  k3_gather<T><<<(N + 255) / 256, 256, 0, stream>>>(d_q, t.perm.p, N, P.qs.p);
+  HFMM_LAUNCH_CHECK();
+  la.E = P.M.p + P.eoff[L];
+  k3_p2m<T><<<nleaves, 64, 0, stream>>>(la);
+  HFMM_LAUNCH_CHECK();
+  for (int l = L - 1; l >= 2; --l) {
+    Tr3Args<T> a{};
+    a.A = P.A.p + P.m2m_off[l];
+    a.B = P.M.p + P.eoff[l + 1];
+    a.C = P.M.p + P.eoff[l];
+    a.RT = P.Kp[l] / 16;
+    a.KS = 8 * P.Kp[l + 1] / 4;
+    a.ncols = 1 << (3 * l);
+    a.crows = P.Kp[l];
+    a.accumulate = 0;
+    a.ldb = 8 * P.Kp[l + 1];
+    a.ldc = P.Kp[l];
+    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + kRG3 - 1) / kRG3, 1);
+    k3_trans<T><<<g, 256, 0, stream>>>(a);
+    HFMM_LAUNCH_CHECK();
+  }
+  if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[1], stream));
+  // M2L on every level
+  for (int l = 2; l <= L; ++l) {
+    Tr3Args<T> a{};
+    a.A = P.A.p + P.m2l_off[l];
+    a.B = P.M.p + P.eoff[l];
+    a.C = P.Lc.p + P.eoff[l];
+    a.RT = P.Kp[l] / 16;
+    a.KS = P.Kp[l] / 4;
+    a.h = 1 << (l - 1);
+    a.nb = 1 << l;
+    a.ncols = a.h * a.h * a.h;
+    a.crows = P.Kp[l];
+    a.accumulate = 0;
+    a.ldb = P.Kp[l];
+    a.ldc = P.Kp[l];
+    a.aslot = (int64_t)P.Kp[l] * P.Kp[l];
+    a.m2l = 1;
+    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + kRG3 - 1) / kRG3, 8);
+    k3_trans<T><<<g, 256, 0, stream>>>(a);
+    HFMM_LAUNCH_CHECK();
+  }
+  if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[2], stream));
+  // downward pass
+  for (int l = 3; l <= L; ++l) {
+    Tr3Args<T> a{};
+    a.A = P.A.p + P.l2l_off[l];
+    a.B = P.Lc.p + P.eoff[l - 1];
+    a.C = P.Lc.p + P.eoff[l];
+    a.RT = 8 * P.Kp[l] / 16;
+    a.KS = P.Kp[l - 1] / 4;
+    a.ncols = 1 << (3 * (l - 1));
+    a.crows = 8 * P.Kp[l];
+    a.accumulate = 1;
+    a.ldb = P.Kp[l - 1];
+    a.ldc = 8 * P.Kp[l];
+    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + kRG3 - 1) / kRG3, 1);
+    k3_trans<T><<<g, 256, 0, stream>>>(a);
+    HFMM_LAUNCH_CHECK();
+  }
+  if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[3], stream));
+  k3_p2p<T><<<nleaves, 64, 0, stream>>>(la);
+  HFMM_LAUNCH_CHECK();
+  if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[4], stream));
+  la.E = P.Lc.p + P.eoff[L];
+  k3_l2p<T><<<nleaves, 64, 0, stream>>>(la);
+  HFMM_LAUNCH_CHECK();
+  if (stage_ms) {
+    HFMM_HIP(hipEventRecord(P.ev[5], stream));
+    HFMM_HIP(hipEventSynchronize(P.ev[5]));
+    for (int s = 0; s < 5; ++s) HFMM_HIP(hipEventElapsedTime(&stage_ms[s], P.ev[s], P.ev[s + 1]));
+    HFMM_HIP(hipEventElapsedTime(&stage_ms[5], P.ev[0], P.ev[5]));
+  }
+}
+
+template void fmm3_apply<float>(Tree3&, double, int, const float2*, float2*, hipStream_t, float*);
+template void fmm3_apply<double>(Tree3&, double, int, const double2*, double2*, hipStream_t, float*);
+
+}  // namespace hfmm

@@ -5,6 +5,7 @@
 #include <new>
 #include <string>
 
+#include "fmm3.h"
 #include "solver.h"
 
 struct hfmm_tree_s {
@@ -12,6 +13,9 @@ struct hfmm_tree_s {
 };
 struct hfmm_solver_s {
   std::unique_ptr<hfmm::Solver> s;
+};
+struct hfmm3_tree_s {
+  std::unique_ptr<hfmm::Tree3> t;
 };
 
 #define HFMM_GUARD_BEGIN try {

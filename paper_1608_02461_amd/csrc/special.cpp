@@ -143,10 +143,11 @@ bool fit_near_poly(double tmax, bool fp32, const int* cand, int ncand, int nplai
   return false;
 }
 
-std::complex<double> volume_self_term(double k, double h) {
-  // 24-point Gauss-Legendre on [0, pi/4]; the integrand is smooth in theta.
-  const int n = 24;
-  std::vector<double> xs(n), ws(n);
+void gauss_legendre(int n, std::vector<double>& xs, std::vector<double>& ws) {
+  // Newton's iteration on P_n from the Chebyshev-like first guess; P_n and
+  // P_{n-1} from the three-term recurrence
+  xs.assign(n, 0.0);
+  ws.assign(n, 0.0);
   for (int i = 0; i < n; ++i) {
     double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), pp = 0;
     for (int it = 0; it < 100; ++it) {
@@ -164,6 +165,13 @@ std::complex<double> volume_self_term(double k, double h) {
     xs[i] = z;
     ws[i] = 2.0 / ((1 - z * z) * pp * pp);
   }
+}
+
+std::complex<double> volume_self_term(double k, double h) {
+  // 24-point Gauss-Legendre on [0, pi/4]; the integrand is smooth in theta.
+  const int n = 24;
+  std::vector<double> xs, ws;
+  gauss_legendre(n, xs, ws);
   const double a = 0.0, b = kPi / 4, half = 0.5 * (b - a), mid = 0.5 * (b + a);
   std::complex<double> acc = 0;
   for (int i = 0; i < n; ++i) {

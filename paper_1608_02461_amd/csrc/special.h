@@ -164,6 +164,8 @@ __host__ __device__ inline double2 h1_general(double x) {
   return r;
 }
 
+// Host: n-point Gauss-Legendre nodes and weights on [-1, 1].
+void gauss_legendre(int n, std::vector<double>& xs, std::vector<double>& ws);
 // Host: J_n(x) for n = 0..nmax.
 void besselj_seq(int nmax, double x, std::vector<double>& J);
 // Host: H_n^(1)(x) = J_n + i Y_n for n = 0..nmax, x > 0.

@@ -54,6 +54,15 @@ struct Tree {
 // Depth rule: 0 for leaf_size <= 0, else max(2, smallest L with leaf*4^L >= n).
 int tree_depth(int64_t n, int leaf_size);
 
+// Stable LSD radix sort (8-bit digits) of (key, value) pairs on the low
+// `nbits` bits of the keys; the sorted pairs are left in ka, va.  Synchronises
+// `stream`.
+void radix_sort_pairs(DevBuf<uint32_t>& ka, DevBuf<int32_t>& va, int n, int nbits, hipStream_t stream);
+
+// Leaf offsets (nleaves + 1 entries) from sorted leaf keys: off[b] is the
+// first slot whose key is >= b.
+void leaf_bounds(const uint32_t* sorted_keys, int n, int64_t nleaves, int32_t* off, hipStream_t stream);
+
 // Builds the tree on `stream` (synchronises it).  Throws Error on bad input.
 std::unique_ptr<Tree> build_tree(const double* d_xy, int64_t n, double x0, double y0, double side,
                                  int leaf_size, hipStream_t stream);

@@ -183,6 +183,33 @@ void scan_excl(uint32_t* a, int64_t m, DevBuf<uint32_t>& sums, hipStream_t st) {
 
 }  // namespace
 
+void radix_sort_pairs(DevBuf<uint32_t>& ka, DevBuf<int32_t>& va, int n, int nbits, hipStream_t stream) {
+  HFMM_REQUIRE(n >= 1 && n < (1 << 31) - kTile, "radix_sort_pairs: bad n");
+  HFMM_REQUIRE(ka.n >= (size_t)n && va.n >= (size_t)n, "radix_sort_pairs: buffers too small");
+  DevBuf<uint32_t> kb(n);
+  DevBuf<int32_t> vb(n);
+  const int ntiles = (n + kTile - 1) / kTile;
+  DevBuf<uint32_t> hist((size_t)256 * ntiles), sums;
+  for (int shift = 0; shift < nbits; shift += 8) {
+    k_digit_hist<<<ntiles, kThreads, 0, stream>>>(ka.p, n, shift, hist.p, ntiles);
+    HFMM_LAUNCH_CHECK();
+    scan_excl(hist.p, (int64_t)256 * ntiles, sums, stream);
+    k_digit_scatter<<<ntiles, kThreads, 0, stream>>>(ka.p, va.p, kb.p, vb.p, n, shift, hist.p, ntiles);
+    HFMM_LAUNCH_CHECK();
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  // the buffers swapped back and forth: the sorted pairs are in ka, va, and
+  // the scratch pair (freed here) is the other one.  Freeing synchronises
+  // nothing, so wait for the passes before the scratch goes.
+  HFMM_HIP(hipStreamSynchronize(stream));
+}
+
+void leaf_bounds(const uint32_t* sorted_keys, int n, int64_t nleaves, int32_t* off, hipStream_t stream) {
+  k_leaf_bounds<<<(n + 255) / 256, 256, 0, stream>>>(sorted_keys, n, nleaves, off);
+  HFMM_LAUNCH_CHECK();
+}
+
 int tree_depth(int64_t n, int leaf_size) {
   if (leaf_size <= 0) return 0;
   int L = 0;

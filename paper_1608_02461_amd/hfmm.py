@@ -84,6 +84,13 @@ _SIGS = {
     "hfmm_solver_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
                          _i32),
     "hfmm_solver_destroy": ([_vp], _i32),
+    "hfmm3_build_tree": ([_vp, _i64, _f64, _f64, _f64, _f64, _i32, _vp, ctypes.POINTER(_vp)], _i32),
+    "hfmm3_tree_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                         ctypes.POINTER(_i32)], _i32),
+    "hfmm3_tree_destroy": ([_vp], _i32),
+    "hfmm3_fmm_apply": ([_vp, _f64, _i32, _i32, _vp, _vp, _vp], _i32),
+    "hfmm3_fmm_apply_timed": ([_vp, _f64, _i32, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp], _i32),
+    "hfmm3_fmm_orders": ([_vp, _f64, _i32, ctypes.POINTER(_i32)], _i32),
 }
 
 
@@ -105,7 +112,7 @@ def lib():
 def header_functions():
     """Entry-point names declared in include/hfmm.h."""
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(hfmm_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hfmm3?_[a-z0-9_]+)\s*\(", text)))
 
 
 def _check(status, allow_not_converged=False):
@@ -293,6 +300,74 @@ def hfmm_fmm_plan_info(tree, k, p, prec=FP64):
     _check(lib().hfmm_fmm_plan_info(tree.handle, float(k), int(p), int(prec), orders, ctypes.byref(deg),
                                     ctypes.byref(g), ctypes.byref(pairs)))
     return {"orders": list(orders), "near_deg": deg.value, "lanes_per_target": g.value, "pairs": pairs.value}
+
+
+# ---------------------------------------------------------------------- 3-D
+STAGES3 = ("upward", "m2l", "l2l", "p2p", "l2p", "total")
+
+
+class Tree3:
+    """Uniform oct-tree over points xyz (n, 3) float64 on the device."""
+
+    def __init__(self, xyz, x0=0.0, y0=0.0, z0=0.0, side=1.0, leaf_size=64, stream=None):
+        _require_cuda(xyz, torch.float64, "xyz")
+        xyz = xyz.contiguous()
+        h = ctypes.c_void_p()
+        _check(lib().hfmm3_build_tree(_ptr(xyz), xyz.shape[0], x0, y0, z0, side, leaf_size, _stream(stream),
+                                      ctypes.byref(h)))
+        self.handle = h
+        self.n = xyz.shape[0]
+        self.device = xyz.device
+
+    def info(self):
+        L, n, nl, mx = _i32(), _i64(), _i64(), _i32()
+        _check(lib().hfmm3_tree_info(self.handle, ctypes.byref(L), ctypes.byref(n), ctypes.byref(nl),
+                                     ctypes.byref(mx)))
+        return {"levels": L.value, "n_points": n.value, "n_leaves": nl.value, "max_leaf_count": mx.value}
+
+    def orders(self, k, p):
+        L = self.info()["levels"]
+        o = (_i32 * (L + 1))()
+        _check(lib().hfmm3_fmm_orders(self.handle, float(k), int(p), o))
+        return list(o)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.hfmm3_tree_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def hfmm3_build_tree(xyz, x0=0.0, y0=0.0, z0=0.0, side=1.0, leaf_size=64, stream=None):
+    return Tree3(xyz, x0, y0, z0, side, leaf_size, stream)
+
+
+def _q3(tree, q, prec):
+    dtype = torch.complex128 if prec == FP64 else torch.complex64
+    _require_cuda(q, dtype, "q")
+    if q.dim() != 1 or q.shape[0] != tree.n:
+        raise ValueError("q must be a vector with one charge per point")
+    return q.contiguous()
+
+
+def hfmm3_fmm_apply(tree, k, p, q, prec=FP64, stream=None):
+    """phi_i = sum_{j != i} q_j exp(i k r_ij) / (4 pi r_ij) by the oct-tree FMM."""
+    qc = _q3(tree, q, prec)
+    phi = torch.empty_like(qc)
+    _check(lib().hfmm3_fmm_apply(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), _stream(stream)))
+    return phi
+
+
+def hfmm3_fmm_apply_timed(tree, k, p, q, prec=FP64, stream=None):
+    """The 3-D apply with per-stage device times; returns (phi, {stage: ms})."""
+    qc = _q3(tree, q, prec)
+    phi = torch.empty_like(qc)
+    ms = (ctypes.c_float * len(STAGES3))()
+    _check(lib().hfmm3_fmm_apply_timed(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), ms,
+                                       _stream(stream)))
+    return phi, dict(zip(STAGES3, list(ms)))
 
 
 def hfmm_fd_helmholtz_matvec(n, h, x, k2=None, k2_const=0.0, stream=None):

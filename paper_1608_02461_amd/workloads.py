@@ -16,6 +16,9 @@ dataset is involved):
                  with k h <= 0.6, 4 right-hand sides each, complex64 N(0,1).
 * ``adjoint_256`` 256 x 256 grid, k^2 constant on 16 x 16 blocks with values in
                  [0.8, 1.2] * 100^2, 512 sampled nodes, f complex N(0,1).
+* ``fmm3_2p20``  the 3-D apply: N = 2^20 uniform points in the unit cube,
+                 complex N(0,1) charges, k = 10, p = 6, leaf 64 (8^5 leaves of
+                 32 points on average), 256 sampled targets.
 """
 
 import numpy as np
@@ -88,3 +91,19 @@ def random_cloud(N, seed, nrhs=1, dtype=np.complex128):
     xy = rng.random((N, 2))
     q = complex_normal(rng, (N, nrhs), dtype)
     return xy, q
+
+
+def fmm3_2p20(N=1 << 20, k=10.0, p=6, seed=6, n_samples=256):
+    rng = np.random.default_rng(seed)
+    xyz = rng.random((N, 3))
+    q = complex_normal(rng, N)
+    samples = np.sort(rng.choice(N, min(n_samples, N), replace=False))
+    return {"xyz": xyz, "q": q, "k": k, "p": p, "leaf": 64, "samples": samples}
+
+
+def random_cloud3(N, seed, dtype=np.complex128):
+    """Uniform points in the unit cube with complex N(0,1) charges (parity cases)."""
+    rng = np.random.default_rng(seed)
+    xyz = rng.random((N, 3))
+    q = complex_normal(rng, N, dtype)
+    return xyz, q
