@@ -641,7 +641,123 @@ def cpu_extra_baselines(workloads):
     return out
 
 
-PROFILE_CASES = ("apply-2p20-fp64", "pass-1024-fp32", "pass-1024-fp64", "solve-1024")
+def m2l3_flops(L, orders, cols_per_block=128):
+    """The 3-D M2L per apply: algorithmic flops (8 P^4 per (target, source)
+    pair of the interaction lists inside the cube, P^2 = (p_l + 1)^2
+    coefficients; a complex multiply-add is 8 real flops) and the MFMA flops
+    the kernel executes (every class member tile of 128 columns, all 189
+    offsets, the real 2P^2 x 2P^2 form padded to 16 rows)."""
+    alg, exe = 0, 0
+    for l in range(2, L + 1):
+        nb, h = 2 ** l, 2 ** (l - 1)
+        P2 = (orders[l] + 1) ** 2
+        kp = (2 * P2 + 15) // 16 * 16
+        pairs = 0
+        for par in range(8):
+            px, py, pz = par & 1, (par >> 1) & 1, (par >> 2) & 1
+            t = [np.arange(h) * 2 + px, np.arange(h) * 2 + py, np.arange(h) * 2 + pz]
+            for dx in range(px - 3, px + 3):
+                cx = int(np.count_nonzero((t[0] - dx >= 0) & (t[0] - dx < nb)))
+                for dy in range(py - 3, py + 3):
+                    cy = int(np.count_nonzero((t[1] - dy >= 0) & (t[1] - dy < nb)))
+                    for dz in range(pz - 3, pz + 3):
+                        if max(abs(dx), abs(dy), abs(dz)) <= 1:
+                            continue
+                        cz = int(np.count_nonzero((t[2] - dz >= 0) & (t[2] - dz < nb)))
+                        pairs += cx * cy * cz
+        alg += pairs * 8 * P2 * P2
+        cols = -(-h ** 3 // cols_per_block) * cols_per_block
+        exe += 8 * cols * 189 * 2 * kp * kp
+    return alg, exe
+
+
+def p2p3_pairs(xyz, L):
+    """Near-field pairs of the oct-tree (27 neighbouring leaves, self pairs excluded)."""
+    nb = 2 ** L
+    ib = np.clip(np.floor(xyz * nb).astype(np.int64), 0, nb - 1)
+    cnt = np.zeros((nb, nb, nb), dtype=np.int64)
+    np.add.at(cnt, (ib[:, 0], ib[:, 1], ib[:, 2]), 1)
+    pad = np.pad(cnt, 1)
+    nsum = np.zeros_like(cnt)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                nsum += pad[1 + dx:1 + dx + nb, 1 + dy:1 + dy + nb, 1 + dz:1 + dz + nb]
+    return int((cnt * nsum).sum() - len(xyz))
+
+
+P2P3_FLOPS_PER_PAIR = 23  # difference 3 + offset 3, r^2 5, sqrt 1, 1/r 1, k r 1, cos and sin 2, G 2, complex MAC 4 + 1 scale
+
+
+def bench_fmm3(dev, hfmm, workloads, torch, runs=10):
+    """The 3-D oct-tree apply (N = 2^20 uniform in the unit cube, k = 10, p = 6,
+    leaf 64): tree build, throughput and per-stage device times in both
+    precisions, the M2L against the MFMA peak of its precision and the P2P
+    pair rate."""
+    w = workloads.fmm3_2p20()
+    xyz = torch.from_numpy(w["xyz"]).to(dev)
+    N, k, p = len(w["xyz"]), w["k"], w["p"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = hfmm.Tree3(xyz, leaf_size=w["leaf"])
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tree2 = hfmm.Tree3(xyz, leaf_size=w["leaf"])
+    torch.cuda.synchronize()
+    t_second = time.perf_counter() - t0
+    tree2.close()
+    info = tree.info()
+    L = info["levels"]
+    orders = tree.orders(k, p)
+    alg, exe = m2l3_flops(L, orders)
+    pairs = p2p3_pairs(w["xyz"], L)
+    out = {"workload": f"3-D FMM apply, N=2^20 uniform points in the unit cube, complex N(0,1) charges, k={k}, "
+                       f"leaf {w['leaf']}, p={p}", "levels": L, "orders": orders,
+           "max_leaf": info["max_leaf_count"], "tree_build_first_ms": round(t_first * 1e3, 3),
+           "tree_build_ms": round(t_second * 1e3, 3), "m2l_algorithmic_flops": alg, "m2l_executed_flops": exe,
+           "p2p_pairs": pairs}
+    phis = {}
+    for name, prec, dt, peak in (("fp32", hfmm.FP32, torch.complex64, 157.3), ("fp64", hfmm.FP64, torch.complex128, 78.6)):
+        q = torch.from_numpy(w["q"]).to(dt).to(dev)
+        t0 = time.perf_counter()
+        hfmm.hfmm3_fmm_apply(tree, k, p, q, prec=prec)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        for _ in range(2):
+            hfmm.hfmm3_fmm_apply(tree, k, p, q, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            phi = hfmm.hfmm3_fmm_apply(tree, k, p, q, prec=prec)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / runs
+        st = {s: 0.0 for s in hfmm.STAGES3}
+        for _ in range(runs):
+            _, ms = hfmm.hfmm3_fmm_apply_timed(tree, k, p, q, prec=prec)
+            for s_ in st:
+                st[s_] += ms[s_] / runs
+        phis[name] = phi.to(torch.complex128).cpu().numpy()
+        m2l_s = st["m2l"] * 1e-3
+        out[name] = {
+            "ms_per_apply": round(dt_s * 1e3, 4), "Mpts_per_s": round(N / dt_s / 1e6, 2),
+            "first_apply_with_plan_s": round(t_plan, 3),
+            "stage_ms": {s_: round(v, 4) for s_, v in st.items()},
+            "m2l_roofline": {"bound": "mfma", "achieved": round(alg / m2l_s / 1e12, 3), "peak": peak,
+                             "unit": "TFLOP/s", "frac": round(alg / m2l_s / 1e12 / peak, 4),
+                             "executed_TFLOP_s": round(exe / m2l_s / 1e12, 3),
+                             "executed_over_algorithmic": round(exe / alg, 3)},
+            "p2p_pairs_per_s": round(pairs / (st["p2p"] * 1e-3), 1),
+            "p2p_alu_TFLOP_s": round(pairs * P2P3_FLOPS_PER_PAIR / (st["p2p"] * 1e-3) / 1e12, 3),
+        }
+        log(f"3-D apply {name}: {out[name]}")
+    out["fp32_vs_fp64_rel"] = float(np.linalg.norm(phis["fp32"] - phis["fp64"]) / np.linalg.norm(phis["fp64"]))
+    tree.close()
+    return out
+
+
+PROFILE_CASES = ("apply-2p20-fp64", "pass-1024-fp32", "pass-1024-fp64", "solve-1024", "apply3-2p20-fp32",
+                 "apply3-2p20-fp64")
 
 
 def copy_probe(torch, dev):
@@ -661,7 +777,9 @@ def profile_case(name, steps, warmup, probe):
     pass-1024-fp64   h^2 f at the interior nodes, k h = 0.3, leaf 32, p = 6);
     solve-1024       solver set-up (tree, boundary inverse, plans) then `steps`
                    complex64-preconditioned FGMRES(50) solves of that system with
-                   the dispersion-matched k0, p = 6."""
+                   the dispersion-matched k0, p = 6;
+    apply3-2p20-fp32 the 3-D oct-tree apply (N = 2^20 in the unit cube, k = 10,
+    apply3-2p20-fp64 leaf 64, p = 6)."""
     import torch
     from paper_1608_02461_amd import hfmm, workloads
     dev = torch.device("cuda:0")
@@ -688,6 +806,12 @@ def profile_case(name, steps, warmup, probe):
         s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=6, leaf_size=w1024["leaf"], prec=hfmm.FP32)
         warmup = 0
         run = lambda: s.solve(f, restart=50, rtol=1e-6, maxit=3000)
+    elif name.startswith("apply3-2p20"):
+        w = workloads.fmm3_2p20()
+        tree = hfmm.Tree3(torch.from_numpy(w["xyz"]).to(dev), leaf_size=w["leaf"])
+        prec, dt = (hfmm.FP32, torch.complex64) if name.endswith("fp32") else (hfmm.FP64, torch.complex128)
+        q = torch.from_numpy(w["q"]).to(dt).to(dev)
+        run = lambda: hfmm.hfmm3_fmm_apply(tree, w["k"], w["p"], q, prec=prec)
     else:
         raise SystemExit(f"unknown profile case {name}; one of {PROFILE_CASES}")
     for _ in range(warmup):
@@ -818,6 +942,7 @@ def main():
         result["precond_accuracy_study"] = bench_pstudy(dev, hfmm, workloads, torch)
         result["m2l_16bit_inputs"] = bench_m2l_rounding(dev, hfmm, workloads, torch, tree, gold, smp)
         result["hbm_kernels"] = bench_hbm(dev, hfmm, workloads, torch, xy)
+        result["fmm3_2p20"] = bench_fmm3(dev, hfmm, workloads, torch)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_direct_sum_baseline(w, smp, k, N)

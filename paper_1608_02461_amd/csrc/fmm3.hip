@@ -328,29 +328,48 @@ __global__ void k3_gather(const cplx<T>* __restrict__ q, const int32_t* __restri
 // ------------------------------------------------------------------ translations on MFMA
 // C[:, col] (+)= A x B[:, col] over 16-row tiles of A (RT of them) and 4-k
 // steps (KS), A laid out per lane: A_frag[rt][ks][lane] = A[16 rt + lane%16][4 ks + lane/16].
-// A block has 4 waves, each with kNC3 column tiles of 16 and up to kRG3 row
-// tiles (grid.y walks the row groups).  M2L mode: grid.z is the parity class
-// of the target boxes, a column is a class member, and the 189 offsets of the
-// class's interaction list are summed (table slot (dx+3)*49 + (dy+3)*7 + dz+3).
-constexpr int kNC3 = 2, kRG3 = 4, kColsPerBlock3 = 4 * kNC3 * 16;
+// A block has 4 waves, each with kNC3 column tiles of 16 and up to RG row
+// tiles (grid.y walks the row groups; RG = 8 in FP32, 4 in FP64).  M2L mode:
+// grid.z is the parity class of the target boxes, a column is a class
+// member, and the 189 offsets of the class's interaction list are summed
+// (table slot (dx+3)*49 + (dy+3)*7 + dz+3, the offsets from `offs`).
+// The (offset, 4-k chunk) iterations are one flat loop: the 4 waves share
+// each A chunk through LDS (double-buffered), and the next chunk's A and B
+// loads are in flight while the current chunk's MFMAs run.
+constexpr int kNC3 = 2, kColsPerBlock3 = 4 * kNC3 * 16;
+template <class T> struct RG3 { static constexpr int v = 8; };
+template <> struct RG3<double> { static constexpr int v = 4; };
 
 template <class T>
 struct Tr3Args {
   const T* A;
   const T* B;
   T* C;
+  const int* offs;  // M2L: [8][189] packed (dx+3) | (dy+3) << 4 | (dz+3) << 8
   int RT, KS, ncols, crows, accumulate;
   int64_t ldb, ldc, aslot;  // column strides; M2L: table stride per offset slot
   int m2l, nb, h;           // M2L: boxes per axis, nb / 2
+  // M2L offset groups: grid.z = 8 S; group g takes offsets [189 g / S,
+  // 189 (g + 1) / S) of its class and, for S > 1, stores its partial sum at
+  // part + g pstride (a later pass adds the S partials)
+  int S;
+  T* part;
+  int64_t pstride;
 };
 
 template <class T>
 __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   typedef typename Acc3<T>::type V4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15, kq = lane >> 4;
-  const int rg0 = blockIdx.y * kRG3;
-  const int nrt = min(kRG3, a.RT - rg0);
-  const int px = blockIdx.z & 1, py = (blockIdx.z >> 1) & 1, pz = (blockIdx.z >> 2) & 1;
+  constexpr int RG = RG3<T>::v;
+  constexpr int ACH = RG * 4 * 64;    // A values per chunk
+  constexpr int APT = ACH / 256;      // per thread
+  __shared__ T abuf[2][ACH];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15, kq = lane >> 4;
+  const int rg0 = blockIdx.y * RG;
+  const int nrt = min(RG, a.RT - rg0);
+  const int par = blockIdx.z & 7, grp = blockIdx.z >> 3;
+  const int o_lo = a.m2l ? 189 * grp / a.S : 0, o_hi = a.m2l ? 189 * (grp + 1) / a.S : 1;
+  const int px = par & 1, py = (par >> 1) & 1, pz = (par >> 2) & 1;
   int tx[kNC3], ty[kNC3], tz[kNC3], obox[kNC3];
   bool colv[kNC3];
 #pragma unroll
@@ -368,61 +387,98 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
       obox[c] = cc;
     }
   }
-  V4 acc[kRG3][kNC3];
-#pragma unroll
-  for (int r = 0; r < kRG3; ++r)
-#pragma unroll
-    for (int c = 0; c < kNC3; ++c) acc[r][c] = V4{0, 0, 0, 0};
-  const int noff = a.m2l ? 216 : 1;
-  for (int o = 0; o < noff; ++o) {
-    const T* Ao = a.A;
-    const T* bcol[kNC3];
-    bool bv[kNC3];
+  const int nch = a.KS >> 2;
+  const int nit = (o_hi - o_lo) * nch;
+  const int* po = a.offs + par * 189 + o_lo;
+  // per-iteration sources: table base and B columns
+  auto locate = [&](int it, const T*& Ab, const T* (&bc)[kNC3], bool (&bv)[kNC3], int& k0) {
+    const int oi = it / nch, ch = it - oi * nch;
+    k0 = ch * 4;
     if (a.m2l) {
-      const int dx = o % 6 + px - 3, dy = (o / 6) % 6 + py - 3, dz = o / 36 + pz - 3;
-      if (max(max(abs(dx), abs(dy)), abs(dz)) <= 1) continue;
-      Ao = a.A + (size_t)((dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)) * a.aslot;
+      const int e = po[oi];
+      const int dx = (e & 15) - 3, dy = ((e >> 4) & 15) - 3, dz = (e >> 8) - 3;
+      Ab = a.A + (size_t)((dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)) * a.aslot;
 #pragma unroll
       for (int c = 0; c < kNC3; ++c) {
         const int sx = tx[c] - dx, sy = ty[c] - dy, sz = tz[c] - dz;
         bv[c] = colv[c] && sx >= 0 && sy >= 0 && sz >= 0 && sx < a.nb && sy < a.nb && sz < a.nb;
         const int sb = bv[c] ? (int)morton3((uint32_t)sx, (uint32_t)sy, (uint32_t)sz) : 0;
-        bcol[c] = a.B + (size_t)sb * a.ldb;
+        bc[c] = a.B + (size_t)sb * a.ldb;
       }
     } else {
+      Ab = a.A;
 #pragma unroll
       for (int c = 0; c < kNC3; ++c) {
         bv[c] = colv[c];
-        bcol[c] = a.B + (size_t)obox[c] * a.ldb;
+        bc[c] = a.B + (size_t)obox[c] * a.ldb;
       }
     }
-    for (int ks0 = 0; ks0 < a.KS; ks0 += 4) {
-      T av[4][kRG3], bw[4][kNC3];
+  };
+  // A chunk element e of this thread: row tile r = e / 256, k step u = (e / 64) % 4, lane e % 64
+  auto loadA = [&](const T* Ab, int k0, T (&ra)[APT]) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+    for (int i = 0; i < APT; ++i) {
+      const int e = i * 256 + tid, r = e >> 8, u = (e >> 6) & 3, ln = e & 63;
+      ra[i] = r < nrt ? Ab[((size_t)(rg0 + r) * a.KS + k0 + u) * 64 + ln] : T(0);
+    }
+  };
+  auto loadB = [&](const T* const (&bc)[kNC3], const bool (&bv)[kNC3], int k0, T (&rb)[4][kNC3]) {
 #pragma unroll
-        for (int r = 0; r < kRG3; ++r)
-          av[u][r] = r < nrt ? Ao[((size_t)(rg0 + r) * a.KS + ks0 + u) * 64 + lane] : T(0);
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int c = 0; c < kNC3; ++c) bw[u][c] = bv[c] ? bcol[c][(ks0 + u) * 4 + kq] : T(0);
-      }
+      for (int c = 0; c < kNC3; ++c) rb[u][c] = bv[c] ? bc[c][(k0 + u) * 4 + kq] : T(0);
+  };
+  V4 acc[RG][kNC3];
+#pragma unroll
+  for (int r = 0; r < RG; ++r)
+#pragma unroll
+    for (int c = 0; c < kNC3; ++c) acc[r][c] = V4{0, 0, 0, 0};
+
+  const T* Ab;
+  const T* bc[kNC3];
+  bool bv[kNC3];
+  int k0;
+  T ra[APT], rb[4][kNC3], rbn[4][kNC3];
+  locate(0, Ab, bc, bv, k0);
+  loadA(Ab, k0, ra);
+  loadB(bc, bv, k0, rb);
+#pragma unroll
+  for (int i = 0; i < APT; ++i) abuf[0][i * 256 + tid] = ra[i];
+  __syncthreads();
+  for (int it = 0; it < nit; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < nit;
+    if (more) {
+      locate(it + 1, Ab, bc, bv, k0);
+      loadA(Ab, k0, ra);
+      loadB(bc, bv, k0, rbn);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+        if (r < nrt) {
+          const T av = abuf[cur][(r * 4 + u) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(av, rb[u][c], acc[r][c]);
+        }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < APT; ++i) abuf[cur ^ 1][i * 256 + tid] = ra[i];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int r = 0; r < kRG3; ++r)
-          if (r < nrt) {
-#pragma unroll
-            for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(av[u][r], bw[u][c], acc[r][c]);
-          }
+        for (int c = 0; c < kNC3; ++c) rb[u][c] = rbn[u][c];
     }
+    __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < kRG3; ++r) {
+  for (int r = 0; r < RG; ++r) {
     if (r >= nrt) continue;
 #pragma unroll
     for (int c = 0; c < kNC3; ++c) {
       if (!colv[c]) continue;
-      T* dst = a.C + (size_t)obox[c] * a.ldc;
+      T* dst = (a.S > 1 ? a.part + grp * a.pstride : a.C) + (size_t)obox[c] * a.ldc;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = 16 * (rg0 + r) + acc_row<T>(kq, q);
@@ -430,6 +486,16 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
       }
     }
   }
+}
+
+// C = sum of the S partial M2L sums (fixed order)
+template <class T>
+__global__ void k3_sum_parts(const T* __restrict__ part, int S, int64_t pstride, T* __restrict__ C) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pstride) return;
+  T s = part[i];
+  for (int g = 1; g < S; ++g) s += part[g * pstride + i];
+  C[i] = s;
 }
 
 // ------------------------------------------------------------------ host tables
@@ -560,6 +626,9 @@ struct Plan3 : Plan3Base {
   std::vector<int> ord, P2, Kp;
   std::vector<size_t> eoff, m2l_off, m2m_off, l2l_off;
   DevBuf<T> M, Lc, A, rec;
+  DevBuf<int> offs;
+  std::vector<int> S;  // M2L offset groups per level
+  DevBuf<T> part;
   DevBuf<cplx<T>> qs, near;
   hipEvent_t ev[6] = {};
   ~Plan3() override {
@@ -688,6 +757,35 @@ Plan3<T>& get_plan3(Tree3& t, double k, int p) {
     }
     P.rec.upload(rec);
   }
+  {
+    // the 189 interaction-list offsets of each parity class, d = target - source
+    std::vector<int> offs;
+    for (int par = 0; par < 8; ++par) {
+      const int px = par & 1, py = (par >> 1) & 1, pz = (par >> 2) & 1;
+      for (int dz = pz - 3; dz <= pz + 2; ++dz)
+        for (int dy = py - 3; dy <= py + 2; ++dy)
+          for (int dx = px - 3; dx <= px + 2; ++dx)
+            if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) >= 2)
+              offs.push_back((dx + 3) | ((dy + 3) << 4) | ((dz + 3) << 8));
+    }
+    if (offs.size() != 8 * 189) throw Error(HFMM_ERR_INTERNAL, "fmm3: interaction offsets are not 189 per class");
+    P.offs.upload(offs);
+  }
+  {
+    // enough blocks to keep about 3 waves on every SIMD: split the 189
+    // offsets of a level whose M2L grid is smaller
+    P.S.assign(L + 1, 1);
+    size_t pmax = 0;
+    for (int l = 2; l <= L; ++l) {
+      const int h = 1 << (l - 1), RT = P.Kp[l] / 16;
+      const int base = 8 * ((h * h * h + kColsPerBlock3 - 1) / kColsPerBlock3) * ((RT + RG3<T>::v - 1) / RG3<T>::v);
+      int S = (768 + base - 1) / base;
+      S = std::max(1, std::min(S, 63));
+      P.S[l] = S;
+      if (S > 1) pmax = std::max(pmax, (size_t)S * ((size_t)1 << (3 * l)) * P.Kp[l]);
+    }
+    if (pmax) P.part.alloc(pmax);
+  }
   P.qs.alloc(t.n);
   P.near.alloc(t.n);
   for (auto& e : P.ev) HFMM_HIP(hipEventCreate(&e));
@@ -794,6 +892,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
   HFMM_LAUNCH_CHECK();
   for (int l = L - 1; l >= 2; --l) {
     Tr3Args<T> a{};
+    a.offs = P.offs.p;
     a.A = P.A.p + P.m2m_off[l];
     a.B = P.M.p + P.eoff[l + 1];
     a.C = P.M.p + P.eoff[l];
@@ -802,9 +901,10 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ncols = 1 << (3 * l);
     a.crows = P.Kp[l];
     a.accumulate = 0;
+    a.S = 1;
     a.ldb = 8 * P.Kp[l + 1];
     a.ldc = P.Kp[l];
-    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + kRG3 - 1) / kRG3, 1);
+    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v, 1);
     k3_trans<T><<<g, 256, 0, stream>>>(a);
     HFMM_LAUNCH_CHECK();
   }
@@ -812,6 +912,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
   // M2L on every level
   for (int l = 2; l <= L; ++l) {
     Tr3Args<T> a{};
+    a.offs = P.offs.p;
     a.A = P.A.p + P.m2l_off[l];
     a.B = P.M.p + P.eoff[l];
     a.C = P.Lc.p + P.eoff[l];
@@ -826,14 +927,22 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ldc = P.Kp[l];
     a.aslot = (int64_t)P.Kp[l] * P.Kp[l];
     a.m2l = 1;
-    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + kRG3 - 1) / kRG3, 8);
+    a.S = P.S[l];
+    a.part = P.part.p;
+    a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
+    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v, 8 * a.S);
     k3_trans<T><<<g, 256, 0, stream>>>(a);
     HFMM_LAUNCH_CHECK();
+    if (a.S > 1) {
+      k3_sum_parts<T><<<(unsigned)((a.pstride + 255) / 256), 256, 0, stream>>>(P.part.p, a.S, a.pstride, a.C);
+      HFMM_LAUNCH_CHECK();
+    }
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[2], stream));
   // downward pass
   for (int l = 3; l <= L; ++l) {
     Tr3Args<T> a{};
+    a.offs = P.offs.p;
     a.A = P.A.p + P.l2l_off[l];
     a.B = P.Lc.p + P.eoff[l - 1];
     a.C = P.Lc.p + P.eoff[l];
@@ -842,9 +951,10 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ncols = 1 << (3 * (l - 1));
     a.crows = 8 * P.Kp[l];
     a.accumulate = 1;
+    a.S = 1;
     a.ldb = P.Kp[l - 1];
     a.ldc = 8 * P.Kp[l];
-    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + kRG3 - 1) / kRG3, 1);
+    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v, 1);
     k3_trans<T><<<g, 256, 0, stream>>>(a);
     HFMM_LAUNCH_CHECK();
   }
