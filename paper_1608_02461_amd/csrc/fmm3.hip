@@ -261,8 +261,29 @@ __global__ __launch_bounds__(64) void k3_l2p(Leaf3Args<T> a) {
   }
 }
 
-// P2P: one wave per target leaf, one lane per target point; the 27
-// neighbouring leaves' points staged through LDS 64 at a time.  Offsets
+// One pair of the near field: G(r) r 4 pi = (cos k r + i sin k r) / r, zero
+// at r = 0.  FP32: the hardware reciprocal square root and the hardware sine
+// and cosine (arguments in turns, k r / 2 pi below a few turns here); FP64:
+// IEEE square root, division and sincos.
+__device__ __forceinline__ void pair3(float r2, float k, float k2pi, float& gr, float& gi) {
+  const float inv = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float t = r2 * inv * k2pi;
+  gr = __builtin_amdgcn_cosf(t) * inv;
+  gi = __builtin_amdgcn_sinf(t) * inv;
+}
+__device__ __forceinline__ void pair3(double r2, double k, double, double& gr, double& gi) {
+  const double r = sqrt(r2);
+  const double inv = r2 > 0.0 ? 1.0 / r : 0.0;
+  double sn, cs;
+  sincos(k * r, &sn, &cs);
+  gr = cs * inv;
+  gi = sn * inv;
+}
+
+// P2P: one wave per target leaf; a leaf of at most 32 points gives each
+// target 2 lanes (even and odd sources, summed by a lane swap at the end),
+// a larger one a lane per target, 64 targets per pass.  The 27
+// neighbouring leaves' points are staged through LDS 64 at a time.  Offsets
 // between leaf centres are whole multiples of the leaf side, so the
 // difference of two points is formed from leaf-relative coordinates.
 template <class T>
@@ -276,9 +297,12 @@ __global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
   const int bx = (int)compact3((uint32_t)leaf), by = (int)compact3((uint32_t)leaf >> 1),
             bz = (int)compact3((uint32_t)leaf >> 2);
   const int nb = 1 << a.L;
-  const T inv4pi = T(1.0 / (4.0 * kPi3));
-  for (int tb = t0; tb < t1; tb += 64) {
-    const int i = tb + lane;
+  const T inv4pi = T(1.0 / (4.0 * kPi3)), k2pi = T(double(a.k) / (2.0 * kPi3));
+  const bool two = t1 - t0 <= 32;
+  const int G = two ? 2 : 1, sub = two ? (lane & 1) : 0, tl = two ? (lane >> 1) : lane;
+  const int per = 64 / G;
+  for (int tb = t0; tb < t1; tb += per) {
+    const int i = tb + tl;
     const bool v = i < t1;
     const V rt = a.rel[v ? i : t0];
     T ar = 0, ai = 0;
@@ -290,6 +314,7 @@ __global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
       const int s0 = a.off[s], s1 = a.off[s + 1];
       // target centre minus source centre
       const T ox = T(-dx) * a.h, oy = T(-dy) * a.h, oz = T(-dz) * a.h;
+      const T cx = rt.x + ox, cy = rt.y + oy, cz = rt.z + oz;
       for (int sb = s0; sb < s1; sb += 64) {
         __syncthreads();
         const int j = sb + lane;
@@ -299,22 +324,23 @@ __global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
         }
         __syncthreads();
         const int cnt = min(64, s1 - sb);
-        for (int jj = 0; jj < cnt; ++jj) {
+        for (int jj = sub; jj < cnt; jj += G) {
           const V ps = sp[jj];
-          const T ddx = (rt.x - ps.x) + ox, ddy = (rt.y - ps.y) + oy, ddz = (rt.z - ps.z) + oz;
+          const T ddx = cx - ps.x, ddy = cy - ps.y, ddz = cz - ps.z;
           const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          const T r = sqrt(r2);
-          const T inv = r2 > T(0) ? T(1) / r : T(0);
-          T sn, cs;
-          sincosT(a.k * r, &sn, &cs);
+          T gr, gi;
+          pair3(r2, a.k, k2pi, gr, gi);
           const cplx<T> qq = sq[jj];
-          const T gr = cs * inv, gi = sn * inv;
           ar += qq.x * gr - qq.y * gi;
           ai += qq.x * gi + qq.y * gr;
         }
       }
     }
-    if (v) a.near_out[i] = mk<T>(ar * inv4pi, ai * inv4pi);
+    if (two) {
+      ar += __shfl_xor(ar, 1);
+      ai += __shfl_xor(ai, 1);
+    }
+    if (v && sub == 0) a.near_out[i] = mk<T>(ar * inv4pi, ai * inv4pi);
   }
 }
 
@@ -349,9 +375,10 @@ struct Tr3Args {
   int RT, KS, ncols, crows, accumulate;
   int64_t ldb, ldc, aslot;  // column strides; M2L: table stride per offset slot
   int m2l, nb, h;           // M2L: boxes per axis, nb / 2
-  // M2L offset groups: grid.z = 8 S; group g takes offsets [189 g / S,
-  // 189 (g + 1) / S) of its class and, for S > 1, stores its partial sum at
-  // part + g pstride (a later pass adds the S partials)
+  // groups: grid.z = 8 S (M2L) or S; group g takes iterations [n g / S,
+  // n (g + 1) / S) of the flat (offset, k chunk) loop of n iterations and,
+  // for S > 1, stores its partial sum at part + g pstride (a later pass
+  // adds the S partials)
   int S;
   T* part;
   int64_t pstride;
@@ -367,8 +394,7 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15, kq = lane >> 4;
   const int rg0 = blockIdx.y * RG;
   const int nrt = min(RG, a.RT - rg0);
-  const int par = blockIdx.z & 7, grp = blockIdx.z >> 3;
-  const int o_lo = a.m2l ? 189 * grp / a.S : 0, o_hi = a.m2l ? 189 * (grp + 1) / a.S : 1;
+  const int par = a.m2l ? (blockIdx.z & 7) : 0, grp = a.m2l ? (blockIdx.z >> 3) : blockIdx.z;
   const int px = par & 1, py = (par >> 1) & 1, pz = (par >> 2) & 1;
   int tx[kNC3], ty[kNC3], tz[kNC3], obox[kNC3];
   bool colv[kNC3];
@@ -388,8 +414,9 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
     }
   }
   const int nch = a.KS >> 2;
-  const int nit = (o_hi - o_lo) * nch;
-  const int* po = a.offs + par * 189 + o_lo;
+  const int nall = (a.m2l ? 189 : 1) * nch;
+  const int it_lo = (int)((int64_t)nall * grp / a.S), it_hi = (int)((int64_t)nall * (grp + 1) / a.S);
+  const int* po = a.offs + par * 189;
   // per-iteration sources: table base and B columns
   auto locate = [&](int it, const T*& Ab, const T* (&bc)[kNC3], bool (&bv)[kNC3], int& k0) {
     const int oi = it / nch, ch = it - oi * nch;
@@ -439,15 +466,15 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   bool bv[kNC3];
   int k0;
   T ra[APT], rb[4][kNC3], rbn[4][kNC3];
-  locate(0, Ab, bc, bv, k0);
+  locate(it_lo, Ab, bc, bv, k0);
   loadA(Ab, k0, ra);
   loadB(bc, bv, k0, rb);
 #pragma unroll
   for (int i = 0; i < APT; ++i) abuf[0][i * 256 + tid] = ra[i];
   __syncthreads();
-  for (int it = 0; it < nit; ++it) {
-    const int cur = it & 1;
-    const bool more = it + 1 < nit;
+  for (int it = it_lo; it < it_hi; ++it) {
+    const int cur = (it - it_lo) & 1;
+    const bool more = it + 1 < it_hi;
     if (more) {
       locate(it + 1, Ab, bc, bv, k0);
       loadA(Ab, k0, ra);
@@ -488,14 +515,41 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   }
 }
 
-// C = sum of the S partial M2L sums (fixed order)
+// C (+)= sum of the S partial sums (fixed order)
 template <class T>
-__global__ void k3_sum_parts(const T* __restrict__ part, int S, int64_t pstride, T* __restrict__ C) {
+__global__ void k3_sum_parts(const T* __restrict__ part, int S, int64_t pstride, int accumulate, T* __restrict__ C) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= pstride) return;
   T s = part[i];
   for (int g = 1; g < S; ++g) s += part[g * pstride + i];
-  C[i] = s;
+  C[i] = accumulate ? C[i] + s : s;
+}
+
+// Blocks of a translation launch (one group) and the groups that bring the
+// launch to about 3 waves per SIMD (at most one per iteration, at most 63).
+template <class T>
+int trans_groups(int ncols, int RT, int nall, bool m2l) {
+  const int base = (m2l ? 8 : 1) * ((ncols + kColsPerBlock3 - 1) / kColsPerBlock3) * ((RT + RG3<T>::v - 1) / RG3<T>::v);
+  int S = (768 + base - 1) / base;
+  return std::max(1, std::min(S, std::min(63, nall)));
+}
+
+template <class T>
+void launch_trans(Tr3Args<T> a, T* part, size_t part_n, hipStream_t stream) {
+  const int nall = (a.m2l ? 189 : 1) * (a.KS / 4);
+  a.S = trans_groups<T>(a.ncols, a.RT, nall, a.m2l != 0);
+  a.part = part;
+  dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v,
+         (a.m2l ? 8 : 1) * a.S);
+  const int acc = a.accumulate;
+  if (a.S > 1) a.accumulate = 0;  // partials are stored
+  HFMM_REQUIRE(a.S == 1 || (part != nullptr && (size_t)a.S * a.pstride <= part_n), "fmm3: partial-sum buffer too small");
+  k3_trans<T><<<g, 256, 0, stream>>>(a);
+  HFMM_LAUNCH_CHECK();
+  if (a.S > 1) {
+    k3_sum_parts<T><<<(unsigned)((a.pstride + 255) / 256), 256, 0, stream>>>(part, a.S, a.pstride, acc, a.C);
+    HFMM_LAUNCH_CHECK();
+  }
 }
 
 // ------------------------------------------------------------------ host tables
@@ -627,7 +681,6 @@ struct Plan3 : Plan3Base {
   std::vector<size_t> eoff, m2l_off, m2m_off, l2l_off;
   DevBuf<T> M, Lc, A, rec;
   DevBuf<int> offs;
-  std::vector<int> S;  // M2L offset groups per level
   DevBuf<T> part;
   DevBuf<cplx<T>> qs, near;
   hipEvent_t ev[6] = {};
@@ -772,17 +825,15 @@ Plan3<T>& get_plan3(Tree3& t, double k, int p) {
     P.offs.upload(offs);
   }
   {
-    // enough blocks to keep about 3 waves on every SIMD: split the 189
-    // offsets of a level whose M2L grid is smaller
-    P.S.assign(L + 1, 1);
+    // partial sums of the translation launches split into groups
     size_t pmax = 0;
     for (int l = 2; l <= L; ++l) {
-      const int h = 1 << (l - 1), RT = P.Kp[l] / 16;
-      const int base = 8 * ((h * h * h + kColsPerBlock3 - 1) / kColsPerBlock3) * ((RT + RG3<T>::v - 1) / RG3<T>::v);
-      int S = (768 + base - 1) / base;
-      S = std::max(1, std::min(S, 63));
-      P.S[l] = S;
-      if (S > 1) pmax = std::max(pmax, (size_t)S * ((size_t)1 << (3 * l)) * P.Kp[l]);
+      const size_t outl = ((size_t)1 << (3 * l)) * P.Kp[l];
+      const int h = 1 << (l - 1);
+      size_t S = trans_groups<T>(h * h * h, P.Kp[l] / 16, 189 * (P.Kp[l] / 16), true);
+      if (l < L) S = std::max<size_t>(S, trans_groups<T>(1 << (3 * l), P.Kp[l] / 16, P.Kp[l + 1] / 2, false));
+      if (l > 2) S = std::max<size_t>(S, trans_groups<T>(1 << (3 * (l - 1)), 8 * P.Kp[l] / 16, P.Kp[l - 1] / 16, false));
+      if (S > 1) pmax = std::max(pmax, S * outl);
     }
     if (pmax) P.part.alloc(pmax);
   }
@@ -901,12 +952,10 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ncols = 1 << (3 * l);
     a.crows = P.Kp[l];
     a.accumulate = 0;
-    a.S = 1;
     a.ldb = 8 * P.Kp[l + 1];
     a.ldc = P.Kp[l];
-    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v, 1);
-    k3_trans<T><<<g, 256, 0, stream>>>(a);
-    HFMM_LAUNCH_CHECK();
+    a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
+    launch_trans<T>(a, P.part.p, P.part.n, stream);
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[1], stream));
   // M2L on every level
@@ -927,16 +976,8 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ldc = P.Kp[l];
     a.aslot = (int64_t)P.Kp[l] * P.Kp[l];
     a.m2l = 1;
-    a.S = P.S[l];
-    a.part = P.part.p;
     a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
-    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v, 8 * a.S);
-    k3_trans<T><<<g, 256, 0, stream>>>(a);
-    HFMM_LAUNCH_CHECK();
-    if (a.S > 1) {
-      k3_sum_parts<T><<<(unsigned)((a.pstride + 255) / 256), 256, 0, stream>>>(P.part.p, a.S, a.pstride, a.C);
-      HFMM_LAUNCH_CHECK();
-    }
+    launch_trans<T>(a, P.part.p, P.part.n, stream);
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[2], stream));
   // downward pass
@@ -951,12 +992,10 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ncols = 1 << (3 * (l - 1));
     a.crows = 8 * P.Kp[l];
     a.accumulate = 1;
-    a.S = 1;
     a.ldb = P.Kp[l - 1];
     a.ldc = 8 * P.Kp[l];
-    dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v, 1);
-    k3_trans<T><<<g, 256, 0, stream>>>(a);
-    HFMM_LAUNCH_CHECK();
+    a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
+    launch_trans<T>(a, P.part.p, P.part.n, stream);
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[3], stream));
   k3_p2p<T><<<nleaves, 64, 0, stream>>>(la);
