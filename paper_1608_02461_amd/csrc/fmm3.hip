@@ -43,6 +43,7 @@ namespace {
 
 constexpr double kPi3 = 3.14159265358979323846;
 constexpr int kMaxP3 = 20;  // largest order of any level
+constexpr int kTaylor3 = 13;  // Taylor terms of the FP64 near-field cosine and sine (k r <= 2)
 
 typedef float f32x4_3 __attribute__((ext_vector_type(4)));
 typedef double f64x4_3 __attribute__((ext_vector_type(4)));
@@ -116,6 +117,10 @@ struct Leaf3Args {
   const T* rec;                       // (a, b) of the Legendre recurrence, then Q_m^m
   int p, P2, Kp, nser, L;
   T k, h;                             // wavenumber, leaf side (P2P)
+  // FP64 P2P: when every near pair has k r <= 2, cos(k r) and sin(k r)/(k r)
+  // as Taylor polynomials in y = (k r)^2 with ntay terms (0: library sincos)
+  int ntay;
+  double tc[16], ts[16];
 };
 
 // jh_n(s) = j_n(s) / s^n for n = 0..p into col[n * 64]: the power series
@@ -279,6 +284,26 @@ __device__ __forceinline__ void pair3(double r2, double k, double, double& gr, d
   gr = cs * inv;
   gi = sn * inv;
 }
+// FP64 with the Taylor form: 1/r from the hardware reciprocal square root and
+// two Newton steps, cos(k r) = C(y) and sin(k r)/r = k S(y), y = k^2 r^2.
+template <int NT>
+__device__ __forceinline__ void pair3_taylor(double r2, double k, double k2, const double* tc, const double* ts,
+                                             double& gr, double& gi) {
+  double y0 = __builtin_amdgcn_rsq(r2);
+  y0 = y0 * (1.5 - 0.5 * r2 * y0 * y0);
+  y0 = y0 * (1.5 - 0.5 * r2 * y0 * y0);
+  const bool nz = r2 > 0.0;
+  const double inv = nz ? y0 : 0.0;
+  const double y = k2 * r2;
+  double c = tc[NT - 1], sv = ts[NT - 1];
+#pragma unroll
+  for (int n = NT - 2; n >= 0; --n) {
+    c = fma(c, y, tc[n]);
+    sv = fma(sv, y, ts[n]);
+  }
+  gr = c * inv;
+  gi = nz ? k * sv : 0.0;
+}
 
 // P2P: one wave per target leaf; a leaf of at most 32 points gives each
 // target 2 lanes (even and odd sources, summed by a lane swap at the end),
@@ -329,7 +354,14 @@ __global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
           const T ddx = cx - ps.x, ddy = cy - ps.y, ddz = cz - ps.z;
           const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
           T gr, gi;
-          pair3(r2, a.k, k2pi, gr, gi);
+          if constexpr (sizeof(T) == 8) {
+            if (a.ntay)
+              pair3_taylor<kTaylor3>(r2, a.k, a.k * a.k, a.tc, a.ts, gr, gi);
+            else
+              pair3(r2, a.k, k2pi, gr, gi);
+          } else {
+            pair3(r2, a.k, k2pi, gr, gi);
+          }
           const cplx<T> qq = sq[jj];
           ar += qq.x * gr - qq.y * gi;
           ai += qq.x * gi + qq.y * gr;
@@ -934,6 +966,18 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
   la.L = L;
   la.k = T(k);
   la.h = T(t.leaf_side());
+  {
+    // the largest k r of a near pair: opposite corners of a 2 x 2 x 2 block of leaves
+    const double krmax = k * 2.0 * std::sqrt(3.0) * t.leaf_side();
+    la.ntay = krmax <= 2.0 ? kTaylor3 : 0;
+    double f = 1.0;  // (2n)! then (2n+1)!
+    for (int n = 0; n < 16; ++n) {
+      const double sg = (n & 1) ? -1.0 : 1.0;
+      if (n > 0) f *= (2.0 * n - 1.0) * (2.0 * n);
+      la.tc[n] = n < kTaylor3 ? sg / f : 0.0;
+      la.ts[n] = n < kTaylor3 ? sg / (f * (2.0 * n + 1.0)) : 0.0;
+    }
+  }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[0], stream));
   // upward pass
   k3_gather<T><<<(N + 255) / 256, 256, 0, stream>>>(d_q, t.perm.p, N, P.qs.p);
