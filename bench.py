@@ -641,33 +641,34 @@ def cpu_extra_baselines(workloads):
     return out
 
 
-def m2l3_flops(L, orders, cols_per_block=128):
+def m2l3_flops(L, orders):
     """The 3-D M2L per apply: algorithmic flops (8 P^4 per (target, source)
     pair of the interaction lists inside the cube, P^2 = (p_l + 1)^2
     coefficients; a complex multiply-add is 8 real flops) and the MFMA flops
-    the kernel executes (every class member tile of 128 columns, all 189
-    offsets, the real 2P^2 x 2P^2 form padded to 16 rows)."""
+    the kernel executes: a wave of 32 class members (columns) runs the real
+    2P^2 x 2P^2 product, padded to Kp = 16-multiple rows and columns, for
+    every offset of its class for which one of its members has a source."""
     alg, exe = 0, 0
     for l in range(2, L + 1):
         nb, h = 2 ** l, 2 ** (l - 1)
         P2 = (orders[l] + 1) ** 2
         kp = (2 * P2 + 15) // 16 * 16
-        pairs = 0
+        m = np.arange(h ** 3)
+        wave = m // 32
+        nw = int(wave.max()) + 1
         for par in range(8):
             px, py, pz = par & 1, (par >> 1) & 1, (par >> 2) & 1
-            t = [np.arange(h) * 2 + px, np.arange(h) * 2 + py, np.arange(h) * 2 + pz]
+            tx, ty, tz = 2 * (m % h) + px, 2 * ((m // h) % h) + py, 2 * (m // (h * h)) + pz
             for dx in range(px - 3, px + 3):
-                cx = int(np.count_nonzero((t[0] - dx >= 0) & (t[0] - dx < nb)))
                 for dy in range(py - 3, py + 3):
-                    cy = int(np.count_nonzero((t[1] - dy >= 0) & (t[1] - dy < nb)))
                     for dz in range(pz - 3, pz + 3):
                         if max(abs(dx), abs(dy), abs(dz)) <= 1:
                             continue
-                        cz = int(np.count_nonzero((t[2] - dz >= 0) & (t[2] - dz < nb)))
-                        pairs += cx * cy * cz
-        alg += pairs * 8 * P2 * P2
-        cols = -(-h ** 3 // cols_per_block) * cols_per_block
-        exe += 8 * cols * 189 * 2 * kp * kp
+                        sx, sy, sz = tx - dx, ty - dy, tz - dz
+                        ok = (sx >= 0) & (sx < nb) & (sy >= 0) & (sy < nb) & (sz >= 0) & (sz < nb)
+                        alg += int(np.count_nonzero(ok)) * 8 * P2 * P2
+                        waves_on = np.count_nonzero(np.bincount(wave[ok], minlength=nw))
+                        exe += int(waves_on) * 32 * 2 * kp * kp
     return alg, exe
 
 

@@ -499,6 +499,9 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   int k0;
   T ra[APT], rb[4][kNC3], rbn[4][kNC3];
   locate(it_lo, Ab, bc, bv, k0);
+  // a wave none of whose columns has a source in this iteration skips its
+  // MFMAs (it still stages A with the block)
+  bool wv = __ballot(bv[0] | bv[1]) != 0;
   loadA(Ab, k0, ra);
   loadB(bc, bv, k0, rb);
 #pragma unroll
@@ -507,20 +510,25 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   for (int it = it_lo; it < it_hi; ++it) {
     const int cur = (it - it_lo) & 1;
     const bool more = it + 1 < it_hi;
+    bool wvn = false;
     if (more) {
       locate(it + 1, Ab, bc, bv, k0);
+      wvn = __ballot(bv[0] | bv[1]) != 0;
       loadA(Ab, k0, ra);
       loadB(bc, bv, k0, rbn);
     }
+    if (wv) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
-        if (r < nrt) {
-          const T av = abuf[cur][(r * 4 + u) * 64 + lane];
+        for (int r = 0; r < RG; ++r)
+          if (r < nrt) {
+            const T av = abuf[cur][(r * 4 + u) * 64 + lane];
 #pragma unroll
-          for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(av, rb[u][c], acc[r][c]);
-        }
+            for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(av, rb[u][c], acc[r][c]);
+          }
+    }
+    wv = wvn;
     if (more) {
 #pragma unroll
       for (int i = 0; i < APT; ++i) abuf[cur ^ 1][i * 256 + tid] = ra[i];
