@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   constexpr int RG = RG3<T>::v;
   constexpr int ACH = RG * 4 * 64;    // A values per chunk
   constexpr int APT = ACH / 256;      // per thread
-  __shared__ T abuf[2][ACH];
+  __shared__ __align__(32) T abuf[2][ACH];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, j = lane & 15, kq = lane >> 4;
   const int rg0 = blockIdx.y * RG;
   const int nrt = min(RG, a.RT - rg0);
@@ -449,10 +449,11 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   const int nall = (a.m2l ? 189 : 1) * nch;
   const int it_lo = (int)((int64_t)nall * grp / a.S), it_hi = (int)((int64_t)nall * (grp + 1) / a.S);
   const int* po = a.offs + par * 189;
-  // per-iteration sources: table base and B columns
-  auto locate = [&](int it, const T*& Ab, const T* (&bc)[kNC3], bool (&bv)[kNC3], int& k0) {
-    const int oi = it / nch, ch = it - oi * nch;
-    k0 = ch * 4;
+  // source columns of offset oi (recomputed only when the offset changes)
+  const T* Ab;
+  const T* bc[kNC3];
+  bool bv[kNC3];
+  auto locate = [&](int oi) {
     if (a.m2l) {
       const int e = po[oi];
       const int dx = (e & 15) - 3, dy = ((e >> 4) & 15) - 3, dz = (e >> 8) - 3;
@@ -473,65 +474,81 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
       }
     }
   };
-  // A chunk element e of this thread: row tile r = e / 256, k step u = (e / 64) % 4, lane e % 64
-  auto loadA = [&](const T* Ab, int k0, T (&ra)[APT]) {
+  // A chunk element e = i * 256 + tid of this thread: row tile r = e / 256,
+  // k step u = (e / 64) % 4, lane ln = e % 64; it goes to LDS at
+  // (r * 64 + ln) * 4 + u, so that a lane reads its 4 k steps of a row tile
+  // with one 16-byte load
+  int aoff[APT], lofs[APT];
+  bool aval[APT];
 #pragma unroll
-    for (int i = 0; i < APT; ++i) {
-      const int e = i * 256 + tid, r = e >> 8, u = (e >> 6) & 3, ln = e & 63;
-      ra[i] = r < nrt ? Ab[((size_t)(rg0 + r) * a.KS + k0 + u) * 64 + ln] : T(0);
-    }
+  for (int i = 0; i < APT; ++i) {
+    const int e = i * 256 + tid, r = e >> 8, u = (e >> 6) & 3, ln = e & 63;
+    aval[i] = r < nrt;
+    aoff[i] = (r * a.KS + u) * 64 + ln;
+    lofs[i] = (r * 64 + ln) * 4 + u;
+  }
+  const size_t abase = (size_t)rg0 * a.KS * 64;
+  auto loadA = [&](int k0, T (&ra)[APT]) {
+    const T* p0 = Ab + abase + (size_t)k0 * 64;
+#pragma unroll
+    for (int i = 0; i < APT; ++i) ra[i] = aval[i] ? p0[aoff[i]] : T(0);
   };
-  auto loadB = [&](const T* const (&bc)[kNC3], const bool (&bv)[kNC3], int k0, T (&rb)[4][kNC3]) {
+  auto loadB = [&](int k0, T (&rb)[4][kNC3]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int c = 0; c < kNC3; ++c) rb[u][c] = bv[c] ? bc[c][(k0 + u) * 4 + kq] : T(0);
   };
+  typedef typename Vec4<T>::type A4;
   V4 acc[RG][kNC3];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
 #pragma unroll
     for (int c = 0; c < kNC3; ++c) acc[r][c] = V4{0, 0, 0, 0};
 
-  const T* Ab;
-  const T* bc[kNC3];
-  bool bv[kNC3];
-  int k0;
   T ra[APT], rb[4][kNC3], rbn[4][kNC3];
-  locate(it_lo, Ab, bc, bv, k0);
+  int oi = it_lo / nch, ch = it_lo - oi * nch;
+  locate(oi);
   // a wave none of whose columns has a source in this iteration skips its
   // MFMAs (it still stages A with the block)
   bool wv = __ballot(bv[0] | bv[1]) != 0;
-  loadA(Ab, k0, ra);
-  loadB(bc, bv, k0, rb);
+  loadA(ch * 4, ra);
+  loadB(ch * 4, rb);
 #pragma unroll
-  for (int i = 0; i < APT; ++i) abuf[0][i * 256 + tid] = ra[i];
+  for (int i = 0; i < APT; ++i) abuf[0][lofs[i]] = ra[i];
   __syncthreads();
   for (int it = it_lo; it < it_hi; ++it) {
     const int cur = (it - it_lo) & 1;
     const bool more = it + 1 < it_hi;
     bool wvn = false;
     if (more) {
-      locate(it + 1, Ab, bc, bv, k0);
+      if (++ch == nch) {
+        ch = 0;
+        locate(++oi);
+      }
       wvn = __ballot(bv[0] | bv[1]) != 0;
-      loadA(Ab, k0, ra);
-      loadB(bc, bv, k0, rbn);
+      loadA(ch * 4, ra);
+      loadB(ch * 4, rbn);
     }
     if (wv) {
+      const A4* ab4 = reinterpret_cast<const A4*>(abuf[cur]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int r = 0; r < RG; ++r)
+        if (r < nrt) {
+          const A4 av = ab4[r * 64 + lane];
 #pragma unroll
-        for (int r = 0; r < RG; ++r)
-          if (r < nrt) {
-            const T av = abuf[cur][(r * 4 + u) * 64 + lane];
-#pragma unroll
-            for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(av, rb[u][c], acc[r][c]);
+          for (int c = 0; c < kNC3; ++c) {
+            acc[r][c] = mfma3(av.x, rb[0][c], acc[r][c]);
+            acc[r][c] = mfma3(av.y, rb[1][c], acc[r][c]);
+            acc[r][c] = mfma3(av.z, rb[2][c], acc[r][c]);
+            acc[r][c] = mfma3(av.w, rb[3][c], acc[r][c]);
           }
+        }
     }
     wv = wvn;
     if (more) {
 #pragma unroll
-      for (int i = 0; i < APT; ++i) abuf[cur ^ 1][i * 256 + tid] = ra[i];
+      for (int i = 0; i < APT; ++i) abuf[cur ^ 1][lofs[i]] = ra[i];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
