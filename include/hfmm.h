@@ -385,16 +385,18 @@ hfmm_status hfmm3_tree_destroy(hfmm3_tree t);
  * The first call for a (k, p, prec) builds and caches the plan: the
  * translation tables (M2L for the 316 offsets of each level, M2M and L2L for
  * the 8 child positions), built on the host and uploaded synchronously, and
- * the expansion arrays.  Async on stream afterwards; applies on one tree
- * must not overlap in time.
+ * the expansion arrays.  Async on stream afterwards: the far-field chain
+ * (P2M, M2M, M2L, L2L) runs on a second stream owned by the tree, forked from
+ * and joined back to `stream` by events, beside the near field (P2P).
+ * Applies on one tree must not overlap in time.
  * Errors: k <= 0, p out of range, an order above 20, leaves too large for k
  * (k times the leaf half-diagonal above 6), FP32 tables that would overflow,
  * a tree of depth < 2. */
 hfmm_status hfmm3_fmm_apply(hfmm3_tree t, double k, int32_t p, hfmm_precision prec, const void* d_q,
                             void* d_phi, hipStream_t stream);
 
-/* The same apply with hipEvents between its stages: ms_stages (host, 6
- * floats) receives [0] the upward pass (charge gather, P2M, M2M), [1] the
+/* The same apply with hipEvents between its stages, which then run one
+ * after another on `stream` (no overlap): ms_stages (host, 6 floats) receives [0] the upward pass (charge gather, P2M, M2M), [1] the
  * M2L of every level, [2] the L2L levels, [3] the P2P, [4] the L2P (which
  * adds the near field and writes caller order) and [5] the total, in ms.
  * Synchronises `stream`. */

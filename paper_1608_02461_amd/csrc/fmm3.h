@@ -51,6 +51,14 @@ struct Tree3 {
   DevBuf<float4> rel32;      // the same in FP32
   // translation plans, keyed by (k, p, precision)
   std::map<std::tuple<double, int, int>, std::unique_ptr<Plan3Base>> plans;
+  // a second stream (default priority, non-blocking) on which the far-field
+  // chain runs beside the near field, and the events that fork and join it
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  Tree3() = default;
+  Tree3(const Tree3&) = delete;
+  Tree3& operator=(const Tree3&) = delete;
+  ~Tree3();
   double leaf_side() const { return side_len / double(1u << L); }
 };
 
@@ -66,7 +74,10 @@ std::unique_ptr<Tree3> build_tree3(const double* d_xyz, int64_t n, double x0, do
 std::vector<int> fmm3_orders(const Tree3& t, double k, int p);
 
 // phi_i = sum_{j, r_ij != 0} exp(i k r_ij) / (4 pi r_ij) q_j, caller order.
-// stage_ms (or NULL): upward (gather, P2M, M2M), M2L, L2L, P2P, L2P, total.
+// The far-field chain (P2M, M2M, M2L, L2L) runs on the tree's second stream
+// beside the P2P; the L2P waits for both.  stage_ms (or NULL): the stages
+// one after another on `stream` (upward: gather, P2M, M2M; M2L; L2L; P2P;
+// L2P; total), each timed with hipEvents.
 template <class T>
 void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, hipStream_t stream,
                 float* stage_ms);

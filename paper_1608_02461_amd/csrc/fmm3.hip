@@ -964,7 +964,19 @@ std::unique_ptr<Tree3> build_tree3(const double* d_xyz, int64_t n, double x0, do
   for (int64_t b = 0; b < t->nleaves; ++b) mx = std::max(mx, off[b + 1] - off[b]);
   t->max_leaf = mx;
   if (off[t->nleaves] != N) throw Error(HFMM_ERR_INTERNAL, "build_tree3: leaf offsets do not sum to n");
+  HFMM_HIP(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+  HFMM_HIP(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming | hipEventDisableSystemFence));
+  HFMM_HIP(hipEventCreateWithFlags(&t->join, hipEventDisableTiming | hipEventDisableSystemFence));
   return t;
+}
+
+Tree3::~Tree3() {
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
 }
 
 template <class T>
@@ -1007,8 +1019,15 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
   // upward pass
   k3_gather<T><<<(N + 255) / 256, 256, 0, stream>>>(d_q, t.perm.p, N, P.qs.p);
   HFMM_LAUNCH_CHECK();
+  // the far-field chain on the side stream beside the P2P (serial when timed)
+  const bool overlap = !stage_ms && t.side;
+  hipStream_t fs = overlap ? t.side : stream;
+  if (overlap) {
+    HFMM_HIP(hipEventRecord(t.fork, stream));
+    HFMM_HIP(hipStreamWaitEvent(fs, t.fork, 0));
+  }
   la.E = P.M.p + P.eoff[L];
-  k3_p2m<T><<<nleaves, 64, 0, stream>>>(la);
+  k3_p2m<T><<<nleaves, 64, 0, fs>>>(la);
   HFMM_LAUNCH_CHECK();
   for (int l = L - 1; l >= 2; --l) {
     Tr3Args<T> a{};
@@ -1024,7 +1043,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ldb = 8 * P.Kp[l + 1];
     a.ldc = P.Kp[l];
     a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
-    launch_trans<T>(a, P.part.p, P.part.n, stream);
+    launch_trans<T>(a, P.part.p, P.part.n, fs);
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[1], stream));
   // M2L on every level
@@ -1046,7 +1065,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.aslot = (int64_t)P.Kp[l] * P.Kp[l];
     a.m2l = 1;
     a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
-    launch_trans<T>(a, P.part.p, P.part.n, stream);
+    launch_trans<T>(a, P.part.p, P.part.n, fs);
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[2], stream));
   // downward pass
@@ -1064,12 +1083,14 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.ldb = P.Kp[l - 1];
     a.ldc = 8 * P.Kp[l];
     a.pstride = ((int64_t)1 << (3 * l)) * P.Kp[l];
-    launch_trans<T>(a, P.part.p, P.part.n, stream);
+    launch_trans<T>(a, P.part.p, P.part.n, fs);
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[3], stream));
+  if (overlap) HFMM_HIP(hipEventRecord(t.join, fs));
   k3_p2p<T><<<nleaves, 64, 0, stream>>>(la);
   HFMM_LAUNCH_CHECK();
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[4], stream));
+  if (overlap) HFMM_HIP(hipStreamWaitEvent(stream, t.join, 0));
   la.E = P.Lc.p + P.eoff[L];
   k3_l2p<T><<<nleaves, 64, 0, stream>>>(la);
   HFMM_LAUNCH_CHECK();

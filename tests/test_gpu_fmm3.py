@@ -103,3 +103,17 @@ def test_fmm3_full_size_sampled():
     say(f"  fp64 {e64:.3e} fp32 {e32:.3e}  fp32 vs fp64 {rel(f32, f64):.3e}  oracle FMM error {eps:.3e}")
     assert e64 <= 2.0 * eps
     assert e32 <= 2.0 * eps and rel(f32, f64) <= 3e-5
+
+
+def test_fmm3_overlapped_equals_serial_timed_apply():
+    # the plain apply runs the far-field chain on the tree's second stream
+    # beside the P2P; the timed apply runs the stages one after another
+    xyz, q = workloads.random_cloud3(20000, 91)
+    t = hfmm.Tree3(to_dev(xyz), leaf_size=16)
+    say("fmm3 overlapped vs serial N=20000")
+    for prec, dt in ((hfmm.FP64, np.complex128), (hfmm.FP32, np.complex64)):
+        qd = to_dev(q.astype(dt))
+        a = to_np(hfmm.hfmm3_fmm_apply(t, 12.0, 5, qd, prec=prec))
+        b, ms = hfmm.hfmm3_fmm_apply_timed(t, 12.0, 5, qd, prec=prec)
+        assert np.array_equal(a, to_np(b))
+        assert set(ms) == set(hfmm.STAGES3) and ms["total"] > 0
