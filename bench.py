@@ -638,6 +638,19 @@ def cpu_extra_baselines(workloads):
         t0 = time.perf_counter()
         oadj.gradient(wa["n"], wa["kb"], wa["f"], wa["P"], d)
         out["adjoint_256_oracle_gradient_s"] = round(time.perf_counter() - t0, 3)
+        # the 3-D apply: the oracle's direct sum from all 2^20 sources to 64
+        # sampled targets (Mpts/s of the full N x N sum by linearity)
+        from oracle import fmm3 as ofmm3
+        w3 = workloads.fmm3_2p20()
+        tg = w3["samples"][:64]
+        t0 = time.perf_counter()
+        ofmm3.direct_sum3(w3["xyz"], w3["q"], w3["k"], targets=w3["xyz"][tg], chunk=8)
+        dt = time.perf_counter() - t0
+        n3 = len(w3["xyz"])
+        out["fmm3_2p20_oracle_direct_sum"] = {
+            "sample": f"all {n3} sources to 64 sampled targets, numpy FP64, {round(dt, 2)} s",
+            "pairs_per_s": round(64 * n3 / dt, 1), "Mpts_per_s_full_sum": round(64 / dt / 1e6, 9)}
+        log(f"CPU 3-D direct sum: {out['fmm3_2p20_oracle_direct_sum']}")
     return out
 
 
