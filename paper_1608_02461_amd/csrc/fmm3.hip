@@ -116,6 +116,7 @@ struct Leaf3Args {
   cplx<T>* out;                       // caller order (L2P)
   const T* rec;                       // (a, b) of the Legendre recurrence, then Q_m^m
   int p, P2, Kp, nser, L;
+  int cp;                             // P2M: points per LDS chunk
   T k, h;                             // wavenumber, leaf side (P2P)
   // FP64 P2P: when every near pair has k r <= 2, cos(k r) and sin(k r)/(k r)
   // as Taylor polynomials in y = (k r)^2 with ntay terms (0: library sincos)
@@ -149,54 +150,102 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// P2M: one wave per leaf; each lane takes one point of a 64-point chunk and
-// walks its R_n^m; the wave sums every coefficient over its lanes.
+// P2M: one wave per leaf, in chunks of CP points, two phases.
+// 1. A lane per point writes its column of a table in LDS (row stride CP + 1):
+//    jh_n (n <= p), jh_n Rh_n^m for m <= n (so that R_n^m = that times
+//    (u_x + i u_y)^m), the powers (u_x + i u_y)^m and the charge.
+// 2. A lane per coefficient pair (n, m) and (n, -m), m >= 0 (G lanes per pair
+//    when the pairs are few, G a power of two), sums over the chunk's points:
+//    M_nm += q conj(R_n^m), M_n,-m += (-1)^m q R_n^m; the G lanes of a pair
+//    add up by shuffles and one of them adds to the leaf's sums in LDS.
 template <class T>
 __global__ __launch_bounds__(64) void k3_p2m(Leaf3Args<T> a) {
-  __shared__ T jh[(kMaxP3 + 1) * 64];
-  __shared__ T acc[2 * (kMaxP3 + 1) * (kMaxP3 + 1)];
+  extern __shared__ __align__(16) unsigned char p2m_smem[];
+  T* acc = reinterpret_cast<T*>(p2m_smem);   // 2 P2
+  T* tab = acc + 2 * a.P2;                    // [E][CP + 1]
+  const int p = a.p, CP = a.cp, S = CP + 1;
+  const int npair = (p + 1) * (p + 2) / 2;
+  T* tjh = tab;                               // rows 0..p
+  T* tjr = tab + (p + 1) * S;                 // rows tri(n, m)
+  T* twr = tjr + npair * S;                   // rows m
+  T* twi = twr + (p + 1) * S;
+  T* tq = twi + (p + 1) * S;                  // 2 rows
   const int leaf = blockIdx.x, lane = threadIdx.x;
   const int b0 = a.off[leaf], b1 = a.off[leaf + 1];
   for (int c = lane; c < 2 * a.P2; c += 64) acc[c] = T(0);
-  __syncthreads();
-  const T* qmm = a.rec + (a.p + 1) * (a.p + 2);
-  for (int base = b0; base < b1; base += 64) {
-    const int i = base + lane;
-    const bool v = i < b1;
-    typename Vec4<T>::type r = a.rel[v ? i : b0];
-    cplx<T> q = a.qs[v ? i : b0];
-    if (!v) q = mk<T>(0, 0);
-    const T ux = a.k * r.x, uy = a.k * r.y, uz = a.k * r.z;
-    const T s2 = ux * ux + uy * uy + uz * uz;
-    jh_all<T>(a.p, a.nser, s2, jh + lane);
-    cplx<T> wm = mk<T>(1, 0);
-    for (int m = 0; m <= a.p; ++m) {
-      if (m > 0) wm = mk<T>(wm.x * ux - wm.y * uy, wm.x * uy + wm.y * ux);
-      T r2 = 0, r1 = qmm[m];
-      const T sg = (m & 1) ? T(-1) : T(1);
-      for (int n = m; n <= a.p; ++n) {
-        if (n > m) {
-          const T* ab = a.rec + 2 * (n * (n + 1) / 2 + m);
-          const T rn = ab[0] * (uz * r1 - ab[1] * s2 * r2);
-          r2 = r1;
-          r1 = rn;
-        }
-        const T jr = jh[n * 64 + lane] * r1;
-        const T bx = jr * wm.x, by = jr * wm.y;  // R_n^m (m >= 0)
-        // q conj(R_n^m)
-        const T pr = wave_sum(q.x * bx + q.y * by), pi = wave_sum(q.y * bx - q.x * by);
-        const int c = n * n + n + m;
-        if (lane == 0) {
-          acc[c] += pr;
-          acc[a.P2 + c] += pi;
-        }
-        if (m > 0) {
-          // conj(R_n^-m) = (-1)^m R_n^m
-          const T nr = wave_sum(sg * (q.x * bx - q.y * by)), ni = wave_sum(sg * (q.x * by + q.y * bx));
-          if (lane == 0) {
-            acc[c - 2 * m] += nr;
-            acc[a.P2 + c - 2 * m] += ni;
+  const T* qmm = a.rec + (p + 1) * (p + 2);
+  int G = 1;
+  while (G * 2 * npair <= 64) G *= 2;
+  for (int base = b0; base < b1; base += CP) {
+    const int cnt = min(CP, b1 - base);
+    __syncthreads();
+    if (lane < cnt) {
+      const int i = base + lane;
+      const typename Vec4<T>::type r = a.rel[i];
+      const cplx<T> q = a.qs[i];
+      const T ux = a.k * r.x, uy = a.k * r.y, uz = a.k * r.z;
+      const T s2 = ux * ux + uy * uy + uz * uz;
+      // jh_n by the series at p and p - 1, then downward
+      tjh[p * S + lane] = jh_series<T>(p, a.nser, s2);
+      if (p >= 1) tjh[(p - 1) * S + lane] = jh_series<T>(p - 1, a.nser, s2);
+      for (int n = p - 1; n >= 1; --n)
+        tjh[(n - 1) * S + lane] = T(2 * n + 1) * tjh[n * S + lane] - s2 * tjh[(n + 1) * S + lane];
+      cplx<T> wm = mk<T>(1, 0);
+      for (int m = 0; m <= p; ++m) {
+        if (m > 0) wm = mk<T>(wm.x * ux - wm.y * uy, wm.x * uy + wm.y * ux);
+        twr[m * S + lane] = wm.x;
+        twi[m * S + lane] = wm.y;
+        T r2 = 0, r1 = qmm[m];
+        for (int n = m; n <= p; ++n) {
+          if (n > m) {
+            const T* ab = a.rec + 2 * (n * (n + 1) / 2 + m);
+            const T rn = ab[0] * (uz * r1 - ab[1] * s2 * r2);
+            r2 = r1;
+            r1 = rn;
           }
+          tjr[(n * (n + 1) / 2 + m) * S + lane] = tjh[n * S + lane] * r1;
+        }
+      }
+      tq[lane] = q.x;
+      tq[S + lane] = q.y;
+    }
+    __syncthreads();
+    for (int base_pair = 0; base_pair < npair; base_pair += 64 / G) {
+      const int pr = base_pair + lane / G, part = lane % G;
+      const bool on = pr < npair;
+      int n = 0;
+      if (on)
+        while ((n + 1) * (n + 2) / 2 <= pr) ++n;
+      const int m = on ? pr - n * (n + 1) / 2 : 0;
+      T pr_r = 0, pr_i = 0, ng_r = 0, ng_i = 0;
+      if (on) {
+        const T* jr = tjr + pr * S;
+        const T* wr = twr + m * S;
+        const T* wi = twi + m * S;
+        for (int j = part; j < cnt; j += G) {
+          const T b = jr[j];
+          const T bx = b * wr[j], by = b * wi[j];
+          const T qx = tq[j], qy = tq[S + j];
+          pr_r += qx * bx + qy * by;
+          pr_i += qy * bx - qx * by;
+          ng_r += qx * bx - qy * by;
+          ng_i += qx * by + qy * bx;
+        }
+      }
+      for (int o = 1; o < G; o <<= 1) {
+        pr_r += __shfl_xor(pr_r, o);
+        pr_i += __shfl_xor(pr_i, o);
+        ng_r += __shfl_xor(ng_r, o);
+        ng_i += __shfl_xor(ng_i, o);
+      }
+      if (on && part == 0) {
+        const int c = n * n + n + m;
+        acc[c] += pr_r;
+        acc[a.P2 + c] += pr_i;
+        if (m > 0) {
+          const T sg = (m & 1) ? T(-1) : T(1);
+          acc[c - 2 * m] += sg * ng_r;
+          acc[a.P2 + c - 2 * m] += sg * ng_i;
         }
       }
     }
@@ -1027,7 +1076,17 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     HFMM_HIP(hipStreamWaitEvent(fs, t.fork, 0));
   }
   la.E = P.M.p + P.eoff[L];
-  k3_p2m<T><<<nleaves, 64, 0, fs>>>(la);
+  {
+    // P2M table: jh (p + 1 rows), jh Rh (pairs), w^m (2 (p + 1)), q (2), row stride cp + 1
+    const int p_ = P.pl, rows = (p_ + 1) + (p_ + 1) * (p_ + 2) / 2 + 2 * (p_ + 1) + 2;
+    size_t lds = 0;
+    for (la.cp = 32; la.cp >= 4; la.cp /= 2) {
+      lds = (2 * (size_t)P.P2[L] + (size_t)rows * (la.cp + 1)) * sizeof(T);
+      if (lds <= 48 * 1024) break;
+    }
+    HFMM_REQUIRE(lds <= 48 * 1024, "fmm3: P2M table too large for LDS (lower p)");
+    k3_p2m<T><<<nleaves, 64, lds, fs>>>(la);
+  }
   HFMM_LAUNCH_CHECK();
   for (int l = L - 1; l >= 2; --l) {
     Tr3Args<T> a{};
