@@ -444,8 +444,11 @@ __global__ void k3_gather(const cplx<T>* __restrict__ q, const int32_t* __restri
 // each A chunk through LDS (double-buffered), and the next chunk's A and B
 // loads are in flight while the current chunk's MFMAs run.
 constexpr int kNC3 = 2, kColsPerBlock3 = 4 * kNC3 * 16;
-template <class T> struct RG3 { static constexpr int v = 8; };
-template <> struct RG3<double> { static constexpr int v = 4; };
+// row tiles per block: FP32 8, FP64 4
+template <class T>
+int pick_rg(int) {
+  return sizeof(T) == 8 ? 4 : 8;
+}
 
 template <class T>
 struct Tr3Args {
@@ -465,10 +468,9 @@ struct Tr3Args {
   int64_t pstride;
 };
 
-template <class T>
+template <class T, int RG>
 __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   typedef typename Acc3<T>::type V4;
-  constexpr int RG = RG3<T>::v;
   constexpr int ACH = RG * 4 * 64;    // A values per chunk
   constexpr int APT = ACH / 256;      // per thread
   __shared__ __align__(32) T abuf[2][ACH];
@@ -523,24 +525,16 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
       }
     }
   };
-  // A chunk element e = i * 256 + tid of this thread: row tile r = e / 256,
-  // k step u = (e / 64) % 4, lane ln = e % 64; it goes to LDS at
-  // (r * 64 + ln) * 4 + u, so that a lane reads its 4 k steps of a row tile
-  // with one 16-byte load
-  int aoff[APT], lofs[APT];
-  bool aval[APT];
-#pragma unroll
-  for (int i = 0; i < APT; ++i) {
-    const int e = i * 256 + tid, r = e >> 8, u = (e >> 6) & 3, ln = e & 63;
-    aval[i] = r < nrt;
-    aoff[i] = (r * a.KS + u) * 64 + ln;
-    lofs[i] = (r * 64 + ln) * 4 + u;
-  }
-  const size_t abase = (size_t)rg0 * a.KS * 64;
+  // A chunk element e = i * 256 + tid of this thread: row tile i, k step
+  // u = tid / 64, lane ln = tid % 64; it goes to LDS at (i * 64 + ln) * 4 + u,
+  // so that a lane reads its 4 k steps of a row tile with one 16-byte load
+  const int lbase = (tid & 63) * 4 + (tid >> 6);
+  const size_t abase = (size_t)rg0 * a.KS * 64 + tid;
+  const size_t astride = (size_t)a.KS * 64;
   auto loadA = [&](int k0, T (&ra)[APT]) {
     const T* p0 = Ab + abase + (size_t)k0 * 64;
 #pragma unroll
-    for (int i = 0; i < APT; ++i) ra[i] = aval[i] ? p0[aoff[i]] : T(0);
+    for (int i = 0; i < APT; ++i) ra[i] = i < nrt ? p0[i * astride] : T(0);
   };
   auto loadB = [&](int k0, T (&rb)[4][kNC3]) {
 #pragma unroll
@@ -564,7 +558,7 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
   loadA(ch * 4, ra);
   loadB(ch * 4, rb);
 #pragma unroll
-  for (int i = 0; i < APT; ++i) abuf[0][lofs[i]] = ra[i];
+  for (int i = 0; i < APT; ++i) abuf[0][i * 256 + lbase] = ra[i];
   __syncthreads();
   for (int it = it_lo; it < it_hi; ++it) {
     const int cur = (it - it_lo) & 1;
@@ -597,7 +591,7 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
     wv = wvn;
     if (more) {
 #pragma unroll
-      for (int i = 0; i < APT; ++i) abuf[cur ^ 1][lofs[i]] = ra[i];
+      for (int i = 0; i < APT; ++i) abuf[cur ^ 1][i * 256 + lbase] = ra[i];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -633,9 +627,12 @@ __global__ void k3_sum_parts(const T* __restrict__ part, int S, int64_t pstride,
 
 // Blocks of a translation launch (one group) and the groups that bring the
 // launch to about 3 waves per SIMD (at most one per iteration, at most 63).
+// (A 7-tile FP32 instance that fits 4 waves per SIMD, with 1024 blocks, was
+// slower: 3.39 against 3.31 ms for the 2^20 apply.)
 template <class T>
 int trans_groups(int ncols, int RT, int nall, bool m2l) {
-  const int base = (m2l ? 8 : 1) * ((ncols + kColsPerBlock3 - 1) / kColsPerBlock3) * ((RT + RG3<T>::v - 1) / RG3<T>::v);
+  const int rg = pick_rg<T>(RT);
+  const int base = (m2l ? 8 : 1) * ((ncols + kColsPerBlock3 - 1) / kColsPerBlock3) * ((RT + rg - 1) / rg);
   int S = (768 + base - 1) / base;
   return std::max(1, std::min(S, std::min(63, nall)));
 }
@@ -645,12 +642,15 @@ void launch_trans(Tr3Args<T> a, T* part, size_t part_n, hipStream_t stream) {
   const int nall = (a.m2l ? 189 : 1) * (a.KS / 4);
   a.S = trans_groups<T>(a.ncols, a.RT, nall, a.m2l != 0);
   a.part = part;
-  dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + RG3<T>::v - 1) / RG3<T>::v,
-         (a.m2l ? 8 : 1) * a.S);
+  const int rg = pick_rg<T>(a.RT);
+  dim3 g((a.ncols + kColsPerBlock3 - 1) / kColsPerBlock3, (a.RT + rg - 1) / rg, (a.m2l ? 8 : 1) * a.S);
   const int acc = a.accumulate;
   if (a.S > 1) a.accumulate = 0;  // partials are stored
   HFMM_REQUIRE(a.S == 1 || (part != nullptr && (size_t)a.S * a.pstride <= part_n), "fmm3: partial-sum buffer too small");
-  k3_trans<T><<<g, 256, 0, stream>>>(a);
+  if constexpr (sizeof(T) == 8)
+    k3_trans<T, 4><<<g, 256, 0, stream>>>(a);
+  else
+    k3_trans<T, 8><<<g, 256, 0, stream>>>(a);
   HFMM_LAUNCH_CHECK();
   if (a.S > 1) {
     k3_sum_parts<T><<<(unsigned)((a.pstride + 255) / 256), 256, 0, stream>>>(part, a.S, a.pstride, acc, a.C);
