@@ -659,13 +659,14 @@ def m2l3_flops(L, orders):
     pair of the interaction lists inside the cube, P^2 = (p_l + 1)^2
     coefficients; a complex multiply-add is 8 real flops) and the MFMA flops
     the kernel executes: a wave of 32 class members (columns) runs the real
-    2P^2 x 2P^2 product, padded to Kp = 16-multiple rows and columns, for
-    every offset of its class for which one of its members has a source."""
+    2P^2 x 2P^2 product, rows padded to a multiple of 16 and k to one of 4,
+    for every offset of its class for which one of its members has a source."""
     alg, exe = 0, 0
     for l in range(2, L + 1):
         nb, h = 2 ** l, 2 ** (l - 1)
         P2 = (orders[l] + 1) ** 2
         kp = (2 * P2 + 15) // 16 * 16
+        ke = (2 * P2 + 3) // 4 * 4  # the k extent the kernel multiplies (K padding skipped)
         m = np.arange(h ** 3)
         wave = m // 32
         nw = int(wave.max()) + 1
@@ -681,7 +682,7 @@ def m2l3_flops(L, orders):
                         ok = (sx >= 0) & (sx < nb) & (sy >= 0) & (sy < nb) & (sz >= 0) & (sz < nb)
                         alg += int(np.count_nonzero(ok)) * 8 * P2 * P2
                         waves_on = np.count_nonzero(np.bincount(wave[ok], minlength=nw))
-                        exe += int(waves_on) * 32 * 2 * kp * kp
+                        exe += int(waves_on) * 32 * 2 * kp * ke
     return alg, exe
 
 

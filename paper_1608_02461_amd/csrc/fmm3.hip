@@ -457,6 +457,7 @@ struct Tr3Args {
   T* C;
   const int* offs;  // M2L: [8][189] packed (dx+3) | (dy+3) << 4 | (dz+3) << 8
   int RT, KS, ncols, crows, accumulate;
+  int KSe;  // k steps that hold data (<= KS; the rest of A and B is zero padding)
   int64_t ldb, ldc, aslot;  // column strides; M2L: table stride per offset slot
   int m2l, nb, h;           // M2L: boxes per axis, nb / 2
   // groups: grid.z = 8 S (M2L) or S; group g takes iterations [n g / S,
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
       obox[c] = cc;
     }
   }
-  const int nch = a.KS >> 2;
+  const int nch = (a.KSe + 3) >> 2;
   const int nall = (a.m2l ? 189 : 1) * nch;
   const int it_lo = (int)((int64_t)nall * grp / a.S), it_hi = (int)((int64_t)nall * (grp + 1) / a.S);
   const int* po = a.offs + par * 189;
@@ -550,7 +551,7 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
     for (int c = 0; c < kNC3; ++c) acc[r][c] = V4{0, 0, 0, 0};
 
   T ra[APT], rb[4][kNC3], rbn[4][kNC3];
-  int oi = it_lo / nch, ch = it_lo - oi * nch;
+  int oi = it_lo / nch, ch = it_lo - oi * nch, chc = ch;
   locate(oi);
   // a wave none of whose columns has a source in this iteration skips its
   // MFMAs (it still stages A with the block)
@@ -573,22 +574,26 @@ __global__ __launch_bounds__(256) void k3_trans(Tr3Args<T> a) {
       loadA(ch * 4, ra);
       loadB(ch * 4, rbn);
     }
+    // k steps of this chunk that hold data (the last chunk of a K that is
+    // not a multiple of 16 skips the padding)
+    const int lim = min(4, a.KSe - 4 * chc);
     if (wv) {
       const A4* ab4 = reinterpret_cast<const A4*>(abuf[cur]);
 #pragma unroll
       for (int r = 0; r < RG; ++r)
         if (r < nrt) {
           const A4 av = ab4[r * 64 + lane];
+          const T avu[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-          for (int c = 0; c < kNC3; ++c) {
-            acc[r][c] = mfma3(av.x, rb[0][c], acc[r][c]);
-            acc[r][c] = mfma3(av.y, rb[1][c], acc[r][c]);
-            acc[r][c] = mfma3(av.z, rb[2][c], acc[r][c]);
-            acc[r][c] = mfma3(av.w, rb[3][c], acc[r][c]);
-          }
+          for (int u = 0; u < 4; ++u)
+            if (u < lim) {
+#pragma unroll
+              for (int c = 0; c < kNC3; ++c) acc[r][c] = mfma3(avu[u], rb[u][c], acc[r][c]);
+            }
         }
     }
     wv = wvn;
+    chc = ch;
     if (more) {
 #pragma unroll
       for (int i = 0; i < APT; ++i) abuf[cur ^ 1][i * 256 + lbase] = ra[i];
@@ -639,7 +644,8 @@ int trans_groups(int ncols, int RT, int nall, bool m2l) {
 
 template <class T>
 void launch_trans(Tr3Args<T> a, T* part, size_t part_n, hipStream_t stream) {
-  const int nall = (a.m2l ? 189 : 1) * (a.KS / 4);
+  HFMM_REQUIRE(a.KSe >= 1 && a.KSe <= a.KS, "fmm3: bad k-step count");
+  const int nall = (a.m2l ? 189 : 1) * ((a.KSe + 3) / 4);
   a.S = trans_groups<T>(a.ncols, a.RT, nall, a.m2l != 0);
   a.part = part;
   const int rg = pick_rg<T>(a.RT);
@@ -1096,6 +1102,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.C = P.M.p + P.eoff[l];
     a.RT = P.Kp[l] / 16;
     a.KS = 8 * P.Kp[l + 1] / 4;
+    a.KSe = a.KS;  // the children's padding lies between them
     a.ncols = 1 << (3 * l);
     a.crows = P.Kp[l];
     a.accumulate = 0;
@@ -1114,6 +1121,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.C = P.Lc.p + P.eoff[l];
     a.RT = P.Kp[l] / 16;
     a.KS = P.Kp[l] / 4;
+    a.KSe = (2 * P.P2[l] + 3) / 4;
     a.h = 1 << (l - 1);
     a.nb = 1 << l;
     a.ncols = a.h * a.h * a.h;
@@ -1136,6 +1144,7 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
     a.C = P.Lc.p + P.eoff[l];
     a.RT = 8 * P.Kp[l] / 16;
     a.KS = P.Kp[l - 1] / 4;
+    a.KSe = (2 * P.P2[l - 1] + 3) / 4;
     a.ncols = 1 << (3 * (l - 1));
     a.crows = 8 * P.Kp[l];
     a.accumulate = 1;
