@@ -444,10 +444,12 @@ __global__ void k3_gather(const cplx<T>* __restrict__ q, const int32_t* __restri
 // each A chunk through LDS (double-buffered), and the next chunk's A and B
 // loads are in flight while the current chunk's MFMAs run.
 constexpr int kNC3 = 2, kColsPerBlock3 = 4 * kNC3 * 16;
-// row tiles per block: FP32 8, FP64 4
+// row tiles per block: FP32 8; FP64 7 for launches of 7 or 14 row tiles
+// (Kp = 112: one row group, so the sources are gathered once; 2 waves per
+// SIMD, yet 4.23 -> 3.49 ms for the M2L of the 2^20 apply), else 4
 template <class T>
-int pick_rg(int) {
-  return sizeof(T) == 8 ? 4 : 8;
+int pick_rg(int RT) {
+  return sizeof(T) == 8 ? (RT % 7 == 0 ? 7 : 4) : 8;
 }
 
 template <class T>
@@ -653,8 +655,12 @@ void launch_trans(Tr3Args<T> a, T* part, size_t part_n, hipStream_t stream) {
   const int acc = a.accumulate;
   if (a.S > 1) a.accumulate = 0;  // partials are stored
   HFMM_REQUIRE(a.S == 1 || (part != nullptr && (size_t)a.S * a.pstride <= part_n), "fmm3: partial-sum buffer too small");
-  if constexpr (sizeof(T) == 8)
-    k3_trans<T, 4><<<g, 256, 0, stream>>>(a);
+  if constexpr (sizeof(T) == 8) {
+    if (rg == 7)
+      k3_trans<T, 7><<<g, 256, 0, stream>>>(a);
+    else
+      k3_trans<T, 4><<<g, 256, 0, stream>>>(a);
+  }
   else
     k3_trans<T, 8><<<g, 256, 0, stream>>>(a);
   HFMM_LAUNCH_CHECK();
