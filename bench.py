@@ -53,6 +53,7 @@ PEAK_HBM = 8000.0       # GB/s
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "p2p_fmm_n1m_k100_p8_fp32_pmc.md")
 M2L_SUMMARY = os.path.join(ROOT, "profiles", "m2l_mfma_fmm_n1m_and_n1024_counters.md")
+FMM3_SUMMARY = os.path.join(ROOT, "profiles", "fmm3_apply_n1m_k10_p6_kernels.md")
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, dense FP32 matrix cores
 PEAK_FP64_MFMA = 78.6
 
@@ -732,6 +733,8 @@ def bench_fmm3(dev, hfmm, workloads, torch, runs=10):
            "max_leaf": info["max_leaf_count"], "tree_build_first_ms": round(t_first * 1e3, 3),
            "tree_build_ms": round(t_second * 1e3, 3), "m2l_algorithmic_flops": alg, "m2l_executed_flops": exe,
            "p2p_pairs": pairs}
+    # calibrated HBM bytes of the M2L stage from the committed counters
+    rec3 = profile_record(FMM3_SUMMARY, "k3_trans")
     phis = {}
     for name, prec, dt, peak in (("fp32", hfmm.FP32, torch.complex64, 157.3), ("fp64", hfmm.FP64, torch.complex128, 78.6)):
         q = torch.from_numpy(w["q"]).to(dt).to(dev)
@@ -760,6 +763,7 @@ def bench_fmm3(dev, hfmm, workloads, torch, runs=10):
             "stage_ms": {s_: round(v, 4) for s_, v in st.items()},
             "m2l_roofline": {"bound": "mfma", "achieved": round(alg / m2l_s / 1e12, 3), "peak": peak,
                              "unit": "TFLOP/s", "frac": round(alg / m2l_s / 1e12 / peak, 4),
+                             "traffic": (rec3["m2l_stage_traffic_bytes_fp32"] if rec3 and name == "fp32" else None),
                              "executed_TFLOP_s": round(exe / m2l_s / 1e12, 3),
                              "executed_over_algorithmic": round(exe / alg, 3)},
             "p2p_pairs_per_s": round(pairs / (st["p2p"] * 1e-3), 1),
