@@ -43,7 +43,9 @@ namespace {
 
 constexpr double kPi3 = 3.14159265358979323846;
 constexpr int kMaxP3 = 20;  // largest order of any level
-constexpr int kTaylor3 = 13;  // Taylor terms of the FP64 near-field cosine and sine (k r <= 2)
+// Taylor terms of the FP64 near-field cosine and sine: 7, 10 or 13, the
+// fewest whose first omitted term is below 1e-17 at the largest k r (<= 2)
+constexpr int kTaylorMax3 = 13;
 
 typedef float f32x4_3 __attribute__((ext_vector_type(4)));
 typedef double f64x4_3 __attribute__((ext_vector_type(4)));
@@ -360,7 +362,7 @@ __device__ __forceinline__ void pair3_taylor(double r2, double k, double k2, con
 // neighbouring leaves' points are staged through LDS 64 at a time.  Offsets
 // between leaf centres are whole multiples of the leaf side, so the
 // difference of two points is formed from leaf-relative coordinates.
-template <class T>
+template <class T, int NT>
 __global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
   typedef typename Vec4<T>::type V;
   __shared__ V sp[64];
@@ -403,14 +405,10 @@ __global__ __launch_bounds__(64) void k3_p2p(Leaf3Args<T> a) {
           const T ddx = cx - ps.x, ddy = cy - ps.y, ddz = cz - ps.z;
           const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
           T gr, gi;
-          if constexpr (sizeof(T) == 8) {
-            if (a.ntay)
-              pair3_taylor<kTaylor3>(r2, a.k, a.k * a.k, a.tc, a.ts, gr, gi);
-            else
-              pair3(r2, a.k, k2pi, gr, gi);
-          } else {
+          if constexpr (NT > 0)
+            pair3_taylor<NT>(r2, a.k, a.k * a.k, a.tc, a.ts, gr, gi);
+          else
             pair3(r2, a.k, k2pi, gr, gi);
-          }
           const cplx<T> qq = sq[jj];
           ar += qq.x * gr - qq.y * gi;
           ai += qq.x * gi + qq.y * gr;
@@ -1067,13 +1065,23 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
   {
     // the largest k r of a near pair: opposite corners of a 2 x 2 x 2 block of leaves
     const double krmax = k * 2.0 * std::sqrt(3.0) * t.leaf_side();
-    la.ntay = krmax <= 2.0 ? kTaylor3 : 0;
+    la.ntay = 0;
+    if (krmax <= 2.0)
+      for (int nt : {7, 10, kTaylorMax3}) {
+        // first omitted cosine term x^(2 nt) / (2 nt)!
+        double term = 1.0;
+        for (int i = 1; i <= 2 * nt; ++i) term *= krmax / i;
+        if (term < 1e-17 || nt == kTaylorMax3) {
+          la.ntay = nt;
+          break;
+        }
+      }
     double f = 1.0;  // (2n)! then (2n+1)!
     for (int n = 0; n < 16; ++n) {
       const double sg = (n & 1) ? -1.0 : 1.0;
       if (n > 0) f *= (2.0 * n - 1.0) * (2.0 * n);
-      la.tc[n] = n < kTaylor3 ? sg / f : 0.0;
-      la.ts[n] = n < kTaylor3 ? sg / (f * (2.0 * n + 1.0)) : 0.0;
+      la.tc[n] = n < la.ntay ? sg / f : 0.0;
+      la.ts[n] = n < la.ntay ? sg / (f * (2.0 * n + 1.0)) : 0.0;
     }
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[0], stream));
@@ -1161,7 +1169,16 @@ void fmm3_apply(Tree3& t, double k, int p, const cplx<T>* d_q, cplx<T>* d_phi, h
   }
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[3], stream));
   if (overlap) HFMM_HIP(hipEventRecord(t.join, fs));
-  k3_p2p<T><<<nleaves, 64, 0, stream>>>(la);
+  if constexpr (sizeof(T) == 8) {
+    switch (la.ntay) {
+      case 7: k3_p2p<T, 7><<<nleaves, 64, 0, stream>>>(la); break;
+      case 10: k3_p2p<T, 10><<<nleaves, 64, 0, stream>>>(la); break;
+      case kTaylorMax3: k3_p2p<T, kTaylorMax3><<<nleaves, 64, 0, stream>>>(la); break;
+      default: k3_p2p<T, 0><<<nleaves, 64, 0, stream>>>(la); break;
+    }
+  } else {
+    k3_p2p<T, 0><<<nleaves, 64, 0, stream>>>(la);
+  }
   HFMM_LAUNCH_CHECK();
   if (stage_ms) HFMM_HIP(hipEventRecord(P.ev[4], stream));
   if (overlap) HFMM_HIP(hipStreamWaitEvent(stream, t.join, 0));

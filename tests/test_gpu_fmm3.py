@@ -25,9 +25,11 @@ def both(t, xyz, q, k, p):
     return f64, f32
 
 
-# k h small enough in the last case (k times twice the leaf diagonal <= 2) for the FP64
-# near field's Taylor form, library sincos in the others
-@pytest.mark.parametrize("N,leaf,k,p", [(700, 16, 10.0, 4), (3000, 8, 6.0, 3), (3000, 8, 4.0, 4)])
+# the FP64 near field: library sincos in the first two cases; the Taylor form
+# with 13, 10 and 7 terms in the last three (k times twice the leaf diagonal
+# 1.73, 1.08, 0.39)
+@pytest.mark.parametrize("N,leaf,k,p", [(700, 16, 10.0, 4), (3000, 8, 6.0, 3), (3000, 8, 4.0, 4),
+                                        (3000, 8, 2.5, 4), (3000, 8, 0.9, 3)])
 def test_fmm3_matches_oracle_fmm(N, leaf, k, p):
     say(f"fmm3 parity N={N} leaf={leaf} k={k} p={p}")
     xyz, q = workloads.random_cloud3(N, 40 + N)
