@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "hfmm.h")
 
 HFMM_OK = 0
 HFMM_NOT_CONVERGED = 1
+HFMM_ERR_ARG = -1
 FP64 = 0
 FP32 = 1
 

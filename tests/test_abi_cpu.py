@@ -68,3 +68,29 @@ def test_tune_cache_file_round_trip(tmp_path):
             hfmm.hfmm_tune_cache_load(str(g))
     hfmm.hfmm_tune_cache_clear()
     assert hfmm.hfmm_tune_cache_size() == 0
+
+
+@pytest.mark.skipif(not os.path.exists(hfmm.LIB_PATH), reason="library not built")
+def test_3d_entry_points_reject_bad_arguments_before_any_device_call():
+    """The oct-tree entry points validate their host arguments first, so
+    these calls return HFMM_ERR_ARG (with a message) without touching a GPU."""
+    L = hfmm.lib()
+    out = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+
+    def st(code):
+        assert code == hfmm.HFMM_ERR_ARG
+        return hfmm.hfmm_last_error()
+
+    assert "out is NULL" in st(L.hfmm3_build_tree(vp(1), 10, 0.0, 0.0, 0.0, 1.0, 8, None, None))
+    assert "n must be >= 1" in st(L.hfmm3_build_tree(vp(1), 0, 0.0, 0.0, 0.0, 1.0, 8, None, ctypes.byref(out)))
+    assert "side" in st(L.hfmm3_build_tree(vp(1), 10, 0.0, 0.0, 0.0, -1.0, 8, None, ctypes.byref(out)))
+    assert "leaf_size" in st(L.hfmm3_build_tree(vp(1), 10, 0.0, 0.0, 0.0, 1.0, 0, None, ctypes.byref(out)))
+    assert "d_xyz is NULL" in st(L.hfmm3_build_tree(None, 10, 0.0, 0.0, 0.0, 1.0, 8, None, ctypes.byref(out)))
+    assert "corner" in st(L.hfmm3_build_tree(vp(1), 10, float("nan"), 0.0, 0.0, 1.0, 8, None, ctypes.byref(out)))
+    assert out.value is None
+    assert "NULL tree" in st(L.hfmm3_fmm_apply(None, 10.0, 6, hfmm.FP64, vp(1), vp(1), None))
+    assert "NULL tree" in st(L.hfmm3_fmm_apply_timed(None, 10.0, 6, hfmm.FP32, vp(1), vp(1), None, None))
+    assert "NULL tree" in st(L.hfmm3_tree_info(None, None, None, None, None))
+    assert "NULL tree" in st(L.hfmm3_fmm_orders(None, 10.0, 6, None))
+    assert L.hfmm3_tree_destroy(None) == hfmm.HFMM_OK
