@@ -21,6 +21,9 @@ the definitions state:
                   exp(i k r) / (4 pi r) (Sec. 5.1.1, Sec. 5.2), with
                   spherical-harmonic expansions and Gaunt-coefficient
                   translations.
+* ``helm3``    -- the 3-D model problem of Sec. 7 on a 7-point grid and its
+                  free-space volume-potential preconditioner (cell self
+                  term by pyramid quadrature).
 * ``bem``      -- the dense BEM preconditioner of Sec. 5.2-5.3 (Dirichlet
                   boundary equation, interior equation, constant elements and
                   the analytic singular diagonal), and the solution with
@@ -35,4 +38,4 @@ Every function names the passage it follows.  Readings of passages where the
 paper is silent or ambiguous are stated at the function.
 """
 
-from . import kernel, fmm, fmm3, bem, fd, fgmres, bicgstab, adjoint  # noqa: F401
+from . import kernel, fmm, fmm3, helm3, bem, fd, fgmres, bicgstab, adjoint  # noqa: F401
