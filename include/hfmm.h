@@ -406,6 +406,42 @@ hfmm_status hfmm3_fmm_apply_timed(hfmm3_tree t, double k, int32_t p, hfmm_precis
 /* Expansion order of each level (host, levels + 1 ints). */
 hfmm_status hfmm3_fmm_orders(hfmm3_tree t, double k, int32_t p, int32_t* orders);
 
+/* ------------------------------------------------------------------------
+ * The 3-D model problem (Sec. 7, eq. helm3, with kappa = k > 0): the 7-point
+ * finite-difference system A u = b, A = -Laplace_h - k^2 on the n^3 interior
+ * nodes (i h, j h, l h) of the unit cube, h = 1/(n+1), x fastest, zero
+ * Dirichlet data.  Vectors are complex128, interleaved, device, n^3 values.
+ *
+ * hfmm3_fd_matvec: y = A x.  Errors: n outside [1, 1024], aliasing.  Async. */
+hfmm_status hfmm3_fd_matvec(int32_t n, double k2, const double* d_x, double* d_y, hipStream_t stream);
+
+/* A solver of that system whose right preconditioner is the volume
+ * potential of the residual by the oct-tree FMM (the 3-D counterpart of the
+ * preconditioner's first pass, Sec. 4-5; no boundary-element correction for
+ * the cube's faces):
+ *   z_i = h^3 sum_{j != i} G(|x_i - x_j|) r_j + c_self r_i,  G = exp(i k r)/(4 pi r),
+ * c_self = the integral of G over the node's cell.  The tree is built over
+ * the nodes with leaf_size; the FMM runs at order p in precond_prec (the
+ * Krylov vectors stay FP64).  Creation builds the tree and the FMM plan
+ * (synchronises `stream`).  Errors: n outside [2, 512], k <= 0, p outside
+ * [1, 20], the FMM plan's own errors. */
+typedef struct hfmm3_solver_s* hfmm3_solver;
+hfmm_status hfmm3_solver_create(int32_t n, double k, int32_t p, int32_t leaf_size, hfmm_precision precond_prec,
+                                hipStream_t stream, hfmm3_solver* out);
+/* z = M^{-1} r (r, z: n^3 complex128, device, not aliased).  Async. */
+hfmm_status hfmm3_precond_apply(hfmm3_solver s, const double* d_r, double* d_z, hipStream_t stream);
+/* Right-preconditioned FGMRES(restart), CGS2, from x0 = d_x; stops when
+ * ||b - A x|| / ||b|| <= rtol (true residual at each cycle start) or after
+ * maxit steps.  restart in [1, 200].  info (host, may be NULL) as for the
+ * 2-D solve (nrhs 1).  Returns HFMM_OK, HFMM_NOT_CONVERGED, HFMM_ERR_NUMERIC
+ * or an argument error.  Synchronises `stream`. */
+hfmm_status hfmm3_fgmres_solve(hfmm3_solver s, const double* d_b, double* d_x, int32_t restart, int32_t maxit,
+                               double rtol, hfmm_solve_info* info, hipStream_t stream);
+/* c_self (host, 2 doubles: re, im), the tree depth and the set-up time (ms);
+ * each output may be NULL. */
+hfmm_status hfmm3_solver_info(hfmm3_solver s, double* self_term, int32_t* levels, double* ms_setup);
+hfmm_status hfmm3_solver_destroy(hfmm3_solver s);
+
 #ifdef __cplusplus
 }
 #endif

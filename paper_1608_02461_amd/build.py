@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libhfmm.so")
 
 # (source, object name, extra flags): near.hip is built once per precision and
 # column-group width so that its kernel instances compile in parallel
-SOURCES = [("tree.hip", "tree", []), ("fmm.hip", "fmm", []), ("fmm3.hip", "fmm3", []), ("solver.hip", "solver", []),
+SOURCES = [("tree.hip", "tree", []), ("fmm.hip", "fmm", []), ("fmm3.hip", "fmm3", []), ("solver3.hip", "solver3", []), ("solver.hip", "solver", []),
            ("special.cpp", "special", []), ("abi.cpp", "abi", []), ("noalloc.hip", "noalloc", [])] + [
     ("near.hip", f"near_{t}_{nr}", [f"-DNEAR_T={t}", f"-DNEAR_NR={nr}"])
     for t in ("float", "double") for nr in (1, 2, 4)]

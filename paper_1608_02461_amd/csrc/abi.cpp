@@ -503,4 +503,85 @@ hfmm_status hfmm3_fmm_orders(hfmm3_tree t, double k, int32_t p, int32_t* orders)
   HFMM_GUARD_END
 }
 
+// ------------------------------------------------------------------ 3-D model problem
+hfmm_status hfmm3_fd_matvec(int32_t n, double k2, const double* d_x, double* d_y, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(n >= 1 && n <= 1024, "fd3_matvec: n must be in [1, 1024]");
+  HFMM_REQUIRE(std::isfinite(k2), "fd3_matvec: k2 must be finite");
+  HFMM_REQUIRE(d_x != nullptr && d_y != nullptr, "fd3_matvec: NULL array");
+  HFMM_REQUIRE(d_x != d_y, "fd3_matvec: x and y must not alias");
+  hfmm::fd3_apply(n, k2, reinterpret_cast<const double2*>(d_x), reinterpret_cast<double2*>(d_y), nullptr, stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_solver_create(int32_t n, double k, int32_t p, int32_t leaf_size, hfmm_precision precond_prec,
+                                hipStream_t stream, hfmm3_solver* out) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(out != nullptr, "solver3_create: out is NULL");
+  *out = nullptr;
+  auto h = std::make_unique<hfmm3_solver_s>();
+  h->s = std::make_unique<hfmm::Solver3>(n, k, p, leaf_size, (int)precond_prec, stream);
+  *out = h.release();
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_precond_apply(hfmm3_solver s, const double* d_r, double* d_z, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "precond3_apply: NULL solver");
+  HFMM_REQUIRE(d_r != nullptr && d_z != nullptr, "precond3_apply: NULL array");
+  HFMM_REQUIRE(d_r != d_z, "precond3_apply: r and z must not alias");
+  s->s->precond(reinterpret_cast<const double2*>(d_r), reinterpret_cast<double2*>(d_z), stream);
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_fgmres_solve(hfmm3_solver s, const double* d_b, double* d_x, int32_t restart, int32_t maxit,
+                               double rtol, hfmm_solve_info* info, hipStream_t stream) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "fgmres3: NULL solver");
+  const hfmm::Solve3Result r = s->s->fgmres(reinterpret_cast<const double2*>(d_b), reinterpret_cast<double2*>(d_x),
+                                            restart, maxit, rtol, stream);
+  if (info) {
+    *info = hfmm_solve_info{};
+    info->iters = r.iters;
+    info->restarts = r.restarts;
+    info->converged = r.converged ? 1 : 0;
+    info->rel_res_true = r.rel_res_true;
+    info->rel_res_est = r.rel_res_est;
+    info->nrhs = 1;
+    info->ms_precond = r.ms_precond;
+    info->ms_total = r.ms_total;
+    info->ms_krylov = r.ms_total - r.ms_precond;
+    info->ms_setup = s->s->ms_setup;
+  }
+  if (r.numeric) {
+    hfmm::set_last_error("fgmres3: NaN or Inf met");
+    return HFMM_ERR_NUMERIC;
+  }
+  return r.converged ? HFMM_OK : HFMM_NOT_CONVERGED;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_solver_info(hfmm3_solver s, double* self_term, int32_t* levels, double* ms_setup) {
+  HFMM_GUARD_BEGIN
+  HFMM_REQUIRE(s != nullptr && s->s, "solver3_info: NULL solver");
+  if (self_term) {
+    self_term[0] = s->s->cself.real();
+    self_term[1] = s->s->cself.imag();
+  }
+  if (levels) *levels = s->s->tree->L;
+  if (ms_setup) *ms_setup = s->s->ms_setup;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
+hfmm_status hfmm3_solver_destroy(hfmm3_solver s) {
+  HFMM_GUARD_BEGIN
+  delete s;
+  return HFMM_OK;
+  HFMM_GUARD_END
+}
+
 }  // extern "C"

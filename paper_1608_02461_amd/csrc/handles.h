@@ -6,6 +6,7 @@
 #include <string>
 
 #include "fmm3.h"
+#include "solver3.h"
 #include "solver.h"
 
 struct hfmm_tree_s {
@@ -16,6 +17,9 @@ struct hfmm_solver_s {
 };
 struct hfmm3_tree_s {
   std::unique_ptr<hfmm::Tree3> t;
+};
+struct hfmm3_solver_s {
+  std::unique_ptr<hfmm::Solver3> s;
 };
 
 #define HFMM_GUARD_BEGIN try {

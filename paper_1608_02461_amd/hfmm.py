@@ -92,6 +92,12 @@ _SIGS = {
     "hfmm3_fmm_apply": ([_vp, _f64, _i32, _i32, _vp, _vp, _vp], _i32),
     "hfmm3_fmm_apply_timed": ([_vp, _f64, _i32, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp], _i32),
     "hfmm3_fmm_orders": ([_vp, _f64, _i32, ctypes.POINTER(_i32)], _i32),
+    "hfmm3_fd_matvec": ([_i32, _f64, _vp, _vp, _vp], _i32),
+    "hfmm3_solver_create": ([_i32, _f64, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)], _i32),
+    "hfmm3_precond_apply": ([_vp, _vp, _vp, _vp], _i32),
+    "hfmm3_fgmres_solve": ([_vp, _vp, _vp, _i32, _i32, _f64, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "hfmm3_solver_info": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)], _i32),
+    "hfmm3_solver_destroy": ([_vp], _i32),
 }
 
 
@@ -369,6 +375,64 @@ def hfmm3_fmm_apply_timed(tree, k, p, q, prec=FP64, stream=None):
     _check(lib().hfmm3_fmm_apply_timed(tree.handle, float(k), int(p), int(prec), _ptr(qc), _ptr(phi), ms,
                                        _stream(stream)))
     return phi, dict(zip(STAGES3, list(ms)))
+
+
+def hfmm3_fd_matvec(n, k2, x, stream=None):
+    """y = (-Laplace_h - k^2) x on the n^3 interior nodes of the unit cube (complex128)."""
+    _require_cuda(x, torch.complex128, "x")
+    if x.dim() != 1 or x.shape[0] != n ** 3:
+        raise ValueError("x must hold n^3 values")
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    _check(lib().hfmm3_fd_matvec(int(n), float(k2), _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+class Solver3:
+    """The 3-D model problem with the oct-tree FMM volume-potential preconditioner."""
+
+    def __init__(self, n, k, p=6, leaf_size=64, prec=FP64, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().hfmm3_solver_create(int(n), float(k), int(p), int(leaf_size), int(prec), _stream(stream),
+                                         ctypes.byref(h)))
+        self.handle = h
+        self.n = n
+        self.N = n ** 3
+
+    def _vec(self, v, name):
+        _require_cuda(v, torch.complex128, name)
+        if v.dim() != 1 or v.shape[0] != self.N:
+            raise ValueError(f"{name} must hold n^3 values")
+        return v.contiguous()
+
+    def precond_apply(self, r, stream=None):
+        r = self._vec(r, "r")
+        z = torch.empty_like(r)
+        _check(lib().hfmm3_precond_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def solve(self, b, x0=None, restart=50, maxit=2000, rtol=1e-6, stream=None, strict=False):
+        b = self._vec(b, "b")
+        x = torch.zeros_like(b) if x0 is None else self._vec(x0, "x0").clone()
+        info = SolveInfo()
+        st = lib().hfmm3_fgmres_solve(self.handle, _ptr(b), _ptr(x), int(restart), int(maxit), float(rtol),
+                                      ctypes.byref(info), _stream(stream))
+        _check(st, allow_not_converged=not strict)
+        return x, info.as_dict()
+
+    def info(self):
+        c = (_f64 * 2)()
+        L, ms = _i32(), _f64()
+        _check(lib().hfmm3_solver_info(self.handle, c, ctypes.byref(L), ctypes.byref(ms)))
+        return {"self_term": complex(c[0], c[1]), "levels": L.value, "ms_setup": ms.value}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.hfmm3_solver_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 def hfmm_fd_helmholtz_matvec(n, h, x, k2=None, k2_const=0.0, stream=None):

@@ -1,0 +1,94 @@
+"""GPU parity of the 3-D model problem (Sec. 7, eq. helm3, kappa = k > 0)
+against the oracle (oracle.helm3): the 7-point matvec, the cell self term,
+the FMM volume-potential preconditioner (element by element against the
+oracle's FMM form on the same tree) and preconditioned FGMRES solves
+(against sparse direct and the oracle FGMRES's iteration count)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fgmres as ofg
+from oracle import helm3 as oh3
+from paper_1608_02461_amd import hfmm, workloads
+from gpu_util import rel, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,k", [(1, 2.0), (5, 3.0), (16, 10.0)])
+def test_fd3_matvec(n, k):
+    rng = np.random.default_rng(n)
+    x = workloads.complex_normal(rng, n ** 3)
+    y = to_np(hfmm.hfmm3_fd_matvec(n, k * k, to_dev(x)))
+    ref = oh3.matrix3(n, k * k) @ x
+    assert rel(y, ref) <= 1e-14
+
+
+def test_precond3_matches_oracle_fmm_form():
+    n, k, p, leaf = 11, 5.0, 6, 8
+    say(f"precond3 n={n} k={k} p={p}")
+    rng = np.random.default_rng(21)
+    r = workloads.complex_normal(rng, n ** 3)
+    ref = oh3.precond3_apply_fmm(n, k, r, p, leaf)
+    for prec, tol in ((hfmm.FP64, 1e-11), (hfmm.FP32, 2e-5)):
+        s = hfmm.Solver3(n, k, p=p, leaf_size=leaf, prec=prec)
+        inf = s.info()
+        c = oh3.self_term3(k, 1.0 / (n + 1))
+        assert abs(inf["self_term"] - c) <= 1e-13 * abs(c)
+        assert inf["levels"] == 3
+        z = to_np(s.precond_apply(to_dev(r)))
+        say(f"  prec {prec}: {rel(z, ref):.2e}")
+        assert rel(z, ref) <= tol
+
+
+def test_solve3_against_oracle_fgmres_and_sparse_direct():
+    n, k, p, leaf = 11, 5.0, 6, 8
+    b = -np.ones(n ** 3, dtype=np.complex128)
+    A = oh3.matrix3(n, k * k)
+    xs = spla.spsolve(A.tocsc(), b)
+    _, oinfo = ofg.fgmres(lambda v: A @ v, lambda v: oh3.precond3_apply_fmm(n, k, v, p, leaf), b,
+                          restart=30, rtol=1e-6)
+    for prec in (hfmm.FP64, hfmm.FP32):
+        s = hfmm.Solver3(n, k, p=p, leaf_size=leaf, prec=prec)
+        x, info = s.solve(to_dev(b), restart=30, rtol=1e-6, strict=True)
+        x = to_np(x)
+        res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        say(f"solve3 n={n} prec {prec}: iters {info['iters']} (oracle {oinfo['iters']}) res {res:.2e}")
+        assert info["converged"] == 1 and res <= 1e-6 and abs(info["rel_res_true"] - res) <= 1e-9
+        assert rel(x, xs) <= 1e-5
+        assert abs(info["iters"] - oinfo["iters"]) <= 2
+
+
+def test_solve3_larger_grid_and_restarts():
+    # 31^3 = 29791 unknowns on a depth-3 tree; FGMRES(10) so that several
+    # restart cycles run
+    n, k = 31, 8.0
+    b = -np.ones(n ** 3, dtype=np.complex128)
+    A = oh3.matrix3(n, k * k)
+    s = hfmm.Solver3(n, k, p=6, leaf_size=64, prec=hfmm.FP32)
+    x, info = s.solve(to_dev(b), restart=10, rtol=1e-7, strict=True)
+    x = to_np(x)
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    say(f"solve3 n={n}: iters {info['iters']} restarts {info['restarts']} res {res:.2e}")
+    assert res <= 1e-7 and info["restarts"] >= 2
+    # x0 = the solution: converged at once
+    x2, info2 = s.solve(to_dev(b), x0=to_dev(x), restart=10, rtol=1e-6)
+    assert info2["iters"] == 0 and info2["converged"] == 1
+    # maxit reached: not converged, reported as such
+    _, info3 = s.solve(to_dev(b), restart=10, maxit=3, rtol=1e-12)
+    assert info3["converged"] == 0 and info3["iters"] == 3
+    # zero right-hand side: x = 0
+    z, info4 = s.solve(to_dev(np.zeros(n ** 3, dtype=np.complex128)))
+    assert info4["converged"] == 1 and float(np.abs(to_np(z)).max()) == 0.0
+
+
+def test_solver3_argument_errors():
+    with pytest.raises(hfmm.HFMMError):
+        hfmm.Solver3(1, 5.0)
+    with pytest.raises(hfmm.HFMMError):
+        hfmm.Solver3(8, -1.0)
+    with pytest.raises(hfmm.HFMMError):
+        hfmm.Solver3(8, 5.0, p=21)
+    s = hfmm.Solver3(8, 5.0, leaf_size=8)
+    with pytest.raises(hfmm.HFMMError):
+        s.solve(to_dev(np.ones(512, dtype=np.complex128)), restart=0)
