@@ -337,6 +337,35 @@ def bench_batch_16x4(dev, hfmm, workloads, torch):
     return out
 
 
+def bench_batch_small(dev, hfmm, workloads, torch):
+    """16 small problems (64 x 64 grids, k = 8..23, one right-hand side each,
+    FGMRES(30) to 1e-6): graph vs eager where launches, not the FMM's work,
+    set the pace of an Arnoldi step."""
+    n = 64
+    rng = np.random.default_rng(11)
+    ks = [8.0 + i for i in range(16)]
+    solvers = [hfmm.Solver(n, k, p=6, leaf_size=32, prec=hfmm.FP32) for k in ks]
+    bs = [torch.from_numpy(workloads.complex_normal(rng, n * n)).to(dev) for _ in ks]
+    torch.cuda.synchronize()
+    out = {"problems": len(ks), "n": n, "k": [ks[0], ks[-1]]}
+    for _, graph in (("graph", True), ("eager", False)):  # untimed first batch per mode
+        hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=30, rtol=1e-6, use_graph=graph)
+    torch.cuda.synchronize()
+    for mode, graph in (("graph", True), ("eager", False)):
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, infos = hfmm.hfmm_fgmres_solve_batched(solvers, bs, restart=30, rtol=1e-6, use_graph=graph)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[mode] = {"t_batch_s": round(dt, 5), "solves_s": round(len(ks) / dt, 2),
+                     "converged": sum(i["converged"] for i in infos), "iters": [i["iters"] for i in infos]}
+        log(f"16 x 64^2 batch {mode}: {out[mode]}")
+    out["graph_over_eager_speedup"] = round(out["eager"]["t_batch_s"] / out["graph"]["t_batch_s"], 3)
+    del solvers
+    return out
+
+
 def bench_adjoint_256(dev, hfmm, workloads, torch):
     from oracle import adjoint as oadj
     from paper_1608_02461_amd.autograd import helmholtz_solve
@@ -775,6 +804,40 @@ def bench_fmm3(dev, hfmm, workloads, torch, runs=10):
     return out
 
 
+def bench_helm3(dev, hfmm, workloads, torch):
+    """The 3-D model problem (7-point grid, n^3 unknowns, k = 10): FGMRES(30)
+    to 1e-6 with the oct-tree FMM volume potential as the preconditioner, in
+    FP32 and FP64, for n = 63 and 127."""
+    out = {}
+    for n in (63, 127):
+        w = workloads.helm3_cube(n)
+        b = torch.from_numpy(w["b"]).to(dev)
+        row = {"unknowns": n ** 3}
+        for name, prec in (("fp32", hfmm.FP32), ("fp64", hfmm.FP64)):
+            t0 = time.perf_counter()
+            s = hfmm.Solver3(n, w["k"], p=w["p"], leaf_size=w["leaf"], prec=prec)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            s.solve(b, restart=30, rtol=1e-6)  # untimed: first-use costs
+            torch.cuda.synchronize()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x, info = s.solve(b, restart=30, rtol=1e-6)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            row[name] = {"s_per_solve": round(dt, 4), "iters": info["iters"], "converged": info["converged"],
+                         "rel_res_true": info["rel_res_true"], "ms_precond_per_iter":
+                         round(info["ms_precond"] / max(1, info["iters"]), 3),
+                         "ms_krylov_total": round(info["ms_krylov"], 2), "setup_s": round(t_setup, 3),
+                         "levels": s.info()["levels"]}
+            log(f"3-D model problem n={n} {name}: {row[name]}")
+            s.close()
+        row["mixed_over_fp64"] = round(row["fp64"]["s_per_solve"] / row["fp32"]["s_per_solve"], 3)
+        out[f"n{n}"] = row
+    return out
+
+
 PROFILE_CASES = ("apply-2p20-fp64", "pass-1024-fp32", "pass-1024-fp64", "solve-1024", "apply3-2p20-fp32",
                  "apply3-2p20-fp64")
 
@@ -956,6 +1019,7 @@ def main():
         result["fmm_2p20"] = bench_fmm_orders(tree, k, N, q32, q64, gold, smp, hfmm, torch, plan)
         result["solve_1024"] = bench_solve_1024(dev, hfmm, workloads, torch)
         result["batch_16x4"] = bench_batch_16x4(dev, hfmm, workloads, torch)
+        result["batch_16_small"] = bench_batch_small(dev, hfmm, workloads, torch)
         result["adjoint_256"] = bench_adjoint_256(dev, hfmm, workloads, torch)
         result["solve_64"] = bench_solve_64(dev, hfmm, workloads, torch)
         result["helm2_dirichlet"] = bench_helm2(dev, hfmm, torch)
@@ -964,6 +1028,7 @@ def main():
         result["m2l_16bit_inputs"] = bench_m2l_rounding(dev, hfmm, workloads, torch, tree, gold, smp)
         result["hbm_kernels"] = bench_hbm(dev, hfmm, workloads, torch, xy)
         result["fmm3_2p20"] = bench_fmm3(dev, hfmm, workloads, torch)
+        result["helm3_solve"] = bench_helm3(dev, hfmm, workloads, torch)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_direct_sum_baseline(w, smp, k, N)

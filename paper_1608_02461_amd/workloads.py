@@ -107,3 +107,10 @@ def random_cloud3(N, seed, dtype=np.complex128):
     xyz = rng.random((N, 3))
     q = complex_normal(rng, N, dtype)
     return xyz, q
+
+
+def helm3_cube(n, k=10.0):
+    """The 3-D model problem (Sec. 7, eq. helm3) on n^3 interior nodes of the
+    unit cube: source 1 (negated for -Laplace - k^2, as in 2-D), u = 0 on the
+    faces.  The paper sets kappa = 0; the Helmholtz kernel needs k > 0."""
+    return {"n": n, "k": k, "b": -np.ones(n ** 3, dtype=np.complex128), "p": 6, "leaf": 64}
