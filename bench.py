@@ -839,7 +839,7 @@ def bench_helm3(dev, hfmm, workloads, torch):
 
 
 PROFILE_CASES = ("apply-2p20-fp64", "pass-1024-fp32", "pass-1024-fp64", "solve-1024", "apply3-2p20-fp32",
-                 "apply3-2p20-fp64")
+                 "apply3-2p20-fp64", "solve3-127-fp32")
 
 
 def copy_probe(torch, dev):
@@ -861,7 +861,10 @@ def profile_case(name, steps, warmup, probe):
                    complex64-preconditioned FGMRES(50) solves of that system with
                    the dispersion-matched k0, p = 6;
     apply3-2p20-fp32 the 3-D oct-tree apply (N = 2^20 in the unit cube, k = 10,
-    apply3-2p20-fp64 leaf 64, p = 6), its stages one after another."""
+    apply3-2p20-fp64 leaf 64, p = 6), its stages one after another;
+    solve3-127-fp32  the 3-D model problem on 127^3 nodes (k = 10, p = 6,
+                   leaf 64): set-up, then `steps` FGMRES(30) solves to 1e-6
+                   with the complex64 volume-potential preconditioner."""
     import torch
     from paper_1608_02461_amd import hfmm, workloads
     dev = torch.device("cuda:0")
@@ -896,6 +899,12 @@ def profile_case(name, steps, warmup, probe):
         # the timed apply: its stages run one after another, as the benchmark's
         # per-stage times (and its M2L roofline) see them
         run = lambda: hfmm.hfmm3_fmm_apply_timed(tree, w["k"], w["p"], q, prec=prec)[0]
+    elif name == "solve3-127-fp32":
+        w = workloads.helm3_cube(127)
+        b3 = torch.from_numpy(w["b"]).to(dev)
+        s3 = hfmm.Solver3(w["n"], w["k"], p=w["p"], leaf_size=w["leaf"], prec=hfmm.FP32)
+        warmup = 0
+        run = lambda: s3.solve(b3, restart=30, rtol=1e-6)
     else:
         raise SystemExit(f"unknown profile case {name}; one of {PROFILE_CASES}")
     for _ in range(warmup):
@@ -905,7 +914,7 @@ def profile_case(name, steps, warmup, probe):
     for _ in range(steps):
         out = run()
     torch.cuda.synchronize()
-    if name == "solve-1024":
+    if name in ("solve-1024", "solve3-127-fp32"):
         log(f"profile {name}: {out[1]}")
     if probe:
         copy_probe(torch, dev)

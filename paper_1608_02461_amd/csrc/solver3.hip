@@ -25,8 +25,9 @@ namespace hfmm {
 
 namespace {
 
-constexpr int kRedBlocks3 = 256;  // blocks of the dot-product partial sums
-constexpr int kMaxDots3 = 8;      // dots per pass of the multi-dot kernel
+constexpr int kRedBlocks3 = 1024;  // blocks of the dot-product partial sums (4 per CU)
+constexpr int kMaxDots3 = 8;       // dots per pass of the multi-dot kernel
+constexpr int kMaxVecs3 = 208;     // V_0 .. V_m for m <= 200, in whole passes of 8
 
 inline int nblk(int64_t n) { return (int)((n + 255) / 256); }
 
@@ -204,8 +205,8 @@ Solver3::Solver3(int n_, double k_, int p_, int leaf, int prec_, hipStream_t st)
     q32.alloc(N);
     phi32.alloc(N);
   }
-  part.alloc((size_t)kMaxDots3 * kRedBlocks3 * 2);
-  cdev.alloc(kMaxDots3);
+  part.alloc((size_t)kMaxVecs3 * kRedBlocks3 * 2);
+  cdev.alloc(kMaxVecs3);
   // the plan (translation tables) now, so that a solve allocates nothing for it
   DevBuf<double2> r0(N), z0(N);
   HFMM_HIP(hipMemsetAsync(r0.p, 0, N * sizeof(double2), st));
@@ -229,35 +230,38 @@ void Solver3::precond(const double2* r, double2* z, hipStream_t st) {
   HFMM_LAUNCH_CHECK();
 }
 
-// conj(V_t) . w for t < nt, summed on the host in a fixed order
+// conj(V_t) . w for t < nt: every pass of 8 writes its own rows of partial
+// sums, one copy back, summed on the host in a fixed order
 void Solver3::mdot(const double2* V, int nt, const double2* x, std::complex<double>* out, hipStream_t st) {
-  std::vector<double> hp((size_t)kMaxDots3 * kRedBlocks3 * 2);
+  HFMM_REQUIRE(nt >= 1 && nt <= kMaxVecs3, "fgmres3: too many basis vectors");
   for (int t0 = 0; t0 < nt; t0 += kMaxDots3) {
     const int c = std::min(kMaxDots3, nt - t0);
-    k3_mdot<<<kRedBlocks3, 256, 0, st>>>(V + t0 * N, N, c, x, part.p);
+    k3_mdot<<<kRedBlocks3, 256, 0, st>>>(V + t0 * N, N, c, x, part.p + (size_t)t0 * kRedBlocks3 * 2);
     HFMM_LAUNCH_CHECK();
-    HFMM_HIP(hipMemcpyAsync(hp.data(), part.p, (size_t)c * kRedBlocks3 * 2 * sizeof(double), hipMemcpyDeviceToHost,
-                            st));
-    HFMM_HIP(hipStreamSynchronize(st));
-    for (int t = 0; t < c; ++t) {
-      double re = 0, im = 0;
-      for (int b = 0; b < kRedBlocks3; ++b) {
-        re += hp[((size_t)t * kRedBlocks3 + b) * 2];
-        im += hp[((size_t)t * kRedBlocks3 + b) * 2 + 1];
-      }
-      out[t0 + t] = {re, im};
+  }
+  std::vector<double> hp((size_t)nt * kRedBlocks3 * 2);
+  HFMM_HIP(hipMemcpyAsync(hp.data(), part.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HFMM_HIP(hipStreamSynchronize(st));
+  for (int t = 0; t < nt; ++t) {
+    double re = 0, im = 0;
+    for (int b = 0; b < kRedBlocks3; ++b) {
+      re += hp[((size_t)t * kRedBlocks3 + b) * 2];
+      im += hp[((size_t)t * kRedBlocks3 + b) * 2 + 1];
     }
+    out[t] = {re, im};
   }
 }
 
+// x -= sum_t V_t c_t: the nt coefficients go up in one copy, then passes of 8
 void Solver3::msub(const double2* V, int nt, const std::complex<double>* c, double2* x, hipStream_t st) {
+  HFMM_REQUIRE(nt >= 1 && nt <= kMaxVecs3, "fgmres3: too many basis vectors");
+  HFMM_HIP(hipMemcpyAsync(cdev.p, c, nt * sizeof(double2), hipMemcpyHostToDevice, st));
   for (int t0 = 0; t0 < nt; t0 += kMaxDots3) {
     const int cn = std::min(kMaxDots3, nt - t0);
-    HFMM_HIP(hipMemcpyAsync(cdev.p, c + t0, cn * sizeof(double2), hipMemcpyHostToDevice, st));
-    k3_msub<<<nblk(N), 256, 0, st>>>(V + t0 * N, N, cn, cdev.p, x);
+    k3_msub<<<nblk(N), 256, 0, st>>>(V + t0 * N, N, cn, cdev.p + t0, x);
     HFMM_LAUNCH_CHECK();
-    HFMM_HIP(hipStreamSynchronize(st));  // cdev is reused
   }
+  HFMM_HIP(hipStreamSynchronize(st));  // the host coefficients and cdev are reused
 }
 
 double Solver3::norm(const double2* x, hipStream_t st) {
