@@ -247,12 +247,15 @@ def bench_solve_1024(dev, hfmm, workloads, torch):
     f = torch.from_numpy(w1024["f"]).to(dev)
     out = {"k": k3, "leaf": w1024["leaf"], "restart": 50}
     k3m = hfmm.hfmm_matched_wavenumber(k3, 1.0 / (n3 + 1))
-    runs = [(f"p{pp}_{name}", pp, prec, k3) for pp in (4, 6, 8)
+    lf = w1024["leaf"]
+    runs = [(f"p{pp}_{name}", pp, prec, k3, lf) for pp in (4, 6, 8)
             for name, prec in (("mixed", hfmm.FP32), ("fp64", hfmm.FP64))]
-    runs += [("p6_mixed_matched_k0", 6, hfmm.FP32, k3m), ("p6_fp64_matched_k0", 6, hfmm.FP64, k3m)]
-    for name, pp, prec, k0 in runs:
+    runs += [("p6_mixed_matched_k0", 6, hfmm.FP32, k3m, lf), ("p6_fp64_matched_k0", 6, hfmm.FP64, k3m, lf)]
+    # the leaf size chosen by the solver's own timing of its two passes (16, 32 or 64)
+    runs += [("p6_mixed_leaf_auto", 6, hfmm.FP32, k3, 0), ("p6_fp64_leaf_auto", 6, hfmm.FP64, k3, 0)]
+    for name, pp, prec, k0, leaf in runs:
         t0 = time.perf_counter()
-        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=pp, leaf_size=w1024["leaf"], prec=prec)
+        s = hfmm.Solver(n3, k0, k2_const=k3 ** 2, p=pp, leaf_size=leaf, prec=prec)
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         dt, x, info = timed_solves(s, f, 2, restart=50, rtol=1e-6, maxit=3000)
@@ -260,7 +263,7 @@ def bench_solve_1024(dev, hfmm, workloads, torch):
                      "iters": info["iters"], "rel_res_true": info["rel_res_true"], "converged": info["converged"],
                      "ms_precond_per_iter": round(info["ms_precond"] / max(1, info["iters"]), 4),
                      "ms_krylov_per_iter": round(info["ms_krylov"] / max(1, info["iters"]), 4),
-                     "setup_s": round(setup, 3), "levels": s.info()["levels"]}
+                     "setup_s": round(setup, 3), "levels": s.info()["levels"], "leaf": s.info()["leaf_size"]}
         log(f"1024^2 solve {name}: {out[name]}")
         del s
     for pp in (4, 6, 8):
