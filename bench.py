@@ -416,6 +416,16 @@ def bench_solve_64(dev, hfmm, workloads, torch):
     dt, x, info = timed_solves(s, f1, 5, restart=30, rtol=1e-6)
     out = {"solves_s": round(1 / dt, 3), "iters": info["iters"], "rel_res_true": info["rel_res_true"],
            "setup_ms": round(info["ms_setup"], 3)}
+    # the same solve in graph mode (the batched entry point with one problem):
+    # its Arnoldi step replayed from a captured graph, flags read every 4 steps
+    hfmm.hfmm_fgmres_solve_batched([s], [f1], restart=30, rtol=1e-6, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        _, ig = hfmm.hfmm_fgmres_solve_batched([s], [f1], restart=30, rtol=1e-6, use_graph=True)
+    torch.cuda.synchronize()
+    dg = (time.perf_counter() - t0) / 5
+    out["graph"] = {"solves_s": round(1 / dg, 3), "iters": ig[0]["iters"], "rel_res_true": ig[0]["rel_res_true"]}
     log(f"64^2 solve: {out}")
     return out
 
