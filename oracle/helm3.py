@@ -82,3 +82,14 @@ def precond3_apply_fmm(n, k, r, p, leaf):
     xyz = grid3(n)
     r = np.asarray(r, dtype=np.complex128)
     return fmm3.fmm3_apply(xyz, h ** 3 * r, k, p, leaf) + self_term3(k, h) * r
+
+
+def precond3_apply_at(n, k, r, idx):
+    """The dense form at the nodes idx only: h^3 sum_{j != i} G(|x_i - x_j|) r_j
+    + c_self r_i for i in idx (the direct sum of the oracle, four targets at a
+    time so that a full-size grid fits in memory)."""
+    h = 1.0 / (n + 1)
+    xyz = grid3(n)
+    r = np.asarray(r, dtype=np.complex128)
+    idx = np.asarray(idx)
+    return h ** 3 * fmm3.direct_sum3(xyz, r, k, targets=xyz[idx], chunk=4) + self_term3(k, h) * r[idx]

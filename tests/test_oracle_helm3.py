@@ -76,3 +76,12 @@ def test_precond3_fmm_form_matches_dense_and_solve():
     # and it helps: fewer iterations than without a preconditioner
     _, info0 = fgmres.fgmres(lambda v: A @ v, lambda v: v, b, restart=30, rtol=1e-8)
     assert info["iters"] < info0["iters"]
+
+
+def test_precond3_at_sampled_nodes_equals_dense():
+    n, k = 5, 3.0
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(n ** 3) + 1j * rng.standard_normal(n ** 3)
+    idx = np.array([0, 7, 62, 124])
+    np.testing.assert_allclose(helm3.precond3_apply_at(n, k, r, idx), helm3.precond3_apply(n, k, r)[idx],
+                               rtol=1e-14, atol=0)
