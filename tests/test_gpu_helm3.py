@@ -92,3 +92,29 @@ def test_solver3_argument_errors():
     s = hfmm.Solver3(8, 5.0, leaf_size=8)
     with pytest.raises(hfmm.HFMMError):
         s.solve(to_dev(np.ones(512, dtype=np.complex128)), restart=0)
+
+
+def test_precond3_full_size_sampled():
+    # the benchmark's grid (127^3 = 2,048,383 nodes, k = 10, leaf 64, depth 5;
+    # nodes on every fourth grid plane lie on leaf faces) against the oracle's
+    # dense form at 24 seeded nodes.  Properties that hold at any size: the
+    # FP64 error is an expansion error (below 1e-3 at p = 6) and falls by more
+    # than 4x from p = 6 to p = 10; FP32 and FP64 agree to 1e-5.
+    n, k = 127, 10.0
+    N = n ** 3
+    rng = np.random.default_rng(31)
+    r = workloads.complex_normal(rng, N)
+    idx = np.sort(rng.choice(N, 24, replace=False))
+    ref = oh3.precond3_apply_at(n, k, r, idx)
+    say(f"precond3 full size n={n}: oracle done")
+    rd = to_dev(r)
+    z = {}
+    for name, p, prec in (("fp64_p6", 6, hfmm.FP64), ("fp32_p6", 6, hfmm.FP32), ("fp64_p10", 10, hfmm.FP64)):
+        s = hfmm.Solver3(n, k, p=p, leaf_size=64, prec=prec)
+        assert s.info()["levels"] == 5
+        z[name] = to_np(s.precond_apply(rd))
+        s.close()
+        say(f"  {name}: error on the samples {rel(z[name][idx], ref):.2e}")
+    e6, e10 = rel(z["fp64_p6"][idx], ref), rel(z["fp64_p10"][idx], ref)
+    assert e6 <= 1e-3 and e10 <= e6 / 4
+    assert rel(z["fp32_p6"], z["fp64_p6"]) <= 1e-5
