@@ -258,3 +258,32 @@ def test_m2l_input_rounding(mode, bound):
     assert np.array_equal(to_np(hfmm.hfmm_fmm_apply(t, k, p, q32, prec=hfmm.FP32)), base32)
     with pytest.raises(hfmm.HFMMError):
         hfmm._check(hfmm.lib().hfmm_tree_set_m2l_input_rounding(t.handle, 3))
+
+
+def _binade_ladder(extra, seed):
+    """Points at 0.5 +- 0.45 * 2^(-i/4) on both axes (i < 80), so that pair
+    distances, and (k r)^2 with them, cover about 40 binades of the FP64
+    near field's table-driven log2, plus `extra` uniform points."""
+    d = 0.45 * 2.0 ** (-np.arange(80) / 4.0)
+    pts = [(0.5 + s * v, 0.5) for v in d for s in (1, -1)] + [(0.5, 0.5 + s * v) for v in d for s in (1, -1)]
+    rng = np.random.default_rng(seed)
+    xy = np.concatenate([np.array(pts), rng.random((extra, 2))])
+    q = workloads.complex_normal(rng, len(xy))
+    return xy, q
+
+
+def test_fp64_near_field_over_many_binades():
+    # all pairs (one leaf): every pair goes through the FP64 near field, whose
+    # log2 is the table-driven reduction; k r from about 1e-5 to 9
+    k = 10.0
+    xy, q = _binade_ladder(0, 3)
+    ref = kernel.direct_sum(xy, q, k)
+    t = hfmm.Tree(to_dev(xy), leaf_size=0)
+    f = to_np(hfmm.hfmm_fmm_apply(t, k, 6, to_dev(q), prec=hfmm.FP64))
+    assert np.abs(f - ref).max() <= 1e-12 * np.abs(ref).max()
+    # on a tree of depth >= 2 the same pairs go through the leaf-block kernel
+    xy, q = _binade_ladder(3000, 4)
+    t = hfmm.Tree(to_dev(xy), leaf_size=16)
+    assert t.info()["levels"] >= 2
+    f = to_np(hfmm.hfmm_fmm_apply(t, k, 8, to_dev(q), prec=hfmm.FP64))
+    assert rel(f, ofmm.fmm(xy, q, k, 8, 16)) <= 1e-10
